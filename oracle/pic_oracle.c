@@ -1,0 +1,857 @@
+/*
+ * pic_oracle.c -- plain FP64 CPU oracle of the 1D3V electrostatic PIC-MCC
+ * method (paper Section 1: explicit leapfrog, Boris pusher, null-collision
+ * Monte Carlo, tabulated cross sections, walls and secondary emission, the
+ * field computed on a mesh from the particles' own charge).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path.
+ *
+ * The paper fixes the scheme but none of its numerical details; every reading
+ * taken here is stated where it is used (linear cloud-in-cell weighting, wall
+ * nodes of half volume, Gauss's law at the walls, isotropic scattering with
+ * the Vahedi-Surendra rotation, uniform ionization energy sharing, charge
+ * exchange with a thermal neutral, a half-Maxwellian flux for secondaries,
+ * Philox4x32-10 keyed by (seed, particle id, step)).
+ *
+ * Plain loops, sequential, FP64 throughout.
+ */
+#include "pic_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define K_B 1.380649e-23
+#define TWO_PI 6.283185307179586476925286766559
+
+typedef struct {
+    double *x, *vx, *vy, *vz;
+    uint32_t* id;
+    int64_t n, cap;
+    uint32_t next_id;
+} pop_t;
+
+typedef struct {
+    int32_t kind;
+    double th;
+    int32_t n;
+    double *e, *s;
+} chan_t;
+
+typedef struct {          /* a particle waiting to be appended after the sweep */
+    double x, vx, vy, vz;
+} birth_t;
+
+typedef struct {
+    birth_t* b;
+    int64_t n, cap;
+} blist_t;
+
+struct orc_sim {
+    orc_config c;
+    double dx;
+    int32_t nn;                       /* mesh nodes */
+    pop_t p[ORC_MAX_SPECIES];
+    chan_t ch[ORC_MAX_SPECIES][ORC_MAX_CHAN];
+    int32_t nch[ORC_MAX_SPECIES];
+    double numax[ORC_MAX_SPECIES];
+    uint32_t t32[ORC_MAX_SPECIES];
+    double *rho, *phi, *ef;
+    double* sum[ORC_MAX_SPECIES];     /* weight sums per node */
+    double* dens[ORC_MAX_SPECIES];
+    uint64_t step;
+    orc_counters cnt;
+    double ke[ORC_MAX_SPECIES], fe;
+    blist_t births[ORC_MAX_SPECIES];
+};
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+ * multiply-xor round function on a 128-bit counter, the 64-bit key bumped by
+ * the Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1) from the top 23 bits: an odd multiple of 2^-24, exact in
+ * both binary32 and binary64, never 0 or 1. */
+double orc_u01(uint32_t x)
+{
+    return (double)(((x >> 9) << 1) | 1u) * (1.0 / 16777216.0);
+}
+
+static void draw(const orc_sim* s, uint32_t id, uint32_t step, int32_t species,
+                 uint32_t call, uint32_t out[4])
+{
+    uint32_t ctr[4] = {id, step, ((uint32_t)species << 24) | call, 0u};
+    uint32_t key[2] = {(uint32_t)(s->c.seed & 0xffffffffu), (uint32_t)(s->c.seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Box-Muller: two standard normals from two uniforms. */
+static void box_muller(double ua, double ub, double* g0, double* g1)
+{
+    double r = sqrt(-2.0 * log(ua));
+    *g0 = r * cos(TWO_PI * ub);
+    *g1 = r * sin(TWO_PI * ub);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boris push over a time h: half electric kick, magnetic rotation with
+ * t = (q/m) B h/2 and s = 2t/(1+|t|^2), half electric kick. */
+void orc_boris(double v[3], const double e[3], const double b[3], double qm, double h)
+{
+    double a = 0.5 * qm * h;
+    double vm[3] = {v[0] + a * e[0], v[1] + a * e[1], v[2] + a * e[2]};
+    double t[3] = {a * b[0], a * b[1], a * b[2]};
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double sf = 2.0 / (1.0 + t2);
+    double sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
+    double vp[3] = {vm[0] + (vm[1] * t[2] - vm[2] * t[1]),
+                    vm[1] + (vm[2] * t[0] - vm[0] * t[2]),
+                    vm[2] + (vm[0] * t[1] - vm[1] * t[0])};
+    double vq[3] = {vm[0] + (vp[1] * sv[2] - vp[2] * sv[1]),
+                    vm[1] + (vp[2] * sv[0] - vp[0] * sv[2]),
+                    vm[2] + (vp[0] * sv[1] - vp[1] * sv[0])};
+    v[0] = vq[0] + a * e[0];
+    v[1] = vq[1] + a * e[1];
+    v[2] = vq[2] + a * e[2];
+}
+
+/* New direction after scattering by polar angle chi and azimuth phi about the
+ * incident unit direction d (Vahedi & Surendra 1995 form, reference axis x;
+ * when d is within 1e-6 of the x axis the y axis is used instead). */
+void orc_rotate(const double d[3], double cos_chi, double phi, double out[3])
+{
+    double sin_chi = sqrt(fmax(0.0, 1.0 - cos_chi * cos_chi));
+    double cp = cos(phi), sp = sin(phi);
+    double a, b, c;                          /* components in the rotated frame */
+    int alt;
+    double ct = d[0];
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    if (st > 1e-6) {
+        a = d[0]; b = d[1]; c = d[2];
+        alt = 0;
+    } else {                                  /* cyclic relabel (y, z, x) */
+        a = d[1]; b = d[2]; c = d[0];
+        ct = a;
+        st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        alt = 1;
+    }
+    double A = sin_chi / st;
+    double na = a * cos_chi + sin_chi * cp * st;
+    double nb = b * cos_chi + A * (sp * c - cp * a * b);
+    double nc = c * cos_chi - A * (sp * b + cp * a * c);
+    if (!alt) {
+        out[0] = na; out[1] = nb; out[2] = nc;
+    } else {
+        out[1] = na; out[2] = nb; out[0] = nc;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+static int is_periodic(const orc_sim* s) { return s->c.bc == ORC_BC_PERIODIC; }
+
+static double node_volume(const orc_sim* s, int i)
+{
+    if (!is_periodic(s) && (i == 0 || i == s->nn - 1)) return 0.5 * s->dx;
+    return s->dx;
+}
+
+/* Cell and in-cell fraction of position x (linear cloud-in-cell weighting,
+ * nodes at i*dx). */
+static void locate(const orc_sim* s, double x, int64_t* c, int64_t* c1, double* f)
+{
+    int64_t nc = s->c.n_cells;
+    double xi = x / s->dx;
+    int64_t k = (int64_t)floor(xi);
+    double fr = xi - (double)k;
+    if (is_periodic(s)) {
+        if (k >= nc) { k -= nc; }
+        if (k < 0) { k += nc; }
+        *c = k;
+        *c1 = (k + 1 == nc) ? 0 : k + 1;
+    } else {
+        if (k >= nc) { k = nc - 1; fr = 1.0; }
+        if (k < 0) { k = 0; fr = 0.0; }
+        *c = k;
+        *c1 = k + 1;
+    }
+    *f = fr;
+}
+
+static double gather(const orc_sim* s, double x)
+{
+    int64_t c, c1;
+    double f;
+    locate(s, x, &c, &c1, &f);
+    return (1.0 - f) * s->ef[c] + f * s->ef[c1];
+}
+
+static double voltage(const orc_sim* s, double t)
+{
+    if (is_periodic(s)) return 0.0;
+    return s->c.v_amp * sin(TWO_PI * s->c.v_freq * t + s->c.v_phase);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cross sections: linear interpolation in ln(eps), clamped to the end values
+ * outside the table, zero below the channel threshold. */
+static double sigma_at(const chan_t* ch, double eps)
+{
+    if (eps < ch->th) return 0.0;
+    if (eps <= ch->e[0]) return ch->s[0];
+    if (eps >= ch->e[ch->n - 1]) return ch->s[ch->n - 1];
+    int lo = 0, hi = ch->n - 1;            /* e[lo] <= eps < e[hi] */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (ch->e[mid] <= eps) lo = mid; else hi = mid;
+    }
+    double t = (log(eps) - log(ch->e[lo])) / (log(ch->e[hi]) - log(ch->e[lo]));
+    return ch->s[lo] + t * (ch->s[hi] - ch->s[lo]);
+}
+
+static int electron_kind(int kind)
+{
+    return kind == ORC_XS_ELASTIC || kind == ORC_XS_EXCITATION || kind == ORC_XS_IONIZATION;
+}
+
+/* Maximum collision frequency of a species and the 32-bit candidate threshold
+ * T32 = floor(P_null 2^32), P_null = 1 - exp(-nu_max dt).  Electron-type
+ * projectiles: 1.05 x the maximum of n_g sum_k sigma_k(eps) v(eps) over a
+ * log-uniform grid ten times finer than the longest table.  Ion-type
+ * projectiles: n_g max(sum_k sigma_k) g_max, g_max the relative speed of a
+ * projectile at the top table energy plus six neutral thermal speeds. */
+static void update_numax(orc_sim* s, int sp)
+{
+    int nch = s->nch[sp];
+    if (nch == 0) { s->numax[sp] = 0.0; s->t32[sp] = 0; return; }
+    double elo = s->ch[sp][0].e[0], ehi = s->ch[sp][0].e[s->ch[sp][0].n - 1];
+    int nmax = 0;
+    for (int k = 0; k < nch; ++k) {
+        if (s->ch[sp][k].e[0] < elo) elo = s->ch[sp][k].e[0];
+        if (s->ch[sp][k].e[s->ch[sp][k].n - 1] > ehi) ehi = s->ch[sp][k].e[s->ch[sp][k].n - 1];
+        if (s->ch[sp][k].n > nmax) nmax = s->ch[sp][k].n;
+    }
+    int m = 10 * nmax;
+    double lelo = log(elo), lehi = log(ehi);
+    double mass = s->c.sp[sp].mass, ng = s->c.gas_density;
+    double best = 0.0;
+    int ion = !electron_kind(s->ch[sp][0].kind);
+    for (int j = 0; j < m; ++j) {
+        double eps = exp(lelo + (double)j * (lehi - lelo) / (double)(m - 1));
+        double sig = 0.0;
+        for (int k = 0; k < nch; ++k) sig += sigma_at(&s->ch[sp][k], eps);
+        double val = ion ? sig : ng * sig * sqrt(2.0 * s->c.e_unit * eps / mass);
+        if (val > best) best = val;
+    }
+    double numax;
+    if (ion) {
+        double gmax = sqrt(2.0 * s->c.e_unit * ehi / mass) +
+                      6.0 * sqrt(K_B * s->c.gas_temp / s->c.gas_mass);
+        numax = ng * best * gmax;
+    } else {
+        numax = 1.05 * best;
+    }
+    double pnull = 1.0 - exp(-numax * s->c.dt);
+    double t = floor(pnull * 4294967296.0);
+    if (t > 4294967295.0) t = 4294967295.0;
+    s->numax[sp] = numax;
+    s->t32[sp] = (uint32_t)t;
+}
+
+/* ------------------------------------------------------------------------ */
+static int pop_alloc(pop_t* p, int64_t cap)
+{
+    p->cap = cap;
+    p->n = 0;
+    p->next_id = 0;
+    size_t n = (size_t)(cap > 0 ? cap : 1);
+    p->x = calloc(n, sizeof(double));
+    p->vx = calloc(n, sizeof(double));
+    p->vy = calloc(n, sizeof(double));
+    p->vz = calloc(n, sizeof(double));
+    p->id = calloc(n, sizeof(uint32_t));
+    return (p->x && p->vx && p->vy && p->vz && p->id) ? ORC_OK : ORC_ENOMEM;
+}
+
+int orc_create(const orc_config* cfg, orc_sim** out)
+{
+    if (!cfg || !out) return ORC_EINVAL;
+    if (cfg->n_cells < 2 || cfg->length <= 0.0 || cfg->dt <= 0.0 || cfg->eps0 <= 0.0 ||
+        cfg->n_species < 1 || cfg->n_species > ORC_MAX_SPECIES ||
+        (cfg->bc != ORC_BC_PERIODIC && cfg->bc != ORC_BC_DIRICHLET))
+        return ORC_EINVAL;
+    for (int k = 0; k < cfg->n_species; ++k) {
+        if (cfg->sp[k].mass <= 0.0 || cfg->sp[k].capacity < cfg->sp[k].n_init ||
+            cfg->sp[k].n_init < 0)
+            return ORC_EINVAL;
+    }
+    orc_sim* s = calloc(1, sizeof(orc_sim));
+    if (!s) return ORC_ENOMEM;
+    s->c = *cfg;
+    s->dx = cfg->length / cfg->n_cells;
+    s->nn = cfg->bc == ORC_BC_PERIODIC ? cfg->n_cells : cfg->n_cells + 1;
+    int rc = ORC_OK;
+    for (int k = 0; k < cfg->n_species; ++k) {
+        if (pop_alloc(&s->p[k], cfg->sp[k].capacity) != ORC_OK) rc = ORC_ENOMEM;
+        s->sum[k] = calloc((size_t)s->nn, sizeof(double));
+        s->dens[k] = calloc((size_t)s->nn, sizeof(double));
+        if (!s->sum[k] || !s->dens[k]) rc = ORC_ENOMEM;
+    }
+    s->rho = calloc((size_t)s->nn, sizeof(double));
+    s->phi = calloc((size_t)s->nn, sizeof(double));
+    s->ef = calloc((size_t)s->nn, sizeof(double));
+    if (!s->rho || !s->phi || !s->ef) rc = ORC_ENOMEM;
+    if (rc != ORC_OK) { orc_free(s); return rc; }
+    *out = s;
+    return ORC_OK;
+}
+
+void orc_free(orc_sim* s)
+{
+    if (!s) return;
+    for (int k = 0; k < ORC_MAX_SPECIES; ++k) {
+        free(s->p[k].x); free(s->p[k].vx); free(s->p[k].vy); free(s->p[k].vz); free(s->p[k].id);
+        free(s->sum[k]); free(s->dens[k]);
+        free(s->births[k].b);
+        for (int j = 0; j < ORC_MAX_CHAN; ++j) { free(s->ch[k][j].e); free(s->ch[k][j].s); }
+    }
+    free(s->rho); free(s->phi); free(s->ef);
+    free(s);
+}
+
+int orc_load_xsec(orc_sim* s, int32_t sp, int32_t kind, double th, int32_t n,
+                  const double* e, const double* sig)
+{
+    if (!s || sp < 0 || sp >= s->c.n_species || n < 2 || !e || !sig) return ORC_EINVAL;
+    if (kind < ORC_XS_ELASTIC || kind > ORC_XS_ION_ISO) return ORC_EINVAL;
+    if (s->nch[sp] >= ORC_MAX_CHAN) return ORC_EINVAL;
+    if (s->c.gas_density <= 0.0 || s->c.gas_mass <= 0.0) return ORC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!(e[i] > 0.0) || !(sig[i] >= 0.0) || !isfinite(sig[i]) || !isfinite(e[i]))
+            return ORC_EINVAL;
+        if (i > 0 && !(e[i] > e[i - 1])) return ORC_EINVAL;
+    }
+    if (s->nch[sp] > 0 && electron_kind(s->ch[sp][0].kind) != electron_kind(kind))
+        return ORC_EINVAL;
+    if (kind == ORC_XS_IONIZATION && (sp != 0 || s->c.n_species < 2)) return ORC_EINVAL;
+    chan_t* ch = &s->ch[sp][s->nch[sp]];
+    ch->e = malloc((size_t)n * sizeof(double));
+    ch->s = malloc((size_t)n * sizeof(double));
+    if (!ch->e || !ch->s) return ORC_ENOMEM;
+    memcpy(ch->e, e, (size_t)n * sizeof(double));
+    memcpy(ch->s, sig, (size_t)n * sizeof(double));
+    ch->n = n;
+    ch->kind = kind;
+    ch->th = th;
+    s->nch[sp] += 1;
+    update_numax(s, sp);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Charge density on the nodes: each particle gives (1-f) to node c and f to
+ * node c+1; a node's density is weight x sum / node volume (dx, or dx/2 at a
+ * wall node). */
+static void deposit(orc_sim* s)
+{
+    int nn = s->nn;
+    for (int i = 0; i < nn; ++i) s->rho[i] = s->c.rho_bg;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        double* S = s->sum[k];
+        for (int i = 0; i < nn; ++i) S[i] = 0.0;
+        for (int64_t p = 0; p < s->p[k].n; ++p) {
+            int64_t c, c1;
+            double f;
+            locate(s, s->p[k].x[p], &c, &c1, &f);
+            S[c] += 1.0 - f;
+            S[c1] += f;
+        }
+        for (int i = 0; i < nn; ++i) {
+            s->dens[k][i] = s->c.sp[k].weight * S[i] / node_volume(s, i);
+            s->rho[i] += s->c.sp[k].charge * s->dens[k][i];
+        }
+    }
+}
+
+/* Poisson -(phi[i-1] - 2 phi[i] + phi[i+1]) / dx^2 = rho[i] / eps0.
+ * Dirichlet: phi[0] = V(t), phi[N] = 0, Thomas algorithm on the interior.
+ * Periodic: the mean charge is removed, the gauge phi[0] = 0 turns the
+ * problem into a Dirichlet one on nodes 1..N-1, and phi is then shifted to
+ * zero mean.  Field: central differences inside; at a wall node Gauss's law
+ * over the half cell, E0 = -(phi1-phi0)/dx - rho0 dx/(2 eps0) and
+ * EN = -(phiN-phiN-1)/dx + rhoN dx/(2 eps0). */
+static int solve(const orc_sim* s, double t, const double* rho, double* phi, double* ef)
+{
+    int nn = s->nn;
+    double dx = s->dx, e0 = s->c.eps0;
+    if (!s->c.field_solve) {
+        for (int i = 0; i < nn; ++i) { phi[i] = 0.0; ef[i] = 0.0; }
+        return ORC_OK;
+    }
+    double* g = malloc((size_t)nn * sizeof(double));
+    double* cp = malloc((size_t)nn * sizeof(double));
+    double* dp = malloc((size_t)nn * sizeof(double));
+    if (!g || !cp || !dp) { free(g); free(cp); free(dp); return ORC_ENOMEM; }
+    double left, right;
+    if (is_periodic(s)) {
+        double mean = 0.0;
+        for (int i = 0; i < nn; ++i) mean += rho[i];
+        mean /= nn;
+        for (int i = 0; i < nn; ++i) g[i] = (rho[i] - mean) * dx * dx / e0;
+        left = 0.0;
+        right = 0.0;
+    } else {
+        for (int i = 0; i < nn; ++i) g[i] = rho[i] * dx * dx / e0;
+        left = voltage(s, t);
+        right = 0.0;
+    }
+    /* interior unknowns 1..m, m = (periodic ? nn-1 : nn-2); boundary values
+     * phi[0] = left and phi[m+1] = right. */
+    int m = is_periodic(s) ? nn - 1 : nn - 2;
+    for (int i = 1; i <= m; ++i) {
+        double d = g[i];
+        if (i == 1) d += left;
+        if (i == m) d += right;
+        double b = 2.0;
+        if (i == 1) {
+            cp[i] = -1.0 / b;
+            dp[i] = d / b;
+        } else {
+            double den = b + cp[i - 1];         /* b - a c'_{i-1}, a = -1 */
+            cp[i] = -1.0 / den;
+            dp[i] = (d + dp[i - 1]) / den;
+        }
+    }
+    phi[0] = left;
+    if (!is_periodic(s)) phi[nn - 1] = right;
+    for (int i = m; i >= 1; --i) {
+        double nxt = (i == m) ? 0.0 : phi[i + 1];   /* phi[m+1] already moved to the rhs */
+        phi[i] = dp[i] - cp[i] * nxt;
+    }
+    if (is_periodic(s)) {
+        double mean = 0.0;
+        for (int i = 0; i < nn; ++i) mean += phi[i];
+        mean /= nn;
+        for (int i = 0; i < nn; ++i) phi[i] -= mean;
+        for (int i = 0; i < nn; ++i) {
+            int im = (i == 0) ? nn - 1 : i - 1, ip = (i == nn - 1) ? 0 : i + 1;
+            ef[i] = (phi[im] - phi[ip]) / (2.0 * dx);
+        }
+    } else {
+        for (int i = 1; i < nn - 1; ++i) ef[i] = (phi[i - 1] - phi[i + 1]) / (2.0 * dx);
+        ef[0] = -(phi[1] - phi[0]) / dx - rho[0] * dx / (2.0 * e0);
+        ef[nn - 1] = -(phi[nn - 1] - phi[nn - 2]) / dx + rho[nn - 1] * dx / (2.0 * e0);
+    }
+    free(g); free(cp); free(dp);
+    return ORC_OK;
+}
+
+static double field_energy(const orc_sim* s)
+{
+    double fe = 0.0;
+    for (int i = 0; i < s->nn; ++i) fe += s->ef[i] * s->ef[i] * node_volume(s, i);
+    return 0.5 * s->c.eps0 * fe;
+}
+
+int orc_refresh_field(orc_sim* s)
+{
+    if (!s) return ORC_EINVAL;
+    deposit(s);
+    int rc = solve(s, (double)s->step * s->c.dt, s->rho, s->phi, s->ef);
+    s->fe = field_energy(s);
+    return rc;
+}
+
+int orc_poisson(const orc_sim* s, double t, const double* rho_in, double* phi_out,
+                double* e_out)
+{
+    if (!s) return ORC_EINVAL;
+    int nn = s->nn;
+    const double* rho = rho_in ? rho_in : s->rho;
+    double* phi = malloc((size_t)nn * sizeof(double));
+    double* ef = malloc((size_t)nn * sizeof(double));
+    if (!phi || !ef) { free(phi); free(ef); return ORC_ENOMEM; }
+    int rc = solve(s, t, rho, phi, ef);
+    if (phi_out) memcpy(phi_out, phi, (size_t)nn * sizeof(double));
+    if (e_out) memcpy(e_out, ef, (size_t)nn * sizeof(double));
+    free(phi); free(ef);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Loading: position from one Philox draw (stratified (j+u)L/N or uniform uL),
+ * optionally mapped through the inverse CDF of n0 (1 + eps cos kx) by Newton's
+ * method; velocity drift + vth x three Box-Muller normals. */
+int orc_load(orc_sim* s)
+{
+    if (!s) return ORC_EINVAL;
+    double L = s->c.length;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        const orc_species* sp = &s->c.sp[k];
+        pop_t* p = &s->p[k];
+        int64_t n = sp->load == ORC_LOAD_NONE ? 0 : sp->n_init;
+        for (int64_t j = 0; j < n; ++j) {
+            uint32_t r0[4], r1[4];
+            draw(s, (uint32_t)j, 0xFFFFFFFFu, k, 0u, r0);
+            draw(s, (uint32_t)j, 0xFFFFFFFFu, k, 1u, r1);
+            double u = orc_u01(r0[0]);
+            double x0 = sp->load == ORC_LOAD_STRATIFIED ? ((double)j + u) * L / (double)n : u * L;
+            double x = x0;
+            if (s->c.perturb_eps != 0.0 && s->c.perturb_mode != 0) {
+                double kw = TWO_PI * s->c.perturb_mode / L, ep = s->c.perturb_eps;
+                for (int it = 0; it < 60; ++it) {
+                    double fx = x + ep / kw * sin(kw * x) - x0;
+                    double d = fx / (1.0 + ep * cos(kw * x));
+                    x -= d;
+                    if (fabs(d) <= 1e-15 * L) break;
+                }
+            }
+            if (x < 0.0) x += L;
+            if (x >= L) x -= L;
+            double g0, g1, g2, g3;
+            box_muller(orc_u01(r1[0]), orc_u01(r1[1]), &g0, &g1);
+            box_muller(orc_u01(r1[2]), orc_u01(r1[3]), &g2, &g3);
+            p->x[j] = x;
+            p->vx[j] = sp->drift[0] + sp->vth * g0;
+            p->vy[j] = sp->drift[1] + sp->vth * g1;
+            p->vz[j] = sp->drift[2] + sp->vth * g2;
+            p->id[j] = (uint32_t)j;
+        }
+        p->n = n;
+        p->next_id = (uint32_t)n;
+    }
+    s->step = 0;
+    int rc = orc_refresh_field(s);
+    if (rc != ORC_OK) return rc;
+    /* leapfrog start: v^{-1/2} = Boris(v^0; E^0, B, -dt/2) */
+    for (int k = 0; k < s->c.n_species; ++k) {
+        pop_t* p = &s->p[k];
+        double qm = s->c.sp[k].charge / s->c.sp[k].mass;
+        for (int64_t j = 0; j < p->n; ++j) {
+            double e[3] = {gather(s, p->x[j]) + s->c.e_ext[0], s->c.e_ext[1], s->c.e_ext[2]};
+            double v[3] = {p->vx[j], p->vy[j], p->vz[j]};
+            orc_boris(v, e, s->c.b_ext, qm, -0.5 * s->c.dt);
+            p->vx[j] = v[0]; p->vy[j] = v[1]; p->vz[j] = v[2];
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_set_particles(orc_sim* s, int32_t k, int64_t n, const double* x, const double* vx,
+                      const double* vy, const double* vz, const uint32_t* id,
+                      uint32_t next_id)
+{
+    if (!s || k < 0 || k >= s->c.n_species || n < 0 || n > s->p[k].cap) return ORC_EINVAL;
+    pop_t* p = &s->p[k];
+    for (int64_t j = 0; j < n; ++j) {
+        if (!(x[j] >= 0.0 && x[j] < s->c.length)) return ORC_EINVAL;
+        if (!isfinite(vx[j]) || !isfinite(vy[j]) || !isfinite(vz[j])) return ORC_ENUMERIC;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        p->x[j] = x[j]; p->vx[j] = vx[j]; p->vy[j] = vy[j]; p->vz[j] = vz[j];
+        p->id[j] = id[j];
+    }
+    p->n = n;
+    p->next_id = next_id;
+    return ORC_OK;
+}
+
+int orc_get_particles(const orc_sim* s, int32_t k, int64_t cap, double* x, double* vx,
+                      double* vy, double* vz, uint32_t* id, int64_t* n, uint32_t* next_id)
+{
+    if (!s || k < 0 || k >= s->c.n_species) return ORC_EINVAL;
+    const pop_t* p = &s->p[k];
+    if (n) *n = p->n;
+    if (next_id) *next_id = p->next_id;
+    if (cap < p->n) return x ? ORC_EINVAL : ORC_OK;
+    for (int64_t j = 0; j < p->n; ++j) {
+        if (x) x[j] = p->x[j];
+        if (vx) vx[j] = p->vx[j];
+        if (vy) vy[j] = p->vy[j];
+        if (vz) vz[j] = p->vz[j];
+        if (id) id[j] = p->id[j];
+    }
+    return ORC_OK;
+}
+
+int orc_set_step(orc_sim* s, uint64_t step) { if (!s) return ORC_EINVAL; s->step = step; return ORC_OK; }
+uint64_t orc_get_step(const orc_sim* s) { return s ? s->step : 0; }
+
+/* ------------------------------------------------------------------------ */
+static int push_birth(blist_t* l, double x, double vx, double vy, double vz)
+{
+    if (l->n == l->cap) {
+        int64_t nc = l->cap ? 2 * l->cap : 1024;
+        birth_t* nb = realloc(l->b, (size_t)nc * sizeof(birth_t));
+        if (!nb) return ORC_ENOMEM;
+        l->b = nb;
+        l->cap = nc;
+    }
+    l->b[l->n].x = x; l->b[l->n].vx = vx; l->b[l->n].vy = vy; l->b[l->n].vz = vz;
+    l->n += 1;
+    return ORC_OK;
+}
+
+/* Null-collision Monte Carlo for one particle of species k at position x with
+ * velocity v (modified in place).  Draw 0 decides candidacy by the integer
+ * test x0 < T32, picks the channel with u1 nu_max against the running sum of
+ * nu_k = n_g sigma_k v, and gives the scattering angles cos(chi) = 1 - 2 u2,
+ * phi = 2 pi u3. */
+static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
+{
+    int nch = s->nch[k];
+    uint32_t r[4];
+    draw(s, id, (uint32_t)s->step, k, 0u, r);
+    if (r[0] >= s->t32[k]) return ORC_OK;
+    s->cnt.candidates[k] += 1;
+    double m = s->c.sp[k].mass, M = s->c.gas_mass, ng = s->c.gas_density;
+    double eu = s->c.e_unit;
+    int ion = !electron_kind(s->ch[k][0].kind);
+    double nu[ORC_MAX_CHAN];
+    double vn[3] = {0.0, 0.0, 0.0};
+    double speed, eps;
+    if (!ion) {
+        double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        speed = sqrt(v2);
+        eps = 0.5 * m * v2 / eu;
+    } else {
+        uint32_t r3[4];
+        draw(s, id, (uint32_t)s->step, k, 3u, r3);
+        double g0, g1, g2, g3, vt = sqrt(K_B * s->c.gas_temp / M);
+        box_muller(orc_u01(r3[0]), orc_u01(r3[1]), &g0, &g1);
+        box_muller(orc_u01(r3[2]), orc_u01(r3[3]), &g2, &g3);
+        vn[0] = vt * g0; vn[1] = vt * g1; vn[2] = vt * g2;
+        double gx = v[0] - vn[0], gy = v[1] - vn[1], gz = v[2] - vn[2];
+        double g2s = gx * gx + gy * gy + gz * gz;
+        speed = sqrt(g2s);
+        eps = 0.5 * m * g2s / eu;
+    }
+    double total = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        nu[c] = ng * sigma_at(&s->ch[k][c], eps) * speed;
+        total += nu[c];
+    }
+    if (total > s->numax[k]) s->cnt.violations[k] += 1;
+    double u1 = orc_u01(r[1]);
+    double target = u1 * s->numax[k];
+    double cum = 0.0;
+    int chosen = -1;
+    for (int c = 0; c < nch; ++c) {
+        cum += nu[c];
+        if (target < cum) { chosen = c; break; }
+    }
+    if (chosen < 0) { s->cnt.nulls[k] += 1; return ORC_OK; }
+    s->cnt.coll[k][chosen] += 1;
+    double cos_chi = 1.0 - 2.0 * orc_u01(r[2]);
+    double phi = TWO_PI * orc_u01(r[3]);
+    const chan_t* ch = &s->ch[k][chosen];
+    if (!ion) {
+        double d[3] = {v[0] / speed, v[1] / speed, v[2] / speed};
+        double nd[3];
+        orc_rotate(d, cos_chi, phi, nd);
+        double eps_new;
+        if (ch->kind == ORC_XS_ELASTIC) {
+            eps_new = eps * (1.0 - 2.0 * m / M * (1.0 - cos_chi));
+        } else if (ch->kind == ORC_XS_EXCITATION) {
+            eps_new = eps - ch->th;
+        } else {  /* ionization: uniform split of eps - threshold */
+            uint32_t r1[4], r2[4];
+            draw(s, id, (uint32_t)s->step, k, 1u, r1);
+            draw(s, id, (uint32_t)s->step, k, 2u, r2);
+            double avail = eps - ch->th;
+            double eps_ej = orc_u01(r1[0]) * avail;
+            eps_new = avail - eps_ej;
+            double ed[3];
+            orc_rotate(d, 1.0 - 2.0 * orc_u01(r1[1]), TWO_PI * orc_u01(r1[2]), ed);
+            double vej = sqrt(2.0 * eps_ej * eu / m);
+            int rc = push_birth(&s->births[0], x, vej * ed[0], vej * ed[1], vej * ed[2]);
+            if (rc) return rc;
+            double g0, g1, g2, g3, vt = sqrt(K_B * s->c.gas_temp / M);
+            box_muller(orc_u01(r2[0]), orc_u01(r2[1]), &g0, &g1);
+            box_muller(orc_u01(r2[2]), orc_u01(r2[3]), &g2, &g3);
+            rc = push_birth(&s->births[1], x, vt * g0, vt * g1, vt * g2);
+            if (rc) return rc;
+        }
+        if (eps_new < 0.0) eps_new = 0.0;
+        double vs = sqrt(2.0 * eps_new * eu / m);
+        v[0] = vs * nd[0]; v[1] = vs * nd[1]; v[2] = vs * nd[2];
+    } else {
+        if (ch->kind == ORC_XS_ION_CX) {            /* charge exchange: ion takes vn */
+            v[0] = vn[0]; v[1] = vn[1]; v[2] = vn[2];
+        } else {                                     /* isotropic in the centre of mass */
+            double mt = m + M;
+            double vc[3] = {(m * v[0] + M * vn[0]) / mt, (m * v[1] + M * vn[1]) / mt,
+                            (m * v[2] + M * vn[2]) / mt};
+            double st = sqrt(fmax(0.0, 1.0 - cos_chi * cos_chi));
+            double gd[3] = {cos_chi, st * cos(phi), st * sin(phi)};
+            double f = M / mt * speed;
+            v[0] = vc[0] + f * gd[0]; v[1] = vc[1] + f * gd[1]; v[2] = vc[2] + f * gd[2];
+        }
+    }
+    return ORC_OK;
+}
+
+/* Secondary electron from an ion absorbed at wall w (0: x = 0, 1: x = L):
+ * emitted with probability gamma; normal speed from the flux-weighted
+ * half-Maxwellian v_see sqrt(-2 ln u), tangential components Maxwellian,
+ * advanced into the gap by u v_n dt. */
+static int emit_secondary(orc_sim* s, int k, uint32_t id, int wall)
+{
+    uint32_t r4[4], r5[4];
+    draw(s, id, (uint32_t)s->step, k, 4u, r4);
+    if (!(orc_u01(r4[0]) < s->c.see_gamma)) return ORC_OK;
+    draw(s, id, (uint32_t)s->step, k, 5u, r5);
+    double vsee = sqrt(s->c.see_temp * s->c.e_unit / s->c.sp[0].mass);
+    double vn = vsee * sqrt(-2.0 * log(orc_u01(r4[1])));
+    double adv = orc_u01(r4[2]) * vn * s->c.dt;
+    double g0, g1;
+    box_muller(orc_u01(r5[0]), orc_u01(r5[1]), &g0, &g1);
+    if (adv >= s->c.length) { s->cnt.dropped += 1; return ORC_OK; }
+    double x = wall == 0 ? adv : s->c.length - adv;
+    double vx = wall == 0 ? vn : -vn;
+    if (!(x >= 0.0 && x < s->c.length)) { s->cnt.dropped += 1; return ORC_OK; }
+    s->cnt.see_emitted[wall] += 1;
+    return push_birth(&s->births[0], x, vx, vsee * g0, vsee * g1);
+}
+
+/* One leapfrog step: for each species in order, each particle in index order:
+ * gather E at x^n, Boris to v^{n+1/2}, move to x^{n+1}, wrap or absorb (with
+ * secondary emission), collide.  Survivors keep their order; births follow,
+ * in the order they were made, with ids from the species counter.  Then the
+ * deposit, and the field at t^{n+1}. */
+static int one_step(orc_sim* s)
+{
+    double L = s->c.length, dt = s->c.dt;
+    int periodic = is_periodic(s);
+    for (int k = 0; k < s->c.n_species; ++k) s->births[k].n = 0;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        pop_t* p = &s->p[k];
+        double qm = s->c.sp[k].charge / s->c.sp[k].mass;
+        double half_mw = 0.5 * s->c.sp[k].mass * s->c.sp[k].weight;
+        double ke = 0.0;
+        int64_t keep = 0;
+        for (int64_t j = 0; j < p->n; ++j) {
+            double x = p->x[j];
+            double v[3] = {p->vx[j], p->vy[j], p->vz[j]};
+            double vold2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            double e[3] = {gather(s, x) + s->c.e_ext[0], s->c.e_ext[1], s->c.e_ext[2]};
+            orc_boris(v, e, s->c.b_ext, qm, dt);
+            double vnew2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            ke += half_mw * 0.5 * (vold2 + vnew2);
+            x += v[0] * dt;
+            if (periodic) {
+                if (x < 0.0) x += L;
+                if (x >= L) x -= L;
+            } else if (x < 0.0 || x >= L) {
+                int wall = x < 0.0 ? 0 : 1;
+                s->cnt.absorbed[k][wall] += 1;
+                if (k > 0 && s->c.sp[k].charge > 0.0 && s->c.see_gamma > 0.0) {
+                    int rc = emit_secondary(s, k, p->id[j], wall);
+                    if (rc) return rc;
+                }
+                continue;
+            }
+            if (s->nch[k] > 0) {
+                int rc = collide(s, k, p->id[j], x, v);
+                if (rc) return rc;
+            }
+            p->x[keep] = x;
+            p->vx[keep] = v[0]; p->vy[keep] = v[1]; p->vz[keep] = v[2];
+            p->id[keep] = p->id[j];
+            keep += 1;
+        }
+        p->n = keep;
+        s->ke[k] = ke;
+    }
+    int rc = ORC_OK;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        pop_t* p = &s->p[k];
+        for (int64_t b = 0; b < s->births[k].n; ++b) {
+            if (p->n >= p->cap) { s->cnt.dropped += s->births[k].n - b; rc = ORC_ECAPACITY; break; }
+            const birth_t* bb = &s->births[k].b[b];
+            p->x[p->n] = bb->x; p->vx[p->n] = bb->vx; p->vy[p->n] = bb->vy; p->vz[p->n] = bb->vz;
+            p->id[p->n] = p->next_id++;
+            p->n += 1;
+        }
+    }
+    s->step += 1;
+    deposit(s);
+    int rs = solve(s, (double)s->step * dt, s->rho, s->phi, s->ef);
+    s->fe = field_energy(s);
+    return rc != ORC_OK ? rc : rs;
+}
+
+int orc_step(orc_sim* s, int32_t n)
+{
+    if (!s || n < 0) return ORC_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        int rc = one_step(s);
+        if (rc != ORC_OK) return rc;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+int orc_n_nodes(const orc_sim* s) { return s ? s->nn : 0; }
+
+int orc_get_field(const orc_sim* s, double* rho, double* phi, double* efield)
+{
+    if (!s) return ORC_EINVAL;
+    size_t b = (size_t)s->nn * sizeof(double);
+    if (rho) memcpy(rho, s->rho, b);
+    if (phi) memcpy(phi, s->phi, b);
+    if (efield) memcpy(efield, s->ef, b);
+    return ORC_OK;
+}
+
+int orc_get_density(const orc_sim* s, int32_t k, double* dens)
+{
+    if (!s || k < 0 || k >= s->c.n_species || !dens) return ORC_EINVAL;
+    memcpy(dens, s->dens[k], (size_t)s->nn * sizeof(double));
+    return ORC_OK;
+}
+
+int orc_get_counters(const orc_sim* s, orc_counters* out)
+{
+    if (!s || !out) return ORC_EINVAL;
+    *out = s->cnt;
+    return ORC_OK;
+}
+
+int orc_get_energy(const orc_sim* s, double* ke, double* fe)
+{
+    if (!s) return ORC_EINVAL;
+    if (ke) for (int k = 0; k < s->c.n_species; ++k) ke[k] = s->ke[k];
+    if (fe) *fe = s->fe;
+    return ORC_OK;
+}
+
+int orc_get_numax(const orc_sim* s, int32_t k, double* numax, uint32_t* t32)
+{
+    if (!s || k < 0 || k >= s->c.n_species) return ORC_EINVAL;
+    if (numax) *numax = s->numax[k];
+    if (t32) *t32 = s->t32[k];
+    return ORC_OK;
+}

@@ -1,0 +1,109 @@
+/*
+ * pic_oracle.h -- plain FP64 CPU oracle of the 1D3V electrostatic PIC-MCC
+ * step (explicit leapfrog, Boris push, null-collision Monte Carlo against
+ * tabulated cross sections, walls with ion-induced secondary emission, and
+ * the 1D Poisson solve on the mesh; paper Section 1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or constant with the GPU library; the two meet only through
+ * the seeded workload records and the published Philox4x32-10 definition that
+ * each side implements on its own.
+ *
+ * Particles are held at absolute FP64 positions x in [0, L) with FP64
+ * velocities and 32-bit ids.  Everything is sequential and in the order the
+ * method states, so that it can be checked by eye.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_SPECIES 4
+#define ORC_MAX_CHAN 8
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ECAPACITY = -4,
+       ORC_ENUMERIC = -5, ORC_ESTATE = -6 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1 };
+enum { ORC_XS_ELASTIC = 0, ORC_XS_EXCITATION = 1, ORC_XS_IONIZATION = 2,
+       ORC_XS_ION_CX = 3, ORC_XS_ION_ISO = 4 };
+enum { ORC_LOAD_STRATIFIED = 0, ORC_LOAD_RANDOM = 1, ORC_LOAD_NONE = 2 };
+
+typedef struct {
+    double charge, mass, weight;      /* C, kg, real particles per m^2 per macro */
+    int64_t capacity, n_init;
+    double vth;                       /* sqrt(kT/m) of the loaded Maxwellian */
+    double drift[3];
+    int32_t load, pad;
+} orc_species;
+
+typedef struct {
+    int32_t n_cells, bc, field_solve, n_species;
+    double length, dt, eps0, rho_bg, e_unit;
+    double v_amp, v_freq, v_phase;
+    double e_ext[3], b_ext[3];
+    double gas_density, gas_temp, gas_mass;
+    double see_gamma, see_temp;
+    double perturb_eps;
+    int32_t perturb_mode, pad;
+    uint64_t seed;
+    orc_species sp[ORC_MAX_SPECIES];
+} orc_config;
+
+/* Counters of one run, all integer-exact. */
+typedef struct {
+    int64_t absorbed[ORC_MAX_SPECIES][2];   /* [species][wall 0 = x<0, 1 = x>=L] */
+    int64_t see_emitted[2];
+    int64_t candidates[ORC_MAX_SPECIES];
+    int64_t nulls[ORC_MAX_SPECIES];
+    int64_t coll[ORC_MAX_SPECIES][ORC_MAX_CHAN];
+    int64_t violations[ORC_MAX_SPECIES];
+    int64_t dropped;
+} orc_counters;
+
+typedef struct orc_sim orc_sim;
+
+int  orc_create(const orc_config* cfg, orc_sim** out);
+void orc_free(orc_sim* s);
+int  orc_load_xsec(orc_sim* s, int32_t species, int32_t kind, double threshold_eV,
+                   int32_t n, const double* energy_eV, const double* sigma_m2);
+/* Load particles (Philox draws at step 0xFFFFFFFF), deposit, solve at t = 0,
+ * and take the backward half step of the leapfrog start. */
+int  orc_load(orc_sim* s);
+/* Replace species state; positions in [0, L). */
+int  orc_set_particles(orc_sim* s, int32_t species, int64_t n, const double* x,
+                       const double* vx, const double* vy, const double* vz,
+                       const uint32_t* id, uint32_t next_id);
+int  orc_get_particles(const orc_sim* s, int32_t species, int64_t cap, double* x,
+                       double* vx, double* vy, double* vz, uint32_t* id, int64_t* n,
+                       uint32_t* next_id);
+int  orc_set_step(orc_sim* s, uint64_t step);
+uint64_t orc_get_step(const orc_sim* s);
+/* Deposit the current particles and solve the field at t = step*dt. */
+int  orc_refresh_field(orc_sim* s);
+int  orc_step(orc_sim* s, int32_t n_steps);
+/* Standalone field solve of the mesh problem for charge density rho_in
+ * (n_nodes values) at time t; phi_out / e_out may be NULL. */
+int  orc_poisson(const orc_sim* s, double t, const double* rho_in, double* phi_out,
+                 double* e_out);
+int  orc_n_nodes(const orc_sim* s);
+int  orc_get_field(const orc_sim* s, double* rho, double* phi, double* efield);
+int  orc_get_density(const orc_sim* s, int32_t species, double* dens);
+int  orc_get_counters(const orc_sim* s, orc_counters* out);
+/* Kinetic energy of each species at the last step (time-centred), field energy. */
+int  orc_get_energy(const orc_sim* s, double* ke_species, double* fe);
+int  orc_get_numax(const orc_sim* s, int32_t species, double* numax, uint32_t* t32);
+
+/* Building blocks exposed for the pins. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u01(uint32_t x);
+void orc_boris(double v[3], const double e[3], const double b[3], double qm, double h);
+void orc_rotate(const double d[3], double cos_chi, double phi, double out[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
