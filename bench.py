@@ -1,0 +1,109 @@
+"""Throughput of the MI355X PIC-MCC step.
+
+One step = one pass of the whole hot path over every particle: gather, Boris
+push, move, boundary handling, collisions, compaction/births, deposition,
+and the field solve.  Default workload: the E x B drift-instability box
+(4e6 electrons + 4e6 xenon ions, 1024 cells, periodic, B = 0.02 T,
+E = 2e4 V/m), particles resident in HBM before timing starts.  Prints one
+JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = 40      # read cell, off, vx, vy, vz; write the same (no draws: no id)
+
+
+def cpu_baseline(cfg, steps):
+    import oracle
+    t0 = time.perf_counter()
+    o = oracle.Oracle(cfg)
+    t1 = time.perf_counter()
+    o.step(steps)
+    t2 = time.perf_counter()
+    n = sum(sp["n_init"] for sp in cfg["species"])
+    return dict(value=n * steps / (t2 - t1), unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"full E x B box ({n} particles), {steps} steps after loading "
+                       f"(load {t1 - t0:.1f} s not counted), single-threaded FP64 C oracle")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--ppt", type=int, default=4)
+    ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2609_17151_amd as P
+
+    torch.cuda.set_device(0)
+    cfg = W.exb()
+    n = sum(sp["n_init"] for sp in cfg["species"])
+    sim = P.Sim(cfg)
+    sim.config_tiles(args.ppt, 256, args.sort_every)
+    sim.step(args.warmup)
+    sim.sync()
+    stream = sim.stream
+    torch.cuda.synchronize()
+    sim.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    sim.sync()
+    ms = start.elapsed_time(end)
+    tm = sim.timing()
+    sim.profile(False)
+    ms_step = ms / args.steps
+    value = n * args.steps / (ms * 1e-3)
+    push_avg_ms = float(tm["push_ms"].sum() / max(tm["push_n"].sum(), 1))
+    per_launch_bytes = (n / 2) * BYTES_PER_PARTICLE_STEP
+    achieved = per_launch_bytes / (push_avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "exb_drift_box: 4e6 e- + 4e6 Xe+, 1024 cells, periodic, "
+                               "B=0.02 T, E=2e4 V/m, dt=5e-12 s",
+                   "particles": n, "cells": cfg["n_cells"], "particles_per_thread": args.ppt,
+                   "sort_every": args.sort_every},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "push_kernel", "avg_launch_ms": push_avg_ms,
+                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+        "breakdown_ms_per_step": {"push": float(tm["push_ms"].sum()) / args.steps,
+                                  "finalize": float(tm["finalize_ms"]) / args.steps},
+    }
+    if not args.no_cpu:
+        sim.close()
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) library for the per-particle step of
+ * the 1D3V electrostatic PIC-MCC method of JC-PIC (paper Section 1): field
+ * gather from the mesh, Boris push in an imposed magnetic field, move,
+ * wall absorption with ion-induced secondary emission, null-collision Monte
+ * Carlo against tabulated cross sections, charge deposition, and the 1D
+ * Poisson solve between steps.
+ *
+ * Conventions for every entry point
+ *   - Return value: pic_status, 0 = PIC_OK, negative = error.  Argument and
+ *     table errors are detected synchronously and leave the state unchanged.
+ *   - Host pointers belong to the caller; data is copied during the call and
+ *     never retained.  Device buffers belong to the library; they are obtained
+ *     through the pic_allocator given to pic_init (hipMalloc when NULL) and
+ *     released by pic_free.
+ *   - Work is queued on the HIP stream given to pic_init.  pic_step returns as
+ *     soon as the work is queued; conditions met on the device (capacity
+ *     overflow, non-finite values, a collision frequency above the bound, a
+ *     cell out of range, a stalled tile chain) are latched in a flag word and
+ *     returned by the next pic_sync or pic_diag.
+ *   - A context is used by one host thread at a time.
+ *
+ * Units: SI, or normalised units when eps0 = 1 and e_unit = 1.  Energies in
+ * eV are kinetic energy / e_unit.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_SPECIES 4
+#define PIC_MAX_CHAN 8
+#define PIC_MAX_BATCH 256
+
+typedef int32_t pic_status;
+#define PIC_OK 0
+#define PIC_EINVAL (-1)      /* bad argument, table or configuration */
+#define PIC_ENOMEM (-2)      /* device or host allocation failed */
+#define PIC_EHIP (-3)        /* a HIP runtime call failed */
+#define PIC_ECAPACITY (-4)   /* particle or birth capacity exceeded (births dropped) */
+#define PIC_ENUMERIC (-5)    /* non-finite particle state */
+#define PIC_ESTATE (-6)      /* call not valid in the current state */
+#define PIC_ESTALL (-7)      /* a tile waited too long for its predecessor */
+
+/* Boundary conditions of the 1D domain [0, L): periodic column or a gap
+ * between two electrodes (Section 1: "between two electrodes", "closed on
+ * itself", Sections 3.5, 3.6). */
+#define PIC_BC_PERIODIC 0
+#define PIC_BC_DIRICHLET 1
+
+/* Collision process kinds (Section 1: tabulated cross sections; Section 3.3:
+ * ion charge exchange).  Electron-type kinds act on a projectile against a
+ * neutral at rest; ion-type kinds use the relative speed to a neutral drawn
+ * from the gas Maxwellian. */
+#define PIC_XS_ELASTIC 0      /* isotropic, recoil loss 2m/M (1 - cos chi) */
+#define PIC_XS_EXCITATION 1   /* threshold energy removed, isotropic */
+#define PIC_XS_IONIZATION 2   /* threshold removed, uniform sharing, e-ion pair born */
+#define PIC_XS_ION_CX 3       /* ion takes the neutral's velocity */
+#define PIC_XS_ION_ISO 4      /* isotropic scattering in the centre of mass */
+
+/* Particle loading (Section 2: a run starts from the beginning or continues
+ * from a stored state). */
+#define PIC_LOAD_STRATIFIED 0 /* x_j = (j + u) L / N */
+#define PIC_LOAD_RANDOM 1     /* x_j = u L */
+#define PIC_LOAD_NONE 2       /* start empty; fill with pic_set_particles */
+
+typedef struct {
+    double charge;      /* C (or normalised) */
+    double mass;        /* kg */
+    double weight;      /* real particles per m^2 per macro-particle */
+    int64_t capacity;   /* maximum macro-particles held */
+    int64_t n_init;     /* macro-particles loaded by pic_init */
+    double vth;         /* sqrt(kT/m) of the loaded Maxwellian, m/s */
+    double drift[3];    /* m/s */
+    int32_t load;       /* PIC_LOAD_* */
+    int32_t pad;
+} pic_species_cfg;
+
+/* One discharge (Section 1: gas, pressure, gap, voltage waveform, magnetic
+ * field, walls and secondary emission).  Species 0 is the electron species; it
+ * receives ionization and secondary electrons.  Species 1, when present, is
+ * the ion species; it receives ionization ions and, if its charge is positive,
+ * emits secondaries at the walls with probability see_gamma. */
+typedef struct {
+    int32_t n_cells;        /* mesh cells; nodes at i*dx, dx = length / n_cells */
+    int32_t bc;             /* PIC_BC_* */
+    int32_t field_solve;    /* 1: Poisson each step; 0: imposed e_ext only */
+    int32_t n_species;
+    double length, dt, eps0;
+    double rho_bg;          /* fixed uniform background charge density */
+    double e_unit;          /* charge unit of the eV energy scale */
+    double v_amp, v_freq, v_phase;  /* phi(0,t) = v_amp sin(2 pi v_freq t + v_phase), phi(L) = 0 */
+    double e_ext[3], b_ext[3];      /* imposed uniform fields */
+    double gas_density, gas_temp, gas_mass;  /* m^-3, K, kg */
+    double see_gamma, see_temp;     /* secondary yield, emission temperature in eV */
+    double perturb_eps;             /* loaded density n0 (1 + eps cos(2 pi m x / L)) */
+    int32_t perturb_mode, pad;
+    uint64_t seed;                  /* Philox key */
+    pic_species_cfg species[PIC_MAX_SPECIES];
+} pic_config;
+
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} pic_allocator;
+
+typedef struct pic_ctx pic_ctx;
+
+/*
+ * pic_init: create a context holding n_batch discharges (1 <= n_batch <=
+ * PIC_MAX_BATCH) that share n_species and bc, load their particles on the
+ * device, deposit, solve the field at t = 0 and take the backward half step
+ * v^{-1/2} = Boris(v^0; E^0, B, -dt/2) of the leapfrog start (Section 1:
+ * explicit leapfrog).  cfg points to n_batch records.  hip_stream is a
+ * hipStream_t (NULL = default stream).  On success *out owns all device
+ * memory.
+ */
+pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator* alloc,
+                    void* hip_stream, pic_ctx** out);
+
+/*
+ * pic_load_xsec: add one collision process for species `species` of discharge
+ * `batch` (-1: all discharges) from a table of n >= 2 points (Section 1:
+ * tabulated cross sections).  energy_eV must be positive and strictly
+ * increasing, sigma_m2 finite and >= 0; values are interpolated linearly in
+ * ln(energy), clamped outside the table, and zero below threshold_eV.
+ * Processes are tried in the order they were added.  Recomputes the species'
+ * maximum collision frequency.  Kinds may not mix electron-type and ion-type
+ * within one species; ionization is accepted on species 0 with n_species >= 2.
+ */
+pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t kind,
+                         double threshold_eV, int32_t n, const double* energy_eV,
+                         const double* sigma_m2);
+
+/*
+ * pic_step: queue n_steps >= 0 full steps of every discharge: gather, Boris
+ * push, move, wall/periodic handling with secondary emission, null-collision
+ * Monte Carlo, compaction and births, deposition, Poisson at t^{n+1}.
+ * Asynchronous.
+ */
+pic_status pic_step(pic_ctx* ctx, int32_t n_steps);
+
+/*
+ * pic_poisson: solve the mesh problem of discharge `batch` at time t_s for
+ * the charge density rho_in (host, n_nodes values; NULL: the last deposited
+ * density) and copy phi and E at the nodes to phi_out / efield_out (host,
+ * n_nodes doubles each; either may be NULL).  n_nodes = n_cells + 1 for
+ * Dirichlet, n_cells for periodic.  Does not change the simulation state.
+ * Synchronous.
+ */
+pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rho_in,
+                       double* phi_out, double* efield_out);
+
+/* Diagnostic selectors for pic_diag; sizes are for one discharge. */
+#define PIC_DIAG_COUNTS 0       /* int64[4 + 2*S]: step, n_nodes, n_species, flags, then per species count, next_id */
+#define PIC_DIAG_RHO 1          /* double[n_nodes]: charge density */
+#define PIC_DIAG_PHI 2          /* double[n_nodes] */
+#define PIC_DIAG_EFIELD 3       /* double[n_nodes] */
+#define PIC_DIAG_DENSITY 4      /* double[S * n_nodes]: number density per species */
+#define PIC_DIAG_ENERGY 5       /* double[S + 1]: time-centred kinetic energy per species of the last step, field energy (J/m^2) */
+#define PIC_DIAG_WALL 6         /* int64[2*S + 2]: absorbed per species per wall, secondaries emitted per wall */
+#define PIC_DIAG_COLL 7         /* int64[S * (3 + PIC_MAX_CHAN)]: candidates, nulls, violations, then per-process counts */
+#define PIC_DIAG_NUMAX 8        /* double[2*S]: nu_max per species, then the 32-bit candidate threshold */
+#define PIC_DIAG_FLAGS 9        /* int64[1]: latched device flag bits (and clears them) */
+#define PIC_DIAG_AVG 10         /* double[1 + (S + 2) * n_nodes]: samples, then mean density per species, mean phi, mean electron energy (eV) */
+#define PIC_DIAG_EEPF 11        /* double[2 * PIC_EEPF_BINS + 2]: bulk and wall electron energy histograms, bin width eV, samples */
+#define PIC_DIAG_RESET_AVG 12   /* no output: clears AVG and EEPF accumulators */
+#define PIC_DIAG_CHARGE 13      /* double[2]: total charge per unit area on the mesh, and from particle counts */
+
+#define PIC_DIAG_TIMING 14      /* double[2 + 2*S]: finalize launches, finalize ms, then per species push launches, push ms (pic_profile) */
+
+#define PIC_EEPF_BINS 256
+
+/*
+ * pic_diag: synchronise the stream, then copy diagnostic `what` of discharge
+ * `batch` into out (host, out_bytes bytes).  Returns PIC_EINVAL if out_bytes
+ * is too small, and any latched device error (after copying).
+ */
+pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t out_bytes);
+
+/*
+ * pic_get_particles: copy the n (<= cap) particles of one species and
+ * discharge in their canonical order (Section 1: a paused run can be resumed):
+ * cell index, in-cell offset in [0,1), velocity, id.  *n_out receives the count
+ * and *next_id the next id the species will assign.  Synchronous.
+ */
+pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap,
+                             int32_t* cell, float* off, float* vx, float* vy, float* vz,
+                             uint32_t* id, int64_t* n_out, uint32_t* next_id);
+
+/*
+ * pic_set_particles: replace the particles of one species and discharge
+ * (n <= capacity), set the step index of the whole context to `step` and the
+ * species' next id, then re-deposit and re-solve the field of that discharge
+ * at t = step * dt.  Positions are cell in [0, n_cells) and off in [0,1).
+ * Non-finite velocities give PIC_ENUMERIC.  Synchronous.
+ */
+pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n,
+                             const int32_t* cell, const float* off, const float* vx,
+                             const float* vy, const float* vz, const uint32_t* id,
+                             uint32_t next_id, uint64_t step);
+
+/* pic_sync: wait for queued work; return a latched device error if any. */
+pic_status pic_sync(pic_ctx* ctx);
+
+/* pic_strerror: static text for a status. */
+const char* pic_strerror(pic_status s);
+
+/* pic_free: wait for queued work and release every buffer. */
+void pic_free(pic_ctx* ctx);
+
+/* pic_set_diag: when enable is non-zero, every step also accumulates the
+ * time averages of the densities, the potential and the electron mean energy
+ * (PIC_DIAG_AVG), and electron energy histograms of bin width
+ * eepf_emax_eV / PIC_EEPF_BINS in the bulk (middle tenth of a bounded gap,
+ * whole domain when periodic) and at the walls (PIC_DIAG_EEPF) (Section 1:
+ * density and potential profiles, electron energy probability functions in
+ * the bulk and at the walls). */
+pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV);
+
+/* pic_profile: when enable is non-zero, pic_step records a pair of HIP
+ * events on the context's stream around every kernel it launches and
+ * accumulates their elapsed times (read with PIC_DIAG_TIMING); enabling
+ * clears the sums.  A measuring aid; it adds two event records per launch. */
+pic_status pic_profile(pic_ctx* ctx, int32_t enable);
+
+/* pic_config_tiles: tile shape of the particle kernels (particles per thread
+ * 1, 2, 4 or 8; threads per workgroup 64..1024 in steps of 64) and the
+ * interval in steps of the sort by cell (0 = never).  Takes effect at the
+ * next pic_step. */
+pic_status pic_config_tiles(pic_ctx* ctx, int32_t particles_per_thread,
+                            int32_t threads_per_group, int32_t sort_every);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,311 @@
+"""Python binding of the MI355X PIC-MCC library (``libpic_mi355x.so``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI of ``include/pic.h``.  PyTorch supplies device memory (through
+the library's allocator hook, backed by torch's caching allocator) and the HIP
+stream.  There is no CPU fallback: without the built library or a GPU the
+constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic_mi355x.so")
+
+MAX_SPECIES = 4
+MAX_CHAN = 8
+EEPF_BINS = 256
+
+OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
+DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14)
+
+
+class SpeciesCfg(C.Structure):
+    _fields_ = [("charge", C.c_double), ("mass", C.c_double), ("weight", C.c_double),
+                ("capacity", C.c_int64), ("n_init", C.c_int64), ("vth", C.c_double),
+                ("drift", C.c_double * 3), ("load", C.c_int32), ("pad", C.c_int32)]
+
+
+class PicConfig(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("bc", C.c_int32), ("field_solve", C.c_int32),
+                ("n_species", C.c_int32), ("length", C.c_double), ("dt", C.c_double),
+                ("eps0", C.c_double), ("rho_bg", C.c_double), ("e_unit", C.c_double),
+                ("v_amp", C.c_double), ("v_freq", C.c_double), ("v_phase", C.c_double),
+                ("e_ext", C.c_double * 3), ("b_ext", C.c_double * 3),
+                ("gas_density", C.c_double), ("gas_temp", C.c_double), ("gas_mass", C.c_double),
+                ("see_gamma", C.c_double), ("see_temp", C.c_double), ("perturb_eps", C.c_double),
+                ("perturb_mode", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64),
+                ("species", SpeciesCfg * MAX_SPECIES)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class PicAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, what):
+        msg = _lib.pic_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """dlopen the built library and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2609_17151_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    dp, fp, ip, up = (C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                      C.POINTER(C.c_uint32))
+    sig = {
+        "pic_init": (i32, [C.POINTER(PicConfig), i32, C.POINTER(PicAllocator), P, C.POINTER(P)]),
+        "pic_load_xsec": (i32, [P, i32, i32, i32, d, i32, dp, dp]),
+        "pic_step": (i32, [P, i32]),
+        "pic_poisson": (i32, [P, i32, d, dp, dp, dp]),
+        "pic_diag": (i32, [P, i32, i32, P, C.c_size_t]),
+        "pic_get_particles": (i32, [P, i32, i32, i64, ip, fp, fp, fp, fp, up,
+                                    C.POINTER(i64), C.POINTER(u32)]),
+        "pic_set_particles": (i32, [P, i32, i32, i64, ip, fp, fp, fp, fp, up, u32, u64]),
+        "pic_sync": (i32, [P]),
+        "pic_strerror": (C.c_char_p, [i32]),
+        "pic_free": (None, [P]),
+        "pic_config_tiles": (i32, [P, i32, i32, i32]),
+        "pic_set_diag": (i32, [P, i32, d]),
+        "pic_profile": (i32, [P, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def make_config(cfg):
+    c = PicConfig()
+    c.n_cells, c.bc, c.field_solve = cfg["n_cells"], cfg["bc"], cfg["field_solve"]
+    c.n_species = len(cfg["species"])
+    for k in ("length", "dt", "eps0", "rho_bg", "e_unit", "v_amp", "v_freq", "v_phase",
+              "gas_density", "gas_temp", "gas_mass", "see_gamma", "see_temp", "perturb_eps"):
+        setattr(c, k, float(cfg[k]))
+    for i in range(3):
+        c.e_ext[i], c.b_ext[i] = cfg["e_ext"][i], cfg["b_ext"][i]
+    c.perturb_mode, c.seed = cfg["perturb_mode"], cfg["seed"]
+    for i, sp in enumerate(cfg["species"]):
+        s = c.species[i]
+        s.charge, s.mass, s.weight = sp["charge"], sp["mass"], sp["weight"]
+        s.capacity, s.n_init, s.vth = sp["capacity"], sp["n_init"], sp["vth"]
+        for j in range(3):
+            s.drift[j] = sp["drift"][j]
+        s.load = sp["load"]
+    return c
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Sim:
+    """A batch of discharges on one GPU (``pic_ctx``)."""
+
+    def __init__(self, cfgs, tables=(), stream=None, torch_alloc=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the PIC library runs only on an MI355X")
+        L = load_library()
+        if isinstance(cfgs, dict):
+            cfgs = [cfgs]
+        self.cfgs = list(cfgs)
+        self.B = len(self.cfgs)
+        self.S = len(self.cfgs[0]["species"])
+        arr = (PicConfig * self.B)(*[make_config(c) for c in self.cfgs])
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._alloc = None
+        if torch_alloc:
+            dev = torch.cuda.current_device()
+            strm = self.stream
+
+            def _a(nbytes, user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
+
+            def _f(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._afn, self._ffn = ALLOC_FN(_a), FREE_FN(_f)
+            self._alloc = PicAllocator(self._afn, self._ffn, None)
+        h = C.c_void_p()
+        rc = L.pic_init(arr, self.B, C.byref(self._alloc) if self._alloc else None,
+                        C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise PicError(rc, "pic_init")
+        self.h = h
+        self.n_nodes = [c["n_cells"] + (1 if c["bc"] == 1 else 0) for c in self.cfgs]
+        for t in tables:
+            self.load_xsec(t["species"], t["kind"], t["threshold"], t["energy"], t["sigma"],
+                           batch=t.get("batch", -1))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pic_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise PicError(rc, what)
+
+    def load_xsec(self, species, kind, threshold, energy, sigma, batch=-1):
+        e = np.ascontiguousarray(energy, dtype=np.float64)
+        s = np.ascontiguousarray(sigma, dtype=np.float64)
+        self._check(_lib.pic_load_xsec(self.h, batch, species, kind, threshold, len(e),
+                                       _ptr(e, C.c_double), _ptr(s, C.c_double)), "pic_load_xsec")
+
+    def step(self, n=1):
+        self._check(_lib.pic_step(self.h, int(n)), "pic_step")
+
+    def sync(self):
+        self._check(_lib.pic_sync(self.h), "pic_sync")
+
+    def config_tiles(self, ppt=4, threads=256, sort_every=0):
+        self._check(_lib.pic_config_tiles(self.h, ppt, threads, sort_every), "pic_config_tiles")
+
+    def set_diag(self, enable=True, eepf_emax=64.0):
+        self._check(_lib.pic_set_diag(self.h, int(enable), float(eepf_emax)), "pic_set_diag")
+
+    def poisson(self, t, rho=None, batch=0):
+        n = self.n_nodes[batch]
+        phi, ef = np.zeros(n), np.zeros(n)
+        r = None
+        if rho is not None:
+            r = np.ascontiguousarray(rho, dtype=np.float64)
+            assert r.shape == (n,)
+        self._check(_lib.pic_poisson(self.h, batch, float(t),
+                                     _ptr(r, C.c_double) if r is not None else None,
+                                     _ptr(phi, C.c_double), _ptr(ef, C.c_double)), "pic_poisson")
+        return phi, ef
+
+    def diag(self, what, count, dtype=np.float64, batch=0, check=True):
+        out = np.zeros(count, dtype=dtype)
+        rc = _lib.pic_diag(self.h, batch, DIAG[what], out.ctypes.data_as(C.c_void_p), out.nbytes)
+        if check:
+            self._check(rc, f"pic_diag({what})")
+        return out
+
+    def counts(self, batch=0):
+        o = self.diag("COUNTS", 4 + 2 * self.S, np.int64, batch, check=False)
+        return dict(step=int(o[0]), n_nodes=int(o[1]), flags=int(o[3]),
+                    count=[int(o[4 + 2 * s]) for s in range(self.S)],
+                    next_id=[int(o[5 + 2 * s]) for s in range(self.S)])
+
+    def rho(self, batch=0):
+        return self.diag("RHO", self.n_nodes[batch], batch=batch)
+
+    def phi(self, batch=0):
+        return self.diag("PHI", self.n_nodes[batch], batch=batch)
+
+    def efield(self, batch=0):
+        return self.diag("EFIELD", self.n_nodes[batch], batch=batch)
+
+    def density(self, batch=0):
+        n = self.n_nodes[batch]
+        return self.diag("DENSITY", self.S * n, batch=batch).reshape(self.S, n)
+
+    def energy(self, batch=0):
+        o = self.diag("ENERGY", self.S + 1, batch=batch)
+        return o[: self.S].copy(), float(o[self.S])
+
+    def wall(self, batch=0):
+        o = self.diag("WALL", 2 * self.S + 2, np.int64, batch)
+        return dict(absorbed=o[: 2 * self.S].reshape(self.S, 2), see_emitted=o[2 * self.S:])
+
+    def coll(self, batch=0):
+        o = self.diag("COLL", self.S * (3 + MAX_CHAN), np.int64, batch).reshape(self.S, 3 + MAX_CHAN)
+        return dict(candidates=o[:, 0], nulls=o[:, 1], violations=o[:, 2], coll=o[:, 3:])
+
+    def numax(self, species, batch=0):
+        o = self.diag("NUMAX", 2 * self.S, batch=batch)
+        return float(o[species]), int(o[self.S + species])
+
+    def flags(self, batch=0):
+        return int(self.diag("FLAGS", 1, np.int64, batch)[0])
+
+    def avg(self, batch=0):
+        n = self.n_nodes[batch]
+        o = self.diag("AVG", 1 + (self.S + 2) * n, batch=batch)
+        prof = o[1:].reshape(self.S + 2, n)
+        return dict(samples=o[0], density=prof[: self.S], phi=prof[self.S], mean_energy=prof[self.S + 1])
+
+    def eepf(self, batch=0):
+        o = self.diag("EEPF", 2 * EEPF_BINS + 2, batch=batch)
+        return dict(bulk=o[:EEPF_BINS], wall=o[EEPF_BINS:2 * EEPF_BINS],
+                    bin_width=o[2 * EEPF_BINS], samples=o[2 * EEPF_BINS + 1])
+
+    def reset_avg(self, batch=0):
+        self._check(_lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0), "pic_diag(RESET_AVG)")
+
+    def profile(self, enable=True):
+        self._check(_lib.pic_profile(self.h, int(enable)), "pic_profile")
+
+    def timing(self):
+        o = self.diag("TIMING", 2 + 2 * self.S)
+        return dict(finalize_n=o[0], finalize_ms=o[1],
+                    push_n=o[2::2].copy(), push_ms=o[3::2].copy())
+
+    def charge(self, batch=0):
+        o = self.diag("CHARGE", 2, batch=batch)
+        return float(o[0]), float(o[1])
+
+    def get_particles(self, species, batch=0):
+        n = C.c_int64()
+        nid = C.c_uint32()
+        self._check(_lib.pic_get_particles(self.h, batch, species, 0, None, None, None, None, None,
+                                           None, C.byref(n), C.byref(nid)), "pic_get_particles")
+        m = n.value
+        cell = np.zeros(m, np.int32)
+        off, vx, vy, vz = (np.zeros(m, np.float32) for _ in range(4))
+        ids = np.zeros(m, np.uint32)
+        self._check(_lib.pic_get_particles(self.h, batch, species, m, _ptr(cell, C.c_int32),
+                                           _ptr(off, C.c_float), _ptr(vx, C.c_float),
+                                           _ptr(vy, C.c_float), _ptr(vz, C.c_float),
+                                           _ptr(ids, C.c_uint32), C.byref(n), C.byref(nid)),
+                    "pic_get_particles")
+        return dict(cell=cell, off=off, vx=vx, vy=vy, vz=vz, id=ids, next_id=nid.value)
+
+    def set_particles(self, species, cell, off, vx, vy, vz, ids, next_id, step, batch=0):
+        cell = np.ascontiguousarray(cell, np.int32)
+        off, vx, vy, vz = (np.ascontiguousarray(a, np.float32) for a in (off, vx, vy, vz))
+        ids = np.ascontiguousarray(ids, np.uint32)
+        self._check(_lib.pic_set_particles(self.h, batch, species, len(cell), _ptr(cell, C.c_int32),
+                                           _ptr(off, C.c_float), _ptr(vx, C.c_float),
+                                           _ptr(vy, C.c_float), _ptr(vz, C.c_float),
+                                           _ptr(ids, C.c_uint32), int(next_id), int(step)),
+                    "pic_set_particles")
+
+
+def declared_functions(header=None):
+    """Names of the functions ``include/pic.h`` declares."""
+    import re
+    header = header or os.path.join(os.path.dirname(HERE), "include", "pic.h")
+    text = open(header).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", text)))

@@ -1,0 +1,987 @@
+// Host side of the C ABI declared in include/pic.h: validation, device
+// allocation, the per-species constants of the push, the collision tables and
+// their frequency bound, kernel launches, and diagnostics readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.h"
+#include "pic_kernels.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr double kBoltzmann = 1.380649e-23;
+constexpr int kTileMax = 1024;     // largest tile (256 threads x 4)
+constexpr int kTileMin = 256;
+
+struct Table {
+    int32_t kind;
+    double th;
+    std::vector<double> e, s;
+};
+
+struct SegHost {
+    std::vector<Table> tabs;
+    double numax = 0.0;
+    uint32_t t32 = 0;
+    void* xs_dev = nullptr;
+};
+
+}  // namespace
+
+struct pic_ctx {
+    hipStream_t stream = nullptr;
+    pic_allocator alloc{};
+    bool has_alloc = false;
+    int B = 0, S = 0;
+    std::vector<pic_config> cfg;
+    std::vector<SegConst> segc;
+    std::vector<SegHost> segh;
+    std::vector<DisConst> disc;
+    DevPtrs d{};
+    std::vector<void*> blocks;
+    int ppt = 4;
+    int sort_every = 0;
+    int64_t steps_since_sort = 0;
+    int diag = 0;
+    double eepf_emax = 64.0;
+    double* poisson_scratch = nullptr;   // rho, phi, e: 3 * nodes_max
+    void* sort_scratch = nullptr;
+    size_t sort_scratch_bytes = 0;
+    std::vector<int64_t> grid_cap;       // per species: sum over discharges of padded capacity
+    // live timing of launches (pic_profile)
+    int prof = 0;
+    std::vector<hipEvent_t> ev;           // pool, reused
+    std::vector<std::pair<int, int>> pending;  // (kind, first event index); kind = species or -1 finalize
+    size_t ev_used = 0;
+    std::vector<double> push_ms, push_n;
+    double fin_ms = 0.0, fin_n = 0.0;
+};
+
+namespace {
+
+void* dev_alloc(pic_ctx* c, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* p = nullptr;
+    if (c->has_alloc) {
+        p = c->alloc.alloc(bytes, c->alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) c->blocks.push_back(p);
+    return p;
+}
+
+void dev_release(pic_ctx* c, void* p)
+{
+    if (!p) return;
+    auto it = std::find(c->blocks.begin(), c->blocks.end(), p);
+    if (it != c->blocks.end()) c->blocks.erase(it);
+    if (c->has_alloc) c->alloc.free(p, c->alloc.user);
+    else (void)hipFree(p);
+}
+
+bool valid_species(const pic_species_cfg& s)
+{
+    return s.mass > 0.0 && std::isfinite(s.mass) && std::isfinite(s.charge) && s.weight > 0.0 &&
+           s.capacity >= s.n_init && s.n_init >= 0 && s.capacity <= (int64_t(1) << 31) &&
+           s.load >= PIC_LOAD_STRATIFIED && s.load <= PIC_LOAD_NONE && s.vth >= 0.0;
+}
+
+pic_status check_cfg(const pic_config& c)
+{
+    if (c.n_cells < 2 || c.n_cells > kMaxCells) return PIC_EINVAL;
+    if (c.bc == PIC_BC_DIRICHLET && c.n_cells + 1 > kFinThreads * kNodesPerThread) return PIC_EINVAL;
+    if (c.bc != PIC_BC_PERIODIC && c.bc != PIC_BC_DIRICHLET) return PIC_EINVAL;
+    if (!(c.length > 0.0) || !(c.dt > 0.0) || !(c.eps0 > 0.0) || !(c.e_unit > 0.0)) return PIC_EINVAL;
+    if (c.n_species < 1 || c.n_species > PIC_MAX_SPECIES) return PIC_EINVAL;
+    if (c.see_gamma < 0.0 || c.see_gamma > 1.0) return PIC_EINVAL;
+    for (int s = 0; s < c.n_species; ++s)
+        if (!valid_species(c.species[s])) return PIC_EINVAL;
+    return PIC_OK;
+}
+
+int64_t pad_cap(int64_t cap) { return std::max<int64_t>(kTileMax, (cap + kTileMax - 1) / kTileMax * kTileMax); }
+
+pic_status hip_st(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
+
+// sigma(eps) of one table: linear in ln(eps), end values outside, zero below threshold
+double sigma_of(const Table& t, double eps)
+{
+    if (eps < t.th) return 0.0;
+    const size_t n = t.e.size();
+    if (eps <= t.e[0]) return t.s[0];
+    if (eps >= t.e[n - 1]) return t.s[n - 1];
+    size_t lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const size_t mid = (lo + hi) / 2;
+        if (t.e[mid] <= eps) lo = mid; else hi = mid;
+    }
+    const double u = (std::log(eps) - std::log(t.e[lo])) / (std::log(t.e[hi]) - std::log(t.e[lo]));
+    return t.s[lo] + u * (t.s[hi] - t.s[lo]);
+}
+
+bool electron_kind(int k) { return k == PIC_XS_ELASTIC || k == PIC_XS_EXCITATION || k == PIC_XS_IONIZATION; }
+
+// Upper bound of the collision frequency and the integer candidate threshold.
+// Electron-type: 1.05 x max over a log-uniform grid ten times finer than the
+// longest table of n_g sum_k sigma_k(eps) sqrt(2 e eps / m).  Ion-type:
+// n_g max(sum_k sigma_k) g_max, g_max = sqrt(2 e eps_top / m) + 6 sqrt(k T_g / M).
+void bound(const pic_config& c, int s, SegHost& h)
+{
+    const auto& T = h.tabs;
+    double elo = T[0].e.front(), ehi = T[0].e.back();
+    size_t nmax = 0;
+    for (const auto& t : T) {
+        elo = std::min(elo, t.e.front());
+        ehi = std::max(ehi, t.e.back());
+        nmax = std::max(nmax, t.e.size());
+    }
+    const int m = 10 * (int)nmax;
+    const double lelo = std::log(elo), lehi = std::log(ehi);
+    const double mass = c.species[s].mass, ng = c.gas_density;
+    const bool ion = !electron_kind(T[0].kind);
+    double best = 0.0;
+    for (int j = 0; j < m; ++j) {
+        const double eps = std::exp(lelo + (double)j * (lehi - lelo) / (double)(m - 1));
+        double sig = 0.0;
+        for (const auto& t : T) sig += sigma_of(t, eps);
+        const double val = ion ? sig : ng * sig * std::sqrt(2.0 * c.e_unit * eps / mass);
+        if (val > best) best = val;
+    }
+    double numax;
+    if (ion) {
+        const double gmax = std::sqrt(2.0 * c.e_unit * ehi / mass) +
+                            6.0 * std::sqrt(kBoltzmann * c.gas_temp / c.gas_mass);
+        numax = ng * best * gmax;
+    } else {
+        numax = 1.05 * best;
+    }
+    const double pnull = 1.0 - std::exp(-numax * c.dt);
+    double t = std::floor(pnull * 4294967296.0);
+    if (t > 4294967295.0) t = 4294967295.0;
+    h.numax = numax;
+    h.t32 = (uint32_t)t;
+}
+
+void fill_push_consts(const pic_config& c, int s, SegConst& sc)
+{
+    const pic_species_cfg& sp = c.species[s];
+    const double dx = c.length / c.n_cells;
+    const double qm = sp.charge / sp.mass;
+    sc.qm = qm;
+    sc.qmh = (float)(0.5 * qm * c.dt);
+    double t[3], t2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        t[k] = 0.5 * qm * c.b_ext[k] * c.dt;
+        t2 += t[k] * t[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        sc.tv[k] = (float)t[k];
+        sc.sv[k] = (float)(2.0 * t[k] / (1.0 + t2));
+        sc.eext[k] = (float)c.e_ext[k];
+    }
+    sc.dtdx = (float)(c.dt / dx);
+    sc.mw_half = 0.5 * sp.mass * sp.weight;
+    sc.q = sp.charge;
+    sc.w = sp.weight;
+    sc.mass = (float)sp.mass;
+    sc.compacts = c.bc == PIC_BC_DIRICHLET ? 1 : 0;
+    sc.half_m_over_e = (float)(0.5 * sp.mass / c.e_unit);
+    sc.two_e_over_m = (float)(2.0 * c.e_unit / sp.mass);
+    sc.two_e_over_me = (float)(2.0 * c.e_unit / c.species[0].mass);
+    sc.emits = (s >= 1 && sp.charge > 0.0 && c.see_gamma > 0.0 && c.bc == PIC_BC_DIRICHLET) ? 1 : 0;
+    sc.see_k = (uint32_t)std::min(16777217.0, std::ceil(c.see_gamma * 16777216.0));
+    sc.vsee = (float)std::sqrt(c.see_temp * c.e_unit / c.species[0].mass);
+    sc.dtdx_e = (float)(c.dt / dx);
+}
+
+// Collision constants of a segment from its host tables: the frequency bound,
+// and the table n_g sigma_k / nu_max on a uniform ln(eps) grid (the input grid
+// itself when every process shares one log-uniform grid, else 4096 points).
+pic_status build_xs(pic_ctx* ctx, int b, int s)
+{
+    const pic_config& c = ctx->cfg[b];
+    SegHost& h = ctx->segh[b * ctx->S + s];
+    SegConst& sc = ctx->segc[b * ctx->S + s];
+    const int nch = (int)h.tabs.size();
+    bound(c, s, h);
+    bool shared = true;
+    const auto& e0 = h.tabs[0].e;
+    for (const auto& t : h.tabs)
+        if (t.e != e0) shared = false;
+    if (shared && e0.size() >= 2) {
+        const double hstep = (std::log(e0.back()) - std::log(e0.front())) / (double)(e0.size() - 1);
+        for (size_t i = 0; i + 1 < e0.size(); ++i) {
+            const double d = std::log(e0[i + 1]) - std::log(e0[i]);
+            if (std::fabs(d - hstep) > 1e-9 * hstep) {
+                shared = false;
+                break;
+            }
+        }
+    }
+    double elo = e0.front(), ehi = e0.back();
+    for (const auto& t : h.tabs) {
+        elo = std::min(elo, t.e.front());
+        ehi = std::max(ehi, t.e.back());
+    }
+    const int n = shared ? (int)e0.size() : 4096;
+    const double l0 = std::log(elo), l1 = std::log(ehi);
+    std::vector<float> xs((size_t)n * nch);
+    const double scale = c.gas_density / h.numax;
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < nch; ++k) {
+            const Table& t = h.tabs[k];
+            double sig;
+            if (shared) {
+                sig = t.s[i];
+            } else {
+                const double eps = std::exp(l0 + (l1 - l0) * (double)i / (double)(n - 1));
+                const double keep_th = t.th;
+                Table tt = t;
+                tt.th = 0.0;              // threshold applied in the kernel
+                sig = sigma_of(tt, eps);
+                (void)keep_th;
+            }
+            xs[(size_t)i * nch + k] = (float)(sig * scale);
+        }
+    }
+    void* p = dev_alloc(ctx, xs.size() * sizeof(float));
+    if (!p) return PIC_ENOMEM;
+    if (hipMemcpy(p, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return PIC_EHIP;
+    if (h.xs_dev) dev_release(ctx, h.xs_dev);
+    h.xs_dev = p;
+    sc.xs = (const float*)p;
+    sc.xs_n = n;
+    sc.xs_ln0 = (float)l0;
+    sc.xs_inv_dln = (float)((double)(n - 1) / (l1 - l0));
+    sc.nch = nch;
+    sc.ion_type = electron_kind(h.tabs[0].kind) ? 0 : 1;
+    sc.t32 = h.t32;
+    for (int k = 0; k < nch; ++k) {
+        sc.kind[k] = h.tabs[k].kind;
+        sc.th[k] = (float)h.tabs[k].th;
+    }
+    const double m = c.species[s].mass, M = c.gas_mass;
+    sc.mr2 = (float)(2.0 * m / M);
+    sc.vt_gas = (float)std::sqrt(kBoltzmann * c.gas_temp / M);
+    sc.m_frac = (float)(m / (m + M));
+    sc.M_frac = (float)(M / (m + M));
+    return PIC_OK;
+}
+
+pic_status upload_segc(pic_ctx* ctx, int idx)
+{
+    return hip_st(hipMemcpy(ctx->d.segc + idx, &ctx->segc[idx], sizeof(SegConst), hipMemcpyHostToDevice));
+}
+
+pic_status flags_status(uint32_t f)
+{
+    if (f & kFlagStall) return PIC_ESTALL;
+    if (f & kFlagCapacity) return PIC_ECAPACITY;
+    if (f & (kFlagNumeric | kFlagCell)) return PIC_ENUMERIC;
+    return PIC_OK;
+}
+
+int64_t max_count_of(pic_ctx* ctx, int only_b)
+{
+    int64_t m = 0;
+    for (int b = 0; b < ctx->B; ++b) {
+        if (only_b >= 0 && b != only_b) continue;
+        for (int s = 0; s < ctx->S; ++s) m = std::max(m, ctx->segc[b * ctx->S + s].cap);
+    }
+    return m;
+}
+
+// event pair around a launch when profiling
+int prof_begin(pic_ctx* c)
+{
+    if (!c->prof) return -1;
+    if (c->ev_used + 2 > c->ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            c->ev.push_back(e);
+        }
+    }
+    const int i = (int)c->ev_used;
+    c->ev_used += 2;
+    (void)hipEventRecord(c->ev[i], c->stream);
+    return i;
+}
+
+void prof_end(pic_ctx* c, int i, int kind)
+{
+    if (i < 0) return;
+    (void)hipEventRecord(c->ev[i + 1], c->stream);
+    c->pending.emplace_back(kind, i);
+}
+
+// fold finished event pairs into the sums
+void prof_collect(pic_ctx* c)
+{
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& pr : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[pr.second], c->ev[pr.second + 1]) != hipSuccess) continue;
+        if (pr.first < 0) {
+            c->fin_ms += ms;
+            c->fin_n += 1.0;
+        } else {
+            c->push_ms[pr.first] += ms;
+            c->push_n[pr.first] += 1.0;
+        }
+    }
+    c->pending.clear();
+    c->ev_used = 0;
+}
+
+pic_status solve_after_deposit(pic_ctx* ctx, int only_b)
+{
+    if (launch_deposit(ctx->d, only_b, max_count_of(ctx, only_b), ctx->stream) != hipSuccess) return PIC_EHIP;
+    FinArgs fa{};
+    fa.d = ctx->d;
+    fa.mode = kFinSolve;
+    fa.only_b = only_b;
+    if (launch_finalize(fa, ctx->stream) != hipSuccess) return PIC_EHIP;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pic_strerror(pic_status s)
+{
+    switch (s) {
+        case PIC_OK: return "ok";
+        case PIC_EINVAL: return "invalid argument";
+        case PIC_ENOMEM: return "out of memory";
+        case PIC_EHIP: return "HIP runtime error";
+        case PIC_ECAPACITY: return "particle capacity exceeded";
+        case PIC_ENUMERIC: return "non-finite or out-of-range particle state";
+        case PIC_ESTATE: return "invalid state";
+        case PIC_ESTALL: return "tile chain stalled";
+        default: return "unknown status";
+    }
+}
+
+void pic_free(pic_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    std::vector<void*> bl = ctx->blocks;
+    for (void* p : bl) dev_release(ctx, p);
+    delete ctx;
+}
+
+pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator* alloc, void* hip_stream,
+                    pic_ctx** out)
+{
+    if (!cfg || !out || n_batch < 1 || n_batch > PIC_MAX_BATCH) return PIC_EINVAL;
+    for (int b = 0; b < n_batch; ++b) {
+        if (check_cfg(cfg[b]) != PIC_OK) return PIC_EINVAL;
+        if (cfg[b].n_species != cfg[0].n_species) return PIC_EINVAL;
+    }
+    pic_ctx* ctx = new (std::nothrow) pic_ctx();
+    if (!ctx) return PIC_ENOMEM;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (alloc && alloc->alloc && alloc->free) {
+        ctx->alloc = *alloc;
+        ctx->has_alloc = true;
+    }
+    const int B = n_batch, S = cfg[0].n_species;
+    ctx->B = B;
+    ctx->S = S;
+    ctx->cfg.assign(cfg, cfg + B);
+    ctx->segc.assign((size_t)B * S, SegConst{});
+    ctx->segh.assign((size_t)B * S, SegHost{});
+    ctx->disc.assign(B, DisConst{});
+    DevPtrs& d = ctx->d;
+    d.B = B;
+    d.S = S;
+    int nodes_max = 0, cells_max = 0;
+    for (int b = 0; b < B; ++b) {
+        nodes_max = std::max(nodes_max, cfg[b].bc == PIC_BC_PERIODIC ? cfg[b].n_cells : cfg[b].n_cells + 1);
+        cells_max = std::max(cells_max, cfg[b].n_cells);
+    }
+    d.nodes_max = nodes_max;
+    d.cells_max = cells_max;
+    ctx->grid_cap.assign(S, 0);
+    pic_status rc = PIC_OK;
+    auto A = [&](size_t bytes) -> void* {
+        void* p = dev_alloc(ctx, bytes);
+        if (!p) rc = PIC_ENOMEM;
+        return p;
+    };
+    // particle storage
+    for (int b = 0; b < B && rc == PIC_OK; ++b) {
+        const pic_config& c = cfg[b];
+        DisConst& dc = ctx->disc[b];
+        dc.n_cells = c.n_cells;
+        dc.n_nodes = c.bc == PIC_BC_PERIODIC ? c.n_cells : c.n_cells + 1;
+        dc.bc = c.bc;
+        dc.field_solve = c.field_solve ? 1 : 0;
+        dc.dx = c.length / c.n_cells;
+        dc.dt = c.dt;
+        dc.L = c.length;
+        dc.eps0 = c.eps0;
+        dc.rho_bg = c.rho_bg;
+        dc.v_amp = c.v_amp;
+        dc.v_freq = c.v_freq;
+        dc.v_phase = c.v_phase;
+        for (int k = 0; k < 3; ++k) {
+            dc.e_ext[k] = c.e_ext[k];
+            dc.b_ext[k] = c.b_ext[k];
+        }
+        dc.key0 = (uint32_t)(c.seed & 0xffffffffu);
+        dc.key1 = (uint32_t)(c.seed >> 32);
+        for (int s = 0; s < S && rc == PIC_OK; ++s) {
+            SegConst& sc = ctx->segc[b * S + s];
+            const int64_t cap = pad_cap(c.species[s].capacity);
+            sc.cap = c.species[s].capacity;
+            ctx->grid_cap[s] += cap;
+            const int copies = c.bc == PIC_BC_DIRICHLET ? 2 : 1;
+            for (int k = 0; k < copies; ++k) {
+                sc.cell[k] = (int32_t*)A(cap * 4);
+                sc.off[k] = (float*)A(cap * 4);
+                sc.vx[k] = (float*)A(cap * 4);
+                sc.vy[k] = (float*)A(cap * 4);
+                sc.vz[k] = (float*)A(cap * 4);
+                sc.id[k] = (uint32_t*)A(cap * 4);
+            }
+            if (copies == 1) {
+                sc.cell[1] = sc.cell[0]; sc.off[1] = sc.off[0]; sc.vx[1] = sc.vx[0];
+                sc.vy[1] = sc.vy[0]; sc.vz[1] = sc.vz[0]; sc.id[1] = sc.id[0];
+            }
+            const int64_t bcap = std::max<int64_t>(16384, cap / 8);
+            sc.bcap = bcap;
+            sc.bcell = (int32_t*)A(bcap * 4);
+            sc.boff = (float*)A(bcap * 4);
+            sc.bvx = (float*)A(bcap * 4);
+            sc.bvy = (float*)A(bcap * 4);
+            sc.bvz = (float*)A(bcap * 4);
+            sc.bid = (uint32_t*)A(bcap * 4);
+            fill_push_consts(c, s, sc);
+        }
+    }
+    int64_t tiles_max = 0;
+    for (int s = 0; s < S; ++s) tiles_max = std::max(tiles_max, ctx->grid_cap[s] / kTileMin + B);
+    d.tiles_max = tiles_max;
+    if (rc == PIC_OK) {
+        d.segc = (SegConst*)A(sizeof(SegConst) * B * S);
+        d.segs = (SegState*)A(sizeof(SegState) * B * S);
+        d.disc = (DisConst*)A(sizeof(DisConst) * B);
+        d.diss = (DisState*)A(sizeof(DisState) * B);
+        d.acc = (unsigned long long*)A(8ull * B * S * nodes_max);
+        d.eacc = (unsigned long long*)A(8ull * B * nodes_max);
+        d.rho = (double*)A(8ull * B * nodes_max);
+        d.phi = (double*)A(8ull * B * nodes_max);
+        d.ef = (double*)A(8ull * B * nodes_max);
+        d.dens = (double*)A(8ull * B * S * nodes_max);
+        d.epair = (float2*)A(8ull * B * cells_max);
+        d.avg = (double*)A(8ull * B * (S + 2) * nodes_max);
+        d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
+        d.status = (unsigned long long*)A(8ull * S * 2 * tiles_max);
+        d.tile_ctr = (unsigned int*)A(4ull * S * 2);
+        d.ke_part = (double*)A(8ull * S * tiles_max);
+        ctx->poisson_scratch = (double*)A(8ull * 3 * nodes_max);
+    }
+    if (rc != PIC_OK) {
+        pic_free(ctx);
+        return rc;
+    }
+    std::vector<SegState> ss((size_t)B * S);
+    std::memset(ss.data(), 0, ss.size() * sizeof(SegState));
+    for (int b = 0; b < B; ++b)
+        for (int s = 0; s < S; ++s) {
+            const pic_species_cfg& sp = cfg[b].species[s];
+            const int64_t n = sp.load == PIC_LOAD_NONE ? 0 : sp.n_init;
+            ss[b * S + s].count = n;
+            ss[b * S + s].surv = n;
+            ss[b * S + s].next_id = (uint32_t)n;
+        }
+    std::vector<DisState> ds(B);
+    std::memset(ds.data(), 0, ds.size() * sizeof(DisState));
+    hipStream_t st = ctx->stream;
+    bool ok = hipMemcpy(d.segc, ctx->segc.data(), sizeof(SegConst) * B * S, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(d.segs, ss.data(), sizeof(SegState) * B * S, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(d.disc, ctx->disc.data(), sizeof(DisConst) * B, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(d.diss, ds.data(), sizeof(DisState) * B, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.acc, 0, 8ull * B * S * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.status, 0, 8ull * S * 2 * tiles_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * S * 2, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * S * tiles_max, st) == hipSuccess;
+    for (int b = 0; b < B && ok; ++b)
+        for (int s = 0; s < S && ok; ++s) {
+            const pic_species_cfg& sp = cfg[b].species[s];
+            LoadArgs la{};
+            la.d = d;
+            la.b = b;
+            la.s = s;
+            la.n = sp.load == PIC_LOAD_NONE ? 0 : sp.n_init;
+            la.load = sp.load;
+            la.vth = sp.vth;
+            for (int k = 0; k < 3; ++k) la.drift[k] = sp.drift[k];
+            la.perturb_eps = cfg[b].perturb_eps;
+            la.perturb_mode = cfg[b].perturb_mode;
+            ok = launch_load(la, st) == hipSuccess;
+        }
+    if (ok) ok = solve_after_deposit(ctx, -1) == PIC_OK;
+    if (ok) ok = launch_halfstep(d, -1, max_count_of(ctx, -1), st) == hipSuccess;
+    if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        pic_free(ctx);
+        return PIC_EHIP;
+    }
+    *out = ctx;
+    return PIC_OK;
+}
+
+pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t kind, double threshold,
+                         int32_t n, const double* energy, const double* sigma)
+{
+    if (!ctx || !energy || !sigma || n < 2) return PIC_EINVAL;
+    if (batch < -1 || batch >= ctx->B || species < 0 || species >= ctx->S) return PIC_EINVAL;
+    if (kind < PIC_XS_ELASTIC || kind > PIC_XS_ION_ISO || !(threshold >= 0.0)) return PIC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!(energy[i] > 0.0) || !std::isfinite(energy[i]) || !(sigma[i] >= 0.0) || !std::isfinite(sigma[i]))
+            return PIC_EINVAL;
+        if (i > 0 && !(energy[i] > energy[i - 1])) return PIC_EINVAL;
+    }
+    if (kind == PIC_XS_IONIZATION && (species != 0 || ctx->S < 2)) return PIC_EINVAL;
+    const int b0 = batch < 0 ? 0 : batch, b1 = batch < 0 ? ctx->B : batch + 1;
+    for (int b = b0; b < b1; ++b) {
+        const pic_config& c = ctx->cfg[b];
+        const SegHost& h = ctx->segh[b * ctx->S + species];
+        if (!(c.gas_density > 0.0) || !(c.gas_mass > 0.0)) return PIC_EINVAL;
+        if ((int)h.tabs.size() >= kMaxChan) return PIC_EINVAL;
+        if (!h.tabs.empty() && electron_kind(h.tabs[0].kind) != electron_kind(kind)) return PIC_EINVAL;
+    }
+    pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
+    for (int b = b0; b < b1 && rc == PIC_OK; ++b) {
+        SegHost& h = ctx->segh[b * ctx->S + species];
+        Table t;
+        t.kind = kind;
+        t.th = threshold;
+        t.e.assign(energy, energy + n);
+        t.s.assign(sigma, sigma + n);
+        h.tabs.push_back(t);
+        rc = build_xs(ctx, b, species);
+        if (rc == PIC_OK) rc = upload_segc(ctx, b * ctx->S + species);
+    }
+    return rc;
+}
+
+pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t sort_every)
+{
+    if (!ctx || (ppt != 1 && ppt != 2 && ppt != 4) || threads != 256 || sort_every != 0) return PIC_EINVAL;
+    pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
+    if (rc != PIC_OK) return rc;
+    // a new tile size renumbers tiles: clear every chain word
+    rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max));
+    if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2));
+    ctx->ppt = ppt;
+    ctx->sort_every = sort_every;
+    ctx->steps_since_sort = 0;
+    return rc;
+}
+
+pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV)
+{
+    if (!ctx || !(eepf_emax_eV > 0.0)) return PIC_EINVAL;
+    ctx->diag = enable ? 1 : 0;
+    ctx->eepf_emax = eepf_emax_eV;
+    return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
+{
+    if (!ctx || n_steps < 0) return PIC_EINVAL;
+    const int S = ctx->S, B = ctx->B;
+    const int T = 256 * ctx->ppt;
+    int nn_max = 0, nc_max = 0, bulk_lo = 0, bulk_hi = 0;
+    for (int b = 0; b < B; ++b) {
+        nn_max = std::max(nn_max, ctx->disc[b].n_nodes);
+        nc_max = std::max(nc_max, ctx->disc[b].n_cells);
+    }
+    {
+        // bulk EEPF window: the middle tenth of the gap of discharge 0 (all
+        // cells when periodic)
+        const DisConst& d0 = ctx->disc[0];
+        if (d0.bc == PIC_BC_PERIODIC) {
+            bulk_lo = 0;
+            bulk_hi = d0.n_cells;
+        } else {
+            bulk_lo = (int)std::floor(0.45 * d0.n_cells);
+            bulk_hi = std::max(bulk_lo + 1, (int)std::ceil(0.55 * d0.n_cells));
+        }
+    }
+    std::vector<bool> general(S, false);
+    std::vector<int64_t> grid(S, 0);
+    for (int s = 0; s < S; ++s) {
+        for (int b = 0; b < B; ++b) {
+            const SegConst& sc = ctx->segc[b * S + s];
+            if (sc.compacts || sc.nch > 0 || sc.emits) general[s] = true;
+            grid[s] += (pad_cap(sc.cap) + T - 1) / T;
+        }
+    }
+    if (push_lds_bytes(nn_max, nc_max, ctx->diag) > 65536) return PIC_EINVAL;
+    hipStream_t st = ctx->stream;
+    for (int it = 0; it < n_steps; ++it) {
+        if (ctx->sort_every > 0 && ++ctx->steps_since_sort >= ctx->sort_every) {
+            ctx->steps_since_sort = 0;
+            for (int s = 0; s < S; ++s)
+                if (launch_sort(ctx->d, s, max_count_of(ctx, -1), ctx->sort_scratch, ctx->sort_scratch_bytes,
+                                st) != hipSuccess)
+                    return PIC_EHIP;
+        }
+        for (int s = 0; s < S; ++s) {
+            PushArgs pa{};
+            pa.d = ctx->d;
+            pa.species = s;
+            pa.diag = ctx->diag;
+            pa.eepf_inv_bin = (float)(kEepfBins / ctx->eepf_emax);
+            pa.bulk_lo = bulk_lo;
+            pa.bulk_hi = bulk_hi;
+            pa.nodes_max_dyn = nn_max;
+            pa.cells_max_dyn = nc_max;
+            const int pe = prof_begin(ctx);
+            if (launch_push(pa, ctx->ppt, general[s], grid[s], st) != hipSuccess) return PIC_EHIP;
+            prof_end(ctx, pe, s);
+        }
+        FinArgs fa{};
+        fa.d = ctx->d;
+        fa.mode = kFinStep;
+        fa.diag = ctx->diag;
+        fa.only_b = -1;
+        const int pe = prof_begin(ctx);
+        if (launch_finalize(fa, st) != hipSuccess) return PIC_EHIP;
+        prof_end(ctx, pe, -1);
+        if (ctx->ev_used + 8 > 4096) prof_collect(ctx);
+    }
+    return PIC_OK;
+}
+
+pic_status pic_profile(pic_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return PIC_EINVAL;
+    prof_collect(ctx);
+    ctx->prof = enable ? 1 : 0;
+    if (enable) {
+        ctx->push_ms.assign(ctx->S, 0.0);
+        ctx->push_n.assign(ctx->S, 0.0);
+        ctx->fin_ms = ctx->fin_n = 0.0;
+    }
+    return PIC_OK;
+}
+
+pic_status pic_sync(pic_ctx* ctx)
+{
+    if (!ctx) return PIC_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    std::vector<DisState> ds(ctx->B);
+    if (hipMemcpy(ds.data(), ctx->d.diss, sizeof(DisState) * ctx->B, hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EHIP;
+    uint32_t f = 0;
+    for (const auto& x : ds) f |= x.flags;
+    return flags_status(f);
+}
+
+pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rho_in, double* phi_out,
+                       double* e_out)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B) return PIC_EINVAL;
+    const int nn = ctx->disc[batch].n_nodes;
+    const size_t nm = ctx->d.nodes_max;
+    double* rho_d = ctx->poisson_scratch;
+    double* phi_d = rho_d + nm;
+    double* e_d = phi_d + nm;
+    hipStream_t st = ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EHIP;
+    hipError_t e;
+    if (rho_in) e = hipMemcpy(rho_d, rho_in, nn * sizeof(double), hipMemcpyHostToDevice);
+    else e = hipMemcpy(rho_d, ctx->d.rho + (size_t)batch * nm, nn * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) return PIC_EHIP;
+    FinArgs fa{};
+    fa.d = ctx->d;
+    fa.mode = kFinExternal;
+    fa.only_b = batch;
+    fa.t_ext = t_s;
+    fa.rho_ext = rho_d;
+    fa.phi_out = phi_d;
+    fa.e_out = e_d;
+    if (launch_finalize(fa, st) != hipSuccess) return PIC_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EHIP;
+    if (phi_out && hipMemcpy(phi_out, phi_d, nn * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EHIP;
+    if (e_out && hipMemcpy(e_out, e_d, nn * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EHIP;
+    return PIC_OK;
+}
+
+pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, int32_t* cell,
+                             float* off, float* vx, float* vy, float* vz, uint32_t* id, int64_t* n_out,
+                             uint32_t* next_id)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S) return PIC_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    const int idx = batch * ctx->S + species;
+    SegState ss;
+    if (hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+    if (n_out) *n_out = ss.count;
+    if (next_id) *next_id = ss.next_id;
+    if (!cell && !off && !vx && !vy && !vz && !id) return PIC_OK;
+    if (cap < ss.count) return PIC_EINVAL;
+    const SegConst& sc = ctx->segc[idx];
+    const int p = ss.parity;
+    const size_t nb = (size_t)ss.count * 4;
+    bool ok = true;
+    if (cell) ok = ok && hipMemcpy(cell, sc.cell[p], nb, hipMemcpyDeviceToHost) == hipSuccess;
+    if (off) ok = ok && hipMemcpy(off, sc.off[p], nb, hipMemcpyDeviceToHost) == hipSuccess;
+    if (vx) ok = ok && hipMemcpy(vx, sc.vx[p], nb, hipMemcpyDeviceToHost) == hipSuccess;
+    if (vy) ok = ok && hipMemcpy(vy, sc.vy[p], nb, hipMemcpyDeviceToHost) == hipSuccess;
+    if (vz) ok = ok && hipMemcpy(vz, sc.vz[p], nb, hipMemcpyDeviceToHost) == hipSuccess;
+    if (id) ok = ok && hipMemcpy(id, sc.id[p], nb, hipMemcpyDeviceToHost) == hipSuccess;
+    return ok ? PIC_OK : PIC_EHIP;
+}
+
+pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const int32_t* cell,
+                             const float* off, const float* vx, const float* vy, const float* vz,
+                             const uint32_t* id, uint32_t next_id, uint64_t step)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S || n < 0) return PIC_EINVAL;
+    const int idx = batch * ctx->S + species;
+    const SegConst& sc = ctx->segc[idx];
+    if (n > sc.cap || (n > 0 && (!cell || !off || !vx || !vy || !vz || !id))) return PIC_EINVAL;
+    const int nc = ctx->disc[batch].n_cells;
+    for (int64_t k = 0; k < n; ++k) {
+        if (cell[k] < 0 || cell[k] >= nc || !(off[k] >= 0.0f && off[k] < 1.0f)) return PIC_EINVAL;
+        if (!std::isfinite(vx[k]) || !std::isfinite(vy[k]) || !std::isfinite(vz[k])) return PIC_ENUMERIC;
+    }
+    hipStream_t st = ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EHIP;
+    SegState ss;
+    if (hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+    const int p = ss.parity;
+    const size_t nb = (size_t)n * 4;
+    bool ok = true;
+    if (n > 0) {
+        ok = ok && hipMemcpy(sc.cell[p], cell, nb, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(sc.off[p], off, nb, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(sc.vx[p], vx, nb, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(sc.vy[p], vy, nb, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(sc.vz[p], vz, nb, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(sc.id[p], id, nb, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    ss.count = n;
+    ss.surv = n;
+    ss.next_id = next_id;
+    ss.births = ss.see_births = 0;
+    ss.ntiles = 0;
+    ok = ok && hipMemcpy(ctx->d.segs + idx, &ss, sizeof(SegState), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return PIC_EHIP;
+    // the whole context moves to `step`
+    std::vector<DisState> ds(ctx->B);
+    if (hipMemcpy(ds.data(), ctx->d.diss, sizeof(DisState) * ctx->B, hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EHIP;
+    for (auto& x : ds) x.step = step;
+    if (hipMemcpy(ctx->d.diss, ds.data(), sizeof(DisState) * ctx->B, hipMemcpyHostToDevice) != hipSuccess)
+        return PIC_EHIP;
+    // chain words and counters follow the step parity: start them clean
+    if (hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max) != hipSuccess) return PIC_EHIP;
+    if (hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2) != hipSuccess) return PIC_EHIP;
+    if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * ctx->d.nodes_max, 0,
+                  8ull * ctx->S * ctx->d.nodes_max) != hipSuccess)
+        return PIC_EHIP;
+    pic_status rc = solve_after_deposit(ctx, batch);
+    if (rc != PIC_OK) return rc;
+    return hip_st(hipStreamSynchronize(st));
+}
+
+pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t out_bytes)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B) return PIC_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    const int S = ctx->S;
+    const int nn = ctx->disc[batch].n_nodes;
+    const size_t nm = ctx->d.nodes_max;
+    std::vector<SegState> ss(S);
+    DisState ds;
+    if (hipMemcpy(ss.data(), ctx->d.segs + (size_t)batch * S, sizeof(SegState) * S, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(&ds, ctx->d.diss + batch, sizeof(DisState), hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EHIP;
+    auto need = [&](size_t bytes) { return out && out_bytes >= bytes; };
+    auto d2h = [&](void* dst, const void* src, size_t bytes) {
+        return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+    };
+    bool ok = true;
+    switch (what) {
+        case PIC_DIAG_COUNTS: {
+            if (!need(8 * (4 + 2 * S))) return PIC_EINVAL;
+            int64_t* o = (int64_t*)out;
+            o[0] = (int64_t)ds.step;
+            o[1] = nn;
+            o[2] = S;
+            o[3] = ds.flags;
+            for (int s = 0; s < S; ++s) {
+                o[4 + 2 * s] = ss[s].count;
+                o[5 + 2 * s] = ss[s].next_id;
+            }
+            break;
+        }
+        case PIC_DIAG_RHO:
+        case PIC_DIAG_PHI:
+        case PIC_DIAG_EFIELD: {
+            if (!need(8ull * nn)) return PIC_EINVAL;
+            const double* src = what == PIC_DIAG_RHO ? ctx->d.rho : (what == PIC_DIAG_PHI ? ctx->d.phi : ctx->d.ef);
+            ok = d2h(out, src + (size_t)batch * nm, 8ull * nn);
+            break;
+        }
+        case PIC_DIAG_DENSITY: {
+            if (!need(8ull * S * nn)) return PIC_EINVAL;
+            for (int s = 0; s < S && ok; ++s)
+                ok = d2h((double*)out + (size_t)s * nn, ctx->d.dens + ((size_t)batch * S + s) * nm, 8ull * nn);
+            break;
+        }
+        case PIC_DIAG_ENERGY: {
+            if (!need(8ull * (S + 1))) return PIC_EINVAL;
+            double* o = (double*)out;
+            for (int s = 0; s < S; ++s) o[s] = ss[s].ke;
+            o[S] = ds.fe;
+            break;
+        }
+        case PIC_DIAG_WALL: {
+            if (!need(8ull * (2 * S + 2))) return PIC_EINVAL;
+            int64_t* o = (int64_t*)out;
+            int64_t see0 = 0, see1 = 0;
+            for (int s = 0; s < S; ++s) {
+                o[2 * s] = (int64_t)ss[s].absorbed[0];
+                o[2 * s + 1] = (int64_t)ss[s].absorbed[1];
+                see0 += (int64_t)ss[s].see[0];
+                see1 += (int64_t)ss[s].see[1];
+            }
+            o[2 * S] = see0;
+            o[2 * S + 1] = see1;
+            break;
+        }
+        case PIC_DIAG_COLL: {
+            if (!need(8ull * S * (3 + kMaxChan))) return PIC_EINVAL;
+            int64_t* o = (int64_t*)out;
+            for (int s = 0; s < S; ++s) {
+                int64_t* r = o + (size_t)s * (3 + kMaxChan);
+                r[0] = (int64_t)ss[s].cand;
+                r[1] = (int64_t)ss[s].nulls;
+                r[2] = (int64_t)ss[s].viol;
+                for (int k = 0; k < kMaxChan; ++k) r[3 + k] = (int64_t)ss[s].coll[k];
+            }
+            break;
+        }
+        case PIC_DIAG_NUMAX: {
+            if (!need(8ull * 2 * S)) return PIC_EINVAL;
+            double* o = (double*)out;
+            for (int s = 0; s < S; ++s) {
+                o[s] = ctx->segh[(size_t)batch * S + s].numax;
+                o[S + s] = (double)ctx->segh[(size_t)batch * S + s].t32;
+            }
+            break;
+        }
+        case PIC_DIAG_FLAGS: {
+            if (!need(8)) return PIC_EINVAL;
+            *(int64_t*)out = ds.flags;
+            const uint32_t z = 0;
+            ok = hipMemcpy(&ctx->d.diss[batch].flags, &z, 4, hipMemcpyHostToDevice) == hipSuccess;
+            if (!ok) return PIC_EHIP;
+            return PIC_OK;
+        }
+        case PIC_DIAG_AVG: {
+            if (!need(8ull * (1 + (size_t)(S + 2) * nn))) return PIC_EINVAL;
+            double* o = (double*)out;
+            std::vector<double> av((size_t)(S + 2) * nm);
+            ok = d2h(av.data(), ctx->d.avg + (size_t)batch * (S + 2) * nm, av.size() * 8);
+            const double ns = ds.avg_samples;
+            o[0] = ns;
+            for (int k = 0; k < S + 2; ++k)
+                for (int i = 0; i < nn; ++i) {
+                    double v = av[(size_t)k * nm + i];
+                    if (k == S + 1) {
+                        const double ne = av[i];
+                        v = ne > 0.0 ? v / ne : 0.0;          // <eps> = sum(n eps) / sum(n)
+                    } else if (ns > 0.0) {
+                        v /= ns;
+                    }
+                    o[1 + (size_t)k * nn + i] = v;
+                }
+            break;
+        }
+        case PIC_DIAG_EEPF: {
+            if (!need(8ull * (2 * kEepfBins + 2))) return PIC_EINVAL;
+            std::vector<unsigned long long> h(2 * kEepfBins);
+            ok = d2h(h.data(), ctx->d.eepf + (size_t)batch * 2 * kEepfBins, h.size() * 8);
+            double* o = (double*)out;
+            for (int i = 0; i < 2 * kEepfBins; ++i) o[i] = (double)h[i];
+            o[2 * kEepfBins] = ctx->eepf_emax / kEepfBins;
+            o[2 * kEepfBins + 1] = ds.eepf_samples;
+            break;
+        }
+        case PIC_DIAG_RESET_AVG: {
+            ok = hipMemset(ctx->d.avg + (size_t)batch * (S + 2) * nm, 0, 8ull * (S + 2) * nm) == hipSuccess;
+            ok = ok && hipMemset(ctx->d.eepf + (size_t)batch * 2 * kEepfBins, 0, 8ull * 2 * kEepfBins) == hipSuccess;
+            ds.avg_samples = 0.0;
+            ds.eepf_samples = 0.0;
+            ok = ok && hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+            break;
+        }
+        case PIC_DIAG_TIMING: {
+            if (!need(8ull * (2 + 2 * S))) return PIC_EINVAL;
+            prof_collect(ctx);
+            double* o = (double*)out;
+            o[0] = ctx->fin_n;
+            o[1] = ctx->fin_ms;
+            for (int s = 0; s < S; ++s) {
+                o[2 + 2 * s] = s < (int)ctx->push_n.size() ? ctx->push_n[s] : 0.0;
+                o[3 + 2 * s] = s < (int)ctx->push_ms.size() ? ctx->push_ms[s] : 0.0;
+            }
+            break;
+        }
+        case PIC_DIAG_CHARGE: {
+            if (!need(16)) return PIC_EINVAL;
+            std::vector<double> rho(nn);
+            ok = d2h(rho.data(), ctx->d.rho + (size_t)batch * nm, 8ull * nn);
+            const DisConst& dc = ctx->disc[batch];
+            double q = 0.0;
+            for (int i = 0; i < nn; ++i) {
+                const double vol = (dc.bc != PIC_BC_PERIODIC && (i == 0 || i == nn - 1)) ? 0.5 * dc.dx : dc.dx;
+                q += rho[i] * vol;
+            }
+            double qp = dc.rho_bg * dc.L;
+            for (int s = 0; s < S; ++s) qp += ctx->segc[(size_t)batch * S + s].q * ctx->segc[(size_t)batch * S + s].w *
+                                              (double)ss[s].count;
+            ((double*)out)[0] = q;
+            ((double*)out)[1] = qp;
+            break;
+        }
+        default:
+            return PIC_EINVAL;
+    }
+    if (!ok) return PIC_EHIP;
+    return flags_status(ds.flags);
+}
+
+}  // extern "C"

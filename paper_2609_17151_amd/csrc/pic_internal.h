@@ -1,0 +1,138 @@
+// Internal layout of the MI355X PIC-MCC library: constant and mutable state of
+// every (discharge, species) segment and of every discharge, and the kernel
+// argument blocks.  Device memory is structure-of-arrays: per segment, one
+// array per particle field (cell i32, in-cell offset f32, vx/vy/vz f32, id u32),
+// two copies when particles can leave (walls) so that survivors are compacted
+// into the other copy in their original order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kMaxSpecies = PIC_MAX_SPECIES;
+constexpr int kMaxChan = PIC_MAX_CHAN;
+constexpr int kMaxCells = 4096;
+constexpr int kFinThreads = 1024;          // finalize / field-solve workgroup
+constexpr int kNodesPerThread = 4;         // kFinThreads * 4 >= kMaxCells + 1
+constexpr int kEepfBins = PIC_EEPF_BINS;
+
+// latched device flags
+constexpr uint32_t kFlagCapacity = 1u << 0;
+constexpr uint32_t kFlagNumeric = 1u << 1;
+constexpr uint32_t kFlagNuMax = 1u << 2;
+constexpr uint32_t kFlagCell = 1u << 3;
+constexpr uint32_t kFlagStall = 1u << 4;
+
+// Fixed-point scale of the deposit: a particle's weights (1-f, f) become the
+// integers 2^32 - q and q, q = f * 2^32, so sums are exact and independent of
+// the order in which tiles add them.
+constexpr double kDepScale = 4294967296.0;
+
+struct SegConst {
+    // particle storage, [0] and [1] are the two copies (same pointer when the
+    // segment never compacts)
+    int32_t* cell[2];
+    float* off[2];
+    float* vx[2];
+    float* vy[2];
+    float* vz[2];
+    uint32_t* id[2];
+    // births staging
+    int32_t* bcell;
+    float* boff;
+    float* bvx;
+    float* bvy;
+    float* bvz;
+    uint32_t* bid;
+    int64_t cap, bcap;
+    // push
+    float qmh;              // (q/m) dt/2
+    float tv[3], sv[3];     // Boris rotation vectors t and s = 2t/(1+t^2)
+    float dtdx;             // dt/dx
+    float eext[3];          // imposed field
+    double mw_half;         // m w / 2 (kinetic energy per unit area)
+    double q, w, qm;
+    float mass;
+    int32_t compacts;       // 1 when particles can be absorbed (bounded domain)
+    // collisions
+    int32_t nch, ion_type;
+    uint32_t t32;
+    int32_t xs_n;
+    float xs_ln0, xs_inv_dln;
+    const float* xs;        // [xs_n][nch] n_g sigma_k / nu_max on a uniform ln(eps) grid
+    int32_t kind[kMaxChan];
+    float th[kMaxChan];
+    float half_m_over_e, two_e_over_m;
+    float mr2;              // 2 m / M_gas
+    float vt_gas;           // sqrt(k T_g / M_gas)
+    float m_frac, M_frac;   // m/(m+M), M/(m+M)
+    // secondary emission by this (ion) species
+    int32_t emits;
+    uint32_t see_k;         // emit iff (2*(x>>9)+1) < see_k
+    float vsee;             // sqrt(e T_see / m_e)
+    float dtdx_e;           // dt/dx of the electron species (same mesh and dt)
+    // electrons born here: speed from energy
+    float two_e_over_me;
+};
+
+struct DisConst {
+    int32_t n_cells, n_nodes, bc, field_solve;
+    double dx, dt, L, eps0, rho_bg, v_amp, v_freq, v_phase;
+    double e_ext[3], b_ext[3];
+    uint32_t key0, key1;
+};
+
+// mutable, one per segment
+struct SegState {
+    int64_t count;          // particles held
+    int64_t surv;           // survivors of the current step
+    int64_t births;         // species 0: ionization events of the step (one electron and one ion each)
+    int64_t see_births;     // ion species: secondary electrons emitted this step
+    int64_t tile_first, ntiles;  // global tile range of the current step
+    uint32_t next_id;
+    int32_t parity;         // which copy holds the particles
+    unsigned long long absorbed[2], see[2];
+    unsigned long long cand, nulls, viol;
+    unsigned long long coll[kMaxChan];
+    unsigned long long dropped;
+    double ke;              // time-centred kinetic energy of the last step
+};
+
+// mutable, one per discharge
+struct DisState {
+    uint64_t step;
+    uint32_t flags;
+    uint32_t pad;
+    double fe;
+    double avg_samples;
+    double eepf_samples;
+};
+
+struct Ctx;  // host
+
+struct DevPtrs {
+    int32_t B, S;
+    SegConst* segc;              // [B*S]
+    SegState* segs;              // [B*S]
+    DisConst* disc;              // [B]
+    DisState* diss;              // [B]
+    unsigned long long* acc;     // [B][S][nodes_max] deposit sums (fixed point)
+    unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^24)
+    double* rho;                 // [B][nodes_max]
+    double* phi;
+    double* ef;
+    double* dens;                // [B][S][nodes_max]
+    float2* epair;               // [B][cells_max] (E[c], E[c+1]) for the gather
+    double* avg;                 // [B][(S+2)][nodes_max]
+    unsigned long long* eepf;    // [B][2][bins]
+    unsigned long long* status;  // [S][2][tiles_max] tile chain words
+    unsigned int* tile_ctr;      // [S][2]
+    double* ke_part;             // [S][tiles_max]
+    int32_t nodes_max, cells_max;
+    int64_t tiles_max;
+};
+
+}  // namespace pic

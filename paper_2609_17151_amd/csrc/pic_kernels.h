@@ -1,0 +1,53 @@
+// Kernel argument blocks and launchers of the MI355X PIC-MCC library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+struct PushArgs {
+    DevPtrs d;
+    int32_t species;
+    int32_t diag;                 // accumulate electron energy deposit and EEPF
+    float eepf_inv_bin;           // 1 / bin width (eV)
+    int32_t bulk_lo, bulk_hi;     // cells of the bulk EEPF window
+    int32_t nodes_max_dyn, cells_max_dyn;
+};
+
+// finalize modes
+constexpr int kFinStep = 0;       // append births, deposit -> field at t^{n+1}, step++
+constexpr int kFinSolve = 1;      // deposit -> field at t = step dt, no state change but the field
+constexpr int kFinExternal = 2;   // field of rho_ext at t_ext into phi_out / e_out only
+
+struct FinArgs {
+    DevPtrs d;
+    int32_t mode;
+    int32_t diag;
+    int32_t only_b;               // -1: all discharges (grid = B), else this one (grid = 1)
+    double t_ext;
+    const double* rho_ext;
+    double* phi_out;
+    double* e_out;
+};
+
+struct LoadArgs {
+    DevPtrs d;
+    int32_t b, s;
+    int64_t n;
+    int32_t load;
+    double vth, drift[3];
+    double perturb_eps;
+    int32_t perturb_mode;
+};
+
+hipError_t launch_push(const PushArgs& a, int ppt, bool general, int64_t grid, hipStream_t st);
+hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
+hipError_t launch_load(const LoadArgs& a, hipStream_t st);
+hipError_t launch_deposit(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);
+hipError_t launch_halfstep(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);
+hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_count, void* scratch, size_t scratch_bytes,
+                       hipStream_t st);
+size_t push_lds_bytes(int n_nodes, int n_cells, int diag);
+
+}  // namespace pic
