@@ -39,10 +39,24 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--ppt", type=int, default=4)
+    ap.add_argument("--threads", type=int, default=1024)
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n * 4, "reads_bytes": n * 4, "writes_bytes": n * 4}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -54,12 +68,14 @@ def main():
     cfg = W.exb()
     n = sum(sp["n_init"] for sp in cfg["species"])
     sim = P.Sim(cfg)
-    sim.config_tiles(args.ppt, 256, args.sort_every)
+    sim.config_tiles(args.ppt, args.threads, args.sort_every)
+    if args.no_graph:
+        sim.use_graphs(False)
     sim.step(args.warmup)
     sim.sync()
     stream = sim.stream
     torch.cuda.synchronize()
-    sim.profile(True)
+    # timed region: the step loop replayed from captured HIP graphs
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
@@ -68,6 +84,11 @@ def main():
     torch.cuda.synchronize()
     sim.sync()
     ms = start.elapsed_time(end)
+    # the same number of steps again with an event pair around every kernel
+    # launch (direct launches) for the per-kernel durations
+    sim.profile(True)
+    sim.step(args.steps)
+    sim.sync()
     tm = sim.timing()
     sim.profile(False)
     ms_step = ms / args.steps
@@ -90,14 +111,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "exb_drift_box: 4e6 e- + 4e6 Xe+, 1024 cells, periodic, "
                                "B=0.02 T, E=2e4 V/m, dt=5e-12 s",
-                   "particles": n, "cells": cfg["n_cells"], "particles_per_thread": args.ppt,
-                   "sort_every": args.sort_every},
+                   "particles": n, "cells": cfg["n_cells"], "particles_per_thread": args.ppt, "threads_per_group": args.threads,
+                   "sort_every": args.sort_every, "graphs": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "push_kernel", "avg_launch_ms": push_avg_ms,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
         "breakdown_ms_per_step": {"push": float(tm["push_ms"].sum()) / args.steps,
-                                  "finalize": float(tm["finalize_ms"]) / args.steps},
+                                  "finalize": float(tm["finalize_ms"]) / args.steps,
+                                  "finalize_avg_launch_ms": float(tm["finalize_ms"] / max(tm["finalize_n"], 1))},
     }
     if not args.no_cpu:
         sim.close()

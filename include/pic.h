@@ -229,6 +229,13 @@ pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV);
  * clears the sums.  A measuring aid; it adds two event records per launch. */
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
 
+/* pic_use_graphs: when enable is non-zero (the default), pic_step captures a
+ * chunk of consecutive steps once into a HIP graph on a private stream and
+ * replays it on the context's stream, which removes the host launch gaps
+ * between kernels; all per-step state lives on the device, so one capture
+ * serves any number of steps.  Profiling (pic_profile) uses direct launches. */
+pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable);
+
 /* pic_config_tiles: tile shape of the particle kernels (particles per thread
  * 1, 2, 4 or 8; threads per workgroup 64..1024 in steps of 64) and the
  * interval in steps of the sort by cell (0 = never).  Takes effect at the

@@ -87,6 +87,7 @@ def load_library():
         "pic_config_tiles": (i32, [P, i32, i32, i32]),
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_profile": (i32, [P, i32]),
+        "pic_use_graphs": (i32, [P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -263,6 +264,9 @@ class Sim:
 
     def reset_avg(self, batch=0):
         self._check(_lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0), "pic_diag(RESET_AVG)")
+
+    def use_graphs(self, enable=True):
+        self._check(_lib.pic_use_graphs(self.h, int(enable)), "pic_use_graphs")
 
     def profile(self, enable=True):
         self._check(_lib.pic_profile(self.h, int(enable)), "pic_profile")

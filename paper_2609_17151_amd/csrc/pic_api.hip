@@ -18,7 +18,7 @@ using namespace pic;
 namespace {
 
 constexpr double kBoltzmann = 1.380649e-23;
-constexpr int kTileMax = 1024;     // largest tile (256 threads x 4)
+constexpr int kTileMax = 4096;     // largest tile (1024 threads x 4): capacities are padded to it
 constexpr int kTileMin = 256;
 
 struct Table {
@@ -47,7 +47,9 @@ struct pic_ctx {
     std::vector<DisConst> disc;
     DevPtrs d{};
     std::vector<void*> blocks;
-    int ppt = 4;
+    int ppt = 4;                          // particles per thread
+    int threads = 1024;                   // threads per workgroup (streaming kernels)
+    int n_cu = 256;
     int sort_every = 0;
     int64_t steps_since_sort = 0;
     int diag = 0;
@@ -63,6 +65,12 @@ struct pic_ctx {
     size_t ev_used = 0;
     std::vector<double> push_ms, push_n;
     double fin_ms = 0.0, fin_n = 0.0;
+    // replay of a captured chunk of steps
+    int use_graph = 1;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_steps = 0;
+    uint64_t g_key = 0;
 };
 
 namespace {
@@ -360,6 +368,10 @@ pic_status solve_after_deposit(pic_ctx* ctx, int only_b)
 
 }  // namespace
 
+namespace {
+void drop_graph(pic_ctx* ctx);
+}
+
 extern "C" {
 
 const char* pic_strerror(pic_status s)
@@ -382,6 +394,8 @@ void pic_free(pic_ctx* ctx)
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     std::vector<void*> bl = ctx->blocks;
     for (void* p : bl) dev_release(ctx, p);
     delete ctx;
@@ -398,6 +412,12 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     pic_ctx* ctx = new (std::nothrow) pic_ctx();
     if (!ctx) return PIC_ENOMEM;
     ctx->stream = (hipStream_t)hip_stream;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ctx->n_cu = prop.multiProcessorCount;
+    }
     if (alloc && alloc->alloc && alloc->free) {
         ctx->alloc = *alloc;
         ctx->has_alloc = true;
@@ -445,6 +465,14 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         for (int k = 0; k < 3; ++k) {
             dc.e_ext[k] = c.e_ext[k];
             dc.b_ext[k] = c.b_ext[k];
+        }
+        dc.c2 = dc.dx * dc.dx / c.eps0;
+        dc.inv_2dx = 1.0 / (2.0 * dc.dx);
+        dc.inv_dx = 1.0 / dc.dx;
+        dc.wall_coef = dc.dx / (2.0 * c.eps0);
+        for (int s = 0; s < S; ++s) {
+            dc.dens_coef[s] = c.species[s].weight / dc.dx / kDepScale;
+            dc.q[s] = c.species[s].charge;
         }
         dc.key0 = (uint32_t)(c.seed & 0xffffffffu);
         dc.key1 = (uint32_t)(c.seed >> 32);
@@ -590,13 +618,16 @@ pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t k
 
 pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t sort_every)
 {
-    if (!ctx || (ppt != 1 && ppt != 2 && ppt != 4) || threads != 256 || sort_every != 0) return PIC_EINVAL;
+    if (!ctx || (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) ||
+        (threads != 256 && threads != 512 && threads != 1024) || sort_every != 0)
+        return PIC_EINVAL;
     pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
     if (rc != PIC_OK) return rc;
     // a new tile size renumbers tiles: clear every chain word
     rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max));
     if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2));
     ctx->ppt = ppt;
+    ctx->threads = threads;
     ctx->sort_every = sort_every;
     ctx->steps_since_sort = 0;
     return rc;
@@ -610,71 +641,173 @@ pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV)
     return PIC_OK;
 }
 
-pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
+namespace {
+
+struct StepPlan {
+    std::vector<PushArgs> pa;
+    std::vector<int> ppt, threads;
+    std::vector<bool> general;
+    std::vector<int64_t> grid;
+    FinArgs fa{};
+    uint64_t key = 0;
+};
+
+pic_status plan_step(pic_ctx* ctx, StepPlan& p)
 {
-    if (!ctx || n_steps < 0) return PIC_EINVAL;
     const int S = ctx->S, B = ctx->B;
-    const int T = 256 * ctx->ppt;
     int nn_max = 0, nc_max = 0, bulk_lo = 0, bulk_hi = 0;
     for (int b = 0; b < B; ++b) {
         nn_max = std::max(nn_max, ctx->disc[b].n_nodes);
         nc_max = std::max(nc_max, ctx->disc[b].n_cells);
     }
-    {
-        // bulk EEPF window: the middle tenth of the gap of discharge 0 (all
-        // cells when periodic)
-        const DisConst& d0 = ctx->disc[0];
-        if (d0.bc == PIC_BC_PERIODIC) {
-            bulk_lo = 0;
-            bulk_hi = d0.n_cells;
-        } else {
-            bulk_lo = (int)std::floor(0.45 * d0.n_cells);
-            bulk_hi = std::max(bulk_lo + 1, (int)std::ceil(0.55 * d0.n_cells));
-        }
+    // bulk EEPF window: the middle tenth of the gap of discharge 0 (all cells
+    // when periodic)
+    const DisConst& d0 = ctx->disc[0];
+    if (d0.bc == PIC_BC_PERIODIC) {
+        bulk_lo = 0;
+        bulk_hi = d0.n_cells;
+    } else {
+        bulk_lo = (int)std::floor(0.45 * d0.n_cells);
+        bulk_hi = std::max(bulk_lo + 1, (int)std::ceil(0.55 * d0.n_cells));
     }
-    std::vector<bool> general(S, false);
-    std::vector<int64_t> grid(S, 0);
+    // per species: streaming or general kernel, tile size, persistent grid
+    const size_t lds = push_lds_bytes(nn_max, nc_max, ctx->diag);
+    if (lds > 65536) return PIC_EINVAL;
+    p.pa.assign(S, PushArgs{});
+    p.ppt.assign(S, ctx->ppt);
+    p.threads.assign(S, ctx->threads);
+    p.general.assign(S, false);
+    p.grid.assign(S, 0);
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+    mix((uint64_t)ctx->diag);
     for (int s = 0; s < S; ++s) {
         for (int b = 0; b < B; ++b) {
             const SegConst& sc = ctx->segc[b * S + s];
-            if (sc.compacts || sc.nch > 0 || sc.emits) general[s] = true;
-            grid[s] += (pad_cap(sc.cap) + T - 1) / T;
+            if (sc.compacts || sc.nch > 0 || sc.emits) p.general[s] = true;
         }
+        push_shape(p.ppt[s], p.threads[s], p.general[s]);
+        const int T = p.threads[s] * p.ppt[s];
+        int64_t tiles = 0;
+        for (int b = 0; b < B; ++b) tiles += (pad_cap(ctx->segc[b * S + s].cap) + T - 1) / T;
+        const int64_t resident = (int64_t)push_occupancy(p.ppt[s], p.threads[s], p.general[s], lds) * ctx->n_cu;
+        p.grid[s] = std::max<int64_t>(1, std::min(tiles, resident));
+        PushArgs& pa = p.pa[s];
+        pa.d = ctx->d;
+        pa.species = s;
+        pa.diag = ctx->diag;
+        pa.eepf_inv_bin = (float)(kEepfBins / ctx->eepf_emax);
+        pa.bulk_lo = bulk_lo;
+        pa.bulk_hi = bulk_hi;
+        pa.nodes_max_dyn = nn_max;
+        pa.cells_max_dyn = nc_max;
+        mix((uint64_t)p.ppt[s]);
+        mix((uint64_t)p.threads[s]);
+        mix((uint64_t)p.general[s]);
+        mix((uint64_t)p.grid[s]);
     }
-    if (push_lds_bytes(nn_max, nc_max, ctx->diag) > 65536) return PIC_EINVAL;
-    hipStream_t st = ctx->stream;
-    for (int it = 0; it < n_steps; ++it) {
+    p.fa.d = ctx->d;
+    p.fa.mode = kFinStep;
+    p.fa.diag = ctx->diag;
+    p.fa.only_b = -1;
+    mix((uint64_t)ctx->sort_every);
+    p.key = key;
+    return PIC_OK;
+}
+
+// queue `n` steps on stream st; `prof` wraps every launch in an event pair
+pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st, bool prof)
+{
+    for (int it = 0; it < n; ++it) {
         if (ctx->sort_every > 0 && ++ctx->steps_since_sort >= ctx->sort_every) {
             ctx->steps_since_sort = 0;
-            for (int s = 0; s < S; ++s)
+            for (int s = 0; s < ctx->S; ++s)
                 if (launch_sort(ctx->d, s, max_count_of(ctx, -1), ctx->sort_scratch, ctx->sort_scratch_bytes,
                                 st) != hipSuccess)
                     return PIC_EHIP;
         }
-        for (int s = 0; s < S; ++s) {
-            PushArgs pa{};
-            pa.d = ctx->d;
-            pa.species = s;
-            pa.diag = ctx->diag;
-            pa.eepf_inv_bin = (float)(kEepfBins / ctx->eepf_emax);
-            pa.bulk_lo = bulk_lo;
-            pa.bulk_hi = bulk_hi;
-            pa.nodes_max_dyn = nn_max;
-            pa.cells_max_dyn = nc_max;
-            const int pe = prof_begin(ctx);
-            if (launch_push(pa, ctx->ppt, general[s], grid[s], st) != hipSuccess) return PIC_EHIP;
+        for (int s = 0; s < ctx->S; ++s) {
+            const int pe = prof ? prof_begin(ctx) : -1;
+            if (launch_push(p.pa[s], p.ppt[s], p.threads[s], p.general[s], p.grid[s], st) != hipSuccess)
+                return PIC_EHIP;
             prof_end(ctx, pe, s);
         }
-        FinArgs fa{};
-        fa.d = ctx->d;
-        fa.mode = kFinStep;
-        fa.diag = ctx->diag;
-        fa.only_b = -1;
-        const int pe = prof_begin(ctx);
-        if (launch_finalize(fa, st) != hipSuccess) return PIC_EHIP;
+        const int pe = prof ? prof_begin(ctx) : -1;
+        if (launch_finalize(p.fa, st) != hipSuccess) return PIC_EHIP;
         prof_end(ctx, pe, -1);
-        if (ctx->ev_used + 8 > 4096) prof_collect(ctx);
+        if (prof && ctx->ev_used + 8 > 4096) prof_collect(ctx);
     }
+    return PIC_OK;
+}
+
+void drop_graph(pic_ctx* ctx)
+{
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->g_steps = 0;
+}
+
+// capture `n` steps into a replayable graph (on a private capture stream)
+pic_status capture_steps(pic_ctx* ctx, const StepPlan& p, int n)
+{
+    drop_graph(ctx);
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return PIC_EHIP;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
+    const int64_t saved = ctx->steps_since_sort;
+    const pic_status rc = enqueue_steps(ctx, p, n, ctx->cap_stream, false);
+    ctx->steps_since_sort = saved;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (rc != PIC_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != PIC_OK ? rc : PIC_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        ctx->gexec = nullptr;
+        return PIC_EHIP;
+    }
+    ctx->g_steps = n;
+    ctx->g_key = p.key;
+    return PIC_OK;
+}
+
+constexpr int kGraphSteps = 32;
+
+}  // namespace
+
+pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
+{
+    if (!ctx || n_steps < 0) return PIC_EINVAL;
+    StepPlan p;
+    pic_status rc = plan_step(ctx, p);
+    if (rc != PIC_OK) return rc;
+    hipStream_t st = ctx->stream;
+    int left = n_steps;
+    // replays of a captured chunk; the sort interval must divide the chunk so
+    // that every replay sorts at the same steps
+    const bool graph_ok = ctx->use_graph && !ctx->prof &&
+                          (ctx->sort_every == 0 || (kGraphSteps % ctx->sort_every == 0 && ctx->steps_since_sort == 0));
+    if (graph_ok && left >= kGraphSteps) {
+        if (!ctx->gexec || ctx->g_key != p.key || ctx->g_steps != kGraphSteps) {
+            rc = capture_steps(ctx, p, kGraphSteps);
+            if (rc != PIC_OK) return rc;
+        }
+        while (left >= kGraphSteps) {
+            if (hipGraphLaunch(ctx->gexec, st) != hipSuccess) return PIC_EHIP;
+            left -= kGraphSteps;
+        }
+    }
+    return enqueue_steps(ctx, p, left, st, ctx->prof != 0);
+}
+
+pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return PIC_EINVAL;
+    ctx->use_graph = enable ? 1 : 0;
+    if (!enable) drop_graph(ctx);
     return PIC_OK;
 }
 

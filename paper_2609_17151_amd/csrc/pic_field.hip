@@ -9,8 +9,8 @@
 // the equations read d[i] = d[0] - G[i], G[i] = g[1] + ... + g[i], so
 // phi[i] = phi[0] + i d[0] - K[i] with K[i] = G[0] + ... + G[i-1]; the far
 // boundary value fixes d[0] (Dirichlet: phi[N] = 0; periodic: phi[N] = phi[0]
-// after removing the mean charge).  One 1024-thread workgroup per discharge,
-// four nodes per thread, FP64 scans in a fixed order.
+// after removing the mean charge).  Both nested sums come out of one scan of
+// (n, S, P) triples over contiguous runs of nodes, in a fixed order, in FP64.
 #include "pic_device.h"
 #include "pic_internal.h"
 #include "pic_kernels.h"
@@ -19,288 +19,325 @@ namespace pic {
 
 namespace {
 
-__device__ double block_excl_scan(double v, double* s_w, double& total)
+constexpr int kFT = kFinThreads;          // finalize threads
+constexpr int kWaves = kFT / 64;
+constexpr int kBook = kFT - 64;           // first thread of the bookkeeping wave
+
+// Prefix state of a run of nodes for the two nested sums of the solve:
+// n nodes, S = sum of g, P = sum over the run of the running sums of g.
+// Appending run B after run A: n = nA + nB, S = SA + SB, P = PA + PB + nB SA.
+// The all-zero run is the identity.
+struct Run {
+    double n, S, P;
+};
+
+__device__ __forceinline__ Run run_combine(const Run& A, const Run& B)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const double incl = wave_incl_scan_f64(v);
-    if (lane == 63) s_w[wid] = incl;
-    __syncthreads();
-    double off = 0.0, tot = 0.0;
-    const int nw = blockDim.x >> 6;
-    for (int w = 0; w < nw; ++w) {
-        if (w < wid) off += s_w[w];
-        tot += s_w[w];
-    }
-    __syncthreads();
-    total = tot;
-    return off + incl - v;
+    return Run{A.n + B.n, A.S + B.S, A.P + B.P + B.n * A.S};
 }
 
-__device__ double block_sum(double v, double* s_w)
+// DPP move of a double within a wave (zero where the source lane is invalid
+// or the destination row is masked off)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-    double tot;
-    (void)block_excl_scan(v, s_w, tot);
-    return tot;
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffu), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void run_step(Run& v)
+{
+    Run o;
+    o.n = dpp_f64<CTRL, ROW_MASK>(v.n);
+    o.S = dpp_f64<CTRL, ROW_MASK>(v.S);
+    o.P = dpp_f64<CTRL, ROW_MASK>(v.P);
+    v = run_combine(o, v);
+}
+
+// inclusive scan of Run over a wave, lanes in order: row shifts 1, 2, 4, 8
+// within each row of 16 lanes, then the last lane of row 0 into rows 1 and 3
+// and the last lane of row 1 into rows 2 and 3
+__device__ __forceinline__ Run wave_run_scan(Run v)
+{
+    run_step<0x111, 0xf>(v);   // row_shr:1
+    run_step<0x112, 0xf>(v);   // row_shr:2
+    run_step<0x114, 0xf>(v);   // row_shr:4
+    run_step<0x118, 0xf>(v);   // row_shr:8
+    run_step<0x142, 0xa>(v);   // row_bcast:15
+    run_step<0x143, 0xc>(v);   // row_bcast:31
+    return v;
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs a)
+// One workgroup per discharge, one node per thread (up to four).  The last
+// wave does the particle bookkeeping of the step (births appended after the
+// survivors, counts, ids, parity, kinetic-energy partial sums) while the others
+// turn the deposit into densities and charge.  Poisson: every thread forms
+// the run of its node, a wave-level scan and one 16-entry scan across waves
+// give K[i] and G[i] at every node, and phi follows directly.
+__global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
 {
-    constexpr int P = kNodesPerThread;
     const DevPtrs& d = a.d;
     const int b = a.only_b >= 0 ? a.only_b : (int)blockIdx.x;
-    const int S = d.S, tid = threadIdx.x;
+    const int S = d.S, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const DisConst& dc = d.disc[b];
     DisState& ds = d.diss[b];
     const int nn = dc.n_nodes, nc = dc.n_cells;
     const int periodic = dc.bc == PIC_BC_PERIODIC;
     const size_t nb = (size_t)b * d.nodes_max;
 
-    __shared__ double s_w[kFinThreads / 64];
-    __shared__ double s_phi[kMaxCells + 1];   // phi, then E
-    __shared__ double s_bcast[4];
+    __shared__ double s_a[kMaxCells + 1];     // rho, then phi
+    __shared__ double s_bc[4];                // rho at the walls
+    __shared__ double s_w[kWaves];
+    __shared__ Run s_run[kWaves * kNodesPerThread];
 
-    // ---- births after the survivors; counts, ids and copies ---------------
-    if (a.mode == kFinStep) {
-        const int64_t n_ion = d.segs[b * S + 0].births;
-        const int64_t n_see = S > 1 ? d.segs[b * S + 1].see_births : 0;
-        for (int s = 0; s < S; ++s) {
-            const SegConst& sc = d.segc[b * S + s];
-            SegState& st = d.segs[b * S + s];
-            const int64_t surv = st.surv;
-            const int64_t nbirth = s == 0 ? n_ion + n_see : (s == 1 ? n_ion : 0);
-            int64_t nmove = nbirth;
-            if (nmove > sc.bcap) nmove = sc.bcap;
-            if (nmove > sc.cap - surv) nmove = sc.cap - surv;
-            const int out = sc.compacts ? (st.parity ^ 1) : st.parity;
-            for (int64_t k = tid; k < nmove; k += kFinThreads) {
-                sc.cell[out][surv + k] = sc.bcell[k];
-                sc.off[out][surv + k] = sc.boff[k];
-                sc.vx[out][surv + k] = sc.bvx[k];
-                sc.vy[out][surv + k] = sc.bvy[k];
-                sc.vz[out][surv + k] = sc.bvz[k];
-                sc.id[out][surv + k] = sc.bid[k];
-            }
-            // kinetic energy of the step, tiles summed in a fixed order
-            double kp = 0.0;
-            for (int64_t t = tid; t < st.ntiles; t += kFinThreads)
-                kp += d.ke_part[(size_t)s * d.tiles_max + st.tile_first + t];
-            const double ke = block_sum(kp, s_w);
-            __syncthreads();
-            if (tid == 0) {
-                if (nmove < nbirth) {
-                    atomicOr(&ds.flags, kFlagCapacity);
-                    st.dropped += (unsigned long long)(nbirth - nmove);
+    if (tid >= kBook) {
+        // ---- bookkeeping wave: every load first, then the updates -------------
+        if (a.mode == kFinStep) {
+            int64_t surv[kMaxSpecies], tfirst[kMaxSpecies], ntl[kMaxSpecies];
+            int par[kMaxSpecies];
+            const int64_t n_ion = d.segs[b * S + 0].births;
+            const int64_t n_see = S > 1 ? d.segs[b * S + 1].see_births : 0;
+#pragma unroll
+            for (int s = 0; s < kMaxSpecies; ++s) {
+                if (s < S) {
+                    const SegState& st = d.segs[b * S + s];
+                    surv[s] = st.surv;
+                    par[s] = st.parity;
+                    tfirst[s] = st.tile_first;
+                    ntl[s] = st.ntiles;
                 }
-                st.count = surv + nmove;
-                st.next_id += (uint32_t)nmove;
-                st.parity = out;
-                st.ke = ke;
             }
-            __syncthreads();
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int s = 0; s < kMaxSpecies; ++s) {
+                if (s >= S) break;
+                const SegConst& sc = d.segc[b * S + s];
                 SegState& st = d.segs[b * S + s];
-                st.births = 0;
-                st.see_births = 0;
-                st.surv = st.count;
-                st.ntiles = 0;
+                const int64_t nbirth = s == 0 ? n_ion + n_see : (s == 1 ? n_ion : 0);
+                int64_t nmove = nbirth;
+                if (nmove > sc.bcap) nmove = sc.bcap;
+                if (nmove > sc.cap - surv[s]) nmove = sc.cap - surv[s];
+                const int out = sc.compacts ? (par[s] ^ 1) : par[s];
+                for (int64_t k = lane; k < nmove; k += 64) {
+                    sc.cell[out][surv[s] + k] = sc.bcell[k];
+                    sc.off[out][surv[s] + k] = sc.boff[k];
+                    sc.vx[out][surv[s] + k] = sc.bvx[k];
+                    sc.vy[out][surv[s] + k] = sc.bvy[k];
+                    sc.vz[out][surv[s] + k] = sc.bvz[k];
+                    sc.id[out][surv[s] + k] = sc.bid[k];
+                }
+                if (a.diag) {
+                    // kinetic-energy partials of the step's tiles (runs leave
+                    // zeros elsewhere), fixed order, cleared after reading
+                    double* kpp = d.ke_part + (size_t)s * d.tiles_max + tfirst[s];
+                    double acc_k = 0.0;
+                    for (int64_t t = lane; t < ntl[s]; t += 64) {
+                        acc_k += kpp[t];
+                        kpp[t] = 0.0;
+                    }
+                    acc_k = wave_sum_f64(acc_k);
+                    if (lane == 0) st.ke = acc_k;
+                }
+                if (lane == 0) {
+                    if (nmove < nbirth) {
+                        atomicOr(&ds.flags, kFlagCapacity);
+                        st.dropped += (unsigned long long)(nbirth - nmove);
+                    }
+                    st.count = surv[s] + nmove;
+                    st.next_id += (uint32_t)nmove;
+                    st.parity = out;
+                    st.see_births = 0;
+                    st.surv = surv[s] + nmove;
+                    st.ntiles = 0;
+                }
             }
-        }
-    }
-
-    // ---- densities and charge ---------------------------------------------
-    double rho[P];
-    const double dx = dc.dx;
-#pragma unroll
-    for (int j = 0; j < P; ++j) rho[j] = 0.0;
-    if (a.mode == kFinExternal) {
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int i = tid * P + j;
-            if (i < nn) rho[j] = a.rho_ext[i];
+            if (lane == 0) d.segs[b * S + 0].births = 0;
         }
     } else {
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int i = tid * P + j;
-            if (i < nn) rho[j] = dc.rho_bg;
-        }
-        for (int s = 0; s < S; ++s) {
-            const SegConst& sc = d.segc[b * S + s];
-            unsigned long long* acc = d.acc + ((size_t)b * S + s) * d.nodes_max;
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int i = tid * P + j;
-                if (i >= nn) continue;
-                const double sum = (double)acc[i] * (1.0 / kDepScale);
-                acc[i] = 0ull;
-                const double vol = (!periodic && (i == 0 || i == nn - 1)) ? 0.5 * dx : dx;
-                const double den = sc.w * sum / vol;
-                d.dens[((size_t)b * S + s) * d.nodes_max + i] = den;
-                rho[j] += sc.q * den;
+        // ---- densities and charge (into s_a) ------------------------------------
+        for (int i = tid; i < nn; i += kBook) {
+            double r;
+            if (a.mode == kFinExternal) {
+                r = a.rho_ext[i];
+            } else {
+                r = dc.rho_bg;
+                const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
+                for (int s = 0; s < S; ++s) {
+                    unsigned long long* acc = d.acc + ((size_t)b * S + s) * d.nodes_max;
+                    const double den = (double)acc[i] * (dc.dens_coef[s] * wall);
+                    acc[i] = 0ull;
+                    d.dens[((size_t)b * S + s) * d.nodes_max + i] = den;
+                    r += dc.q[s] * den;
+                }
+                d.rho[nb + i] = r;
             }
+            s_a[i] = r;
         }
-    }
-
-    // ---- Poisson -------------------------------------------------------------
-    double phi[P];
-    const double t = a.mode == kFinExternal ? a.t_ext
-                   : (double)(ds.step + (a.mode == kFinStep ? 1 : 0)) * dc.dt;
-    if (!dc.field_solve) {
-#pragma unroll
-        for (int j = 0; j < P; ++j) phi[j] = 0.0;
-    } else {
-        const double c2 = dx * dx / dc.eps0;
-        double mean = 0.0;
-        if (periodic) {
-            double loc = 0.0;
-#pragma unroll
-            for (int j = 0; j < P; ++j) loc += rho[j];
-            mean = block_sum(loc, s_w) / nn;
-        }
-        double g[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int i = tid * P + j;
-            g[j] = 0.0;
-            if (i >= 1 && (periodic ? i < nn : i < nn - 1)) g[j] = (rho[j] - mean) * c2;
-        }
-        // G = inclusive prefix of g
-        double G[P], run = 0.0;
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            run += g[j];
-            G[j] = run;
-        }
-        double totg;
-        const double offg = block_excl_scan(run, s_w, totg);
-#pragma unroll
-        for (int j = 0; j < P; ++j) G[j] += offg;
-        // K = exclusive prefix of G
-        double K[P], runk = 0.0;
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int i = tid * P + j;
-            K[j] = runk;
-            if (i < nn) runk += G[j];
-        }
-        double totG;
-        const double offk = block_excl_scan(runk, s_w, totG);
-#pragma unroll
-        for (int j = 0; j < P; ++j) K[j] += offk;
-        double phi0, d0;
-        const int N = nc;
-        if (periodic) {
-            phi0 = 0.0;
-            d0 = totG / N;                       // H = sum_{i<N} G[i]
-        } else {
-            phi0 = dc.v_amp * sin(6.283185307179586476925286766559 * dc.v_freq * t + dc.v_phase);
-            // H = K[N] = sum_{i<N} G[i] = totG - G[N]
-            if (tid * P <= N && N < tid * P + P) s_bcast[0] = G[N - tid * P];
-            __syncthreads();
-            const double H = totG - s_bcast[0];
-            d0 = (0.0 - phi0 + H) / N;
-        }
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int i = tid * P + j;
-            phi[j] = phi0 + (double)i * d0 - K[j];
-        }
-        if (!periodic) {
-            if (tid * P <= N && N < tid * P + P) phi[N - tid * P] = 0.0;
-            if (tid == 0) phi[0] = phi0;
-        } else {
-            double loc = 0.0;
-#pragma unroll
-            for (int j = 0; j < P; ++j)
-                if (tid * P + j < nn) loc += phi[j];
-            const double pm = block_sum(loc, s_w) / nn;
-#pragma unroll
-            for (int j = 0; j < P; ++j) phi[j] -= pm;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int i = tid * P + j;
-        if (i < nn) s_phi[i] = phi[j];
-    }
-    // wall charge for Gauss's law at the electrodes
-    if (!periodic) {
-        if (tid == 0) s_bcast[1] = rho[0];
-        if (tid * P <= nn - 1 && nn - 1 < tid * P + P) s_bcast[2] = rho[nn - 1 - tid * P];
     }
     __syncthreads();
 
-    // ---- field at the nodes ----------------------------------------------------
-    double ef[P];
-    double fe_loc = 0.0;
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int i = tid * P + j;
-        ef[j] = 0.0;
-        if (i >= nn || !dc.field_solve) continue;
-        if (periodic) {
-            const int im = i == 0 ? nn - 1 : i - 1, ip = i == nn - 1 ? 0 : i + 1;
-            ef[j] = (s_phi[im] - s_phi[ip]) / (2.0 * dx);
-        } else if (i == 0) {
-            ef[j] = -(s_phi[1] - s_phi[0]) / dx - s_bcast[1] * dx / (2.0 * dc.eps0);
-        } else if (i == nn - 1) {
-            ef[j] = -(s_phi[nn - 1] - s_phi[nn - 2]) / dx + s_bcast[2] * dx / (2.0 * dc.eps0);
-        } else {
-            ef[j] = (s_phi[i - 1] - s_phi[i + 1]) / (2.0 * dx);
-        }
+    // ---- Poisson: phi[i] = phi0 + i d0 - K[i] (file header) -------------------
+    const double t = a.mode == kFinExternal ? a.t_ext
+                   : (double)(ds.step + (a.mode == kFinStep ? 1 : 0)) * dc.dt;
+    double phi[kNodesPerThread];
+    if (!periodic && tid == 0) {
+        s_bc[0] = s_a[0];
+        s_bc[1] = s_a[nn - 1];
     }
-    if (a.mode == kFinExternal) {
+    if (dc.field_solve) {
+        double mean = 0.0;
+        if (periodic) {
+            double loc = 0.0;
+            for (int i = tid; i < nn; i += kFT) loc += s_a[i];
+            loc = wave_sum_f64(loc);
+            if (lane == 0) s_w[wid] = loc;
+            __syncthreads();
+            double tot = 0.0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const int i = tid * P + j;
+            for (int w = 0; w < kWaves; ++w) tot += s_w[w];
+            mean = tot / nn;
+        }
+        // node i = k * kFT + tid: chunk k of the nodes, one node per thread
+        const double c2 = dc.c2;
+        Run inc[kNodesPerThread];
+#pragma unroll
+        for (int k = 0; k < kNodesPerThread; ++k) {
+            inc[k] = Run{0.0, 0.0, 0.0};
+            if (k * kFT >= nn) {                           // empty chunk (uniform)
+                if (lane == 63) s_run[k * kWaves + wid] = inc[k];
+                continue;
+            }
+            const int i = k * kFT + tid;
+            Run v{0.0, 0.0, 0.0};
             if (i < nn) {
-                if (a.phi_out) a.phi_out[i] = phi[j];
-                if (a.e_out) a.e_out[i] = ef[j];
+                const bool unknown = i >= 1 && (periodic ? i < nn : i < nn - 1);
+                const double g = unknown ? (s_a[i] - mean) * c2 : 0.0;
+                v = Run{1.0, g, g};
+            }
+            inc[k] = wave_run_scan(v);
+            if (lane == 63) s_run[k * kWaves + wid] = inc[k];
+        }
+        __syncthreads();
+        // exclusive prefix of every wave of every chunk (chunks in order)
+        if (tid < 64) {                                   // wave 0; each lane its own entry
+            const int nw = kWaves * kNodesPerThread;      // 64 entries: one wave
+            const Run v = tid < nw ? s_run[tid] : Run{0.0, 0.0, 0.0};
+            const Run vi = wave_run_scan(v);
+            Run ex;
+            ex.n = __shfl_up(vi.n, 1, 64);
+            ex.S = __shfl_up(vi.S, 1, 64);
+            ex.P = __shfl_up(vi.P, 1, 64);
+            if (tid == 0) ex = Run{0.0, 0.0, 0.0};
+            if (tid < nw) s_run[tid] = ex;
+            if (tid == 63) {
+                s_bc[2] = vi.S;                           // S and P over all nodes
+                s_bc[3] = vi.P;
             }
         }
-        return;
-    }
-    __syncthreads();                     // every thread has read s_phi
-    double* s_ef = s_phi;
+        __syncthreads();
+        const double totS = s_bc[2], totP = s_bc[3];
+        double phi0, d0;
+        if (periodic) {
+            phi0 = 0.0;
+            d0 = totP / nc;                              // H = sum_{i<N} G[i]
+        } else {
+            phi0 = dc.v_amp * sin(6.283185307179586476925286766559 * dc.v_freq * t + dc.v_phase);
+            d0 = (totP - totS - phi0) / nc;              // H = P - G[N], phi[N] = 0
+        }
+        double phis = 0.0;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int i = tid * P + j;
-        if (i >= nn) continue;
-        d.rho[nb + i] = rho[j];
-        d.phi[nb + i] = phi[j];
-        d.ef[nb + i] = ef[j];
-        s_ef[i] = ef[j];
-        const double vol = (!periodic && (i == 0 || i == nn - 1)) ? 0.5 * dx : dx;
-        fe_loc += ef[j] * ef[j] * vol;
+        for (int k = 0; k < kNodesPerThread; ++k) {
+            const int i = k * kFT + tid;
+            phi[k] = 0.0;
+            if (i >= nn) continue;
+            // inclusive run through i; K[i] excludes node i: P_incl - G[i]
+            const Run full = run_combine(s_run[k * kWaves + wid], inc[k]);
+            double ph = phi0 + (double)i * d0 - (full.P - full.S);
+            if (!periodic && i == nn - 1) ph = 0.0;
+            if (i == 0) ph = phi0;
+            phi[k] = ph;
+            phis += ph;
+        }
+        if (periodic) {                                  // zero-mean gauge
+            phis = wave_sum_f64(phis);
+            __syncthreads();
+            if (lane == 0) s_w[wid] = phis;
+            __syncthreads();
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) tot += s_w[w];
+            const double pm = tot / nn;
+#pragma unroll
+            for (int k = 0; k < kNodesPerThread; ++k) phi[k] -= pm;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kNodesPerThread; ++k) phi[k] = 0.0;
     }
-    const double fe = 0.5 * dc.eps0 * block_sum(fe_loc, s_w);
-    // block_sum synchronised the block, so s_ef is complete
-    for (int c = tid; c < nc; c += kFinThreads) {
+    __syncthreads();                                     // every read of rho is done
+#pragma unroll
+    for (int k = 0; k < kNodesPerThread; ++k) {
+        const int i = k * kFT + tid;
+        if (i < nn) s_a[i] = phi[k];
+    }
+    __syncthreads();
+
+    // ---- field at the nodes (all threads) ------------------------------------
+    auto efield = [&](int i) -> double {
+        if (!dc.field_solve) return 0.0;
+        if (periodic) {
+            const int im = i == 0 ? nn - 1 : i - 1, ip = i == nn - 1 ? 0 : i + 1;
+            return (s_a[im] - s_a[ip]) * dc.inv_2dx;
+        }
+        if (i == 0) return -(s_a[1] - s_a[0]) * dc.inv_dx - s_bc[0] * dc.wall_coef;
+        if (i == nn - 1) return -(s_a[nn - 1] - s_a[nn - 2]) * dc.inv_dx + s_bc[1] * dc.wall_coef;
+        return (s_a[i - 1] - s_a[i + 1]) * dc.inv_2dx;
+    };
+    double fe_loc = 0.0;
+    for (int i = tid; i < nn; i += kFT) {
+        const double e = efield(i);
+        const double vol = (!periodic && (i == 0 || i == nn - 1)) ? 0.5 : 1.0;
+        fe_loc += e * e * vol;
+        if (a.mode == kFinExternal) {
+            if (a.phi_out) a.phi_out[i] = s_a[i];
+            if (a.e_out) a.e_out[i] = e;
+        } else {
+            d.phi[nb + i] = s_a[i];
+            d.ef[nb + i] = e;
+        }
+    }
+    if (a.mode == kFinExternal) return;
+    for (int c = tid; c < nc; c += kFT) {
         const int c1 = (periodic && c + 1 == nc) ? 0 : c + 1;
-        d.epair[(size_t)b * d.cells_max + c] = make_float2((float)s_ef[c], (float)s_ef[c1]);
+        d.epair[(size_t)b * d.cells_max + c] = make_float2((float)efield(c), (float)efield(c1));
     }
+    // field energy: per-wave sums, added in wave order
+    fe_loc = wave_sum_f64(fe_loc);
+    if (lane == 0) s_w[wid] = fe_loc;
 
     // ---- time averages -------------------------------------------------------
     if (a.mode == kFinStep && a.diag) {
         double* av = d.avg + (size_t)b * (S + 2) * d.nodes_max;
         unsigned long long* ea = d.eacc + nb;
-        for (int i = tid; i < nn; i += kFinThreads) {
+        const double ecoef = dc.dens_coef[0] * kDepScale / 1048576.0;   // w / dx / 2^20
+        for (int i = tid; i < nn; i += kFT) {
             for (int s = 0; s < S; ++s)
                 av[(size_t)s * d.nodes_max + i] += d.dens[((size_t)b * S + s) * d.nodes_max + i];
-            av[(size_t)S * d.nodes_max + i] += d.phi[nb + i];
-            const double vol = (!periodic && (i == 0 || i == nn - 1)) ? 0.5 * dx : dx;
-            const double esum = (double)ea[i] * (1.0 / 1048576.0);   // eV x weight fraction
+            av[(size_t)S * d.nodes_max + i] += s_a[i];
+            const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
+            av[(size_t)(S + 1) * d.nodes_max + i] += (double)ea[i] * ecoef * wall;   // n_e <eps>
             ea[i] = 0ull;
-            av[(size_t)(S + 1) * d.nodes_max + i] += d.segc[b * S].w * esum / vol;  // n_e <eps>
         }
     }
+    __syncthreads();
     if (tid == 0) {
-        ds.fe = fe;
+        double fe = 0.0;
+        for (int w = 0; w < kWaves; ++w) fe += s_w[w];
+        ds.fe = 0.5 * dc.eps0 * dc.dx * fe;
         if (a.mode == kFinStep) {
             if (a.diag) {
                 ds.avg_samples += 1.0;
@@ -314,7 +351,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs a)
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st)
 {
     const unsigned g = a.only_b >= 0 ? 1u : (unsigned)a.d.B;
-    hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(kFinThreads), 0, st, a);
+    hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(kFT), 0, st, a);
     return hipGetLastError();
 }
 

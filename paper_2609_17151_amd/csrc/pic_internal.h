@@ -15,8 +15,8 @@ namespace pic {
 constexpr int kMaxSpecies = PIC_MAX_SPECIES;
 constexpr int kMaxChan = PIC_MAX_CHAN;
 constexpr int kMaxCells = 4096;
-constexpr int kFinThreads = 1024;          // finalize / field-solve workgroup
-constexpr int kNodesPerThread = 4;         // kFinThreads * 4 >= kMaxCells + 1
+constexpr int kFinThreads = 1024;          // finalize / field-solve workgroup (4 nodes per thread at most)
+constexpr int kNodesPerThread = 4;         // kFinThreads * 4 >= nodes of a bounded mesh
 constexpr int kEepfBins = PIC_EEPF_BINS;
 
 // latched device flags
@@ -82,6 +82,11 @@ struct DisConst {
     int32_t n_cells, n_nodes, bc, field_solve;
     double dx, dt, L, eps0, rho_bg, v_amp, v_freq, v_phase;
     double e_ext[3], b_ext[3];
+    double c2;                 // dx^2 / eps0
+    double inv_2dx, inv_dx;
+    double wall_coef;          // dx / (2 eps0)
+    double dens_coef[kMaxSpecies];   // weight / dx / 2^32 (interior node; twice at a wall node)
+    double q[kMaxSpecies];     // species charge
     uint32_t key0, key1;
 };
 

@@ -41,7 +41,8 @@ struct LoadArgs {
     int32_t perturb_mode;
 };
 
-hipError_t launch_push(const PushArgs& a, int ppt, bool general, int64_t grid, hipStream_t st);
+hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, int64_t grid, hipStream_t st);
+void push_shape(int& ppt, int& threads, bool general);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
 hipError_t launch_load(const LoadArgs& a, hipStream_t st);
 hipError_t launch_deposit(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);
@@ -49,5 +50,6 @@ hipError_t launch_halfstep(const DevPtrs& d, int only_b, int64_t max_count, hipS
 hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_count, void* scratch, size_t scratch_bytes,
                        hipStream_t st);
 size_t push_lds_bytes(int n_nodes, int n_cells, int diag);
+int push_occupancy(int ppt, int threads, bool general, size_t lds);
 
 }  // namespace pic

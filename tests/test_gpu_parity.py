@@ -177,6 +177,7 @@ def test_gpu_runs_are_bit_reproducible(pic):
 def test_langmuir_energy_and_frequency_on_gpu(pic):
     cfg = W.langmuir()
     sim = pic.Sim(cfg)
+    sim.set_diag(True)                 # kinetic energy is kept with the diagnostics
     L = cfg["length"]
     nn = sim.n_nodes[0]
     sn = np.sin(2 * np.pi * np.arange(nn) / nn)
@@ -237,3 +238,25 @@ def test_capacity_overflow_latched(pic):
     with pytest.raises(pic.PicError) as e:
         sim.sync()
     assert e.value.code == pic.ECAPACITY
+
+
+@pytest.mark.parametrize("which", ["langmuir", "argon"])
+def test_graph_replays_match_direct_launches(pic, which):
+    # replays of the captured step chunk, with eager work and readbacks in
+    # between, equal direct launches bit for bit after every replay
+    if which == "langmuir":
+        cfg, tabs = W.langmuir(n_particles=1 << 15), ()
+    else:
+        cfg, tabs = small_argon(n_init=20000, seed=13)
+    a = pic.Sim(cfg, tabs)
+    b = pic.Sim(cfg, tabs)
+    b.use_graphs(False)
+    for rep in range(4):
+        a.step(32)
+        b.step(32)
+        assert a.counts() == b.counts()
+        for s in range(len(cfg["species"])):
+            pa, pb = a.get_particles(s), b.get_particles(s)
+            for k in ("cell", "off", "vx", "vy", "vz", "id"):
+                assert np.array_equal(pa[k], pb[k]), (rep, s, k)
+        assert np.array_equal(a.efield(), b.efield())
