@@ -229,6 +229,11 @@ pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV);
  * clears the sums.  A measuring aid; it adds two event records per launch. */
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
 
+/* pic_sort: queue a stable sort of every species of every discharge by cell
+ * index (particles with equal cells keep their order).  pic_config_tiles can
+ * make pic_step do this every K steps.  Asynchronous. */
+pic_status pic_sort(pic_ctx* ctx);
+
 /* pic_use_graphs: when enable is non-zero (the default), pic_step captures a
  * chunk of consecutive steps once into a HIP graph on a private stream and
  * replays it on the context's stream, which removes the host launch gaps

@@ -88,6 +88,7 @@ def load_library():
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
+        "pic_sort": (i32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -264,6 +265,9 @@ class Sim:
 
     def reset_avg(self, batch=0):
         self._check(_lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0), "pic_diag(RESET_AVG)")
+
+    def sort(self):
+        self._check(_lib.pic_sort(self.h), "pic_sort")
 
     def use_graphs(self, enable=True):
         self._check(_lib.pic_use_graphs(self.h, int(enable)), "pic_use_graphs")

@@ -57,6 +57,7 @@ struct pic_ctx {
     double* poisson_scratch = nullptr;   // rho, phi, e: 3 * nodes_max
     void* sort_scratch = nullptr;
     size_t sort_scratch_bytes = 0;
+    int64_t sort_tiles = 0;
     std::vector<int64_t> grid_cap;       // per species: sum over discharges of padded capacity
     // live timing of launches (pic_profile)
     int prof = 0;
@@ -481,7 +482,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
             const int64_t cap = pad_cap(c.species[s].capacity);
             sc.cap = c.species[s].capacity;
             ctx->grid_cap[s] += cap;
-            const int copies = c.bc == PIC_BC_DIRICHLET ? 2 : 1;
+            const int copies = 2;                 // compaction and the sort write the other copy
             for (int k = 0; k < copies; ++k) {
                 sc.cell[k] = (int32_t*)A(cap * 4);
                 sc.off[k] = (float*)A(cap * 4);
@@ -619,10 +620,22 @@ pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t k
 pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t sort_every)
 {
     if (!ctx || (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) ||
-        (threads != 256 && threads != 512 && threads != 1024) || sort_every != 0)
+        (threads != 256 && threads != 512 && threads != 1024) || sort_every < 0)
         return PIC_EINVAL;
     pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
     if (rc != PIC_OK) return rc;
+    if (sort_every > 0 && !ctx->sort_scratch) {
+        int64_t tiles = 0;
+        for (int s = 0; s < ctx->S; ++s) {
+            int64_t ts = 0;
+            for (int b = 0; b < ctx->B; ++b) ts += sort_tiles_for(pad_cap(ctx->segc[b * ctx->S + s].cap));
+            tiles = std::max(tiles, ts);
+        }
+        ctx->sort_tiles = tiles;
+        ctx->sort_scratch_bytes = sort_scratch_bytes(tiles, ctx->B, ctx->d.cells_max);
+        ctx->sort_scratch = dev_alloc(ctx, ctx->sort_scratch_bytes);
+        if (!ctx->sort_scratch) return PIC_ENOMEM;
+    }
     // a new tile size renumbers tiles: clear every chain word
     rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max));
     if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2));
@@ -722,8 +735,8 @@ pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st,
         if (ctx->sort_every > 0 && ++ctx->steps_since_sort >= ctx->sort_every) {
             ctx->steps_since_sort = 0;
             for (int s = 0; s < ctx->S; ++s)
-                if (launch_sort(ctx->d, s, max_count_of(ctx, -1), ctx->sort_scratch, ctx->sort_scratch_bytes,
-                                st) != hipSuccess)
+                if (launch_sort(ctx->d, s, ctx->sort_tiles, ctx->sort_scratch, ctx->sort_scratch_bytes, st) !=
+                    hipSuccess)
                     return PIC_EHIP;
         }
         for (int s = 0; s < ctx->S; ++s) {
@@ -786,8 +799,14 @@ pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
     if (rc != PIC_OK) return rc;
     hipStream_t st = ctx->stream;
     int left = n_steps;
-    // replays of a captured chunk; the sort interval must divide the chunk so
-    // that every replay sorts at the same steps
+    // direct steps until the sort counter is back at zero, so that every
+    // replay of the captured chunk sorts at the same steps
+    while (ctx->sort_every > 0 && ctx->steps_since_sort != 0 && left > 0) {
+        rc = enqueue_steps(ctx, p, 1, st, ctx->prof != 0);
+        if (rc != PIC_OK) return rc;
+        --left;
+    }
+    // replays of a captured chunk; the sort interval must divide the chunk
     const bool graph_ok = ctx->use_graph && !ctx->prof &&
                           (ctx->sort_every == 0 || (kGraphSteps % ctx->sort_every == 0 && ctx->steps_since_sort == 0));
     if (graph_ok && left >= kGraphSteps) {
@@ -801,6 +820,28 @@ pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
         }
     }
     return enqueue_steps(ctx, p, left, st, ctx->prof != 0);
+}
+
+pic_status pic_sort(pic_ctx* ctx)
+{
+    if (!ctx) return PIC_EINVAL;
+    if (!ctx->sort_scratch) {
+        int64_t tiles = 0;
+        for (int s = 0; s < ctx->S; ++s) {
+            int64_t ts = 0;
+            for (int b = 0; b < ctx->B; ++b) ts += sort_tiles_for(pad_cap(ctx->segc[b * ctx->S + s].cap));
+            tiles = std::max(tiles, ts);
+        }
+        ctx->sort_tiles = tiles;
+        ctx->sort_scratch_bytes = sort_scratch_bytes(tiles, ctx->B, ctx->d.cells_max);
+        ctx->sort_scratch = dev_alloc(ctx, ctx->sort_scratch_bytes);
+        if (!ctx->sort_scratch) return PIC_ENOMEM;
+    }
+    for (int s = 0; s < ctx->S; ++s)
+        if (launch_sort(ctx->d, s, ctx->sort_tiles, ctx->sort_scratch, ctx->sort_scratch_bytes, ctx->stream) !=
+            hipSuccess)
+            return PIC_EHIP;
+    return PIC_OK;
 }
 
 pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable)

@@ -47,8 +47,10 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
 hipError_t launch_load(const LoadArgs& a, hipStream_t st);
 hipError_t launch_deposit(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);
 hipError_t launch_halfstep(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);
-hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_count, void* scratch, size_t scratch_bytes,
+hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_tiles, void* scratch, size_t scratch_bytes,
                        hipStream_t st);
+size_t sort_scratch_bytes(int64_t max_tiles, int B, int cells_max);
+int64_t sort_tiles_for(int64_t padded_count);
 size_t push_lds_bytes(int n_nodes, int n_cells, int diag);
 int push_occupancy(int ppt, int threads, bool general, size_t lds);
 

@@ -260,3 +260,49 @@ def test_graph_replays_match_direct_launches(pic, which):
             for k in ("cell", "off", "vx", "vy", "vz", "id"):
                 assert np.array_equal(pa[k], pb[k]), (rep, s, k)
         assert np.array_equal(a.efield(), b.efield())
+
+
+def _stable_by_cell(p):
+    o = np.argsort(p["cell"], kind="stable")
+    return {k: (v[o] if k != "next_id" else v) for k, v in p.items()}
+
+
+@pytest.mark.parametrize("which", ["langmuir", "argon", "batched"])
+def test_sort_is_a_stable_sort_by_cell(pic, which):
+    if which == "langmuir":
+        cfgs, tabs = [W.langmuir(n_particles=100_000, capacity=100_000)], ()
+    elif which == "argon":
+        cfg, tabs = small_argon(n_init=30000, seed=21)
+        cfgs = [cfg]
+    else:
+        cfgs = [W.langmuir(n_particles=n, n_cells=nc, seed=sd, capacity=n)
+                for n, nc, sd in ((5000, 64, 1), (70_001, 128, 2), (12_345, 100, 3))]
+        tabs = ()
+    sim = pic.Sim(cfgs, tabs)
+    sim.step(25)
+    before = [[sim.get_particles(s, b) for s in range(sim.S)] for b in range(sim.B)]
+    sim.sort()
+    for b in range(sim.B):
+        for s in range(sim.S):
+            got = sim.get_particles(s, b)
+            exp = _stable_by_cell(before[b][s])
+            for k in ("cell", "off", "vx", "vy", "vz", "id"):
+                assert np.array_equal(got[k], exp[k]), (b, s, k)
+    sim.sync()
+
+
+def test_periodic_sort_changes_order_not_physics(pic):
+    # collisionless: the deposit is order-independent, so sorting every few
+    # steps leaves the field bit-identical and the particles equal up to order
+    cfg = W.langmuir(n_particles=1 << 16)
+    a, b = pic.Sim(cfg), pic.Sim(cfg)
+    b.config_tiles(4, 1024, 5)
+    for _ in range(3):
+        a.step(40)
+        b.step(40)
+        assert np.array_equal(a.efield(), b.efield())
+    pa, pb = a.get_particles(0), b.get_particles(0)
+    oa, ob = np.argsort(pa["id"]), np.argsort(pb["id"])
+    for k in ("cell", "off", "vx", "vy", "vz", "id"):
+        assert np.array_equal(pa[k][oa], pb[k][ob]), k
+    assert not np.array_equal(pa["id"], pb["id"])
