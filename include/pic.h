@@ -229,6 +229,11 @@ pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV);
  * clears the sums.  A measuring aid; it adds two event records per launch. */
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
 
+/* pic_retire: a retired discharge (retired != 0) is skipped by pic_step and
+ * keeps its state; a batched sweep retires discharges as they converge.
+ * Synchronous. */
+pic_status pic_retire(pic_ctx* ctx, int32_t batch, int32_t retired);
+
 /* pic_sort: queue a stable sort of every species of every discharge by cell
  * index (particles with equal cells keep their order).  pic_config_tiles can
  * make pic_step do this every K steps.  Asynchronous. */

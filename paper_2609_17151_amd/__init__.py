@@ -89,6 +89,7 @@ def load_library():
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
+        "pic_retire": (i32, [P, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -265,6 +266,9 @@ class Sim:
 
     def reset_avg(self, batch=0):
         self._check(_lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0), "pic_diag(RESET_AVG)")
+
+    def retire(self, batch, retired=True):
+        self._check(_lib.pic_retire(self.h, batch, int(retired)), "pic_retire")
 
     def sort(self):
         self._check(_lib.pic_sort(self.h), "pic_sort")

@@ -514,7 +514,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.segs = (SegState*)A(sizeof(SegState) * B * S);
         d.disc = (DisConst*)A(sizeof(DisConst) * B);
         d.diss = (DisState*)A(sizeof(DisState) * B);
-        d.acc = (unsigned long long*)A(8ull * B * S * nodes_max);
+        d.acc = (unsigned long long*)A(8ull * B * S * kRep * nodes_max);
+        d.cnt = (unsigned long long*)A(8ull * B * S * kRep * C_N);
         d.eacc = (unsigned long long*)A(8ull * B * nodes_max);
         d.rho = (double*)A(8ull * B * nodes_max);
         d.phi = (double*)A(8ull * B * nodes_max);
@@ -525,6 +526,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
         d.status = (unsigned long long*)A(8ull * S * 2 * tiles_max);
         d.tile_ctr = (unsigned int*)A(4ull * S * 2);
+        d.tick = (unsigned long long*)A(8);
         d.ke_part = (double*)A(8ull * S * tiles_max);
         ctx->poisson_scratch = (double*)A(8ull * 3 * nodes_max);
     }
@@ -549,12 +551,14 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemcpy(d.segs, ss.data(), sizeof(SegState) * B * S, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(d.disc, ctx->disc.data(), sizeof(DisConst) * B, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(d.diss, ds.data(), sizeof(DisState) * B, hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.acc, 0, 8ull * B * S * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.acc, 0, 8ull * B * S * kRep * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.cnt, 0, 8ull * B * S * kRep * C_N, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.status, 0, 8ull * S * 2 * tiles_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * S * 2, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * S * tiles_max, st) == hipSuccess;
     for (int b = 0; b < B && ok; ++b)
         for (int s = 0; s < S && ok; ++s) {
@@ -822,6 +826,14 @@ pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
     return enqueue_steps(ctx, p, left, st, ctx->prof != 0);
 }
 
+pic_status pic_retire(pic_ctx* ctx, int32_t batch, int32_t retired)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B) return PIC_EINVAL;
+    const int32_t v = retired ? 1 : 0;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    return hip_st(hipMemcpy(&ctx->d.diss[batch].retired, &v, sizeof(v), hipMemcpyHostToDevice));
+}
+
 pic_status pic_sort(pic_ctx* ctx)
 {
     if (!ctx) return PIC_EINVAL;
@@ -980,8 +992,8 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     // chain words and counters follow the step parity: start them clean
     if (hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max) != hipSuccess) return PIC_EHIP;
     if (hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2) != hipSuccess) return PIC_EHIP;
-    if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * ctx->d.nodes_max, 0,
-                  8ull * ctx->S * ctx->d.nodes_max) != hipSuccess)
+    if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * kRep * ctx->d.nodes_max, 0,
+                  8ull * ctx->S * kRep * ctx->d.nodes_max) != hipSuccess)
         return PIC_EHIP;
     pic_status rc = solve_after_deposit(ctx, batch);
     if (rc != PIC_OK) return rc;
@@ -997,6 +1009,14 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
     const size_t nm = ctx->d.nodes_max;
     std::vector<SegState> ss(S);
     DisState ds;
+    std::vector<unsigned long long> cr((size_t)S * kRep * C_N);
+    std::vector<unsigned long long> ev((size_t)S * C_N, 0ull);   // counters summed over copies
+    if (hipMemcpy(cr.data(), ctx->d.cnt + (size_t)batch * S * kRep * C_N, cr.size() * 8, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return PIC_EHIP;
+    for (int s = 0; s < S; ++s)
+        for (int r = 0; r < kRep; ++r)
+            for (int k = 0; k < C_N; ++k) ev[(size_t)s * C_N + k] += cr[((size_t)s * kRep + r) * C_N + k];
     if (hipMemcpy(ss.data(), ctx->d.segs + (size_t)batch * S, sizeof(SegState) * S, hipMemcpyDeviceToHost) !=
             hipSuccess ||
         hipMemcpy(&ds, ctx->d.diss + batch, sizeof(DisState), hipMemcpyDeviceToHost) != hipSuccess)
@@ -1046,10 +1066,10 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             int64_t* o = (int64_t*)out;
             int64_t see0 = 0, see1 = 0;
             for (int s = 0; s < S; ++s) {
-                o[2 * s] = (int64_t)ss[s].absorbed[0];
-                o[2 * s + 1] = (int64_t)ss[s].absorbed[1];
-                see0 += (int64_t)ss[s].see[0];
-                see1 += (int64_t)ss[s].see[1];
+                o[2 * s] = (int64_t)ev[(size_t)s * C_N + C_ABS0];
+                o[2 * s + 1] = (int64_t)ev[(size_t)s * C_N + C_ABS1];
+                see0 += (int64_t)ev[(size_t)s * C_N + C_SEE0];
+                see1 += (int64_t)ev[(size_t)s * C_N + C_SEE1];
             }
             o[2 * S] = see0;
             o[2 * S + 1] = see1;
@@ -1060,10 +1080,10 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             int64_t* o = (int64_t*)out;
             for (int s = 0; s < S; ++s) {
                 int64_t* r = o + (size_t)s * (3 + kMaxChan);
-                r[0] = (int64_t)ss[s].cand;
-                r[1] = (int64_t)ss[s].nulls;
-                r[2] = (int64_t)ss[s].viol;
-                for (int k = 0; k < kMaxChan; ++k) r[3 + k] = (int64_t)ss[s].coll[k];
+                r[0] = (int64_t)ev[(size_t)s * C_N + C_CAND];
+                r[1] = (int64_t)ev[(size_t)s * C_N + C_NULL];
+                r[2] = (int64_t)ev[(size_t)s * C_N + C_VIOL];
+                for (int k = 0; k < kMaxChan; ++k) r[3 + k] = (int64_t)ev[(size_t)s * C_N + C_COLL + k];
             }
             break;
         }

@@ -89,6 +89,8 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     const int nn = dc.n_nodes, nc = dc.n_cells;
     const int periodic = dc.bc == PIC_BC_PERIODIC;
     const size_t nb = (size_t)b * d.nodes_max;
+    if (a.mode == kFinStep && blockIdx.x == 0 && threadIdx.x == 0) *d.tick += 1ull;
+    if (a.mode == kFinStep && ds.retired) return;   // a retired discharge stays as it is
 
     __shared__ double s_a[kMaxCells + 1];     // rho, then phi
     __shared__ double s_bc[4];                // rho at the walls
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                 if (lane == 0) {
                     if (nmove < nbirth) {
                         atomicOr(&ds.flags, kFlagCapacity);
-                        st.dropped += (unsigned long long)(nbirth - nmove);
+                        d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(nbirth - nmove);
                     }
                     st.count = surv[s] + nmove;
                     st.next_id += (uint32_t)nmove;
@@ -167,9 +169,14 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                 r = dc.rho_bg;
                 const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
                 for (int s = 0; s < S; ++s) {
-                    unsigned long long* acc = d.acc + ((size_t)b * S + s) * d.nodes_max;
-                    const double den = (double)acc[i] * (dc.dens_coef[s] * wall);
-                    acc[i] = 0ull;
+                    unsigned long long* acc = d.acc + ((size_t)b * S + s) * kRep * d.nodes_max;
+                    unsigned long long sum = 0ull;
+#pragma unroll
+                    for (int r = 0; r < kRep; ++r) {
+                        sum += acc[(size_t)r * d.nodes_max + i];
+                        acc[(size_t)r * d.nodes_max + i] = 0ull;
+                    }
+                    const double den = (double)sum * (dc.dens_coef[s] * wall);
                     d.dens[((size_t)b * S + s) * d.nodes_max + i] = den;
                     r += dc.q[s] * den;
                 }
@@ -364,9 +371,9 @@ __global__ __launch_bounds__(256) void load_kernel(LoadArgs a)
     const DisConst& dc = d.disc[a.b];
     const SegConst& sc = d.segc[a.b * d.S + a.s];
     const double L = dc.L;
-    const uint4 r0 = philox10((uint32_t)j, 0xFFFFFFFFu, ((uint32_t)a.s << 24) | 0u, (uint32_t)a.b,
+    const uint4 r0 = philox10((uint32_t)j, 0xFFFFFFFFu, ((uint32_t)a.s << 24) | 0u, 0u,
                               dc.key0, dc.key1);
-    const uint4 r1 = philox10((uint32_t)j, 0xFFFFFFFFu, ((uint32_t)a.s << 24) | 1u, (uint32_t)a.b,
+    const uint4 r1 = philox10((uint32_t)j, 0xFFFFFFFFu, ((uint32_t)a.s << 24) | 1u, 0u,
                               dc.key0, dc.key1);
     const double u = u01d(r0.x);
     const double x0 = a.load == PIC_LOAD_STRATIFIED ? ((double)j + u) * L / (double)a.n : u * L;
@@ -446,7 +453,7 @@ __global__ __launch_bounds__(256) void deposit_kernel(DevPtrs d, int only_b)
         atomicAdd(&hist[c1], (unsigned long long)q);
     }
     __syncthreads();
-    unsigned long long* acc = d.acc + ((size_t)b * d.S + s) * d.nodes_max;
+    unsigned long long* acc = d.acc + (((size_t)b * d.S + s) * kRep + blockIdx.x % kRep) * d.nodes_max;
     for (int i = threadIdx.x; i < nn; i += 256) {
         const unsigned long long v = hist[i];
         if (v) atomicAdd(&acc[i], v);

@@ -26,6 +26,13 @@ constexpr uint32_t kFlagNuMax = 1u << 2;
 constexpr uint32_t kFlagCell = 1u << 3;
 constexpr uint32_t kFlagStall = 1u << 4;
 
+// Copies of the deposit accumulators and event counters: workgroup w adds into
+// copy w % kRep, so no address takes more than 1/kRep of the atomics (device-
+// scope atomics on one address serialise); readers sum the copies.
+constexpr int kRep = 1;
+// event counters per segment
+enum { C_ABS0, C_ABS1, C_SEE0, C_SEE1, C_CAND, C_NULL, C_VIOL, C_DROP, C_COLL, C_N = C_COLL + kMaxChan };
+
 // Fixed-point scale of the deposit: a particle's weights (1-f, f) become the
 // integers 2^32 - q and q, q = f * 2^32, so sums are exact and independent of
 // the order in which tiles add them.
@@ -99,10 +106,6 @@ struct SegState {
     int64_t tile_first, ntiles;  // global tile range of the current step
     uint32_t next_id;
     int32_t parity;         // which copy holds the particles
-    unsigned long long absorbed[2], see[2];
-    unsigned long long cand, nulls, viol;
-    unsigned long long coll[kMaxChan];
-    unsigned long long dropped;
     double ke;              // time-centred kinetic energy of the last step
 };
 
@@ -110,7 +113,7 @@ struct SegState {
 struct DisState {
     uint64_t step;
     uint32_t flags;
-    uint32_t pad;
+    int32_t retired;        // non-zero: skipped by the step kernels
     double fe;
     double avg_samples;
     double eepf_samples;
@@ -124,7 +127,8 @@ struct DevPtrs {
     SegState* segs;              // [B*S]
     DisConst* disc;              // [B]
     DisState* diss;              // [B]
-    unsigned long long* acc;     // [B][S][nodes_max] deposit sums (fixed point)
+    unsigned long long* acc;     // [B][S][kRep][nodes_max] deposit sums (fixed point)
+    unsigned long long* cnt;     // [B][S][kRep][C_N] event counters
     unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^24)
     double* rho;                 // [B][nodes_max]
     double* phi;
@@ -135,6 +139,7 @@ struct DevPtrs {
     unsigned long long* eepf;    // [B][2][bins]
     unsigned long long* status;  // [S][2][tiles_max] tile chain words
     unsigned int* tile_ctr;      // [S][2]
+    unsigned long long* tick;    // steps taken by the context (parity of the chain words)
     double* ke_part;             // [S][tiles_max]
     int32_t nodes_max, cells_max;
     int64_t tiles_max;

@@ -40,8 +40,6 @@ constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint32_t kSpinLimit = 1u << 20;
 
-// counters gathered per workgroup
-enum { C_ABS0, C_ABS1, C_SEE0, C_SEE1, C_CAND, C_NULL, C_VIOL, C_DROP, C_COLL, C_N = C_COLL + kMaxChan };
 
 struct Birth {
     int32_t cell;
@@ -209,9 +207,9 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
                 atomicAdd(&d.eepf[((size_t)b * 2 + 1) * kEepfBins + bin], 1ull);
         }
         if (GENERAL && sc.emits) {
-            const uint4 r4 = philox10(pid, step, ((uint32_t)s << 24) | 4u, (uint32_t)b, dc.key0, dc.key1);
+            const uint4 r4 = philox10(pid, step, ((uint32_t)s << 24) | 4u, 0u, dc.key0, dc.key1);
             if (odd24(r4.x) < sc.see_k) {
-                const uint4 r5 = philox10(pid, step, ((uint32_t)s << 24) | 5u, (uint32_t)b, dc.key0, dc.key1);
+                const uint4 r5 = philox10(pid, step, ((uint32_t)s << 24) | 5u, 0u, dc.key0, dc.key1);
                 const float vn = sc.vsee * sqrtf(-2.0f * logf(u01f(r4.y)));
                 const float adv = u01f(r4.z) * vn * sc.dtdx_e;   // cells
                 float g0, g1;
@@ -250,7 +248,7 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
     }
     if (!GENERAL || sc.nch == 0) return true;
     // null-collision Monte Carlo: integer candidate test on the first draw
-    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), (uint32_t)b, dc.key0, dc.key1);
+    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
     if (r.x >= sc.t32) return true;
     atomicAdd(&s_cnt[C_CAND], 1u);
     float nu[kMaxChan];
@@ -261,7 +259,7 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
         speed = sqrtf(v2);
         eps = sc.half_m_over_e * v2;
     } else {
-        const uint4 r3 = philox10(pid, step, ((uint32_t)s << 24) | 3u, (uint32_t)b, dc.key0, dc.key1);
+        const uint4 r3 = philox10(pid, step, ((uint32_t)s << 24) | 3u, 0u, dc.key0, dc.key1);
         float g0, g1, g2, g3;
         box_muller_f(u01f(r3.x), u01f(r3.y), g0, g1);
         box_muller_f(u01f(r3.z), u01f(r3.w), g2, g3);
@@ -308,8 +306,8 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
         } else if (kind == PIC_XS_EXCITATION) {
             enew = eps - sc.th[ch];
         } else {
-            const uint4 r1 = philox10(pid, step, ((uint32_t)s << 24) | 1u, (uint32_t)b, dc.key0, dc.key1);
-            const uint4 r2 = philox10(pid, step, ((uint32_t)s << 24) | 2u, (uint32_t)b, dc.key0, dc.key1);
+            const uint4 r1 = philox10(pid, step, ((uint32_t)s << 24) | 1u, 0u, dc.key0, dc.key1);
+            const uint4 r2 = philox10(pid, step, ((uint32_t)s << 24) | 2u, 0u, dc.key0, dc.key1);
             const float avail = eps - sc.th[ch];
             const float eej = u01f(r1.x) * avail;
             enew = avail - eej;
@@ -404,7 +402,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     __shared__ unsigned int s_cnt[C_N];
     __shared__ float s_red[kBS / 64];
 
-    const uint32_t par = (uint32_t)(d.diss[0].step & 1u);
+    const uint32_t par = (uint32_t)(*d.tick & 1u);
     unsigned long long* status = d.status + ((size_t)s * 2 + par) * d.tiles_max;
 
     // ---- tiles per segment, prefix over discharges (B <= 256: 4 per lane) ----
@@ -414,7 +412,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int bb = lane * 4 + j;
-            const int64_t n = (bb < B) ? d.segs[bb * S + s].count : 0;
+            const int64_t n = (bb < B && !d.diss[bb].retired) ? d.segs[bb * S + s].count : 0;
             run += (n + T - 1) / T;
             loc[j] = run;
         }
@@ -464,7 +462,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     auto flush = [&](int cb) {
         __syncthreads();
         const DisConst& dcf = d.disc[cb];
-        unsigned long long* acc_s = d.acc + ((size_t)cb * S + s) * d.nodes_max;
+        const int rep = blockIdx.x % kRep;
+        unsigned long long* acc_s = d.acc + (((size_t)cb * S + s) * kRep + rep) * d.nodes_max;
         for (int i = tid; i < dcf.n_nodes; i += kBS) {
             const unsigned long long v = hist[i];
             if (v) atomicAdd(&acc_s[i], v);
@@ -481,24 +480,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 if (v) atomicAdd(&eg[i], (unsigned long long)v);
             }
         }
-        SegState& stf = d.segs[cb * S + s];
+        unsigned long long* cnt = d.cnt + (((size_t)cb * S + s) * kRep + rep) * C_N;
         if (tid < C_N) {
             const unsigned int v = s_cnt[tid];
-            if (v) {
-                unsigned long long* dst;
-                switch (tid) {
-                    case C_ABS0: dst = &stf.absorbed[0]; break;
-                    case C_ABS1: dst = &stf.absorbed[1]; break;
-                    case C_SEE0: dst = &stf.see[0]; break;
-                    case C_SEE1: dst = &stf.see[1]; break;
-                    case C_CAND: dst = &stf.cand; break;
-                    case C_NULL: dst = &stf.nulls; break;
-                    case C_VIOL: dst = &stf.viol; break;
-                    case C_DROP: dst = &stf.dropped; break;
-                    default: dst = &stf.coll[tid - C_COLL]; break;
-                }
-                atomicAdd(dst, (unsigned long long)v);
-            }
+            if (v) atomicAdd(&cnt[tid], (unsigned long long)v);
             s_cnt[tid] = 0;
         }
         if (!GENERAL && a.diag) {
@@ -512,7 +497,13 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     for (;;) {
         int64_t t;
         if (GENERAL) {
-            if (tid == 0) s_tile = (int64_t)atomicAdd(&d.tile_ctr[s * 2 + par], 1u);
+            if (tid == 0) {
+                // a plain read first: surplus workgroups leave without
+                // contending on the ticket counter
+                unsigned int* ctr = &d.tile_ctr[s * 2 + par];
+                const unsigned int seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_tile = (int64_t)seen >= NT ? NT : (int64_t)atomicAdd(ctr, 1u);
+            }
             __syncthreads();
             t = s_tile;
         } else {
@@ -624,12 +615,14 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 if (!(born & (1u << j))) continue;
-                unsigned long long* acc_b = d.acc + (size_t)b * S * d.nodes_max;
-                if (s == 0) {
+                const int rep = blockIdx.x % kRep;
+                if (s == 0) {   // the electron into this histogram, the ion into species 1
                     lds_deposit(hist, bt[j].cell, bt[j].off, nc, periodic);
-                    global_deposit(acc_b + d.nodes_max, bt[j].cell, bt[j].off, nc, periodic);
-                } else {
-                    global_deposit(acc_b, bt[j].cell, bt[j].off, nc, periodic);
+                    global_deposit(d.acc + (((size_t)b * S + 1) * kRep + rep) * d.nodes_max, bt[j].cell,
+                                   bt[j].off, nc, periodic);
+                } else {        // a secondary electron into species 0
+                    global_deposit(d.acc + (((size_t)b * S + 0) * kRep + rep) * d.nodes_max, bt[j].cell,
+                                   bt[j].off, nc, periodic);
                 }
             }
         }

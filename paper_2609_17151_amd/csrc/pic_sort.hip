@@ -47,7 +47,7 @@ __device__ __forceinline__ void seg_prefix(const DevPtrs& d, int s, int64_t* pre
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int bb = lane * 4 + j;
-            const int64_t n = (bb < d.B) ? d.segs[bb * d.S + s].count : 0;
+            const int64_t n = (bb < d.B && !d.diss[bb].retired) ? d.segs[bb * d.S + s].count : 0;
             run += (n + kSTile - 1) / kSTile;
             loc[j] = run;
         }

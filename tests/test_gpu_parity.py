@@ -306,3 +306,48 @@ def test_periodic_sort_changes_order_not_physics(pic):
     for k in ("cell", "off", "vx", "vy", "vz", "id"):
         assert np.array_equal(pa[k][oa], pb[k][ob]), k
     assert not np.array_equal(pa["id"], pb["id"])
+
+
+def _uneven_argon_batch():
+    cfgs = []
+    for i, (n, nc, gap, v) in enumerate(((8000, 200, 0.015, 150.0), (30000, 400, 0.025, 200.0),
+                                         (15000, 317, 0.021, 320.0))):
+        cfg = W.argon_rf(n_init=n, n_cells=nc, gap=gap, v_amp=v, seed=100 + i, capacity=4 * n,
+                         weight=3e13 / n)
+        cfgs.append(cfg)
+    return cfgs
+
+
+def test_batched_discharges_equal_single_runs(pic):
+    cfgs = _uneven_argon_batch()
+    tabs = W.argon_tables()
+    batch = pic.Sim(cfgs, tabs)
+    batch.step(120)
+    for b, cfg in enumerate(cfgs):
+        one = pic.Sim(cfg, tabs)
+        one.step(120)
+        assert batch.counts(b) == one.counts()
+        for s in range(2):
+            pb, po = batch.get_particles(s, b), one.get_particles(s)
+            for k in ("cell", "off", "vx", "vy", "vz", "id"):
+                assert np.array_equal(pb[k], po[k]), (b, s, k)
+        assert np.array_equal(batch.efield(b), one.efield())
+        one.close()
+
+
+def test_retired_discharge_is_frozen(pic):
+    cfgs = _uneven_argon_batch()
+    tabs = W.argon_tables()
+    batch = pic.Sim(cfgs, tabs)
+    batch.step(40)
+    frozen = [batch.get_particles(s, 0) for s in range(2)]
+    batch.retire(0)
+    batch.step(70)                      # not a multiple of the graph chunk
+    for s in range(2):
+        now = batch.get_particles(s, 0)
+        for k in ("cell", "off", "vx", "id"):
+            assert np.array_equal(now[k], frozen[s][k])
+    assert batch.counts(0)["step"] == 40 and batch.counts(1)["step"] == 110
+    one = pic.Sim(cfgs[2], tabs)
+    one.step(110)
+    assert np.array_equal(batch.get_particles(1, 2)["vx"], one.get_particles(1)["vx"])
