@@ -59,6 +59,20 @@ class PicError(RuntimeError):
 
 
 _lib = None
+_live = []          # weak references to open contexts, closed before torch unloads
+
+
+def _close_all():
+    for r in list(_live):
+        sim = r()
+        if sim is not None:
+            sim.close()
+
+
+import atexit        # noqa: E402
+import weakref       # noqa: E402
+
+atexit.register(_close_all)
 
 
 def load_library():
@@ -148,7 +162,8 @@ class Sim:
                 return torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
 
             def _f(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                if torch.cuda is not None:
+                    torch.cuda.caching_allocator_delete(ptr)
 
             self._afn, self._ffn = ALLOC_FN(_a), FREE_FN(_f)
             self._alloc = PicAllocator(self._afn, self._ffn, None)
@@ -158,6 +173,7 @@ class Sim:
         if rc != OK:
             raise PicError(rc, "pic_init")
         self.h = h
+        _live.append(weakref.ref(self))
         self.n_nodes = [c["n_cells"] + (1 if c["bc"] == 1 else 0) for c in self.cfgs]
         for t in tables:
             self.load_xsec(t["species"], t["kind"], t["threshold"], t["energy"], t["sigma"],
