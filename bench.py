@@ -18,6 +18,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 40      # read cell, off, vx, vy, vz; write the same (no draws: no id)
+PUSH_SOURCES = ("pic_push.hip", "pic_device.h", "pic_internal.h")
+COUNTERS = os.path.join(ROOT, "profiles", "push_kernel_exb_counters.txt")
+
+
+def push_source_hash():
+    """SHA-256 over the sources the push kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in PUSH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_17151_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per push launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary, each scaled by the factor a plain copy of known size
+    gives; None when the summary is absent or the kernel has changed since."""
+    try:
+        kv = {}
+        with open(COUNTERS) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") != push_source_hash():
+            return None
+        fetch = float(kv["push_fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["push_write_kib_per_dispatch"]) * float(kv["write_scale"])
+        return (fetch + write) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, steps):
@@ -42,7 +74,7 @@ def main():
     ap.add_argument("--threads", type=int, default=1024)
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
@@ -114,9 +146,10 @@ def main():
                    "particles": n, "cells": cfg["n_cells"], "particles_per_thread": args.ppt, "threads_per_group": args.threads,
                    "sort_every": args.sort_every, "graphs": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "push_kernel", "avg_launch_ms": push_avg_ms,
-                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP,
+                     "algorithmic_bytes_per_launch": per_launch_bytes},
         "breakdown_ms_per_step": {"push": float(tm["push_ms"].sum()) / args.steps,
                                   "finalize": float(tm["finalize_ms"]) / args.steps,
                                   "finalize_avg_launch_ms": float(tm["finalize_ms"] / max(tm["finalize_n"], 1))},
