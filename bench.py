@@ -125,8 +125,8 @@ def main():
     sim.profile(False)
     ms_step = ms / args.steps
     value = n * args.steps / (ms * 1e-3)
-    push_avg_ms = float(tm["push_ms"].sum() / max(tm["push_n"].sum(), 1))
-    per_launch_bytes = (n / 2) * BYTES_PER_PARTICLE_STEP
+    push_avg_ms = tm["push_ms"] / max(tm["push_n"], 1.0)
+    per_launch_bytes = n * BYTES_PER_PARTICLE_STEP        # one launch moves every species
     achieved = per_launch_bytes / (push_avg_ms * 1e-3) / 1e9
     out = {
         "metric": "particle-steps/s",
@@ -150,7 +150,7 @@ def main():
                      "kernel": "push_kernel", "avg_launch_ms": push_avg_ms,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
-        "breakdown_ms_per_step": {"push": float(tm["push_ms"].sum()) / args.steps,
+        "breakdown_ms_per_step": {"push": tm["push_ms"] / args.steps,
                                   "finalize": float(tm["finalize_ms"]) / args.steps,
                                   "finalize_avg_launch_ms": float(tm["finalize_ms"] / max(tm["finalize_n"], 1))},
     }

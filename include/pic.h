@@ -172,7 +172,7 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_DIAG_RESET_AVG 12   /* no output: clears AVG and EEPF accumulators */
 #define PIC_DIAG_CHARGE 13      /* double[2]: total charge per unit area on the mesh, and from particle counts */
 
-#define PIC_DIAG_TIMING 14      /* double[2 + 2*S]: finalize launches, finalize ms, then per species push launches, push ms (pic_profile) */
+#define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
 
 #define PIC_EEPF_BINS 256
 

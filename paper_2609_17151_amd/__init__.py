@@ -296,9 +296,9 @@ class Sim:
         self._check(_lib.pic_profile(self.h, int(enable)), "pic_profile")
 
     def timing(self):
-        o = self.diag("TIMING", 2 + 2 * self.S)
-        return dict(finalize_n=o[0], finalize_ms=o[1],
-                    push_n=o[2::2].copy(), push_ms=o[3::2].copy())
+        o = self.diag("TIMING", 4)
+        return dict(finalize_n=float(o[0]), finalize_ms=float(o[1]),
+                    push_n=float(o[2]), push_ms=float(o[3]))
 
     def charge(self, batch=0):
         o = self.diag("CHARGE", 2, batch=batch)

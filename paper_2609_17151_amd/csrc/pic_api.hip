@@ -64,7 +64,7 @@ struct pic_ctx {
     std::vector<hipEvent_t> ev;           // pool, reused
     std::vector<std::pair<int, int>> pending;  // (kind, first event index); kind = species or -1 finalize
     size_t ev_used = 0;
-    std::vector<double> push_ms, push_n;
+    double push_ms = 0.0, push_n = 0.0;
     double fin_ms = 0.0, fin_n = 0.0;
     // replay of a captured chunk of steps
     int use_graph = 1;
@@ -348,8 +348,8 @@ void prof_collect(pic_ctx* c)
             c->fin_ms += ms;
             c->fin_n += 1.0;
         } else {
-            c->push_ms[pr.first] += ms;
-            c->push_n[pr.first] += 1.0;
+            c->push_ms += ms;
+            c->push_n += 1.0;
         }
     }
     c->pending.clear();
@@ -495,19 +495,32 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
                 sc.cell[1] = sc.cell[0]; sc.off[1] = sc.off[0]; sc.vx[1] = sc.vx[0];
                 sc.vy[1] = sc.vy[0]; sc.vz[1] = sc.vz[0]; sc.id[1] = sc.id[0];
             }
+            // ionization stages its pairs in species 0 (electrons) and 1 (ions)
             const int64_t bcap = std::max<int64_t>(16384, cap / 8);
-            sc.bcap = bcap;
-            sc.bcell = (int32_t*)A(bcap * 4);
-            sc.boff = (float*)A(bcap * 4);
-            sc.bvx = (float*)A(bcap * 4);
-            sc.bvy = (float*)A(bcap * 4);
-            sc.bvz = (float*)A(bcap * 4);
-            sc.bid = (uint32_t*)A(bcap * 4);
+            sc.bcap = (S > 1 && s <= 1) ? bcap : 0;
+            if (sc.bcap) {
+                sc.bcell = (int32_t*)A(bcap * 4);
+                sc.boff = (float*)A(bcap * 4);
+                sc.bvx = (float*)A(bcap * 4);
+                sc.bvy = (float*)A(bcap * 4);
+                sc.bvz = (float*)A(bcap * 4);
+            }
             fill_push_consts(c, s, sc);
+            // an emitting ion species stages its secondary electrons
+            sc.scap = sc.emits ? std::max<int64_t>(16384, pad_cap(c.species[0].capacity) / 8) : 0;
+            if (sc.scap) {
+                sc.scell = (int32_t*)A(sc.scap * 4);
+                sc.soff = (float*)A(sc.scap * 4);
+                sc.svx = (float*)A(sc.scap * 4);
+                sc.svy = (float*)A(sc.scap * 4);
+                sc.svz = (float*)A(sc.scap * 4);
+            }
         }
     }
-    int64_t tiles_max = 0;
-    for (int s = 0; s < S; ++s) tiles_max = std::max(tiles_max, ctx->grid_cap[s] / kTileMin + B);
+    // tiles are numbered over every segment of the context
+    int64_t tiles_max = (int64_t)B * S;
+    for (int s = 0; s < S; ++s) tiles_max += ctx->grid_cap[s] / kTileMin;
+    if (tiles_max > kMaxTiles) rc = PIC_EINVAL;
     d.tiles_max = tiles_max;
     if (rc == PIC_OK) {
         d.segc = (SegConst*)A(sizeof(SegConst) * B * S);
@@ -524,10 +537,10 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.epair = (float2*)A(8ull * B * cells_max);
         d.avg = (double*)A(8ull * B * (S + 2) * nodes_max);
         d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
-        d.status = (unsigned long long*)A(8ull * S * 2 * tiles_max);
-        d.tile_ctr = (unsigned int*)A(4ull * S * 2);
+        d.status = (unsigned long long*)A(8ull * 2 * tiles_max);
+        d.tile_ctr = (unsigned int*)A(4ull * 2);
         d.tick = (unsigned long long*)A(8);
-        d.ke_part = (double*)A(8ull * S * tiles_max);
+        d.ke_part = (double*)A(8ull * tiles_max);
         ctx->poisson_scratch = (double*)A(8ull * 3 * nodes_max);
     }
     if (rc != PIC_OK) {
@@ -556,10 +569,10 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.status, 0, 8ull * S * 2 * tiles_max, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * S * 2, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.status, 0, 8ull * 2 * tiles_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * 2, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * S * tiles_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * tiles_max, st) == hipSuccess;
     for (int b = 0; b < B && ok; ++b)
         for (int s = 0; s < S && ok; ++s) {
             const pic_species_cfg& sp = cfg[b].species[s];
@@ -641,8 +654,8 @@ pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t 
         if (!ctx->sort_scratch) return PIC_ENOMEM;
     }
     // a new tile size renumbers tiles: clear every chain word
-    rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max));
-    if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2));
+    rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * 2 * ctx->d.tiles_max));
+    if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * 2));
     ctx->ppt = ppt;
     ctx->threads = threads;
     ctx->sort_every = sort_every;
@@ -661,10 +674,10 @@ pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV)
 namespace {
 
 struct StepPlan {
-    std::vector<PushArgs> pa;
-    std::vector<int> ppt, threads;
-    std::vector<bool> general;
-    std::vector<int64_t> grid;
+    PushArgs pa{};
+    int ppt = 4, threads = 256;
+    bool general = false;
+    int64_t grid = 1;
     FinArgs fa{};
     uint64_t key = 0;
 };
@@ -687,42 +700,38 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
         bulk_lo = (int)std::floor(0.45 * d0.n_cells);
         bulk_hi = std::max(bulk_lo + 1, (int)std::ceil(0.55 * d0.n_cells));
     }
-    // per species: streaming or general kernel, tile size, persistent grid
+    // one launch for every segment: the general kernel as soon as any segment
+    // can lose, gain or collide particles; tile shape; persistent grid
     const size_t lds = push_lds_bytes(nn_max, nc_max, ctx->diag);
     if (lds > 65536) return PIC_EINVAL;
-    p.pa.assign(S, PushArgs{});
-    p.ppt.assign(S, ctx->ppt);
-    p.threads.assign(S, ctx->threads);
-    p.general.assign(S, false);
-    p.grid.assign(S, 0);
+    p.ppt = ctx->ppt;
+    p.threads = ctx->threads;
+    p.general = false;
+    for (int g = 0; g < B * S; ++g) {
+        const SegConst& sc = ctx->segc[g];
+        if (sc.compacts || sc.nch > 0 || sc.emits) p.general = true;
+    }
+    push_shape(p.ppt, p.threads, p.general);
+    const int T = p.threads * p.ppt;
+    int64_t tiles = 0;
+    for (int g = 0; g < B * S; ++g) tiles += (pad_cap(ctx->segc[g].cap) + T - 1) / T;
+    const int64_t resident = (int64_t)push_occupancy(p.ppt, p.threads, p.general, lds) * ctx->n_cu;
+    p.grid = std::max<int64_t>(1, std::min(tiles, resident));
+    PushArgs& pa = p.pa;
+    pa.d = ctx->d;
+    pa.diag = ctx->diag;
+    pa.eepf_inv_bin = (float)(kEepfBins / ctx->eepf_emax);
+    pa.bulk_lo = bulk_lo;
+    pa.bulk_hi = bulk_hi;
+    pa.nodes_max_dyn = nn_max;
+    pa.cells_max_dyn = nc_max;
     uint64_t key = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
     mix((uint64_t)ctx->diag);
-    for (int s = 0; s < S; ++s) {
-        for (int b = 0; b < B; ++b) {
-            const SegConst& sc = ctx->segc[b * S + s];
-            if (sc.compacts || sc.nch > 0 || sc.emits) p.general[s] = true;
-        }
-        push_shape(p.ppt[s], p.threads[s], p.general[s]);
-        const int T = p.threads[s] * p.ppt[s];
-        int64_t tiles = 0;
-        for (int b = 0; b < B; ++b) tiles += (pad_cap(ctx->segc[b * S + s].cap) + T - 1) / T;
-        const int64_t resident = (int64_t)push_occupancy(p.ppt[s], p.threads[s], p.general[s], lds) * ctx->n_cu;
-        p.grid[s] = std::max<int64_t>(1, std::min(tiles, resident));
-        PushArgs& pa = p.pa[s];
-        pa.d = ctx->d;
-        pa.species = s;
-        pa.diag = ctx->diag;
-        pa.eepf_inv_bin = (float)(kEepfBins / ctx->eepf_emax);
-        pa.bulk_lo = bulk_lo;
-        pa.bulk_hi = bulk_hi;
-        pa.nodes_max_dyn = nn_max;
-        pa.cells_max_dyn = nc_max;
-        mix((uint64_t)p.ppt[s]);
-        mix((uint64_t)p.threads[s]);
-        mix((uint64_t)p.general[s]);
-        mix((uint64_t)p.grid[s]);
-    }
+    mix((uint64_t)p.ppt);
+    mix((uint64_t)p.threads);
+    mix((uint64_t)p.general);
+    mix((uint64_t)p.grid);
     p.fa.d = ctx->d;
     p.fa.mode = kFinStep;
     p.fa.diag = ctx->diag;
@@ -743,12 +752,9 @@ pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st,
                     hipSuccess)
                     return PIC_EHIP;
         }
-        for (int s = 0; s < ctx->S; ++s) {
-            const int pe = prof ? prof_begin(ctx) : -1;
-            if (launch_push(p.pa[s], p.ppt[s], p.threads[s], p.general[s], p.grid[s], st) != hipSuccess)
-                return PIC_EHIP;
-            prof_end(ctx, pe, s);
-        }
+        const int pp = prof ? prof_begin(ctx) : -1;
+        if (launch_push(p.pa, p.ppt, p.threads, p.general, p.grid, st) != hipSuccess) return PIC_EHIP;
+        prof_end(ctx, pp, 0);
         const int pe = prof ? prof_begin(ctx) : -1;
         if (launch_finalize(p.fa, st) != hipSuccess) return PIC_EHIP;
         prof_end(ctx, pe, -1);
@@ -870,8 +876,7 @@ pic_status pic_profile(pic_ctx* ctx, int32_t enable)
     prof_collect(ctx);
     ctx->prof = enable ? 1 : 0;
     if (enable) {
-        ctx->push_ms.assign(ctx->S, 0.0);
-        ctx->push_n.assign(ctx->S, 0.0);
+        ctx->push_ms = ctx->push_n = 0.0;
         ctx->fin_ms = ctx->fin_n = 0.0;
     }
     return PIC_OK;
@@ -990,8 +995,8 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     if (hipMemcpy(ctx->d.diss, ds.data(), sizeof(DisState) * ctx->B, hipMemcpyHostToDevice) != hipSuccess)
         return PIC_EHIP;
     // chain words and counters follow the step parity: start them clean
-    if (hipMemset(ctx->d.status, 0, 8ull * ctx->S * 2 * ctx->d.tiles_max) != hipSuccess) return PIC_EHIP;
-    if (hipMemset(ctx->d.tile_ctr, 0, 4ull * ctx->S * 2) != hipSuccess) return PIC_EHIP;
+    if (hipMemset(ctx->d.status, 0, 8ull * 2 * ctx->d.tiles_max) != hipSuccess) return PIC_EHIP;
+    if (hipMemset(ctx->d.tile_ctr, 0, 4ull * 2) != hipSuccess) return PIC_EHIP;
     if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * kRep * ctx->d.nodes_max, 0,
                   8ull * ctx->S * kRep * ctx->d.nodes_max) != hipSuccess)
         return PIC_EHIP;
@@ -1143,15 +1148,13 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             break;
         }
         case PIC_DIAG_TIMING: {
-            if (!need(8ull * (2 + 2 * S))) return PIC_EINVAL;
+            if (!need(8ull * 4)) return PIC_EINVAL;
             prof_collect(ctx);
             double* o = (double*)out;
             o[0] = ctx->fin_n;
             o[1] = ctx->fin_ms;
-            for (int s = 0; s < S; ++s) {
-                o[2 + 2 * s] = s < (int)ctx->push_n.size() ? ctx->push_n[s] : 0.0;
-                o[3 + 2 * s] = s < (int)ctx->push_ms.size() ? ctx->push_ms[s] : 0.0;
-            }
+            o[2] = ctx->push_n;
+            o[3] = ctx->push_ms;
             break;
         }
         case PIC_DIAG_CHARGE: {

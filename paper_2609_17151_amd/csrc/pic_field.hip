@@ -100,10 +100,9 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     if (tid >= kBook) {
         // ---- bookkeeping wave: every load first, then the updates -------------
         if (a.mode == kFinStep) {
-            int64_t surv[kMaxSpecies], tfirst[kMaxSpecies], ntl[kMaxSpecies];
+            int64_t surv[kMaxSpecies], tfirst[kMaxSpecies], ntl[kMaxSpecies], see[kMaxSpecies];
             int par[kMaxSpecies];
             const int64_t n_ion = d.segs[b * S + 0].births;
-            const int64_t n_see = S > 1 ? d.segs[b * S + 1].see_births : 0;
 #pragma unroll
             for (int s = 0; s < kMaxSpecies; ++s) {
                 if (s < S) {
@@ -112,6 +111,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     par[s] = st.parity;
                     tfirst[s] = st.tile_first;
                     ntl[s] = st.ntiles;
+                    see[s] = st.see_births;
                 }
             }
 #pragma unroll
@@ -119,23 +119,38 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                 if (s >= S) break;
                 const SegConst& sc = d.segc[b * S + s];
                 SegState& st = d.segs[b * S + s];
-                const int64_t nbirth = s == 0 ? n_ion + n_see : (s == 1 ? n_ion : 0);
-                int64_t nmove = nbirth;
-                if (nmove > sc.bcap) nmove = sc.bcap;
-                if (nmove > sc.cap - surv[s]) nmove = sc.cap - surv[s];
                 const int out = sc.compacts ? (par[s] ^ 1) : par[s];
-                for (int64_t k = lane; k < nmove; k += 64) {
-                    sc.cell[out][surv[s] + k] = sc.bcell[k];
-                    sc.off[out][surv[s] + k] = sc.boff[k];
-                    sc.vx[out][surv[s] + k] = sc.bvx[k];
-                    sc.vy[out][surv[s] + k] = sc.bvy[k];
-                    sc.vz[out][surv[s] + k] = sc.bvz[k];
-                    sc.id[out][surv[s] + k] = sc.bid[k];
+                // births in the order the step made them: ionization pairs, then
+                // (electrons only) the secondaries of each ion species in turn
+                int64_t pos = surv[s], want = 0;
+                const uint32_t id0 = st.next_id;
+                auto append = [&](const int32_t* c_, const float* o_, const float* x_, const float* y_,
+                                  const float* z_, int64_t n, int64_t ncap) {
+                    want += n;
+                    int64_t m = n < ncap ? n : ncap;
+                    if (m > sc.cap - pos) m = sc.cap - pos;
+                    for (int64_t k = lane; k < m; k += 64) {
+                        sc.cell[out][pos + k] = c_[k];
+                        sc.off[out][pos + k] = o_[k];
+                        sc.vx[out][pos + k] = x_[k];
+                        sc.vy[out][pos + k] = y_[k];
+                        sc.vz[out][pos + k] = z_[k];
+                        sc.id[out][pos + k] = id0 + (uint32_t)(pos - surv[s] + k);
+                    }
+                    if (m > 0) pos += m;
+                };
+                if (s <= 1 && S > 1) append(sc.bcell, sc.boff, sc.bvx, sc.bvy, sc.bvz, n_ion, sc.bcap);
+                if (s == 0) {
+                    for (int s2 = 1; s2 < S; ++s2) {
+                        const SegConst& se = d.segc[b * S + s2];
+                        if (se.emits) append(se.scell, se.soff, se.svx, se.svy, se.svz, see[s2], se.scap);
+                    }
                 }
+                const int64_t nmove = pos - surv[s];
                 if (a.diag) {
                     // kinetic-energy partials of the step's tiles (runs leave
                     // zeros elsewhere), fixed order, cleared after reading
-                    double* kpp = d.ke_part + (size_t)s * d.tiles_max + tfirst[s];
+                    double* kpp = d.ke_part + tfirst[s];
                     double acc_k = 0.0;
                     for (int64_t t = lane; t < ntl[s]; t += 64) {
                         acc_k += kpp[t];
@@ -145,15 +160,15 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     if (lane == 0) st.ke = acc_k;
                 }
                 if (lane == 0) {
-                    if (nmove < nbirth) {
+                    if (nmove < want) {
                         atomicOr(&ds.flags, kFlagCapacity);
-                        d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(nbirth - nmove);
+                        d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(want - nmove);
                     }
-                    st.count = surv[s] + nmove;
-                    st.next_id += (uint32_t)nmove;
+                    st.count = pos;
+                    st.next_id = id0 + (uint32_t)nmove;
                     st.parity = out;
                     st.see_births = 0;
-                    st.surv = surv[s] + nmove;
+                    st.surv = pos;
                     st.ntiles = 0;
                 }
             }

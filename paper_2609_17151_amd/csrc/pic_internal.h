@@ -18,6 +18,8 @@ constexpr int kMaxCells = 4096;
 constexpr int kFinThreads = 1024;          // finalize / field-solve workgroup (4 nodes per thread at most)
 constexpr int kNodesPerThread = 4;         // kFinThreads * 4 >= nodes of a bounded mesh
 constexpr int kEepfBins = PIC_EEPF_BINS;
+constexpr int kMaxSeg = PIC_MAX_BATCH * PIC_MAX_SPECIES;   // (discharge, species) segments of a context
+constexpr int64_t kMaxTiles = 1ll << 30;                    // tile numbers fit in int32
 
 // latched device flags
 constexpr uint32_t kFlagCapacity = 1u << 0;
@@ -47,14 +49,21 @@ struct SegConst {
     float* vy[2];
     float* vz[2];
     uint32_t* id[2];
-    // births staging
+    // staging of the particles born into this segment by ionization, in the
+    // order of the ionizing electrons (ids are given when they are appended)
     int32_t* bcell;
     float* boff;
     float* bvx;
     float* bvy;
     float* bvz;
-    uint32_t* bid;
-    int64_t cap, bcap;
+    // staging of the secondary electrons this (ion) segment emits, in the order
+    // of the absorbed ions (appended to the electrons after the ionization births)
+    int32_t* scell;
+    float* soff;
+    float* svx;
+    float* svy;
+    float* svz;
+    int64_t cap, bcap, scap;
     // push
     float qmh;              // (q/m) dt/2
     float tv[3], sv[3];     // Boris rotation vectors t and s = 2t/(1+t^2)
@@ -103,7 +112,7 @@ struct SegState {
     int64_t surv;           // survivors of the current step
     int64_t births;         // species 0: ionization events of the step (one electron and one ion each)
     int64_t see_births;     // ion species: secondary electrons emitted this step
-    int64_t tile_first, ntiles;  // global tile range of the current step
+    int64_t tile_first, ntiles;  // tile range of the current step (tiles are numbered over all segments)
     uint32_t next_id;
     int32_t parity;         // which copy holds the particles
     double ke;              // time-centred kinetic energy of the last step
@@ -137,10 +146,10 @@ struct DevPtrs {
     float2* epair;               // [B][cells_max] (E[c], E[c+1]) for the gather
     double* avg;                 // [B][(S+2)][nodes_max]
     unsigned long long* eepf;    // [B][2][bins]
-    unsigned long long* status;  // [S][2][tiles_max] tile chain words
-    unsigned int* tile_ctr;      // [S][2]
+    unsigned long long* status;  // [2][tiles_max] tile chain words (by parity of the tick)
+    unsigned int* tile_ctr;      // [2] tile tickets
     unsigned long long* tick;    // steps taken by the context (parity of the chain words)
-    double* ke_part;             // [S][tiles_max]
+    double* ke_part;             // [tiles_max] kinetic-energy partial sums by tile
     int32_t nodes_max, cells_max;
     int64_t tiles_max;
 };

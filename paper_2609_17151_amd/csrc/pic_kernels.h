@@ -8,7 +8,6 @@ namespace pic {
 
 struct PushArgs {
     DevPtrs d;
-    int32_t species;
     int32_t diag;                 // accumulate electron energy deposit and EEPF
     float eepf_inv_bin;           // 1 / bin width (eV)
     int32_t bulk_lo, bulk_hi;     // cells of the bulk EEPF window

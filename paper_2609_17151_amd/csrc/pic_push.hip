@@ -1,14 +1,16 @@
-// Fused particle kernel of one leapfrog step for one species over every
-// discharge of a context (paper Section 1: explicit leapfrog, Boris pusher,
-// walls and secondary emission, null-collision Monte Carlo with tabulated cross
-// sections; the charge of the particles deposited on the mesh).
+// Fused particle kernel of one leapfrog step for every species of every
+// discharge of a context, in one launch (paper Section 1: explicit leapfrog,
+// Boris pusher, walls and secondary emission, null-collision Monte Carlo with
+// tabulated cross sections; the charge of the particles deposited on the mesh).
 //
-// Work is cut into tiles of T = 256 * PPT consecutive particles of one
-// (discharge, species) segment; each thread owns PPT consecutive particles and
-// moves them with 16-byte vector loads.  A workgroup is persistent over many
-// tiles: it stages the (E[c], E[c+1]) pairs of a discharge in LDS and zeroes
-// its deposit histogram once per run of tiles of that discharge, and flushes
-// the histogram once at the end of the run.
+// Work is cut into tiles of T = threads * PPT consecutive particles of one
+// (discharge, species) segment; tiles are numbered over all segments,
+// discharge-major, so one launch covers the whole step and no species waits
+// for another.  Each thread owns PPT consecutive particles and moves them with
+// 16-byte vector loads.  A workgroup is persistent over many tiles: it stages
+// the (E[c], E[c+1]) pairs of a discharge in LDS once per run of tiles of that
+// discharge, and zeroes and flushes its deposit histogram once per run of
+// tiles of one segment.
 //
 // Two modes.  Streaming (nothing can leave or be born: periodic, no
 // collisions): each workgroup takes a fixed contiguous range of tiles and
@@ -16,8 +18,10 @@
 // order by an atomic ticket; survivors are compacted into the other copy in
 // their original order and births are staged in canonical order, through a
 // block prefix sum plus a decoupled look-back across the tiles of the segment
-// (every tile waits only for tiles already handed out, so it cannot deadlock;
-// the wait is bounded and a stall is latched).
+// (every tile waits only for tiles of its segment already handed out, so it
+// cannot deadlock; the wait is bounded and a stall is latched).  Births are
+// staged per segment (ionization pairs by the electrons, secondary electrons
+// by each ion species); the finalize appends them and gives their ids.
 //
 // Per particle: gather E by linear weighting, Boris push in the imposed B,
 // cell-relative move in FP32, periodic wrap or absorption (with secondary
@@ -390,12 +394,12 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     constexpr int kBS = BS;
     constexpr int T = kBS * PPT;
     const DevPtrs& d = a.d;
-    const int s = a.species, S = d.S, B = d.B;
+    const int S = d.S, NS = d.B * d.S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int64_t s_pref[PIC_MAX_BATCH + 1];
-    __shared__ int64_t s_tile;
+    __shared__ int32_t s_pref[kMaxSeg + 1];   // first tile of every segment (discharge-major)
+    __shared__ int32_t s_tile;
     __shared__ uint32_t s_wave[kBS / 64];
     __shared__ uint64_t s_excl_surv;
     __shared__ uint32_t s_excl_birth;
@@ -403,43 +407,44 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     __shared__ float s_red[kBS / 64];
 
     const uint32_t par = (uint32_t)(*d.tick & 1u);
-    unsigned long long* status = d.status + ((size_t)s * 2 + par) * d.tiles_max;
+    unsigned long long* status = d.status + (size_t)par * d.tiles_max;
 
-    // ---- tiles per segment, prefix over discharges (B <= 256: 4 per lane) ----
+    // ---- tiles per segment, prefix over the segments (up to 16 per lane) -----
     if (wid == 0) {
-        int64_t loc[4];
-        int64_t run = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int bb = lane * 4 + j;
-            const int64_t n = (bb < B && !d.diss[bb].retired) ? d.segs[bb * S + s].count : 0;
-            run += (n + T - 1) / T;
-            loc[j] = run;
+        const int per = (NS + 63) >> 6;
+        const int g0 = lane * per;
+        int32_t run = 0;
+        for (int j = 0; j < per; ++j) {
+            const int g = g0 + j;
+            if (g < NS) {
+                const int64_t n = d.diss[g / S].retired ? 0 : d.segs[g].count;
+                run += (int32_t)((n + T - 1) / T);
+                s_pref[g + 1] = run;
+            }
         }
-        int64_t incl = run;
+        int32_t incl = run;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
-            const int64_t o = __shfl_up(incl, dd, 64);
+            const int32_t o = __shfl_up(incl, dd, 64);
             if (lane >= dd) incl += o;
         }
-        const int64_t excl = incl - run;
+        const int32_t excl = incl - run;
         if (lane == 0) s_pref[0] = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int bb = lane * 4 + j;
-            if (bb < B) s_pref[bb + 1] = excl + loc[j];
+        for (int j = 0; j < per; ++j) {
+            const int g = g0 + j;
+            if (g < NS) s_pref[g + 1] += excl;
         }
     }
     if (tid < C_N) s_cnt[tid] = 0;
     // the next step's chain words start cleared
     {
-        unsigned long long* nxt = d.status + ((size_t)s * 2 + (par ^ 1u)) * d.tiles_max;
+        unsigned long long* nxt = d.status + (size_t)(par ^ 1u) * d.tiles_max;
         for (int64_t t = (int64_t)blockIdx.x * kBS + tid; t < d.tiles_max; t += (int64_t)gridDim.x * kBS)
             __hip_atomic_store(&nxt[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (blockIdx.x == 0 && tid == 0) d.tile_ctr[s * 2 + (par ^ 1u)] = 0u;
+        if (blockIdx.x == 0 && tid == 0) d.tile_ctr[par ^ 1u] = 0u;
     }
     __syncthreads();
-    const int64_t NT = s_pref[B];
+    const int32_t NT = s_pref[NS];
 
     // LDS layout: deposit histogram, [energy histogram, EEPF], E pairs
     const int nn_max = a.nodes_max_dyn;
@@ -448,27 +453,28 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     unsigned int* eepf = reinterpret_cast<unsigned int*>(ehist + (a.diag ? nn_max : 0));
     float2* ep = reinterpret_cast<float2*>(eepf + (a.diag ? kEepfBins : 0));
 
-    int cur_b = -1;
-    int64_t run_first = 0;
+    int cur_g = -1, cur_b = -1;
+    int32_t run_first = 0;
     float ke_run = 0.0f;
-    int64_t t_next = 0, t_end = 0;
+    int32_t t_next = 0, t_end = 0;
     if (!GENERAL) {
-        const int64_t chunk = (NT + gridDim.x - 1) / gridDim.x;
-        t_next = (int64_t)blockIdx.x * chunk;
+        const int32_t chunk = (NT + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+        t_next = (int32_t)blockIdx.x * chunk;
         t_end = t_next + chunk < NT ? t_next + chunk : NT;
     }
 
-    // flush the run of tiles of discharge cb: deposit, diagnostics, counters
-    auto flush = [&](int cb) {
+    // flush the run of tiles of segment cg: deposit, diagnostics, counters
+    auto flush = [&](int cg) {
         __syncthreads();
+        const int cb = cg / S, cs = cg - cb * S;
         const DisConst& dcf = d.disc[cb];
         const int rep = blockIdx.x % kRep;
-        unsigned long long* acc_s = d.acc + (((size_t)cb * S + s) * kRep + rep) * d.nodes_max;
+        unsigned long long* acc_s = d.acc + ((size_t)cg * kRep + rep) * d.nodes_max;
         for (int i = tid; i < dcf.n_nodes; i += kBS) {
             const unsigned long long v = hist[i];
             if (v) atomicAdd(&acc_s[i], v);
         }
-        if (a.diag && s == 0) {
+        if (a.diag && cs == 0) {
             unsigned long long* ea = d.eacc + (size_t)cb * d.nodes_max;
             for (int i = tid; i < dcf.n_nodes; i += kBS) {
                 const unsigned long long v = ehist[i];
@@ -480,7 +486,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 if (v) atomicAdd(&eg[i], (unsigned long long)v);
             }
         }
-        unsigned long long* cnt = d.cnt + (((size_t)cb * S + s) * kRep + rep) * C_N;
+        unsigned long long* cnt = d.cnt + ((size_t)cg * kRep + rep) * C_N;
         if (tid < C_N) {
             const unsigned int v = s_cnt[tid];
             if (v) atomicAdd(&cnt[tid], (unsigned long long)v);
@@ -489,20 +495,20 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         if (!GENERAL && a.diag) {
             // kinetic energy of the run (ranges are fixed, so the grouping is too)
             const double kt = block_sum_f32<BS>(ke_run, s_red);
-            if (tid == 0) d.ke_part[(size_t)s * d.tiles_max + run_first] = 0.5 * d.segc[cb * S + s].mw_half * kt;
+            if (tid == 0) d.ke_part[run_first] = 0.5 * d.segc[cg].mw_half * kt;
             ke_run = 0.0f;
         }
     };
 
     for (;;) {
-        int64_t t;
+        int32_t t;
         if (GENERAL) {
             if (tid == 0) {
                 // a plain read first: surplus workgroups leave without
                 // contending on the ticket counter
-                unsigned int* ctr = &d.tile_ctr[s * 2 + par];
+                unsigned int* ctr = &d.tile_ctr[par];
                 const unsigned int seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_tile = (int64_t)seen >= NT ? NT : (int64_t)atomicAdd(ctr, 1u);
+                s_tile = (int32_t)seen >= NT ? NT : (int32_t)atomicAdd(ctr, 1u);
             }
             __syncthreads();
             t = s_tile;
@@ -511,32 +517,35 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             if (t >= t_end) break;
         }
         if (t >= NT) break;
-        // segment of tile t
-        int lo = 0, hi = B;
+        // segment of tile t: the last g with s_pref[g] <= t
+        int lo = 0, hi = NS;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (s_pref[mid] <= t) lo = mid; else hi = mid;
         }
-        const int b = lo;
+        const int sg = lo;
+        const int b = sg / S, s = sg - b * S;
         const DisConst& dc = d.disc[b];
-        if (b != cur_b) {
-            if (cur_b >= 0) flush(cur_b);
+        if (sg != cur_g) {
+            if (cur_g >= 0) flush(cur_g);
             __syncthreads();
-            const float2* epg = d.epair + (size_t)b * d.cells_max;
-            for (int i = tid; i < dc.n_cells; i += kBS) ep[i] = epg[i];
+            if (b != cur_b) {
+                const float2* epg = d.epair + (size_t)b * d.cells_max;
+                for (int i = tid; i < dc.n_cells; i += kBS) ep[i] = epg[i];
+            }
             for (int i = tid; i < dc.n_nodes; i += kBS) hist[i] = 0ull;
             if (a.diag && s == 0) {
                 for (int i = tid; i < dc.n_nodes; i += kBS) ehist[i] = 0ull;
                 for (int i = tid; i < kEepfBins; i += kBS) eepf[i] = 0u;
             }
             __syncthreads();
+            cur_g = sg;
             cur_b = b;
             run_first = t;
         }
-        const int64_t tile_first = s_pref[b];
-        const int64_t ntiles = s_pref[b + 1] - tile_first;
-        const int64_t tin = t - tile_first;
-        const int sg = b * S + s;
+        const int32_t tile_first = s_pref[sg];
+        const int32_t ntiles = s_pref[sg + 1] - tile_first;
+        const int32_t tin = t - tile_first;
         const SegConst& sc = d.segc[sg];
         SegState& st = d.segs[sg];
         const int64_t n = st.count;
@@ -545,7 +554,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         const uint32_t step = (uint32_t)d.diss[b].step;
         const int in = st.parity;
         const int out = sc.compacts ? (in ^ 1) : in;
-        const int64_t base = tin * T + (int64_t)tid * PPT;
+        const int64_t base = (int64_t)tin * T + (int64_t)tid * PPT;
 
         int32_t cell[PPT];
         float off[PPT], vx[PPT], vy[PPT], vz[PPT];
@@ -612,10 +621,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 
         // ---- general: births deposit, block scan, look-back, writes ----------
         if (born) {
+            const int rep = blockIdx.x % kRep;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 if (!(born & (1u << j))) continue;
-                const int rep = blockIdx.x % kRep;
                 if (s == 0) {   // the electron into this histogram, the ion into species 1
                     lds_deposit(hist, bt[j].cell, bt[j].off, nc, periodic);
                     global_deposit(d.acc + (((size_t)b * S + 1) * kRep + rep) * d.nodes_max, bt[j].cell,
@@ -644,7 +653,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             double kt = 0.0;
 #pragma unroll
             for (int w = 0; w < kBS / 64; ++w) kt += (double)s_red[w];
-            d.ke_part[(size_t)s * d.tiles_max + t] = 0.5 * sc.mw_half * kt;
+            d.ke_part[t] = 0.5 * sc.mw_half * kt;
         }
         uint64_t excl_surv = 0;
         uint32_t excl_birth = 0;
@@ -656,12 +665,12 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             } else {
                 if (lane == 0)
                     __hip_atomic_store(&status[t], agg_word | kFlagAgg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                int64_t j0 = t - 1;
+                int32_t j0 = t - 1;
                 uint64_t sum_s = 0, sum_b = 0;
                 bool done = false;
                 uint32_t spins = 0;
                 while (!done) {
-                    const int64_t jj = j0 - lane;
+                    const int32_t jj = j0 - lane;
                     uint64_t w = kFlagInc;        // before the segment start: inclusive zero
                     if (jj >= tile_first)
                         w = __hip_atomic_load(&status[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -743,41 +752,46 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             }
         }
         if (born) {
-            // species 0 births are ionization pairs (electron + ion); an ion
-            // species' births are secondary electrons, placed after them
-            const int eseg = b * S + 0;
-            const SegConst& se = d.segc[eseg];
-            const int64_t base_e = (s == 0) ? 0 : d.segs[eseg].births;
+            // electron births of species 0 are ionization pairs (electron into
+            // this segment's staging, ion into species 1's); an ion species'
+            // births are secondary electrons, staged in its own segment
             uint64_t k = (uint64_t)excl_birth + (texcl >> 16);
+            if (s == 0) {
+                const SegConst& si = d.segc[b * S + 1];
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                if (!(born & (1u << j))) continue;
-                const int64_t ke = base_e + (int64_t)k;
-                if (ke < se.bcap) {
-                    se.bcell[ke] = bt[j].cell;
-                    se.boff[ke] = bt[j].off;
-                    se.bvx[ke] = bt[j].vx;
-                    se.bvy[ke] = bt[j].vy;
-                    se.bvz[ke] = bt[j].vz;
-                    se.bid[ke] = d.segs[eseg].next_id + (uint32_t)ke;
-                } else {
-                    atomicOr(&d.diss[b].flags, kFlagCapacity);
-                }
-                if (s == 0) {
-                    const int iseg = b * S + 1;
-                    const SegConst& si = d.segc[iseg];
-                    if ((int64_t)k < si.bcap) {
+                for (int j = 0; j < PPT; ++j) {
+                    if (!(born & (1u << j))) continue;
+                    if ((int64_t)k < sc.bcap && (int64_t)k < si.bcap) {
+                        sc.bcell[k] = bt[j].cell;
+                        sc.boff[k] = bt[j].off;
+                        sc.bvx[k] = bt[j].vx;
+                        sc.bvy[k] = bt[j].vy;
+                        sc.bvz[k] = bt[j].vz;
                         si.bcell[k] = bt[j].cell;
                         si.boff[k] = bt[j].off;
                         si.bvx[k] = bt[j].ivx;
                         si.bvy[k] = bt[j].ivy;
                         si.bvz[k] = bt[j].ivz;
-                        si.bid[k] = d.segs[iseg].next_id + (uint32_t)k;
                     } else {
                         atomicOr(&d.diss[b].flags, kFlagCapacity);
                     }
+                    ++k;
                 }
-                ++k;
+            } else {
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    if (!(born & (1u << j))) continue;
+                    if ((int64_t)k < sc.scap) {
+                        sc.scell[k] = bt[j].cell;
+                        sc.soff[k] = bt[j].off;
+                        sc.svx[k] = bt[j].vx;
+                        sc.svy[k] = bt[j].vy;
+                        sc.svz[k] = bt[j].vz;
+                    } else {
+                        atomicOr(&d.diss[b].flags, kFlagCapacity);
+                    }
+                    ++k;
+                }
             }
         }
         // the last tile of the segment records the step's totals
@@ -791,7 +805,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
         __syncthreads();                     // s_tile, s_wave and s_red are reused
     }
-    if (cur_b >= 0) flush(cur_b);
+    if (cur_g >= 0) flush(cur_g);
 }
 
 #define PIC_KERNELS(X)   \
