@@ -3,6 +3,7 @@
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It wraps ``liboracle.so`` (plain C, built from
 ``pic_oracle.c`` by :func:`build`) and shares no code with the GPU library.
+``oracle.mlp`` is the FP64 reference of the warm-start network.
 """
 from __future__ import annotations
 

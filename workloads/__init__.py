@@ -230,3 +230,28 @@ def random_particles(cfg, s, n, seed, vscale=None):
     v = rng.normal(0.0, vs, (3, n))
     ids = np.arange(n, dtype=np.uint32)
     return x, v[0].copy(), v[1].copy(), v[2].copy(), ids
+
+
+# --------------------------------------------------------------------------
+# Warm-start network: layer widths and seeded initial weights.
+# --------------------------------------------------------------------------
+WARM_WIDTHS = (5, 256, 256, 256, 768)
+
+
+def mlp_init(widths=WARM_WIDTHS, seed=7):
+    """Seeded initial parameters, flat, one [n_out][n_in + 1] block per layer
+    (bias last): weights normal with variance 2 / n_in, biases zero."""
+    rng = np.random.default_rng(seed)
+    blocks = []
+    for i in range(len(widths) - 1):
+        n_in, n_out = widths[i], widths[i + 1]
+        w = np.zeros((n_out, n_in + 1))
+        w[:, :n_in] = rng.normal(0.0, math.sqrt(2.0 / n_in), (n_out, n_in))
+        blocks.append(w.ravel())
+    return np.concatenate(blocks)
+
+
+def mlp_batch(n, n_in, n_out, seed):
+    """Seeded inputs of unit scale and targets of unit scale for network tests."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, 1.0, (n, n_in)), rng.normal(0.0, 1.0, (n, n_out))
