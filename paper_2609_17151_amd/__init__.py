@@ -104,6 +104,15 @@ def load_library():
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
         "pic_retire": (i32, [P, i32, i32]),
+        "pic_mlp_create": (i32, [ip, i32, i32, C.POINTER(PicAllocator), P, C.POINTER(P)]),
+        "pic_mlp_n_params": (i64, [P]),
+        "pic_mlp_set_params": (i32, [P, fp, i64]),
+        "pic_mlp_get_params": (i32, [P, fp, i64]),
+        "pic_mlp_forward": (i32, [P, i32, P, P]),
+        "pic_mlp_train_step": (i32, [P, i32, P, P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+        "pic_mlp_grad": (i32, [P, i32, P, P, fp, fp]),
+        "pic_mlp_sync": (i32, [P]),
+        "pic_mlp_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -331,9 +340,96 @@ class Sim:
                     "pic_set_particles")
 
 
-def declared_functions(header=None):
-    """Names of the functions ``include/pic.h`` declares."""
+def declared_functions(headers=None):
+    """Names of the functions the headers under ``include/`` declare."""
     import re
-    header = header or os.path.join(os.path.dirname(HERE), "include", "pic.h")
-    text = open(header).read()
-    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", text)))
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    headers = headers or [os.path.join(inc, h) for h in ("pic.h", "pic_mlp.h")]
+    names = set()
+    for h in headers:
+        names |= set(re.findall(r"\b(pic_[a-z_]+)\s*\(", open(h).read()))
+    return sorted(names)
+
+
+class MLP:
+    """The warm-start network (``pic_mlp``): BF16 matrix-core training and
+    inference; inputs, targets and outputs are float32 CUDA tensors."""
+
+    def __init__(self, widths, max_batch, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the network runs only on an MI355X")
+        L = load_library()
+        self._torch = torch
+        self.widths = tuple(int(w) for w in widths)
+        self.max_batch = int(max_batch)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        w = (C.c_int32 * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        rc = L.pic_mlp_create(w, len(self.widths), self.max_batch, None, C.c_void_p(self.stream.cuda_stream),
+                              C.byref(h))
+        if rc != OK:
+            raise PicError(rc, "pic_mlp_create")
+        self.h = h
+        self.n_params = int(L.pic_mlp_n_params(h))
+        self._loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        _live.append(weakref.ref(self))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pic_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise PicError(rc, what)
+
+    def _dev(self, a, cols):
+        t = self._torch
+        a = t.as_tensor(a, dtype=t.float32, device="cuda").contiguous()
+        if a.dim() != 2 or a.shape[1] != cols:
+            raise ValueError(f"expected [batch, {cols}], got {tuple(a.shape)}")
+        return a
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(_lib.pic_mlp_set_params(self.h, _ptr(p, C.c_float), p.size), "pic_mlp_set_params")
+
+    def params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(_lib.pic_mlp_get_params(self.h, _ptr(p, C.c_float), p.size), "pic_mlp_get_params")
+        return p
+
+    def forward(self, x):
+        x = self._dev(x, self.widths[0])
+        y = self._torch.empty((x.shape[0], self.widths[-1]), dtype=self._torch.float32, device="cuda")
+        self._check(_lib.pic_mlp_forward(self.h, x.shape[0], x.data_ptr(), y.data_ptr()), "pic_mlp_forward")
+        self._keep = x
+        return y
+
+    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam update; returns the batch loss as a 1-element CUDA tensor
+        (taken before the update)."""
+        x, t = self._dev(x, self.widths[0]), self._dev(t, self.widths[-1])
+        loss = self._torch.empty(1, dtype=self._torch.float32, device="cuda")
+        self._check(_lib.pic_mlp_train_step(self.h, x.shape[0], x.data_ptr(), t.data_ptr(), lr, beta1, beta2,
+                                            eps, loss.data_ptr()), "pic_mlp_train_step")
+        self._keep = (x, t)
+        return loss
+
+    def grad(self, x, t):
+        x, t = self._dev(x, self.widths[0]), self._dev(t, self.widths[-1])
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = np.empty(1, dtype=np.float32)
+        self._check(_lib.pic_mlp_grad(self.h, x.shape[0], x.data_ptr(), t.data_ptr(), _ptr(g, C.c_float),
+                                      _ptr(loss, C.c_float)), "pic_mlp_grad")
+        return float(loss[0]), g
+
+    def sync(self):
+        self._check(_lib.pic_mlp_sync(self.h), "pic_mlp_sync")

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic_mi355x.so")
-SOURCES = ["pic_push.hip", "pic_field.hip", "pic_sort.hip", "pic_api.hip"]
+SOURCES = ["pic_push.hip", "pic_field.hip", "pic_sort.hip", "pic_api.hip", "mlp.hip"]
+EXPORTING = ("pic_api.hip", "mlp.hip")     # define the extern "C" boundary
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -22,7 +23,7 @@ def build(verbose=False):
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if src == "pic_api.hip":
+        if src in EXPORTING:
             cmd.insert(1, "-fvisibility=default")
             cmd = [c for c in cmd if c != "-fvisibility=hidden"]
         if verbose:

@@ -11,7 +11,8 @@ import paper_2609_17151_amd as P
 def test_header_declares_the_boundary():
     names = P.declared_functions()
     for n in ("pic_init", "pic_load_xsec", "pic_step", "pic_poisson", "pic_diag",
-              "pic_get_particles", "pic_set_particles", "pic_sync", "pic_strerror", "pic_free"):
+              "pic_get_particles", "pic_set_particles", "pic_sync", "pic_strerror", "pic_free",
+              "pic_mlp_create", "pic_mlp_forward", "pic_mlp_train_step", "pic_mlp_grad", "pic_mlp_free"):
         assert n in names
 
 
@@ -36,3 +37,5 @@ def test_no_cpu_fallback():
     import workloads as W
     with pytest.raises(RuntimeError):
         P.Sim(W.langmuir(n_particles=1024))
+    with pytest.raises(RuntimeError):
+        P.MLP(W.WARM_WIDTHS, 16)
