@@ -538,7 +538,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.avg = (double*)A(8ull * B * (S + 2) * nodes_max);
         d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
         d.status = (unsigned long long*)A(8ull * 2 * tiles_max);
-        d.tile_ctr = (unsigned int*)A(4ull * 2);
+        d.tile_ctr = (unsigned int*)A(4ull * 4);
         d.tick = (unsigned long long*)A(8);
         d.ke_part = (double*)A(8ull * tiles_max);
         ctx->poisson_scratch = (double*)A(8ull * 3 * nodes_max);
@@ -570,7 +570,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.status, 0, 8ull * 2 * tiles_max, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * 2, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * 4, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * tiles_max, st) == hipSuccess;
     for (int b = 0; b < B && ok; ++b)
@@ -655,7 +655,7 @@ pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t 
     }
     // a new tile size renumbers tiles: clear every chain word
     rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * 2 * ctx->d.tiles_max));
-    if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * 2));
+    if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * 4));
     ctx->ppt = ppt;
     ctx->threads = threads;
     ctx->sort_every = sort_every;
@@ -996,7 +996,7 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
         return PIC_EHIP;
     // chain words and counters follow the step parity: start them clean
     if (hipMemset(ctx->d.status, 0, 8ull * 2 * ctx->d.tiles_max) != hipSuccess) return PIC_EHIP;
-    if (hipMemset(ctx->d.tile_ctr, 0, 4ull * 2) != hipSuccess) return PIC_EHIP;
+    if (hipMemset(ctx->d.tile_ctr, 0, 4ull * 4) != hipSuccess) return PIC_EHIP;
     if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * kRep * ctx->d.nodes_max, 0,
                   8ull * ctx->S * kRep * ctx->d.nodes_max) != hipSuccess)
         return PIC_EHIP;

@@ -147,7 +147,7 @@ struct DevPtrs {
     double* avg;                 // [B][(S+2)][nodes_max]
     unsigned long long* eepf;    // [B][2][bins]
     unsigned long long* status;  // [2][tiles_max] tile chain words (by parity of the tick)
-    unsigned int* tile_ctr;      // [2] tile tickets
+    unsigned int* tile_ctr;      // [4]: tile tickets by parity, then tiles used by the last step of each parity
     unsigned long long* tick;    // steps taken by the context (parity of the chain words)
     double* ke_part;             // [tiles_max] kinetic-energy partial sums by tile
     int32_t nodes_max, cells_max;

@@ -436,15 +436,19 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
     }
     if (tid < C_N) s_cnt[tid] = 0;
-    // the next step's chain words start cleared
+    // the next step's chain words start cleared: the previous step (the other
+    // parity) wrote only its first tile_ctr[2 + (par ^ 1)] words, and nobody
+    // reads them during this step
     {
         unsigned long long* nxt = d.status + (size_t)(par ^ 1u) * d.tiles_max;
-        for (int64_t t = (int64_t)blockIdx.x * kBS + tid; t < d.tiles_max; t += (int64_t)gridDim.x * kBS)
+        const int64_t hw = d.tile_ctr[2 + (par ^ 1u)];
+        for (int64_t t = (int64_t)blockIdx.x * kBS + tid; t < hw; t += (int64_t)gridDim.x * kBS)
             __hip_atomic_store(&nxt[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (blockIdx.x == 0 && tid == 0) d.tile_ctr[par ^ 1u] = 0u;
     }
     __syncthreads();
     const int32_t NT = s_pref[NS];
+    if (blockIdx.x == 0 && tid == 0) d.tile_ctr[2 + par] = GENERAL ? (unsigned int)NT : 0u;   // read by the next step only
 
     // LDS layout: deposit histogram, [energy histogram, EEPF], E pairs
     const int nn_max = a.nodes_max_dyn;
