@@ -157,7 +157,7 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
                        double* phi_out, double* efield_out);
 
 /* Diagnostic selectors for pic_diag; sizes are for one discharge. */
-#define PIC_DIAG_COUNTS 0       /* int64[4 + 2*S]: step, n_nodes, n_species, flags, then per species count, next_id */
+#define PIC_DIAG_COUNTS 0       /* int64[4 + 2*S]: step, n_nodes, n_species, flags, then per species live count, next_id */
 #define PIC_DIAG_RHO 1          /* double[n_nodes]: charge density */
 #define PIC_DIAG_PHI 2          /* double[n_nodes] */
 #define PIC_DIAG_EFIELD 3       /* double[n_nodes] */
@@ -187,7 +187,11 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
  * pic_get_particles: copy the n (<= cap) particles of one species and
  * discharge in their canonical order (Section 1: a paused run can be resumed):
  * cell index, in-cell offset in [0,1), velocity, id.  *n_out receives the count
- * and *next_id the next id the species will assign.  Synchronous.
+ * and *next_id the next id the species will assign.  The canonical order is
+ * the survivors of every step in their previous order followed by that step's
+ * births in the order of their parents.  When particle arrays are requested
+ * and absorbed particles still leave holes, the context is compacted first
+ * (the order is unchanged).  Synchronous.
  */
 pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap,
                              int32_t* cell, float* off, float* vx, float* vy, float* vz,
@@ -247,11 +251,14 @@ pic_status pic_sort(pic_ctx* ctx);
 pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable);
 
 /* pic_config_tiles: tile shape of the particle kernels (particles per thread
- * 1, 2, 4 or 8; threads per workgroup 64..1024 in steps of 64) and the
- * interval in steps of the sort by cell (0 = never).  Takes effect at the
- * next pic_step. */
+ * 1, 2, 4 or 8; threads per workgroup 256, 512 or 1024; the nearest built
+ * shape is used), the interval in steps of the sort by cell (0 = never) and
+ * the interval in steps of the compaction that removes the holes absorbed
+ * particles leave (1 .. 1024, default 16; bounded runs only).  With graphs,
+ * intervals that divide 32 keep the replayed chunk.  Takes effect at the next
+ * pic_step. */
 pic_status pic_config_tiles(pic_ctx* ctx, int32_t particles_per_thread,
-                            int32_t threads_per_group, int32_t sort_every);
+                            int32_t threads_per_group, int32_t sort_every, int32_t compact_every);
 
 #ifdef __cplusplus
 }

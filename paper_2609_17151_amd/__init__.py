@@ -98,7 +98,7 @@ def load_library():
         "pic_sync": (i32, [P]),
         "pic_strerror": (C.c_char_p, [i32]),
         "pic_free": (None, [P]),
-        "pic_config_tiles": (i32, [P, i32, i32, i32]),
+        "pic_config_tiles": (i32, [P, i32, i32, i32, i32]),
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
@@ -215,8 +215,8 @@ class Sim:
     def sync(self):
         self._check(_lib.pic_sync(self.h), "pic_sync")
 
-    def config_tiles(self, ppt=4, threads=256, sort_every=0):
-        self._check(_lib.pic_config_tiles(self.h, ppt, threads, sort_every), "pic_config_tiles")
+    def config_tiles(self, ppt=4, threads=256, sort_every=0, compact_every=16):
+        self._check(_lib.pic_config_tiles(self.h, ppt, threads, sort_every, compact_every), "pic_config_tiles")
 
     def set_diag(self, enable=True, eepf_emax=64.0):
         self._check(_lib.pic_set_diag(self.h, int(enable), float(eepf_emax)), "pic_set_diag")

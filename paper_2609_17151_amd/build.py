@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic_mi355x.so")
-SOURCES = ["pic_push.hip", "pic_field.hip", "pic_sort.hip", "pic_api.hip", "mlp.hip"]
+SOURCES = ["pic_push.hip", "pic_field.hip", "pic_sort.hip", "pic_compact.hip", "pic_api.hip", "mlp.hip"]
 EXPORTING = ("pic_api.hip", "mlp.hip")     # define the extern "C" boundary
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

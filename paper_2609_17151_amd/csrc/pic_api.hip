@@ -19,7 +19,6 @@ namespace {
 
 constexpr double kBoltzmann = 1.380649e-23;
 constexpr int kTileMax = 4096;     // largest tile (1024 threads x 4): capacities are padded to it
-constexpr int kTileMin = 256;
 
 struct Table {
     int32_t kind;
@@ -52,6 +51,9 @@ struct pic_ctx {
     int n_cu = 256;
     int sort_every = 0;
     int64_t steps_since_sort = 0;
+    int compact_every = 16;              // steps between compactions of the holes
+    int64_t steps_since_compact = 0;
+    int64_t compact_tiles = 0;           // grid of the compaction passes
     int diag = 0;
     double eepf_emax = 64.0;
     double* poisson_scratch = nullptr;   // rho, phi, e: 3 * nodes_max
@@ -495,28 +497,11 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
                 sc.cell[1] = sc.cell[0]; sc.off[1] = sc.off[0]; sc.vx[1] = sc.vx[0];
                 sc.vy[1] = sc.vy[0]; sc.vz[1] = sc.vz[0]; sc.id[1] = sc.id[0];
             }
-            // ionization stages its pairs in species 0 (electrons) and 1 (ions)
-            const int64_t bcap = std::max<int64_t>(16384, cap / 8);
-            sc.bcap = (S > 1 && s <= 1) ? bcap : 0;
-            if (sc.bcap) {
-                sc.bcell = (int32_t*)A(bcap * 4);
-                sc.boff = (float*)A(bcap * 4);
-                sc.bvx = (float*)A(bcap * 4);
-                sc.bvy = (float*)A(bcap * 4);
-                sc.bvz = (float*)A(bcap * 4);
-            }
             fill_push_consts(c, s, sc);
-            // an emitting ion species stages its secondary electrons
-            sc.scap = sc.emits ? std::max<int64_t>(16384, pad_cap(c.species[0].capacity) / 8) : 0;
-            if (sc.scap) {
-                sc.scell = (int32_t*)A(sc.scap * 4);
-                sc.soff = (float*)A(sc.scap * 4);
-                sc.svx = (float*)A(sc.scap * 4);
-                sc.svy = (float*)A(sc.scap * 4);
-                sc.svz = (float*)A(sc.scap * 4);
-            }
         }
     }
+    ctx->compact_tiles = 0;
+    for (int g = 0; g < B * S; ++g) ctx->compact_tiles += compact_tiles_for(pad_cap(ctx->segc[g].cap));
     // tiles are numbered over every segment of the context
     int64_t tiles_max = (int64_t)B * S;
     for (int s = 0; s < S; ++s) tiles_max += ctx->grid_cap[s] / kTileMin;
@@ -537,8 +522,9 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.epair = (float2*)A(8ull * B * cells_max);
         d.avg = (double*)A(8ull * B * (S + 2) * nodes_max);
         d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
-        d.status = (unsigned long long*)A(8ull * 2 * tiles_max);
-        d.tile_ctr = (unsigned int*)A(4ull * 4);
+        d.births = (Birth*)A(sizeof(Birth) * (size_t)tiles_max * kBirthsPerTileMin);
+        d.bcnt = (int32_t*)A(4ull * tiles_max);
+        d.ccnt = (uint32_t*)A(4ull * tiles_max);
         d.tick = (unsigned long long*)A(8);
         d.ke_part = (double*)A(8ull * tiles_max);
         ctx->poisson_scratch = (double*)A(8ull * 3 * nodes_max);
@@ -554,7 +540,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
             const pic_species_cfg& sp = cfg[b].species[s];
             const int64_t n = sp.load == PIC_LOAD_NONE ? 0 : sp.n_init;
             ss[b * S + s].count = n;
-            ss[b * S + s].surv = n;
+            ss[b * S + s].live = n;
             ss[b * S + s].next_id = (uint32_t)n;
         }
     std::vector<DisState> ds(B);
@@ -569,8 +555,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.status, 0, 8ull * 2 * tiles_max, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.tile_ctr, 0, 4ull * 4, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.bcnt, 0, 4ull * tiles_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * tiles_max, st) == hipSuccess;
     for (int b = 0; b < B && ok; ++b)
@@ -634,10 +619,12 @@ pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t k
     return rc;
 }
 
-pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t sort_every)
+pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t sort_every,
+                            int32_t compact_every)
 {
     if (!ctx || (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) ||
-        (threads != 256 && threads != 512 && threads != 1024) || sort_every < 0)
+        (threads != 256 && threads != 512 && threads != 1024) || sort_every < 0 || compact_every < 1 ||
+        compact_every > 1024)
         return PIC_EINVAL;
     pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
     if (rc != PIC_OK) return rc;
@@ -653,13 +640,12 @@ pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t 
         ctx->sort_scratch = dev_alloc(ctx, ctx->sort_scratch_bytes);
         if (!ctx->sort_scratch) return PIC_ENOMEM;
     }
-    // a new tile size renumbers tiles: clear every chain word
-    rc = hip_st(hipMemset(ctx->d.status, 0, 8ull * 2 * ctx->d.tiles_max));
-    if (rc == PIC_OK) rc = hip_st(hipMemset(ctx->d.tile_ctr, 0, 4ull * 4));
     ctx->ppt = ppt;
     ctx->threads = threads;
     ctx->sort_every = sort_every;
     ctx->steps_since_sort = 0;
+    ctx->compact_every = compact_every;
+    ctx->steps_since_compact = 0;
     return rc;
 }
 
@@ -736,7 +722,9 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.fa.mode = kFinStep;
     p.fa.diag = ctx->diag;
     p.fa.only_b = -1;
+    p.fa.births_per_tile = T / kBirthsDiv;
     mix((uint64_t)ctx->sort_every);
+    mix((uint64_t)ctx->compact_every);
     p.key = key;
     return PIC_OK;
 }
@@ -758,6 +746,11 @@ pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st,
         const int pe = prof ? prof_begin(ctx) : -1;
         if (launch_finalize(p.fa, st) != hipSuccess) return PIC_EHIP;
         prof_end(ctx, pe, -1);
+        // the general kernel leaves holes where particles were absorbed
+        if (p.general && ++ctx->steps_since_compact >= ctx->compact_every) {
+            ctx->steps_since_compact = 0;
+            if (launch_compact(ctx->d, ctx->compact_tiles, st) != hipSuccess) return PIC_EHIP;
+        }
         if (prof && ctx->ev_used + 8 > 4096) prof_collect(ctx);
     }
     return PIC_OK;
@@ -778,9 +771,10 @@ pic_status capture_steps(pic_ctx* ctx, const StepPlan& p, int n)
         return PIC_EHIP;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
-    const int64_t saved = ctx->steps_since_sort;
+    const int64_t saved = ctx->steps_since_sort, saved_c = ctx->steps_since_compact;
     const pic_status rc = enqueue_steps(ctx, p, n, ctx->cap_stream, false);
     ctx->steps_since_sort = saved;
+    ctx->steps_since_compact = saved_c;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (rc != PIC_OK || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -809,16 +803,22 @@ pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
     if (rc != PIC_OK) return rc;
     hipStream_t st = ctx->stream;
     int left = n_steps;
-    // direct steps until the sort counter is back at zero, so that every
-    // replay of the captured chunk sorts at the same steps
-    while (ctx->sort_every > 0 && ctx->steps_since_sort != 0 && left > 0) {
+    // direct steps until the sort and compaction counters are back at zero,
+    // so that every replay of the captured chunk sorts and compacts at the
+    // same steps
+    auto aligned = [&]() {
+        return (ctx->sort_every == 0 || ctx->steps_since_sort == 0) &&
+               (!p.general || ctx->steps_since_compact == 0);
+    };
+    const bool divides = (ctx->sort_every == 0 || kGraphSteps % ctx->sort_every == 0) &&
+                         (!p.general || kGraphSteps % ctx->compact_every == 0);
+    while (divides && !aligned() && left > 0) {
         rc = enqueue_steps(ctx, p, 1, st, ctx->prof != 0);
         if (rc != PIC_OK) return rc;
         --left;
     }
-    // replays of a captured chunk; the sort interval must divide the chunk
-    const bool graph_ok = ctx->use_graph && !ctx->prof &&
-                          (ctx->sort_every == 0 || (kGraphSteps % ctx->sort_every == 0 && ctx->steps_since_sort == 0));
+    // replays of a captured chunk; the intervals must divide the chunk
+    const bool graph_ok = ctx->use_graph && !ctx->prof && divides && aligned();
     if (graph_ok && left >= kGraphSteps) {
         if (!ctx->gexec || ctx->g_key != p.key || ctx->g_steps != kGraphSteps) {
             rc = capture_steps(ctx, p, kGraphSteps);
@@ -935,10 +935,18 @@ pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     const int idx = batch * ctx->S + species;
     SegState ss;
     if (hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
-    if (n_out) *n_out = ss.count;
+    if (n_out) *n_out = ss.live;
     if (next_id) *next_id = ss.next_id;
     if (!cell && !off && !vx && !vy && !vz && !id) return PIC_OK;
-    if (cap < ss.count) return PIC_EINVAL;
+    if (cap < ss.live) return PIC_EINVAL;
+    if (ss.count != ss.live) {
+        // holes first: the copy holds the live particles in their order
+        if (launch_compact(ctx->d, ctx->compact_tiles, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess ||
+            hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_EHIP;
+        if (ss.count != ss.live) return PIC_ESTATE;
+    }
     const SegConst& sc = ctx->segc[idx];
     const int p = ss.parity;
     const size_t nb = (size_t)ss.count * 4;
@@ -981,9 +989,9 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
         ok = ok && hipMemcpy(sc.id[p], id, nb, hipMemcpyHostToDevice) == hipSuccess;
     }
     ss.count = n;
-    ss.surv = n;
+    ss.live = n;
+    ss.dead = 0;
     ss.next_id = next_id;
-    ss.births = ss.see_births = 0;
     ss.ntiles = 0;
     ok = ok && hipMemcpy(ctx->d.segs + idx, &ss, sizeof(SegState), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return PIC_EHIP;
@@ -994,9 +1002,6 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     for (auto& x : ds) x.step = step;
     if (hipMemcpy(ctx->d.diss, ds.data(), sizeof(DisState) * ctx->B, hipMemcpyHostToDevice) != hipSuccess)
         return PIC_EHIP;
-    // chain words and counters follow the step parity: start them clean
-    if (hipMemset(ctx->d.status, 0, 8ull * 2 * ctx->d.tiles_max) != hipSuccess) return PIC_EHIP;
-    if (hipMemset(ctx->d.tile_ctr, 0, 4ull * 4) != hipSuccess) return PIC_EHIP;
     if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * kRep * ctx->d.nodes_max, 0,
                   8ull * ctx->S * kRep * ctx->d.nodes_max) != hipSuccess)
         return PIC_EHIP;
@@ -1040,7 +1045,7 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             o[2] = S;
             o[3] = ds.flags;
             for (int s = 0; s < S; ++s) {
-                o[4 + 2 * s] = ss[s].count;
+                o[4 + 2 * s] = ss[s].live;
                 o[5 + 2 * s] = ss[s].next_id;
             }
             break;
@@ -1169,7 +1174,7 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             }
             double qp = dc.rho_bg * dc.L;
             for (int s = 0; s < S; ++s) qp += ctx->segc[(size_t)batch * S + s].q * ctx->segc[(size_t)batch * S + s].w *
-                                              (double)ss[s].count;
+                                              (double)ss[s].live;
             ((double*)out)[0] = q;
             ((double*)out)[1] = qp;
             break;

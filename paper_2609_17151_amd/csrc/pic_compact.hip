@@ -1,0 +1,202 @@
+// Stable compaction of the particle slots: the live particles of every
+// segment that has holes move, in their order, to the front of the other
+// copy, and the copies swap.  Run every few steps (the push leaves holes where
+// particles were absorbed).
+//
+// Tiles of 1024 slots (256 threads, 4 consecutive slots each), numbered over
+// the segments that have holes.  Four plain passes, no waiting between
+// workgroups:
+//   count:   live particles of every tile
+//   scan:    per segment, exclusive scan of its tiles' counts (first slot of
+//            every tile), checked against the segment's live count
+//   scatter: every live particle written to its tile's first slot + its rank
+//            in the tile
+//   finish:  copies swap, count = live
+#include "pic_device.h"
+#include "pic_internal.h"
+#include "pic_kernels.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int kCT = 256;              // threads per compaction tile
+constexpr int kCP = 4;                // slots per thread
+constexpr int kCTile = kCT * kCP;
+
+__device__ __forceinline__ bool has_holes(const DevPtrs& d, int g)
+{
+    return !d.diss[g / d.S].retired && d.segs[g].count != d.segs[g].live;
+}
+
+// first tile of every segment with holes (16 segments per lane at most), in LDS
+__device__ __forceinline__ void hole_prefix(const DevPtrs& d, int32_t* pref)
+{
+    const int NS = d.B * d.S, lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        const int per = (NS + 63) >> 6, g0 = lane * per;
+        int32_t run = 0;
+        for (int j = 0; j < per; ++j) {
+            const int g = g0 + j;
+            if (g < NS) {
+                if (has_holes(d, g)) run += (int32_t)((d.segs[g].count + kCTile - 1) / kCTile);
+                pref[g + 1] = run;
+            }
+        }
+        int32_t incl = run;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int32_t o = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += o;
+        }
+        const int32_t excl = incl - run;
+        if (lane == 0) pref[0] = 0;
+        for (int j = 0; j < per; ++j) {
+            const int g = g0 + j;
+            if (g < NS) pref[g + 1] += excl;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int seg_of_tile(const int32_t* pref, int NS, int32_t t)
+{
+    int lo = 0, hi = NS;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// live flags of this thread's slots
+__device__ __forceinline__ uint32_t live_mask(const int32_t* cell, int64_t base, int64_t n)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < kCP; ++j)
+        if (base + j < n && cell[base + j] >= 0) m |= 1u << j;
+    return m;
+}
+
+// exclusive scan over the workgroup of v; total in *tot
+__device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t* s_w, uint32_t* tot)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan_u32(v);
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    uint32_t wex = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < kCT / 64; ++w) {
+        if (w < wid) wex += s_w[w];
+        t += s_w[w];
+    }
+    *tot = t;
+    return wex + incl - v;
+}
+
+__global__ __launch_bounds__(kCT) void compact_count_kernel(DevPtrs d)
+{
+    __shared__ int32_t pref[kMaxSeg + 1];
+    __shared__ uint32_t s_w[kCT / 64];
+    hole_prefix(d, pref);
+    const int NS = d.B * d.S;
+    const int32_t t = (int32_t)blockIdx.x;
+    if (t >= pref[NS]) return;
+    const int g = seg_of_tile(pref, NS, t);
+    const SegConst& sc = d.segc[g];
+    const SegState& st = d.segs[g];
+    const int64_t base = (int64_t)(t - pref[g]) * kCTile + (int64_t)threadIdx.x * kCP;
+    const uint32_t m = live_mask(sc.cell[st.parity], base, st.count);
+    uint32_t tot;
+    (void)block_excl((uint32_t)__popc(m), s_w, &tot);
+    if (threadIdx.x == 0) d.ccnt[t] = tot;
+}
+
+__global__ __launch_bounds__(1024) void compact_scan_kernel(DevPtrs d)
+{
+    __shared__ int32_t pref[kMaxSeg + 1];
+    __shared__ uint32_t s_w[16];
+    hole_prefix(d, pref);
+    const int g = blockIdx.x;
+    if (g >= d.B * d.S || !has_holes(d, g)) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int32_t t0 = pref[g], nt = pref[g + 1] - pref[g];
+    uint32_t run = 0;
+    for (int32_t r0 = 0; r0 < nt; r0 += 1024) {
+        const int32_t i = r0 + (int32_t)threadIdx.x;
+        const uint32_t v = i < nt ? d.ccnt[t0 + i] : 0u;
+        const uint32_t incl = wave_incl_scan_u32(v);
+        if (lane == 63) s_w[wid] = incl;
+        __syncthreads();
+        uint32_t wex = 0, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wid) wex += s_w[w];
+            tot += s_w[w];
+        }
+        if (i < nt) d.ccnt[t0 + i] = run + wex + incl - v;
+        run += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && (int64_t)run != d.segs[g].live) atomicOr(&d.diss[g / d.S].flags, kFlagCell);
+}
+
+__global__ __launch_bounds__(kCT) void compact_scatter_kernel(DevPtrs d)
+{
+    __shared__ int32_t pref[kMaxSeg + 1];
+    __shared__ uint32_t s_w[kCT / 64];
+    hole_prefix(d, pref);
+    const int NS = d.B * d.S;
+    const int32_t t = (int32_t)blockIdx.x;
+    if (t >= pref[NS]) return;
+    const int g = seg_of_tile(pref, NS, t);
+    const SegConst& sc = d.segc[g];
+    const SegState& st = d.segs[g];
+    const int in = st.parity, out = in ^ 1;
+    const int64_t base = (int64_t)(t - pref[g]) * kCTile + (int64_t)threadIdx.x * kCP;
+    const uint32_t m = live_mask(sc.cell[in], base, st.count);
+    uint32_t tot;
+    int64_t dst = (int64_t)d.ccnt[t] + block_excl((uint32_t)__popc(m), s_w, &tot);
+#pragma unroll
+    for (int j = 0; j < kCP; ++j) {
+        if (!(m & (1u << j))) continue;
+        const int64_t i = base + j;
+        if (dst >= st.live) {                      // cannot happen when the counts agree
+            atomicOr(&d.diss[g / d.S].flags, kFlagCell);
+            break;
+        }
+        sc.cell[out][dst] = sc.cell[in][i];
+        sc.off[out][dst] = sc.off[in][i];
+        sc.vx[out][dst] = sc.vx[in][i];
+        sc.vy[out][dst] = sc.vy[in][i];
+        sc.vz[out][dst] = sc.vz[in][i];
+        sc.id[out][dst] = sc.id[in][i];
+        ++dst;
+    }
+}
+
+__global__ __launch_bounds__(256) void compact_finish_kernel(DevPtrs d)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= d.B * d.S || !has_holes(d, g)) return;
+    SegState& st = d.segs[g];
+    st.parity ^= 1;
+    st.count = st.live;
+}
+
+}  // namespace
+
+hipError_t launch_compact(const DevPtrs& d, int64_t max_tiles, hipStream_t st)
+{
+    const int NS = d.B * d.S;
+    hipLaunchKernelGGL(compact_count_kernel, dim3((unsigned)max_tiles), dim3(kCT), 0, st, d);
+    hipLaunchKernelGGL(compact_scan_kernel, dim3((unsigned)NS), dim3(1024), 0, st, d);
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3((unsigned)max_tiles), dim3(kCT), 0, st, d);
+    hipLaunchKernelGGL(compact_finish_kernel, dim3((unsigned)((NS + 255) / 256)), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+int64_t compact_tiles_for(int64_t padded_count) { return (padded_count + kCTile - 1) / kCTile; }
+
+}  // namespace pic

@@ -1,4 +1,4 @@
-// Field side of the step: births appended after the survivors, the deposit
+// Field side of the step: births appended after the last slot, the deposit
 // turned into densities and charge, the 1D Poisson problem solved in FP64, the
 // field at the nodes (paper Section 1: the field computed on a mesh from the
 // particles' own charge; voltage waveform on the driven electrode), and the
@@ -73,10 +73,10 @@ __device__ __forceinline__ Run wave_run_scan(Run v)
 
 }  // namespace
 
-// One workgroup per discharge, one node per thread (up to four).  The last
-// wave does the particle bookkeeping of the step (births appended after the
-// survivors, counts, ids, parity, kinetic-energy partial sums) while the others
-// turn the deposit into densities and charge.  Poisson: every thread forms
+// One workgroup per discharge, one node per thread (up to four).  All threads
+// first append the step's births; then the last wave does the bookkeeping
+// (counts, ids, kinetic-energy partial sums) while the others turn the
+// deposit into densities and charge.  Poisson: every thread forms
 // the run of its node, a wave-level scan and one 16-entry scan across waves
 // give K[i] and G[i] at every node, and phi follows directly.
 __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
@@ -97,62 +97,93 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     __shared__ double s_w[kWaves];
     __shared__ Run s_run[kWaves * kNodesPerThread];
 
-    if (tid >= kBook) {
-        // ---- bookkeeping wave: every load first, then the updates -------------
-        if (a.mode == kFinStep) {
-            int64_t surv[kMaxSpecies], tfirst[kMaxSpecies], ntl[kMaxSpecies], see[kMaxSpecies];
-            int par[kMaxSpecies];
-            const int64_t n_ion = d.segs[b * S + 0].births;
+    // ---- births, appended after the last slot in the order of their tiles --
+    // (and, inside a tile, of their parents): ionization electrons, then the
+    // secondaries of each emitting ion species in turn; ionization ions in the
+    // order of their electrons.  All threads, one tile per thread per round.
+    __shared__ int64_t s_app[kMaxSpecies], s_want[kMaxSpecies];
+    __shared__ uint32_t s_scan[kWaves];
+    if (a.mode == kFinStep) {
+        const SegState& s0 = d.segs[b * S + 0];
+        const SegConst& c0 = d.segc[b * S + 0];
+        const int64_t slot0 = s0.count, slot1 = S > 1 ? d.segs[b * S + 1].count : 0;
+        const uint32_t id0 = s0.next_id, id1 = S > 1 ? d.segs[b * S + 1].next_id : 0u;
+        const int io0 = s0.parity, io1 = S > 1 ? d.segs[b * S + 1].parity : 0;
+        const int64_t cap0 = c0.cap, cap1 = S > 1 ? d.segc[b * S + 1].cap : 0;
+        int64_t pos0 = slot0, pos1 = slot1;
+        for (int src = 0; src < S; ++src) {
+            const int g = b * S + src;
+            if (src > 0 && !d.segc[g].emits) continue;
+            const int64_t tf = d.segs[g].tile_first, nt = d.segs[g].ntiles;
+            const bool pair = src == 0 && S > 1;            // ionization: an ion with every electron
+            for (int64_t r0 = 0; r0 < nt; r0 += kFT) {
+                const int64_t i = r0 + tid;
+                const uint32_t c = i < nt ? (uint32_t)d.bcnt[tf + i] : 0u;
+                const uint32_t incl = wave_incl_scan_u32(c);
+                if (lane == 63) s_scan[wid] = incl;
+                __syncthreads();
+                uint32_t wex = 0, tot = 0;
 #pragma unroll
-            for (int s = 0; s < kMaxSpecies; ++s) {
-                if (s < S) {
-                    const SegState& st = d.segs[b * S + s];
-                    surv[s] = st.surv;
-                    par[s] = st.parity;
-                    tfirst[s] = st.tile_first;
-                    ntl[s] = st.ntiles;
-                    see[s] = st.see_births;
+                for (int w = 0; w < kWaves; ++w) {
+                    if (w < wid) wex += s_scan[w];
+                    tot += s_scan[w];
                 }
+                const int64_t ex = (int64_t)(wex + incl - c);
+                const Birth* bs = d.births + (size_t)(tf + i) * a.births_per_tile;
+                for (uint32_t k = 0; k < c; ++k) {
+                    const Birth bb = bs[k];
+                    const int64_t e = pos0 + ex + k;
+                    if (e < cap0) {
+                        c0.cell[io0][e] = bb.cell;
+                        c0.off[io0][e] = bb.off;
+                        c0.vx[io0][e] = bb.vx;
+                        c0.vy[io0][e] = bb.vy;
+                        c0.vz[io0][e] = bb.vz;
+                        c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
+                    }
+                    if (pair) {
+                        const SegConst& c1 = d.segc[b * S + 1];
+                        const int64_t q = pos1 + ex + k;
+                        if (q < cap1) {
+                            c1.cell[io1][q] = bb.cell;
+                            c1.off[io1][q] = bb.off;
+                            c1.vx[io1][q] = bb.ivx;
+                            c1.vy[io1][q] = bb.ivy;
+                            c1.vz[io1][q] = bb.ivz;
+                            c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
+                        }
+                    }
+                }
+                pos0 += tot;
+                if (pair) pos1 += tot;
+                __syncthreads();                          // s_scan is reused
             }
+        }
+        if (tid == 0) {
+            for (int s = 0; s < S; ++s) {
+                s_want[s] = s == 0 ? pos0 - slot0 : (s == 1 ? pos1 - slot1 : 0);
+                s_app[s] = 0;
+            }
+            s_app[0] = (pos0 < cap0 ? pos0 : cap0) - slot0;
+            if (S > 1) s_app[1] = (pos1 < cap1 ? pos1 : cap1) - slot1;
+        }
+        __syncthreads();
+    }
+
+    if (tid >= kBook) {
+        // ---- bookkeeping wave: counts, ids, kinetic energy --------------------
+        if (a.mode == kFinStep) {
 #pragma unroll
             for (int s = 0; s < kMaxSpecies; ++s) {
                 if (s >= S) break;
-                const SegConst& sc = d.segc[b * S + s];
                 SegState& st = d.segs[b * S + s];
-                const int out = sc.compacts ? (par[s] ^ 1) : par[s];
-                // births in the order the step made them: ionization pairs, then
-                // (electrons only) the secondaries of each ion species in turn
-                int64_t pos = surv[s], want = 0;
-                const uint32_t id0 = st.next_id;
-                auto append = [&](const int32_t* c_, const float* o_, const float* x_, const float* y_,
-                                  const float* z_, int64_t n, int64_t ncap) {
-                    want += n;
-                    int64_t m = n < ncap ? n : ncap;
-                    if (m > sc.cap - pos) m = sc.cap - pos;
-                    for (int64_t k = lane; k < m; k += 64) {
-                        sc.cell[out][pos + k] = c_[k];
-                        sc.off[out][pos + k] = o_[k];
-                        sc.vx[out][pos + k] = x_[k];
-                        sc.vy[out][pos + k] = y_[k];
-                        sc.vz[out][pos + k] = z_[k];
-                        sc.id[out][pos + k] = id0 + (uint32_t)(pos - surv[s] + k);
-                    }
-                    if (m > 0) pos += m;
-                };
-                if (s <= 1 && S > 1) append(sc.bcell, sc.boff, sc.bvx, sc.bvy, sc.bvz, n_ion, sc.bcap);
-                if (s == 0) {
-                    for (int s2 = 1; s2 < S; ++s2) {
-                        const SegConst& se = d.segc[b * S + s2];
-                        if (se.emits) append(se.scell, se.soff, se.svx, se.svy, se.svz, see[s2], se.scap);
-                    }
-                }
-                const int64_t nmove = pos - surv[s];
+                const int64_t tfirst = st.tile_first, ntl = st.ntiles;
                 if (a.diag) {
-                    // kinetic-energy partials of the step's tiles (runs leave
-                    // zeros elsewhere), fixed order, cleared after reading
-                    double* kpp = d.ke_part + tfirst[s];
+                    // kinetic-energy partials of the step's runs (zeros
+                    // elsewhere), fixed order, cleared after reading
+                    double* kpp = d.ke_part + tfirst;
                     double acc_k = 0.0;
-                    for (int64_t t = lane; t < ntl[s]; t += 64) {
+                    for (int64_t t = lane; t < ntl; t += 64) {
                         acc_k += kpp[t];
                         kpp[t] = 0.0;
                     }
@@ -160,19 +191,18 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     if (lane == 0) st.ke = acc_k;
                 }
                 if (lane == 0) {
-                    if (nmove < want) {
+                    const int64_t app = s_app[s], want = s_want[s];
+                    if (app < want) {
                         atomicOr(&ds.flags, kFlagCapacity);
-                        d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(want - nmove);
+                        d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(want - app);
                     }
-                    st.count = pos;
-                    st.next_id = id0 + (uint32_t)nmove;
-                    st.parity = out;
-                    st.see_births = 0;
-                    st.surv = pos;
+                    st.count += app;
+                    st.live += app - st.dead;
+                    st.dead = 0;
+                    st.next_id += (uint32_t)app;
                     st.ntiles = 0;
                 }
             }
-            if (lane == 0) d.segs[b * S + 0].births = 0;
         }
     } else {
         // ---- densities and charge (into s_a) ------------------------------------

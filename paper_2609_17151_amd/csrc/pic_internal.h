@@ -20,6 +20,9 @@ constexpr int kNodesPerThread = 4;         // kFinThreads * 4 >= nodes of a boun
 constexpr int kEepfBins = PIC_EEPF_BINS;
 constexpr int kMaxSeg = PIC_MAX_BATCH * PIC_MAX_SPECIES;   // (discharge, species) segments of a context
 constexpr int64_t kMaxTiles = 1ll << 30;                    // tile numbers fit in int32
+constexpr int kTileMin = 256;                               // smallest tile of the push (particles)
+constexpr int kBirthsDiv = 16;                              // a tile stages up to T / 16 births per step
+constexpr int kBirthsPerTileMin = kTileMin / kBirthsDiv;
 
 // latched device flags
 constexpr uint32_t kFlagCapacity = 1u << 0;
@@ -40,6 +43,14 @@ enum { C_ABS0, C_ABS1, C_SEE0, C_SEE1, C_CAND, C_NULL, C_VIOL, C_DROP, C_COLL, C
 // the order in which tiles add them.
 constexpr double kDepScale = 4294967296.0;
 
+// a staged birth: the electron (ionization or secondary) and, for
+// ionization, the velocity of the ion born with it
+struct Birth {
+    int32_t cell;
+    float off, vx, vy, vz;
+    float ivx, ivy, ivz;
+};
+
 struct SegConst {
     // particle storage, [0] and [1] are the two copies (same pointer when the
     // segment never compacts)
@@ -49,21 +60,7 @@ struct SegConst {
     float* vy[2];
     float* vz[2];
     uint32_t* id[2];
-    // staging of the particles born into this segment by ionization, in the
-    // order of the ionizing electrons (ids are given when they are appended)
-    int32_t* bcell;
-    float* boff;
-    float* bvx;
-    float* bvy;
-    float* bvz;
-    // staging of the secondary electrons this (ion) segment emits, in the order
-    // of the absorbed ions (appended to the electrons after the ionization births)
-    int32_t* scell;
-    float* soff;
-    float* svx;
-    float* svy;
-    float* svz;
-    int64_t cap, bcap, scap;
+    int64_t cap;
     // push
     float qmh;              // (q/m) dt/2
     float tv[3], sv[3];     // Boris rotation vectors t and s = 2t/(1+t^2)
@@ -106,12 +103,13 @@ struct DisConst {
     uint32_t key0, key1;
 };
 
-// mutable, one per segment
+// mutable, one per segment.  Slots [0, count) hold the particles in their
+// canonical order, with holes (cell < 0) where particles were absorbed since
+// the last compaction; births are appended after the last slot.
 struct SegState {
-    int64_t count;          // particles held
-    int64_t surv;           // survivors of the current step
-    int64_t births;         // species 0: ionization events of the step (one electron and one ion each)
-    int64_t see_births;     // ion species: secondary electrons emitted this step
+    int64_t count;          // slots in use (live particles and holes)
+    int64_t live;           // live particles
+    int64_t dead;           // particles absorbed in the current step
     int64_t tile_first, ntiles;  // tile range of the current step (tiles are numbered over all segments)
     uint32_t next_id;
     int32_t parity;         // which copy holds the particles
@@ -146,9 +144,10 @@ struct DevPtrs {
     float2* epair;               // [B][cells_max] (E[c], E[c+1]) for the gather
     double* avg;                 // [B][(S+2)][nodes_max]
     unsigned long long* eepf;    // [B][2][bins]
-    unsigned long long* status;  // [2][tiles_max] tile chain words (by parity of the tick)
-    unsigned int* tile_ctr;      // [4]: tile tickets by parity, then tiles used by the last step of each parity
-    unsigned long long* tick;    // steps taken by the context (parity of the chain words)
+    Birth* births;               // [tiles_max * kBirthsPerTileMin] births staged by tile, in particle order
+    int32_t* bcnt;               // [tiles_max] births staged by each tile
+    unsigned long long* tick;    // steps taken by the context
+    uint32_t* ccnt;              // [tiles_max] compaction: live particles of each tile, then their first slot
     double* ke_part;             // [tiles_max] kinetic-energy partial sums by tile
     int32_t nodes_max, cells_max;
     int64_t tiles_max;

@@ -24,6 +24,7 @@ struct FinArgs {
     int32_t mode;
     int32_t diag;
     int32_t only_b;               // -1: all discharges (grid = B), else this one (grid = 1)
+    int32_t births_per_tile;      // staging slots of a push tile
     double t_ext;
     const double* rho_ext;
     double* phi_out;
@@ -48,6 +49,8 @@ hipError_t launch_deposit(const DevPtrs& d, int only_b, int64_t max_count, hipSt
 hipError_t launch_halfstep(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);
 hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_tiles, void* scratch, size_t scratch_bytes,
                        hipStream_t st);
+hipError_t launch_compact(const DevPtrs& d, int64_t max_tiles, hipStream_t st);
+int64_t compact_tiles_for(int64_t padded_count);
 size_t sort_scratch_bytes(int64_t max_tiles, int B, int cells_max);
 int64_t sort_tiles_for(int64_t padded_count);
 size_t push_lds_bytes(int n_nodes, int n_cells, int diag);

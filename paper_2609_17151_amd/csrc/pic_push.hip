@@ -3,25 +3,23 @@
 // Boris pusher, walls and secondary emission, null-collision Monte Carlo with
 // tabulated cross sections; the charge of the particles deposited on the mesh).
 //
-// Work is cut into tiles of T = threads * PPT consecutive particles of one
-// (discharge, species) segment; tiles are numbered over all segments,
-// discharge-major, so one launch covers the whole step and no species waits
-// for another.  Each thread owns PPT consecutive particles and moves them with
-// 16-byte vector loads.  A workgroup is persistent over many tiles: it stages
-// the (E[c], E[c+1]) pairs of a discharge in LDS once per run of tiles of that
+// Work is cut into tiles of T = threads * PPT consecutive particle slots of
+// one (discharge, species) segment; tiles are numbered over all segments,
+// discharge-major, and every workgroup takes a fixed contiguous range of
+// tiles, so one launch covers the whole step with no waiting between
+// workgroups.  Each thread owns PPT consecutive slots and moves them with
+// 16-byte vector loads and stores, in place.  A workgroup stages the
+// (E[c], E[c+1]) pairs of a discharge in LDS once per run of tiles of that
 // discharge, and zeroes and flushes its deposit histogram once per run of
 // tiles of one segment.
 //
-// Two modes.  Streaming (nothing can leave or be born: periodic, no
-// collisions): each workgroup takes a fixed contiguous range of tiles and
-// writes particles back in place.  General: tiles are handed out in launch
-// order by an atomic ticket; survivors are compacted into the other copy in
-// their original order and births are staged in canonical order, through a
-// block prefix sum plus a decoupled look-back across the tiles of the segment
-// (every tile waits only for tiles of its segment already handed out, so it
-// cannot deadlock; the wait is bounded and a stall is latched).  Births are
-// staged per segment (ionization pairs by the electrons, secondary electrons
-// by each ion species); the finalize appends them and gives their ids.
+// Absorbed particles leave holes (cell = -1) that later steps skip; a stable
+// compaction every few steps removes them.  Holes do not change the order of
+// the live particles, and births are appended after the last slot in the
+// order of their parents, so the particle order after a compaction is the
+// order that compacting every step would give.  Births are staged per tile in
+// particle order (a block scan of the birth flags) and appended by the
+// finalize in tile order, which also gives their ids.
 //
 // Per particle: gather E by linear weighting, Boris push in the imposed B,
 // cell-relative move in FP32, periodic wrap or absorption (with secondary
@@ -29,6 +27,9 @@
 // collision.  Deposition: LDS histogram in 64-bit fixed point flushed with
 // integer atomics, so sums are exact and independent of the order of tiles and
 // runs are bit-reproducible without global float atomics.
+//
+// Streaming instances (GENERAL = false) serve periodic runs without
+// collisions, where nothing can be absorbed or born: no ids, holes or births.
 #include "pic_device.h"
 #include "pic_internal.h"
 #include "pic_kernels.h"
@@ -36,20 +37,6 @@
 namespace pic {
 
 namespace {
-
-constexpr uint64_t kSurvMask = (1ull << 38) - 1;
-constexpr int kBirthShift = 38;
-constexpr uint64_t kBirthMask = (1ull << 24) - 1;
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagInc = 2ull << 62;
-constexpr uint32_t kSpinLimit = 1u << 20;
-
-
-struct Birth {
-    int32_t cell;
-    float off, vx, vy, vz;   // the electron (ionization or secondary)
-    float ivx, ivy, ivz;     // the ion born with it (ionization only)
-};
 
 __device__ __forceinline__ void lds_deposit(unsigned long long* hist, int c, float f, int n_cells,
                                             int periodic)
@@ -393,21 +380,16 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 {
     constexpr int kBS = BS;
     constexpr int T = kBS * PPT;
+    constexpr int kBirthsPerTile = T / kBirthsDiv;
     const DevPtrs& d = a.d;
     const int S = d.S, NS = d.B * d.S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_pref[kMaxSeg + 1];   // first tile of every segment (discharge-major)
-    __shared__ int32_t s_tile;
     __shared__ uint32_t s_wave[kBS / 64];
-    __shared__ uint64_t s_excl_surv;
-    __shared__ uint32_t s_excl_birth;
     __shared__ unsigned int s_cnt[C_N];
     __shared__ float s_red[kBS / 64];
-
-    const uint32_t par = (uint32_t)(*d.tick & 1u);
-    unsigned long long* status = d.status + (size_t)par * d.tiles_max;
 
     // ---- tiles per segment, prefix over the segments (up to 16 per lane) -----
     if (wid == 0) {
@@ -436,19 +418,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
     }
     if (tid < C_N) s_cnt[tid] = 0;
-    // the next step's chain words start cleared: the previous step (the other
-    // parity) wrote only its first tile_ctr[2 + (par ^ 1)] words, and nobody
-    // reads them during this step
-    {
-        unsigned long long* nxt = d.status + (size_t)(par ^ 1u) * d.tiles_max;
-        const int64_t hw = d.tile_ctr[2 + (par ^ 1u)];
-        for (int64_t t = (int64_t)blockIdx.x * kBS + tid; t < hw; t += (int64_t)gridDim.x * kBS)
-            __hip_atomic_store(&nxt[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (blockIdx.x == 0 && tid == 0) d.tile_ctr[par ^ 1u] = 0u;
-    }
     __syncthreads();
     const int32_t NT = s_pref[NS];
-    if (blockIdx.x == 0 && tid == 0) d.tile_ctr[2 + par] = GENERAL ? (unsigned int)NT : 0u;   // read by the next step only
 
     // LDS layout: deposit histogram, [energy histogram, EEPF], E pairs
     const int nn_max = a.nodes_max_dyn;
@@ -460,14 +431,13 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     int cur_g = -1, cur_b = -1;
     int32_t run_first = 0;
     float ke_run = 0.0f;
-    int32_t t_next = 0, t_end = 0;
-    if (!GENERAL) {
-        const int32_t chunk = (NT + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
-        t_next = (int32_t)blockIdx.x * chunk;
-        t_end = t_next + chunk < NT ? t_next + chunk : NT;
-    }
+    // a fixed contiguous range of tiles per workgroup
+    const int32_t chunk = (NT + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+    const int32_t t_begin = (int32_t)blockIdx.x * chunk;
+    const int32_t t_end = t_begin + chunk < NT ? t_begin + chunk : NT;
 
-    // flush the run of tiles of segment cg: deposit, diagnostics, counters
+    // flush the run of tiles of segment cg: deposit, diagnostics, counters,
+    // kinetic energy (ranges are fixed, so the grouping of the sums is too)
     auto flush = [&](int cg) {
         __syncthreads();
         const int cb = cg / S, cs = cg - cb * S;
@@ -493,34 +463,21 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         unsigned long long* cnt = d.cnt + ((size_t)cg * kRep + rep) * C_N;
         if (tid < C_N) {
             const unsigned int v = s_cnt[tid];
-            if (v) atomicAdd(&cnt[tid], (unsigned long long)v);
+            if (v) {
+                atomicAdd(&cnt[tid], (unsigned long long)v);
+                if (tid == C_ABS0 || tid == C_ABS1)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[cg].dead), (unsigned long long)v);
+            }
             s_cnt[tid] = 0;
         }
-        if (!GENERAL && a.diag) {
-            // kinetic energy of the run (ranges are fixed, so the grouping is too)
+        if (a.diag) {
             const double kt = block_sum_f32<BS>(ke_run, s_red);
             if (tid == 0) d.ke_part[run_first] = 0.5 * d.segc[cg].mw_half * kt;
             ke_run = 0.0f;
         }
     };
 
-    for (;;) {
-        int32_t t;
-        if (GENERAL) {
-            if (tid == 0) {
-                // a plain read first: surplus workgroups leave without
-                // contending on the ticket counter
-                unsigned int* ctr = &d.tile_ctr[par];
-                const unsigned int seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_tile = (int32_t)seen >= NT ? NT : (int32_t)atomicAdd(ctr, 1u);
-            }
-            __syncthreads();
-            t = s_tile;
-        } else {
-            t = t_next++;
-            if (t >= t_end) break;
-        }
-        if (t >= NT) break;
+    for (int32_t t = t_begin; t < t_end; ++t) {
         // segment of tile t: the last g with s_pref[g] <= t
         int lo = 0, hi = NS;
         while (hi - lo > 1) {
@@ -556,258 +513,116 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         const int nc = dc.n_cells;
         const int periodic = dc.bc == PIC_BC_PERIODIC;
         const uint32_t step = (uint32_t)d.diss[b].step;
-        const int in = st.parity;
-        const int out = sc.compacts ? (in ^ 1) : in;
+        const int io = st.parity;                 // updated in place
         const int64_t base = (int64_t)tin * T + (int64_t)tid * PPT;
 
         int32_t cell[PPT];
         float off[PPT], vx[PPT], vy[PPT], vz[PPT];
         uint32_t pid[PPT];
-        vload<PPT, int4>(sc.cell[in] + base, cell);
-        vload<PPT, float4>(sc.off[in] + base, off);
-        vload<PPT, float4>(sc.vx[in] + base, vx);
-        vload<PPT, float4>(sc.vy[in] + base, vy);
-        vload<PPT, float4>(sc.vz[in] + base, vz);
+        vload<PPT, int4>(sc.cell[io] + base, cell);
+        vload<PPT, float4>(sc.off[io] + base, off);
+        vload<PPT, float4>(sc.vx[io] + base, vx);
+        vload<PPT, float4>(sc.vy[io] + base, vy);
+        vload<PPT, float4>(sc.vz[io] + base, vz);
         if (GENERAL) {
-            vload<PPT, uint4>(sc.id[in] + base, pid);
+            vload<PPT, uint4>(sc.id[io] + base, pid);
         } else {
 #pragma unroll
             for (int j = 0; j < PPT; ++j) pid[j] = 0u;
         }
 
-        uint32_t alive = 0, born = 0;
+        uint32_t born = 0;
         Birth bt[GENERAL ? PPT : 1];
         float ke_tile = 0.0f;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (base + j >= n) continue;
+            if (GENERAL && cell[j] < 0) continue;          // a hole: absorbed earlier
             bool bj = false;
             Birth& bb = bt[GENERAL ? j : 0];
             const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, cell[j], off[j], vx[j], vy[j],
                                                vz[j], pid[j], ke_tile, bj, bb);
             if (keep) {
-                alive |= 1u << j;
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
                 if (a.diag && s == 0)
                     electron_diag(sc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
+            } else {
+                cell[j] = -1;                              // absorbed: leaves a hole
             }
             if (GENERAL && bj) born |= 1u << j;
         }
+        ke_run += ke_tile;
 
-        if (!GENERAL) {
-            ke_run += ke_tile;
-            // in place; every particle stays at its index
-            if (base + PPT <= n) {
-                vstore<PPT, int4>(sc.cell[out] + base, cell);
-                vstore<PPT, float4>(sc.off[out] + base, off);
-                vstore<PPT, float4>(sc.vx[out] + base, vx);
-                vstore<PPT, float4>(sc.vy[out] + base, vy);
-                vstore<PPT, float4>(sc.vz[out] + base, vz);
-            } else {
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (base + j < n) {
-                        sc.cell[out][base + j] = cell[j];
-                        sc.off[out][base + j] = off[j];
-                        sc.vx[out][base + j] = vx[j];
-                        sc.vy[out][base + j] = vy[j];
-                        sc.vz[out][base + j] = vz[j];
-                    }
-                }
-            }
-            if (tid == 0 && tin == ntiles - 1) {
-                st.tile_first = tile_first;
-                st.ntiles = ntiles;
-                st.surv = n;
-            }
-            continue;
-        }
-
-        // ---- general: births deposit, block scan, look-back, writes ----------
-        if (born) {
+        if (GENERAL) {
+            // births: deposited now, staged in particle order for the finalize
             const int rep = blockIdx.x % kRep;
+            if (born) {
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                if (!(born & (1u << j))) continue;
-                if (s == 0) {   // the electron into this histogram, the ion into species 1
-                    lds_deposit(hist, bt[j].cell, bt[j].off, nc, periodic);
-                    global_deposit(d.acc + (((size_t)b * S + 1) * kRep + rep) * d.nodes_max, bt[j].cell,
-                                   bt[j].off, nc, periodic);
-                } else {        // a secondary electron into species 0
-                    global_deposit(d.acc + (((size_t)b * S + 0) * kRep + rep) * d.nodes_max, bt[j].cell,
-                                   bt[j].off, nc, periodic);
+                for (int j = 0; j < PPT; ++j) {
+                    if (!(born & (1u << j))) continue;
+                    if (s == 0) {   // the electron into this histogram, the ion into species 1
+                        lds_deposit(hist, bt[j].cell, bt[j].off, nc, periodic);
+                        global_deposit(d.acc + (((size_t)b * S + 1) * kRep + rep) * d.nodes_max, bt[j].cell,
+                                       bt[j].off, nc, periodic);
+                    } else {        // a secondary electron into species 0
+                        global_deposit(d.acc + (((size_t)b * S + 0) * kRep + rep) * d.nodes_max, bt[j].cell,
+                                       bt[j].off, nc, periodic);
+                    }
+                }
+            }
+            const uint32_t nb = (uint32_t)__popc(born);
+            const uint32_t incl = wave_incl_scan_u32(nb);
+            if (lane == 63) s_wave[wid] = incl;
+            __syncthreads();
+            uint32_t wexcl = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < kBS / 64; ++w) {
+                if (w < wid) wexcl += s_wave[w];
+                tot += s_wave[w];
+            }
+            if (born) {
+                Birth* dst = d.births + (size_t)t * kBirthsPerTile;
+                uint32_t k = wexcl + incl - nb;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    if (!(born & (1u << j))) continue;
+                    if (k < (uint32_t)kBirthsPerTile) dst[k] = bt[j];
+                    ++k;
+                }
+            }
+            if (tid == 0) {
+                d.bcnt[t] = (int32_t)(tot < (uint32_t)kBirthsPerTile ? tot : (uint32_t)kBirthsPerTile);
+                if (tot > (uint32_t)kBirthsPerTile) {
+                    atomicOr(&d.diss[b].flags, kFlagCapacity);
+                    atomicAdd(&s_cnt[C_DROP], tot - (uint32_t)kBirthsPerTile);
                 }
             }
         }
-        const uint32_t packed = (uint32_t)__popc(alive) | ((uint32_t)__popc(born) << 16);
-        const uint32_t incl = wave_incl_scan_u32(packed);
-        if (lane == 63) s_wave[wid] = incl;
-        const float kw = wave_sum_f32(ke_tile);
-        if (lane == 0) s_red[wid] = kw;
-        __syncthreads();
-        uint32_t wexcl = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < kBS / 64; ++w) {
-            if (w < wid) wexcl += s_wave[w];
-            tot += s_wave[w];
-        }
-        const uint32_t texcl = wexcl + incl - packed;
-        const uint32_t agg_surv = tot & 0xFFFFu, agg_birth = tot >> 16;
-        if (tid == 0 && a.diag) {
-            double kt = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBS / 64; ++w) kt += (double)s_red[w];
-            d.ke_part[t] = 0.5 * sc.mw_half * kt;
-        }
-        uint64_t excl_surv = 0;
-        uint32_t excl_birth = 0;
-        if (wid == 0) {
-            const uint64_t agg_word = (uint64_t)agg_surv | ((uint64_t)agg_birth << kBirthShift);
-            if (tin == 0) {
-                if (lane == 0)
-                    __hip_atomic_store(&status[t], agg_word | kFlagInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                if (lane == 0)
-                    __hip_atomic_store(&status[t], agg_word | kFlagAgg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                int32_t j0 = t - 1;
-                uint64_t sum_s = 0, sum_b = 0;
-                bool done = false;
-                uint32_t spins = 0;
-                while (!done) {
-                    const int32_t jj = j0 - lane;
-                    uint64_t w = kFlagInc;        // before the segment start: inclusive zero
-                    if (jj >= tile_first)
-                        w = __hip_atomic_load(&status[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    while (__any((w >> 62) == 0)) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if ((w >> 62) == 0 && jj >= tile_first)
-                            w = __hip_atomic_load(&status[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (++spins > kSpinLimit) {
-                            if (lane == 0) atomicOr(&d.diss[b].flags, kFlagStall);
-                            if ((w >> 62) == 0) w = kFlagInc;
-                        }
-                    }
-                    const uint64_t incm = __ballot((w >> 62) == 2);
-                    int last = 63;
-                    if (incm) {
-                        last = __ffsll((unsigned long long)incm) - 1;
-                        done = true;
-                    }
-                    uint64_t vs_ = (lane <= last) ? (w & kSurvMask) : 0;
-                    uint64_t vb_ = (lane <= last) ? ((w >> kBirthShift) & kBirthMask) : 0;
-#pragma unroll
-                    for (int dd = 32; dd >= 1; dd >>= 1) {
-                        vs_ += __shfl_xor(vs_, dd, 64);
-                        vb_ += __shfl_xor(vb_, dd, 64);
-                    }
-                    sum_s += vs_;
-                    sum_b += vb_;
-                    j0 -= 64;
-                }
-                excl_surv = sum_s;
-                excl_birth = (uint32_t)sum_b;
-                if (lane == 0) {
-                    const uint64_t inc = ((excl_surv + agg_surv) & kSurvMask) |
-                                         (((uint64_t)(excl_birth + agg_birth) & kBirthMask) << kBirthShift);
-                    __hip_atomic_store(&status[t], inc | kFlagInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            if (lane == 0) {
-                s_excl_surv = excl_surv;
-                s_excl_birth = excl_birth;
-            }
-        }
-        __syncthreads();
-        excl_surv = s_excl_surv;
-        excl_birth = s_excl_birth;
 
-        if (!sc.compacts) {
-            if (base + PPT <= n) {
-                vstore<PPT, int4>(sc.cell[out] + base, cell);
-                vstore<PPT, float4>(sc.off[out] + base, off);
-                vstore<PPT, float4>(sc.vx[out] + base, vx);
-                vstore<PPT, float4>(sc.vy[out] + base, vy);
-                vstore<PPT, float4>(sc.vz[out] + base, vz);
-            } else {
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (base + j < n) {
-                        sc.cell[out][base + j] = cell[j];
-                        sc.off[out][base + j] = off[j];
-                        sc.vx[out][base + j] = vx[j];
-                        sc.vy[out][base + j] = vy[j];
-                        sc.vz[out][base + j] = vz[j];
-                    }
-                }
-            }
+        // in place; every particle keeps its slot
+        if (base + PPT <= n) {
+            vstore<PPT, int4>(sc.cell[io] + base, cell);
+            vstore<PPT, float4>(sc.off[io] + base, off);
+            vstore<PPT, float4>(sc.vx[io] + base, vx);
+            vstore<PPT, float4>(sc.vy[io] + base, vy);
+            vstore<PPT, float4>(sc.vz[io] + base, vz);
         } else {
-            uint64_t pos = excl_surv + (texcl & 0xFFFFu);
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
-                if (alive & (1u << j)) {
-                    sc.cell[out][pos] = cell[j];
-                    sc.off[out][pos] = off[j];
-                    sc.vx[out][pos] = vx[j];
-                    sc.vy[out][pos] = vy[j];
-                    sc.vz[out][pos] = vz[j];
-                    sc.id[out][pos] = pid[j];
-                    ++pos;
+                if (base + j < n) {
+                    sc.cell[io][base + j] = cell[j];
+                    sc.off[io][base + j] = off[j];
+                    sc.vx[io][base + j] = vx[j];
+                    sc.vy[io][base + j] = vy[j];
+                    sc.vz[io][base + j] = vz[j];
                 }
             }
         }
-        if (born) {
-            // electron births of species 0 are ionization pairs (electron into
-            // this segment's staging, ion into species 1's); an ion species'
-            // births are secondary electrons, staged in its own segment
-            uint64_t k = (uint64_t)excl_birth + (texcl >> 16);
-            if (s == 0) {
-                const SegConst& si = d.segc[b * S + 1];
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (!(born & (1u << j))) continue;
-                    if ((int64_t)k < sc.bcap && (int64_t)k < si.bcap) {
-                        sc.bcell[k] = bt[j].cell;
-                        sc.boff[k] = bt[j].off;
-                        sc.bvx[k] = bt[j].vx;
-                        sc.bvy[k] = bt[j].vy;
-                        sc.bvz[k] = bt[j].vz;
-                        si.bcell[k] = bt[j].cell;
-                        si.boff[k] = bt[j].off;
-                        si.bvx[k] = bt[j].ivx;
-                        si.bvy[k] = bt[j].ivy;
-                        si.bvz[k] = bt[j].ivz;
-                    } else {
-                        atomicOr(&d.diss[b].flags, kFlagCapacity);
-                    }
-                    ++k;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (!(born & (1u << j))) continue;
-                    if ((int64_t)k < sc.scap) {
-                        sc.scell[k] = bt[j].cell;
-                        sc.soff[k] = bt[j].off;
-                        sc.svx[k] = bt[j].vx;
-                        sc.svy[k] = bt[j].vy;
-                        sc.svz[k] = bt[j].vz;
-                    } else {
-                        atomicOr(&d.diss[b].flags, kFlagCapacity);
-                    }
-                    ++k;
-                }
-            }
-        }
-        // the last tile of the segment records the step's totals
         if (tid == 0 && tin == ntiles - 1) {
             st.tile_first = tile_first;
             st.ntiles = ntiles;
-            st.surv = sc.compacts ? (int64_t)(excl_surv + agg_surv) : n;
-            const int64_t nb = (int64_t)excl_birth + agg_birth;
-            if (s == 0) st.births = nb;      // ionization pairs
-            else st.see_births = nb;         // secondaries (read by the finalize only)
         }
-        __syncthreads();                     // s_tile, s_wave and s_red are reused
+        if (GENERAL) __syncthreads();             // s_wave is reused
     }
     if (cur_g >= 0) flush(cur_g);
 }

@@ -16,6 +16,7 @@
 //            into the other copy; then the copies swap.
 // Every step is a plain pass with no waiting between workgroups; particles
 // with equal cells keep their order, so the result equals a stable sort.
+// Holes (slots of absorbed particles, cell < 0) are dropped.
 #include "pic_device.h"
 #include "pic_internal.h"
 #include "pic_kernels.h"
@@ -100,8 +101,9 @@ __device__ __forceinline__ void wave_rank(const int32_t* cell, int64_t wbase, in
 #pragma unroll
     for (int r = 0; r < kSR; ++r) {
         const int64_t idx = wbase + r * 64 + lane;
-        const bool valid = idx < n;
-        const int32_t k = valid ? cell[idx] : 0;
+        const int32_t kc = idx < n ? cell[idx] : -1;
+        const bool valid = kc >= 0;                // holes (absorbed particles) are dropped
+        const int32_t k = valid ? kc : 0;
         const uint64_t pe = peers_of((uint32_t)k, valid, bits);
         const uint32_t before = (uint32_t)__popcll(pe & lt);
         uint32_t cur = 0;
@@ -283,7 +285,11 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(SortArgs a)
 __global__ void sort_swap_kernel(DevPtrs d, int s)
 {
     const int b = threadIdx.x;
-    if (b < d.B) d.segs[b * d.S + s].parity ^= 1;
+    if (b < d.B && !d.diss[b].retired) {
+        SegState& st = d.segs[b * d.S + s];
+        st.parity ^= 1;
+        st.count = st.live;                        // the holes are gone
+    }
 }
 
 hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_tiles, void* scratch, size_t scratch_bytes,
