@@ -749,7 +749,7 @@ pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st,
         // the general kernel leaves holes where particles were absorbed
         if (p.general && ++ctx->steps_since_compact >= ctx->compact_every) {
             ctx->steps_since_compact = 0;
-            if (launch_compact(ctx->d, ctx->compact_tiles, st) != hipSuccess) return PIC_EHIP;
+            if (launch_compact(ctx->d, ctx->compact_tiles, ctx->n_cu, st) != hipSuccess) return PIC_EHIP;
         }
         if (prof && ctx->ev_used + 8 > 4096) prof_collect(ctx);
     }
@@ -941,7 +941,7 @@ pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     if (cap < ss.live) return PIC_EINVAL;
     if (ss.count != ss.live) {
         // holes first: the copy holds the live particles in their order
-        if (launch_compact(ctx->d, ctx->compact_tiles, ctx->stream) != hipSuccess ||
+        if (launch_compact(ctx->d, ctx->compact_tiles, ctx->n_cu, ctx->stream) != hipSuccess ||
             hipStreamSynchronize(ctx->stream) != hipSuccess ||
             hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess)
             return PIC_EHIP;

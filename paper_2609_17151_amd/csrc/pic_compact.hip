@@ -5,16 +5,18 @@
 //
 // Tiles of 1024 slots (256 threads, 4 consecutive slots each), numbered over
 // the segments that have holes.  Four plain passes, no waiting between
-// workgroups:
+// workgroups (the two tile passes run on persistent grids):
 //   count:   live particles of every tile
 //   scan:    per segment, exclusive scan of its tiles' counts (first slot of
 //            every tile), checked against the segment's live count
 //   scatter: every live particle written to its tile's first slot + its rank
-//            in the tile
+//            in the tile (four rounds of 256 neighbouring slots)
 //   finish:  copies swap, count = live
 #include "pic_device.h"
 #include "pic_internal.h"
 #include "pic_kernels.h"
+
+#include <algorithm>
 
 namespace pic {
 
@@ -102,16 +104,17 @@ __global__ __launch_bounds__(kCT) void compact_count_kernel(DevPtrs d)
     __shared__ uint32_t s_w[kCT / 64];
     hole_prefix(d, pref);
     const int NS = d.B * d.S;
-    const int32_t t = (int32_t)blockIdx.x;
-    if (t >= pref[NS]) return;
-    const int g = seg_of_tile(pref, NS, t);
-    const SegConst& sc = d.segc[g];
-    const SegState& st = d.segs[g];
-    const int64_t base = (int64_t)(t - pref[g]) * kCTile + (int64_t)threadIdx.x * kCP;
-    const uint32_t m = live_mask(sc.cell[st.parity], base, st.count);
-    uint32_t tot;
-    (void)block_excl((uint32_t)__popc(m), s_w, &tot);
-    if (threadIdx.x == 0) d.ccnt[t] = tot;
+    for (int32_t t = (int32_t)blockIdx.x; t < pref[NS]; t += (int32_t)gridDim.x) {
+        const int g = seg_of_tile(pref, NS, t);
+        const SegConst& sc = d.segc[g];
+        const SegState& st = d.segs[g];
+        const int64_t base = (int64_t)(t - pref[g]) * kCTile + (int64_t)threadIdx.x * kCP;
+        const uint32_t m = live_mask(sc.cell[st.parity], base, st.count);
+        uint32_t tot;
+        (void)block_excl((uint32_t)__popc(m), s_w, &tot);
+        if (threadIdx.x == 0) d.ccnt[t] = tot;
+        __syncthreads();                           // s_w is reused
+    }
 }
 
 __global__ __launch_bounds__(1024) void compact_scan_kernel(DevPtrs d)
@@ -145,34 +148,39 @@ __global__ __launch_bounds__(1024) void compact_scan_kernel(DevPtrs d)
 __global__ __launch_bounds__(kCT) void compact_scatter_kernel(DevPtrs d)
 {
     __shared__ int32_t pref[kMaxSeg + 1];
-    __shared__ uint32_t s_w[kCT / 64];
+    __shared__ uint32_t s_w[2][kCT / 64];
     hole_prefix(d, pref);
     const int NS = d.B * d.S;
-    const int32_t t = (int32_t)blockIdx.x;
-    if (t >= pref[NS]) return;
-    const int g = seg_of_tile(pref, NS, t);
-    const SegConst& sc = d.segc[g];
-    const SegState& st = d.segs[g];
-    const int in = st.parity, out = in ^ 1;
-    const int64_t base = (int64_t)(t - pref[g]) * kCTile + (int64_t)threadIdx.x * kCP;
-    const uint32_t m = live_mask(sc.cell[in], base, st.count);
-    uint32_t tot;
-    int64_t dst = (int64_t)d.ccnt[t] + block_excl((uint32_t)__popc(m), s_w, &tot);
+    for (int32_t t = (int32_t)blockIdx.x; t < pref[NS]; t += (int32_t)gridDim.x) {
+        const int g = seg_of_tile(pref, NS, t);
+        const SegConst& sc = d.segc[g];
+        const SegState& st = d.segs[g];
+        const int in = st.parity, out = in ^ 1;
+        const int64_t base = (int64_t)(t - pref[g]) * kCTile;
+        // rounds of 256 consecutive slots: lanes read and write neighbours
+        int64_t first = d.ccnt[t];
 #pragma unroll
-    for (int j = 0; j < kCP; ++j) {
-        if (!(m & (1u << j))) continue;
-        const int64_t i = base + j;
-        if (dst >= st.live) {                      // cannot happen when the counts agree
-            atomicOr(&d.diss[g / d.S].flags, kFlagCell);
-            break;
+        for (int r = 0; r < kCP; ++r) {
+            const int64_t i = base + r * kCT + threadIdx.x;
+            const int32_t c = i < st.count ? sc.cell[in][i] : -1;
+            const bool live = c >= 0;
+            uint32_t tot;
+            const int64_t dst = first + block_excl(live ? 1u : 0u, s_w[r & 1], &tot);
+            if (live) {
+                if (dst < st.live) {
+                    sc.cell[out][dst] = c;
+                    sc.off[out][dst] = sc.off[in][i];
+                    sc.vx[out][dst] = sc.vx[in][i];
+                    sc.vy[out][dst] = sc.vy[in][i];
+                    sc.vz[out][dst] = sc.vz[in][i];
+                    sc.id[out][dst] = sc.id[in][i];
+                } else {                           // cannot happen when the counts agree
+                    atomicOr(&d.diss[g / d.S].flags, kFlagCell);
+                }
+            }
+            first += tot;
         }
-        sc.cell[out][dst] = sc.cell[in][i];
-        sc.off[out][dst] = sc.off[in][i];
-        sc.vx[out][dst] = sc.vx[in][i];
-        sc.vy[out][dst] = sc.vy[in][i];
-        sc.vz[out][dst] = sc.vz[in][i];
-        sc.id[out][dst] = sc.id[in][i];
-        ++dst;
+        __syncthreads();                           // s_w is reused
     }
 }
 
@@ -187,12 +195,15 @@ __global__ __launch_bounds__(256) void compact_finish_kernel(DevPtrs d)
 
 }  // namespace
 
-hipError_t launch_compact(const DevPtrs& d, int64_t max_tiles, hipStream_t st)
+hipError_t launch_compact(const DevPtrs& d, int64_t max_tiles, int n_cu, hipStream_t st)
 {
     const int NS = d.B * d.S;
-    hipLaunchKernelGGL(compact_count_kernel, dim3((unsigned)max_tiles), dim3(kCT), 0, st, d);
+    // persistent grids: every workgroup builds the segment prefix once and
+    // strides over the tiles
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_tiles, (int64_t)n_cu * 8));
+    hipLaunchKernelGGL(compact_count_kernel, dim3(grid), dim3(kCT), 0, st, d);
     hipLaunchKernelGGL(compact_scan_kernel, dim3((unsigned)NS), dim3(1024), 0, st, d);
-    hipLaunchKernelGGL(compact_scatter_kernel, dim3((unsigned)max_tiles), dim3(kCT), 0, st, d);
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3(grid), dim3(kCT), 0, st, d);
     hipLaunchKernelGGL(compact_finish_kernel, dim3((unsigned)((NS + 255) / 256)), dim3(256), 0, st, d);
     return hipGetLastError();
 }

@@ -17,10 +17,11 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        // one 32 x 32 -> 64 product gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -78,11 +79,11 @@ __device__ __forceinline__ void scatter_dir(float dx, float dy, float dz, float 
     const float na = a * cos_chi + sin_chi * cp * st;
     const float nb = b * cos_chi + A * (sp * c - cp * a * b);
     const float nc = c * cos_chi - A * (sp * b + cp * a * c);
-    if (!alt) {
-        ox = na; oy = nb; oz = nc;
-    } else {
-        oy = na; oz = nb; ox = nc;
-    }
+    // undo the axis rotation with selects (a branch on the outputs becomes a
+    // dynamically indexed stack array)
+    ox = alt ? nc : na;
+    oy = alt ? na : nb;
+    oz = alt ? nb : nc;
 }
 
 // inclusive scan of one 32-bit value over a 64-wide wave

@@ -58,35 +58,6 @@ __device__ __forceinline__ void global_deposit(unsigned long long* acc, int c, f
     atomicAdd(&acc[c1], (unsigned long long)q);
 }
 
-// n_g sigma_k(eps) / nu_max from the uniform ln(eps) table, zero below threshold
-__device__ __forceinline__ void xs_lookup(const SegConst& sc, float eps, float* out)
-{
-    const float lx = (logf(fmaxf(eps, 1e-30f)) - sc.xs_ln0) * sc.xs_inv_dln;
-    int i;
-    float f;
-    if (!(lx > 0.0f)) {
-        i = 0;
-        f = 0.0f;
-    } else if (lx >= (float)(sc.xs_n - 1)) {
-        i = sc.xs_n - 2;
-        f = 1.0f;
-    } else {
-        i = (int)lx;
-        if (i > sc.xs_n - 2) i = sc.xs_n - 2;
-        f = lx - (float)i;
-    }
-    const float* r0 = sc.xs + (size_t)i * sc.nch;
-    const float* r1 = r0 + sc.nch;
-#pragma unroll
-    for (int k = 0; k < kMaxChan; ++k) {
-        out[k] = 0.0f;
-        if (k < sc.nch) {
-            const float v = r0[k] + f * (r1[k] - r0[k]);
-            out[k] = (eps < sc.th[k]) ? 0.0f : v;
-        }
-    }
-}
-
 template <int N, typename V, typename S>
 __device__ __forceinline__ void vload(const S* __restrict__ p, S* out)
 {
@@ -124,18 +95,52 @@ __device__ __forceinline__ void vstore(S* __restrict__ p, const S* in)
     }
 }
 
-// Everything one particle does in a step.  Returns whether it stays; a birth
-// (ionization pair or secondary electron) is reported through `bt`.
+// The births of a tile, staged in LDS as they happen; `pkey` is the slot of
+// the parent in the tile, so the tile's canonical order is the order of keys.
+// A staged birth is deposited at once: an ionization electron into the
+// workgroup's histogram and its ion into species 1, a secondary electron into
+// species 0.
+// a collision candidate waiting for the tile's collision pass
+struct CollQ {
+    uint32_t key;                  // slot in the tile
+    int32_t c;
+    float f, ux, uy, uz;
+    uint32_t pid;
+};
+
+struct BirthSink {
+    Birth* b;
+    uint32_t* key;
+    unsigned int* n;
+    int cap;
+    uint32_t pkey;
+    unsigned long long* hist;      // this segment's LDS histogram
+    unsigned long long* acc_e;     // species 0 of the discharge
+    unsigned long long* acc_i;     // species 1 of the discharge
+};
+
+__device__ __forceinline__ bool stage_birth(const BirthSink& k, const Birth& x)
+{
+    const unsigned int i = atomicAdd(k.n, 1u);
+    if (i >= (unsigned)k.cap) return false;
+    k.b[i] = x;
+    k.key[i] = k.pkey;
+    return true;
+}
+
+// A particle's step up to the collision test.  Returns whether it stays;
+// secondary electrons go to `sink`; `cand` says whether it is a collision
+// candidate (the collision itself is collide_particle, run for the
+// candidates of a tile together).
 template <bool GENERAL>
 __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, const DisConst& dc,
                                         const PushArgs& a, int s, int b, uint32_t step,
                                         const float2* ep, unsigned int* s_cnt, int& c, float& f,
                                         float& ux, float& uy, float& uz, uint32_t pid, float& ke_sum,
-                                        bool& born, Birth& bt)
+                                        const BirthSink& sink, bool& cand)
 {
     const int nc = dc.n_cells;
     const int periodic = dc.bc == PIC_BC_PERIODIC;
-    born = false;
     if ((unsigned)c >= (unsigned)nc) {     // corrupt state: latch, park the particle
         atomicOr(&d.diss[b].flags, kFlagCell);
         c = 0;
@@ -222,17 +227,24 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
                         }
                     }
                 }
+                bool kept = false;
                 if (bc_ >= 0 && bc_ < nc) {
-                    bt.cell = bc_;
-                    bt.off = fr;
-                    bt.vx = wall == 0 ? vn : -vn;
-                    bt.vy = sc.vsee * g0;
-                    bt.vz = sc.vsee * g1;
-                    born = true;
-                    atomicAdd(&s_cnt[C_SEE0 + wall], 1u);
-                } else {
-                    atomicAdd(&s_cnt[C_DROP], 1u);
+                    Birth x;
+                    x.cell = bc_;
+                    x.off = fr;
+                    x.vx = wall == 0 ? vn : -vn;
+                    x.vy = sc.vsee * g0;
+                    x.vz = sc.vsee * g1;
+                    x.ivx = x.ivy = x.ivz = 0.0f;
+                    kept = stage_birth(sink, x);
+                    if (kept) {
+                        global_deposit(sink.acc_e, bc_, fr, nc, periodic);
+                        atomicAdd(&s_cnt[C_SEE0 + wall], 1u);
+                    } else {
+                        atomicOr(&d.diss[b].flags, kFlagCapacity);
+                    }
                 }
+                if (!kept) atomicAdd(&s_cnt[C_DROP], 1u);
             }
         }
         return false;
@@ -240,9 +252,23 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
     if (!GENERAL || sc.nch == 0) return true;
     // null-collision Monte Carlo: integer candidate test on the first draw
     const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
-    if (r.x >= sc.t32) return true;
+    cand = r.x < sc.t32;
+    return true;
+}
+
+// The collision of a candidate: the energy (electrons: target at rest; ions:
+// relative to a sampled neutral), the channel by the running sum of the
+// tabulated frequencies against the second word of the first draw, then the
+// kinematics of the channel; an ionization stages its pair in `sink`.
+__device__ __forceinline__ void collide_particle(const DevPtrs& d, const SegConst& sc, const DisConst& dc, int s,
+                                                 int b, uint32_t step, unsigned int* s_cnt, int c, float f,
+                                                 float& ux, float& uy, float& uz, uint32_t pid,
+                                                 const BirthSink& sink)
+{
+    const int nc = dc.n_cells;
+    const int periodic = dc.bc == PIC_BC_PERIODIC;
+    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
     atomicAdd(&s_cnt[C_CAND], 1u);
-    float nu[kMaxChan];
     float speed, eps;
     float nvx = 0.0f, nvy = 0.0f, nvz = 0.0f;
     if (!sc.ion_type) {
@@ -262,25 +288,38 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
         speed = sqrtf(g2s);
         eps = sc.half_m_over_e * g2s;
     }
-    xs_lookup(sc, eps, nu);
-    float total = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kMaxChan; ++k) {
-        nu[k] *= speed;
-        total += nu[k];
-    }
-    if (total > 1.0f) atomicAdd(&s_cnt[C_VIOL], 1u);
+    // channel: the first k whose running sum of n_g sigma_k g / nu_max passes
+    // u1, one pass over the table row (the full sum checks the bound)
     const float u1 = u01f(r.y);
     float cum = 0.0f;
     int ch = -1;
-#pragma unroll
-    for (int k = 0; k < kMaxChan; ++k) {
-        cum += nu[k];
-        if (ch < 0 && k < sc.nch && u1 < cum) ch = k;
+    {
+        const float lx = (logf(fmaxf(eps, 1e-30f)) - sc.xs_ln0) * sc.xs_inv_dln;
+        int i;
+        float fr;
+        if (!(lx > 0.0f)) {
+            i = 0;
+            fr = 0.0f;
+        } else if (lx >= (float)(sc.xs_n - 1)) {
+            i = sc.xs_n - 2;
+            fr = 1.0f;
+        } else {
+            i = (int)lx;
+            if (i > sc.xs_n - 2) i = sc.xs_n - 2;
+            fr = lx - (float)i;
+        }
+        const float* r0 = sc.xs + (size_t)i * sc.nch;
+        const float* r1 = r0 + sc.nch;
+        for (int k = 0; k < sc.nch; ++k) {
+            const float v = r0[k] + fr * (r1[k] - r0[k]);
+            cum += ((eps < sc.th[k]) ? 0.0f : v) * speed;
+            if (ch < 0 && u1 < cum) ch = k;
+        }
     }
+    if (cum > 1.0f) atomicAdd(&s_cnt[C_VIOL], 1u);
     if (ch < 0) {
         atomicAdd(&s_cnt[C_NULL], 1u);
-        return true;
+        return;
     }
     atomicAdd(&s_cnt[C_COLL + ch], 1u);
     const float cos_chi = 1.0f - 2.0f * u01f(r.z);
@@ -309,15 +348,22 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
             float g0, g1, g2, g3;
             box_muller_f(u01f(r2.x), u01f(r2.y), g0, g1);
             box_muller_f(u01f(r2.z), u01f(r2.w), g2, g3);
-            bt.cell = c;
-            bt.off = f;
-            bt.vx = vej * edx;
-            bt.vy = vej * edy;
-            bt.vz = vej * edz;
-            bt.ivx = sc.vt_gas * g0;
-            bt.ivy = sc.vt_gas * g1;
-            bt.ivz = sc.vt_gas * g2;
-            born = true;
+            Birth x;
+            x.cell = c;
+            x.off = f;
+            x.vx = vej * edx;
+            x.vy = vej * edy;
+            x.vz = vej * edz;
+            x.ivx = sc.vt_gas * g0;
+            x.ivy = sc.vt_gas * g1;
+            x.ivz = sc.vt_gas * g2;
+            if (stage_birth(sink, x)) {
+                lds_deposit(sink.hist, c, f, nc, periodic);
+                global_deposit(sink.acc_i, c, f, nc, periodic);
+            } else {
+                atomicOr(&d.diss[b].flags, kFlagCapacity);
+                atomicAdd(&s_cnt[C_DROP], 1u);
+            }
         }
         enew = fmaxf(enew, 0.0f);
         const float vs = sqrtf(sc.two_e_over_m * enew);
@@ -340,7 +386,6 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
         uy = cmy + gg * st_ * cp_;
         uz = cmz + gg * st_ * sp_;
     }
-    return true;
 }
 
 __device__ __forceinline__ void electron_diag(const SegConst& sc, const PushArgs& a, unsigned long long* ehist,
@@ -387,9 +432,14 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_pref[kMaxSeg + 1];   // first tile of every segment (discharge-major)
-    __shared__ uint32_t s_wave[kBS / 64];
     __shared__ unsigned int s_cnt[C_N];
     __shared__ float s_red[kBS / 64];
+    constexpr int kSink = GENERAL ? kBirthsPerTile : 1;
+    __shared__ Birth s_bb[kSink];             // births of the current tile
+    __shared__ uint32_t s_bkey[kSink];
+    __shared__ unsigned int s_bn[2];          // their count, by parity of the tile
+    __shared__ CollQ s_q[GENERAL ? T : 1];    // collision candidates of the current tile
+    __shared__ unsigned int s_nq[2];          // their count, by parity of the tile
 
     // ---- tiles per segment, prefix over the segments (up to 16 per lane) -----
     if (wid == 0) {
@@ -418,6 +468,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
     }
     if (tid < C_N) s_cnt[tid] = 0;
+    if (tid < 2) {
+        s_bn[tid] = 0u;
+        s_nq[tid] = 0u;
+    }
     __syncthreads();
     const int32_t NT = s_pref[NS];
 
@@ -531,73 +585,44 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             for (int j = 0; j < PPT; ++j) pid[j] = 0u;
         }
 
-        uint32_t born = 0;
-        Birth bt[GENERAL ? PPT : 1];
+        BirthSink sink;
+        sink.b = s_bb;
+        sink.key = s_bkey;
+        sink.n = &s_bn[t & 1];
+        sink.cap = kBirthsPerTile;
+        sink.hist = hist;
+        sink.acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
+        sink.acc_i = d.acc + ((size_t)b * S + (S > 1 ? 1 : 0)) * kRep * d.nodes_max;
         float ke_tile = 0.0f;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (base + j >= n) continue;
             if (GENERAL && cell[j] < 0) continue;          // a hole: absorbed earlier
-            bool bj = false;
-            Birth& bb = bt[GENERAL ? j : 0];
+            sink.pkey = (uint32_t)(tid * PPT + j);
+            bool cand = false;
             const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, cell[j], off[j], vx[j], vy[j],
-                                               vz[j], pid[j], ke_tile, bj, bb);
+                                               vz[j], pid[j], ke_tile, sink, cand);
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
-                if (a.diag && s == 0)
+                if (GENERAL && cand) {
+                    const unsigned int q = atomicAdd(&s_nq[t & 1], 1u);
+                    CollQ e;
+                    e.key = sink.pkey;
+                    e.c = cell[j];
+                    e.f = off[j];
+                    e.ux = vx[j];
+                    e.uy = vy[j];
+                    e.uz = vz[j];
+                    e.pid = pid[j];
+                    s_q[q] = e;
+                } else if (a.diag && s == 0) {
                     electron_diag(sc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
+                }
             } else {
                 cell[j] = -1;                              // absorbed: leaves a hole
             }
-            if (GENERAL && bj) born |= 1u << j;
         }
         ke_run += ke_tile;
-
-        if (GENERAL) {
-            // births: deposited now, staged in particle order for the finalize
-            const int rep = blockIdx.x % kRep;
-            if (born) {
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (!(born & (1u << j))) continue;
-                    if (s == 0) {   // the electron into this histogram, the ion into species 1
-                        lds_deposit(hist, bt[j].cell, bt[j].off, nc, periodic);
-                        global_deposit(d.acc + (((size_t)b * S + 1) * kRep + rep) * d.nodes_max, bt[j].cell,
-                                       bt[j].off, nc, periodic);
-                    } else {        // a secondary electron into species 0
-                        global_deposit(d.acc + (((size_t)b * S + 0) * kRep + rep) * d.nodes_max, bt[j].cell,
-                                       bt[j].off, nc, periodic);
-                    }
-                }
-            }
-            const uint32_t nb = (uint32_t)__popc(born);
-            const uint32_t incl = wave_incl_scan_u32(nb);
-            if (lane == 63) s_wave[wid] = incl;
-            __syncthreads();
-            uint32_t wexcl = 0, tot = 0;
-#pragma unroll
-            for (int w = 0; w < kBS / 64; ++w) {
-                if (w < wid) wexcl += s_wave[w];
-                tot += s_wave[w];
-            }
-            if (born) {
-                Birth* dst = d.births + (size_t)t * kBirthsPerTile;
-                uint32_t k = wexcl + incl - nb;
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (!(born & (1u << j))) continue;
-                    if (k < (uint32_t)kBirthsPerTile) dst[k] = bt[j];
-                    ++k;
-                }
-            }
-            if (tid == 0) {
-                d.bcnt[t] = (int32_t)(tot < (uint32_t)kBirthsPerTile ? tot : (uint32_t)kBirthsPerTile);
-                if (tot > (uint32_t)kBirthsPerTile) {
-                    atomicOr(&d.diss[b].flags, kFlagCapacity);
-                    atomicAdd(&s_cnt[C_DROP], tot - (uint32_t)kBirthsPerTile);
-                }
-            }
-        }
 
         // in place; every particle keeps its slot
         if (base + PPT <= n) {
@@ -618,11 +643,48 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 }
             }
         }
+        if (GENERAL) {
+            // the tile's collisions together, with full lanes (a candidate in
+            // the main loop would stall its whole wave on the collision path);
+            // the new velocities overwrite the ones stored above
+            __threadfence_block();
+            __syncthreads();
+            const unsigned int nq = s_nq[t & 1];
+            for (unsigned int q = tid; q < nq; q += kBS) {
+                CollQ e = s_q[q];
+                BirthSink qs = sink;
+                qs.pkey = e.key;
+                collide_particle(d, sc, dc, s, b, step, s_cnt, e.c, e.f, e.ux, e.uy, e.uz, e.pid, qs);
+                const int64_t slot = (int64_t)tin * T + e.key;
+                sc.vx[io][slot] = e.ux;
+                sc.vy[io][slot] = e.uy;
+                sc.vz[io][slot] = e.uz;
+                if (a.diag && s == 0) electron_diag(sc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
+            }
+            __syncthreads();
+            // the tile's births in the order of their parents' slots
+            const unsigned int nst = s_bn[t & 1];
+            const int nb = nst < (unsigned)kBirthsPerTile ? (int)nst : kBirthsPerTile;
+            if (tid < nb) {
+                const uint32_t k = s_bkey[tid];
+                int rank = 0;
+                for (int i = 0; i < nb; ++i) rank += s_bkey[i] < k;
+                d.births[(size_t)t * kBirthsPerTile + rank] = s_bb[tid];
+            }
+            if (tid == 0) d.bcnt[t] = nb;
+        }
+
         if (tid == 0 && tin == ntiles - 1) {
             st.tile_first = tile_first;
             st.ntiles = ntiles;
         }
-        if (GENERAL) __syncthreads();             // s_wave is reused
+        if (GENERAL) {
+            __syncthreads();                      // the staged births are read
+            if (tid == 0) {                       // free for tile t + 2 (tile t + 1 counts in the other)
+                s_bn[t & 1] = 0u;
+                s_nq[t & 1] = 0u;
+            }
+        }
     }
     if (cur_g >= 0) flush(cur_g);
 }
@@ -635,8 +697,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     X(4, 512, false)     \
     X(4, 1024, false)    \
     X(1, 256, true)      \
-    X(2, 256, true)      \
-    X(4, 256, true)
+    X(2, 256, true)
 
 #define PIC_INST(P, B, G) template __global__ void push_kernel<P, B, G>(PushArgs);
 PIC_KERNELS(PIC_INST)
@@ -651,13 +712,13 @@ size_t push_lds_bytes(int n_nodes, int n_cells, int diag)
     return b;
 }
 
-// nearest instantiated shape: general kernels run 256 threads and PPT <= 4;
+// nearest instantiated shape: general kernels run 256 threads and PPT <= 2;
 // streaming kernels accept the shapes listed above
 void push_shape(int& ppt, int& threads, bool general)
 {
-    if (general) {
+    if (general) {                // the collision path holds many registers: two per thread at most
         threads = 256;
-        ppt = ppt >= 4 ? 4 : (ppt >= 2 ? 2 : 1);
+        ppt = ppt >= 2 ? 2 : 1;
         return;
     }
     if (threads >= 1024) {
