@@ -75,6 +75,7 @@ def lib():
         L.orc_free.restype = None
         L.orc_load_xsec.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_int32, dp, dp]
         L.orc_load.argtypes = [P]
+        L.orc_load_profiles.argtypes = [P, C.c_int32, dp, dp, C.POINTER(C.c_int64)]
         L.orc_set_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up, C.c_uint32]
         L.orc_get_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_uint32)]
@@ -184,6 +185,14 @@ class Oracle:
 
     def step(self, n=1):
         _check(lib().orc_step(self.h, n), "orc_step")
+
+    def load_profiles(self, density, temp_ev, n):
+        """Replace every species by particles drawn from profiles [S][m]
+        (density, temperature in eV) with n[s] particles each."""
+        dens = np.ascontiguousarray(density, dtype=np.float64)
+        temp = np.ascontiguousarray(temp_ev, dtype=np.float64)
+        nn = (C.c_int64 * len(n))(*[int(v) for v in n])
+        _check(lib().orc_load_profiles(self.h, dens.shape[1], _dp(dens), _dp(temp), nn), "orc_load_profiles")
 
     def refresh_field(self):
         _check(lib().orc_refresh_field(self.h), "orc_refresh_field")

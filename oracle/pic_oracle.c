@@ -559,6 +559,94 @@ int orc_load(orc_sim* s)
     return ORC_OK;
 }
 
+/* Start from profiles: density and temperature given at m points evenly
+ * spread over [0, L], linear in between.  Position x_j solves F(x) = (j + u_j)/n
+ * where F is the integral of the density from 0, divided by its total; it is
+ * found by bisection on the exact integral of the linear pieces.  Velocity:
+ * three Box-Muller normals times sqrt(e T(x_j) / m).  Then the field at the
+ * current step and the leapfrog start, as in orc_load. */
+static double profile_integral(const double* d, const double* cum, int m, double h, double x)
+{
+    /* integral of the linear interpolant of d over [0, x]; cum[i] is the
+     * integral over [0, i h] */
+    int k = (int)floor(x / h);
+    if (k > m - 2) k = m - 2;
+    if (k < 0) k = 0;
+    double t = x - k * h;
+    double slope = (d[k + 1] - d[k]) / h;
+    return cum[k] + d[k] * t + 0.5 * slope * t * t;
+}
+
+int orc_load_profiles(orc_sim* s, int32_t m, const double* dens, const double* temp_ev,
+                      const int64_t* n)
+{
+    if (!s || m < 2 || !dens || !temp_ev || !n) return ORC_EINVAL;
+    double L = s->c.length, h = L / (double)(m - 1);
+    for (int k = 0; k < s->c.n_species; ++k) {
+        const double* d = dens + (size_t)k * m;
+        const double* T = temp_ev + (size_t)k * m;
+        double total = 0.0;
+        for (int i = 0; i < m; ++i) {
+            if (!(d[i] >= 0.0) || !isfinite(d[i]) || !(T[i] >= 0.0) || !isfinite(T[i])) return ORC_EINVAL;
+            if (i + 1 < m) total += 0.5 * (d[i] + d[i + 1]) * h;
+        }
+        if (n[k] < 0 || n[k] > s->p[k].cap || (n[k] > 0 && !(total > 0.0))) return ORC_EINVAL;
+    }
+    for (int k = 0; k < s->c.n_species; ++k) {
+        const double* d = dens + (size_t)k * m;
+        const double* T = temp_ev + (size_t)k * m;
+        pop_t* p = &s->p[k];
+        double* cum = malloc((size_t)m * sizeof(double));
+        if (!cum) return ORC_ENOMEM;
+        cum[0] = 0.0;
+        for (int i = 1; i < m; ++i) cum[i] = cum[i - 1] + 0.5 * (d[i - 1] + d[i]) * h;
+        double total = cum[m - 1];
+        double mass = s->c.sp[k].mass;
+        for (int64_t j = 0; j < n[k]; ++j) {
+            uint32_t r0[4], r1[4];
+            draw(s, (uint32_t)j, 0xFFFFFFFFu, k, 0u, r0);
+            draw(s, (uint32_t)j, 0xFFFFFFFFu, k, 1u, r1);
+            double y = ((double)j + orc_u01(r0[0])) / (double)n[k] * total;
+            double lo = 0.0, hi = L;
+            for (int it = 0; it < 64; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (profile_integral(d, cum, m, h, mid) <= y) lo = mid; else hi = mid;
+            }
+            double x = 0.5 * (lo + hi);
+            if (x >= L) x = L * (1.0 - 1e-16);
+            int c = (int)floor(x / h);
+            if (c > m - 2) c = m - 2;
+            double f = x / h - c;
+            double Tx = T[c] + f * (T[c + 1] - T[c]);
+            double vth = sqrt(s->c.e_unit * Tx / mass);
+            double g0, g1, g2, g3;
+            box_muller(orc_u01(r1[0]), orc_u01(r1[1]), &g0, &g1);
+            box_muller(orc_u01(r1[2]), orc_u01(r1[3]), &g2, &g3);
+            p->x[j] = x;
+            p->vx[j] = vth * g0;
+            p->vy[j] = vth * g1;
+            p->vz[j] = vth * g2;
+            p->id[j] = (uint32_t)j;
+        }
+        free(cum);
+        p->n = n[k];
+        p->next_id = (uint32_t)n[k];
+    }
+    int rc = orc_refresh_field(s);
+    if (rc != ORC_OK) return rc;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        pop_t* p = &s->p[k];
+        double qm = s->c.sp[k].charge / s->c.sp[k].mass;
+        for (int64_t j = 0; j < p->n; ++j) {
+            double e[3] = {gather(s, p->x[j]) + s->c.e_ext[0], s->c.e_ext[1], s->c.e_ext[2]};
+            double v[3] = {p->vx[j], p->vy[j], p->vz[j]};
+            orc_boris(v, e, s->c.b_ext, qm, -0.5 * s->c.dt);
+            p->vx[j] = v[0]; p->vy[j] = v[1]; p->vz[j] = v[2];
+        }
+    }
+    return ORC_OK;
+}
+
 int orc_set_particles(orc_sim* s, int32_t k, int64_t n, const double* x, const double* vx,
                       const double* vy, const double* vz, const uint32_t* id,
                       uint32_t next_id)

@@ -73,6 +73,10 @@ int  orc_load_xsec(orc_sim* s, int32_t species, int32_t kind, double threshold_e
 /* Load particles (Philox draws at step 0xFFFFFFFF), deposit, solve at t = 0,
  * and take the backward half step of the leapfrog start. */
 int  orc_load(orc_sim* s);
+/* start from density and temperature profiles at m points over [0, L]
+ * (arrays [n_species][m]); n[k] particles of species k */
+int  orc_load_profiles(orc_sim* s, int32_t m, const double* density, const double* temp_ev,
+                       const int64_t* n);
 /* Replace species state; positions in [0, L). */
 int  orc_set_particles(orc_sim* s, int32_t species, int64_t n, const double* x,
                        const double* vx, const double* vy, const double* vz,
