@@ -209,6 +209,24 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
                              const float* vy, const float* vz, const uint32_t* id,
                              uint32_t next_id, uint64_t step);
 
+/*
+ * pic_load_profiles: restart discharge `batch` from profiles (a warm start;
+ * Section 1 loads particles into the mesh at the start of a run).  For every
+ * species s, n[s] particles are drawn from the density profile
+ * density[s * m + i] and the temperature profile temp_eV[s * m + i], both
+ * given at the m points x_i = i L / (m - 1) (2 <= m <= 4097) and linear in
+ * between: positions x_j = F^-1((j + u_j) / n[s]) with F the integral of the
+ * density divided by its total (a uniform profile gives the stratified load),
+ * velocities Maxwellian at the local temperature (scale sqrt(e T / m_s)),
+ * ids 0 .. n[s] - 1 and next id n[s].  Then the charge is deposited, the field
+ * solved at the discharge's current time and the velocities moved back half
+ * a step, as at pic_init.  Density values are relative (any positive scale);
+ * negative or non-finite values, a zero total with n[s] > 0, or n[s] above
+ * the capacity give PIC_EINVAL with no state change.  Synchronous.
+ */
+pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const double* density,
+                             const double* temp_eV, const int64_t* n);
+
 /* pic_sync: wait for queued work; return a latched device error if any. */
 pic_status pic_sync(pic_ctx* ctx);
 

@@ -104,6 +104,7 @@ def load_library():
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
         "pic_retire": (i32, [P, i32, i32]),
+        "pic_load_profiles": (i32, [P, i32, i32, dp, dp, C.POINTER(i64)]),
         "pic_mlp_create": (i32, [ip, i32, i32, C.POINTER(PicAllocator), P, C.POINTER(P)]),
         "pic_mlp_n_params": (i64, [P]),
         "pic_mlp_set_params": (i32, [P, fp, i64]),
@@ -291,6 +292,17 @@ class Sim:
 
     def reset_avg(self, batch=0):
         self._check(_lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0), "pic_diag(RESET_AVG)")
+
+    def load_profiles(self, density, temp_ev, n, batch=0):
+        """Restart discharge `batch` from profiles [S][m] (relative density,
+        temperature in eV) with n[s] particles of species s."""
+        dens = np.ascontiguousarray(density, dtype=np.float64)
+        temp = np.ascontiguousarray(temp_ev, dtype=np.float64)
+        if dens.shape != temp.shape or dens.shape[0] != self.S:
+            raise ValueError("density and temperature must both be [n_species, m]")
+        nn = (C.c_int64 * self.S)(*[int(v) for v in n])
+        self._check(_lib.pic_load_profiles(self.h, batch, dens.shape[1], _ptr(dens, C.c_double),
+                                           _ptr(temp, C.c_double), nn), "pic_load_profiles")
 
     def retire(self, batch, retired=True):
         self._check(_lib.pic_retire(self.h, batch, int(retired)), "pic_retire")

@@ -1010,6 +1010,68 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     return hip_st(hipStreamSynchronize(st));
 }
 
+pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const double* density, const double* temp_eV,
+                             const int64_t* n)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || m < 2 || m > kMaxCells + 1 || !density || !temp_eV || !n)
+        return PIC_EINVAL;
+    const int S = ctx->S;
+    const pic_config& c = ctx->cfg[batch];
+    const double h = c.length / (double)(m - 1);
+    // per species: density, its running integral, temperature
+    std::vector<double> tab((size_t)3 * m * S);
+    for (int s = 0; s < S; ++s) {
+        const double* ds = density + (size_t)s * m;
+        const double* ts = temp_eV + (size_t)s * m;
+        double* dd = tab.data() + (size_t)3 * m * s;
+        double* cum = dd + m;
+        double* tt = cum + m;
+        if (n[s] < 0 || n[s] > ctx->segc[batch * S + s].cap) return PIC_EINVAL;
+        for (int i = 0; i < m; ++i) {
+            if (!(ds[i] >= 0.0) || !std::isfinite(ds[i]) || !(ts[i] >= 0.0) || !std::isfinite(ts[i]))
+                return PIC_EINVAL;
+            dd[i] = ds[i];
+            tt[i] = ts[i];
+            cum[i] = i == 0 ? 0.0 : cum[i - 1] + 0.5 * (ds[i - 1] + ds[i]) * h;
+        }
+        if (n[s] > 0 && !(cum[m - 1] > 0.0)) return PIC_EINVAL;
+    }
+    hipStream_t st = ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EHIP;
+    double* dev = (double*)dev_alloc(ctx, sizeof(double) * tab.size());
+    if (!dev) return PIC_ENOMEM;
+    bool ok = hipMemcpy(dev, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) == hipSuccess;
+    std::vector<SegState> ss(S);
+    ok = ok && hipMemcpy(ss.data(), ctx->d.segs + (size_t)batch * S, sizeof(SegState) * S, hipMemcpyDeviceToHost) ==
+                   hipSuccess;
+    for (int s = 0; s < S && ok; ++s) {
+        ProfileArgs pa{};
+        pa.d = ctx->d;
+        pa.b = batch;
+        pa.s = s;
+        pa.m = m;
+        pa.n = n[s];
+        pa.dens = dev + (size_t)3 * m * s;
+        pa.cum = pa.dens + m;
+        pa.temp = pa.cum + m;
+        pa.e_over_m = c.e_unit / c.species[s].mass;
+        ok = launch_profile_load(pa, st) == hipSuccess;
+        ss[s].count = ss[s].live = n[s];
+        ss[s].dead = 0;
+        ss[s].next_id = (uint32_t)n[s];
+        ss[s].ntiles = 0;
+    }
+    ok = ok && hipMemcpy(ctx->d.segs + (size_t)batch * S, ss.data(), sizeof(SegState) * S, hipMemcpyHostToDevice) ==
+                   hipSuccess;
+    ok = ok && hipMemset(ctx->d.acc + (size_t)batch * S * kRep * ctx->d.nodes_max, 0,
+                         8ull * S * kRep * ctx->d.nodes_max) == hipSuccess;
+    ok = ok && solve_after_deposit(ctx, batch) == PIC_OK;
+    ok = ok && launch_halfstep(ctx->d, batch, max_count_of(ctx, batch), st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    dev_release(ctx, dev);
+    return ok ? PIC_OK : PIC_EHIP;
+}
+
 pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t out_bytes)
 {
     if (!ctx || batch < 0 || batch >= ctx->B) return PIC_EINVAL;

@@ -458,6 +458,72 @@ __global__ __launch_bounds__(256) void load_kernel(LoadArgs a)
     sc.id[p][j] = (uint32_t)j;
 }
 
+// Start from profiles: density and temperature at m points evenly spread over
+// [0, L], linear in between.  x_j = F^-1((j + u_j) / n) with F the integral of
+// the density; inside piece k the integral from x_k is h (n_k t + dn t^2 / 2)
+// at x = x_k + t h, so t is the root 2q / (n_k + sqrt(n_k^2 + 2 dn q)) of
+// (dn / 2) t^2 + n_k t = q (this form holds for dn = 0 and dn < 0 too).
+// Velocities: three Box-Muller normals times sqrt(e T(x_j) / m).  Draws as in
+// the plain load, so a uniform profile gives the stratified positions.
+__global__ __launch_bounds__(256) void profile_load_kernel(ProfileArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const DevPtrs& d = a.d;
+    const DisConst& dc = d.disc[a.b];
+    const SegConst& sc = d.segc[a.b * d.S + a.s];
+    const double L = dc.L, h = L / (double)(a.m - 1);
+    const uint4 r0 = philox10((uint32_t)j, 0xFFFFFFFFu, ((uint32_t)a.s << 24) | 0u, 0u, dc.key0, dc.key1);
+    const uint4 r1 = philox10((uint32_t)j, 0xFFFFFFFFu, ((uint32_t)a.s << 24) | 1u, 0u, dc.key0, dc.key1);
+    const double y = ((double)j + u01d(r0.x)) / (double)a.n * a.cum[a.m - 1];
+    int lo = 0, hi = a.m - 1;                 // last piece k with cum[k] <= y
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.cum[mid] <= y) lo = mid; else hi = mid;
+    }
+    const int k = lo;
+    const double nk = a.dens[k], dn = a.dens[k + 1] - nk;
+    const double q = (y - a.cum[k]) / h;
+    double t = 0.0;
+    if (q > 0.0) {
+        const double den = nk + sqrt(fmax(nk * nk + 2.0 * dn * q, 0.0));
+        t = den > 0.0 ? 2.0 * q / den : 1.0;
+    }
+    t = fmin(fmax(t, 0.0), 1.0);
+    double x = ((double)k + t) * h;
+    if (x >= L) x = L * (1.0 - 1e-16);
+    const double xi = x / dc.dx;
+    int c = (int)floor(xi);
+    float f = (float)(xi - (double)c);
+    if (f >= 1.0f) {
+        f -= 1.0f;
+        c += 1;
+    }
+    if (c >= dc.n_cells) {
+        c = dc.n_cells - 1;
+        f = 0x1.fffffep-1f;
+    }
+    const double T = a.temp[k] + t * (a.temp[k + 1] - a.temp[k]);
+    const double vth = sqrt(a.e_over_m * fmax(T, 0.0));
+    double g0, g1, g2, g3;
+    box_muller_d(u01d(r1.x), u01d(r1.y), g0, g1);
+    box_muller_d(u01d(r1.z), u01d(r1.w), g2, g3);
+    const int p = d.segs[a.b * d.S + a.s].parity;
+    sc.cell[p][j] = c;
+    sc.off[p][j] = f;
+    sc.vx[p][j] = (float)(vth * g0);
+    sc.vy[p][j] = (float)(vth * g1);
+    sc.vz[p][j] = (float)(vth * g2);
+    sc.id[p][j] = (uint32_t)j;
+}
+
+hipError_t launch_profile_load(const ProfileArgs& a, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(profile_load_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_load(const LoadArgs& a, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;

@@ -41,6 +41,17 @@ struct LoadArgs {
     int32_t perturb_mode;
 };
 
+struct ProfileArgs {
+    DevPtrs d;
+    int32_t b, s, m;
+    int64_t n;
+    const double* dens;           // [m] density at the points
+    const double* cum;            // [m] integral of the density from 0 to each point
+    const double* temp;           // [m] temperature (eV) at the points
+    double e_over_m;              // e / m of the species
+};
+
+hipError_t launch_profile_load(const ProfileArgs& a, hipStream_t st);
 hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, int64_t grid, hipStream_t st);
 void push_shape(int& ppt, int& threads, bool general);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
