@@ -1,0 +1,198 @@
+"""Wall time per converged discharge: the plain method against batched sweeps
+started from the learned warm start.
+
+    python -m paper_2609_17151_amd.experiments plain   --out c2.npz
+    python -m paper_2609_17151_amd.experiments sweep   --set train --start 0 --count 64 --out t0.npz
+    python -m paper_2609_17151_amd.experiments train   --data t0.npz t1.npz ... --out model.npz
+    python -m paper_2609_17151_amd.experiments sweep   --set heldout --out cold.npz
+    python -m paper_2609_17151_amd.experiments warm    --model model.npz --cold cold.npz --out warm.npz
+
+Converged (steady): the 5-period windows stay within 2 % (relative L2, each
+of n_e, n_i, <eps> at 256 points) of the reference, the mean of periods
+251-300 of the cold run, for 10 windows in a row; the convergence time is
+the end of the first of those windows.  Every run prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+import workloads as W
+
+from . import steady, warm
+from .sweep import Sweep
+
+SETS = {
+    "c4": lambda: W.sweep_draws(64, seed=4),
+    "train": lambda: W.warm_draws(2048, seed=5),
+    "heldout": lambda: W.warm_draws(64, seed=6),
+}
+
+
+def _sim(cfgs):
+    from . import Sim
+    return Sim(cfgs, W.argon_tables())
+
+
+def convergence(windows, ref, window_periods=5):
+    """(first converged window, periods to convergence) or (None, None)."""
+    i = steady.converged_at(windows, ref)
+    return (None, None) if i is None else (i, (i + 1) * window_periods)
+
+
+def cmd_plain(a):
+    """One cold discharge (the 2.5 cm, 30 mTorr, 200 V, 13.56 MHz case) for
+    `periods` RF periods."""
+    draw = dict(pressure_mtorr=30.0, v_amp=200.0, freq=13.56e6, gap=0.025, n_cells=400, see_gamma=0.1)
+    cfg = warm.config(draw, weight=W.PILOT_WEIGHT * a.weight_scale, seed=2)
+    sim = _sim([cfg])
+    sw = Sweep(sim, [warm.steps_per_period(draw)], max_periods=a.periods).run()
+    ref = sw.reference(0)
+    i, per = convergence(sw.windows[0], ref)
+    t_conv = sw.window_time[0][i] if i is not None else None
+    out = dict(kind="plain", periods=a.periods, counts=sim.counts(0)["count"],
+               converged_window=i, converged_periods=per, seconds_to_converge=t_conv,
+               seconds_total=sw.window_time[0][-1], steps=sw.window_step[0][-1],
+               us_per_step=sw.window_time[0][-1] / sw.window_step[0][-1] * 1e6)
+    np.savez(a.out, windows=np.array(sw.windows[0], dtype=np.float32), ref=ref,
+             times=np.array(sw.window_time[0]), steps=np.array(sw.window_step[0]), x=warm.inputs(draw))
+    print(json.dumps(out), flush=True)
+
+
+def cmd_sweep(a):
+    """Cold runs of a set of draws, in batches of up to `batch` discharges
+    grouped by frequency; windows, references and timings per draw."""
+    draws = SETS[a.set]()[a.start:a.start + a.count]
+    order = sorted(range(len(draws)), key=lambda i: -draws[i].get("freq", 13.56e6))
+    X, REF, WIN, TIMES, STEPS, CONV = [], [], [], [], [], []
+    ids = []
+    total = 0.0
+    for k in range(0, len(order), a.batch):
+        grp = order[k:k + a.batch]
+        cfgs = [warm.config(draws[i], weight=W.PILOT_WEIGHT * a.weight_scale, seed=1000 + a.start + i,
+                            capacity=a.capacity) for i in grp]
+        sim = _sim(cfgs)
+        t0 = time.perf_counter()
+        sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in grp], max_periods=a.periods).run()
+        total += time.perf_counter() - t0
+        for j, i in enumerate(grp):
+            ref = sw.reference(j)
+            ids.append(a.start + i)
+            X.append(warm.inputs(draws[i]))
+            REF.append(steady.to_features(ref))
+            WIN.append(np.array(sw.windows[j], dtype=np.float32))
+            TIMES.append(np.array(sw.window_time[j]))
+            STEPS.append(np.array(sw.window_step[j]))
+            CONV.append(convergence(sw.windows[j], ref)[1] or -1)
+        flags = [sim.counts(j)["flags"] for j in range(len(grp))]
+        print(json.dumps(dict(batch=k // a.batch, discharges=len(grp), seconds=time.perf_counter() - t0,
+                              flags=sorted(set(flags)))), flush=True)
+        sim.close()
+    np.savez(a.out, ids=np.array(ids), x=np.array(X), y=np.array(REF), windows=np.array(WIN, dtype=object),
+             times=np.array(TIMES, dtype=object), steps=np.array(STEPS, dtype=object), conv=np.array(CONV))
+    print(json.dumps(dict(kind="sweep", set=a.set, draws=len(draws), seconds=total,
+                          converged=int(np.sum(np.array(CONV) > 0)),
+                          mean_periods_to_converge=float(np.mean([c for c in CONV if c > 0])) if any(
+                              c > 0 for c in CONV) else None)), flush=True)
+
+
+def cmd_train(a):
+    X = np.concatenate([np.load(f, allow_pickle=True)["x"] for f in a.data])
+    Y = np.concatenate([np.load(f, allow_pickle=True)["y"] for f in a.data])
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(len(X))
+    nv = max(1, len(X) // 10)
+    va, tr = perm[:nv], perm[nv:]
+    t0 = time.perf_counter()
+    m = warm.Model().fit(X[tr], Y[tr], steps=a.steps, lr=a.lr, batch=a.batch)
+    secs = time.perf_counter() - t0
+    st = m.state()
+    np.savez(a.out, **st, history=np.array(m.history))
+    print(json.dumps(dict(kind="train", samples=len(tr), validation=len(va), steps=a.steps, seconds=secs,
+                          train_loss=m.loss(X[tr], Y[tr]), validation_loss=m.loss(X[va], Y[va]))), flush=True)
+
+
+def cmd_warm(a):
+    """Held-out draws started from the network, run together until each has
+    converged to its cold run's reference (then retired)."""
+    cold = np.load(a.cold, allow_pickle=True)
+    st = np.load(a.model)
+    draws = SETS["heldout"]()
+    ids = [int(i) for i in cold["ids"]]
+    refs = {i: steady.from_features(y) for i, y in zip(ids, cold["y"])}
+    t0 = time.perf_counter()
+    m = warm.Model(widths=tuple(int(w) for w in st["widths"]))
+    m.set_state(st)
+    feats = m.predict(np.array([warm.inputs(draws[i]) for i in ids]))
+    cfgs = [warm.config(draws[i], weight=W.PILOT_WEIGHT * a.weight_scale, seed=1000 + i, capacity=a.capacity,
+                        cold=False) for i in ids]
+    sim = _sim(cfgs)
+    for j in range(len(ids)):
+        warm.start_from_features(sim, j, cfgs[j], feats[j])
+    t_ready = time.perf_counter() - t0
+    # the reference is stored as features: back to profiles for the distance
+    ref_prof = [refs[i] for i in ids]
+
+    def stop(j, sw):
+        return steady.converged_at(sw.windows[j], ref_prof[j]) is not None
+
+    sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in ids], max_periods=a.periods).run(stop=stop)
+    conv, t_conv = [], []
+    for j in range(len(ids)):
+        i, per = convergence(sw.windows[j], ref_prof[j])
+        conv.append(per if per is not None else -1)
+        t_conv.append(t_ready + sw.window_time[j][i] if i is not None else None)
+    done = [t for t in t_conv if t is not None]
+    cold_conv = [int(c) for c in cold["conv"]]
+    out = dict(kind="warm", draws=len(ids), seconds_inference_and_load=t_ready,
+               converged=len(done), seconds_to_last_convergence=max(done) if done else None,
+               seconds_per_converged_discharge=(max(done) / len(ids)) if len(done) == len(ids) else None,
+               mean_periods_warm=float(np.mean([c for c in conv if c > 0])) if done else None,
+               mean_periods_cold=float(np.mean([c for c in cold_conv if c > 0])) if any(
+                   c > 0 for c in cold_conv) else None)
+    np.savez(a.out, ids=np.array(ids), conv=np.array(conv), cold_conv=np.array(cold_conv),
+             t_conv=np.array([t if t is not None else -1.0 for t in t_conv]),
+             windows=np.array([np.array(w, dtype=np.float32) for w in sw.windows], dtype=object))
+    print(json.dumps(out), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="experiments")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    p = sub.add_parser("plain")
+    p.add_argument("--periods", type=int, default=300)
+    p.add_argument("--weight-scale", type=float, default=1.0)
+    p.add_argument("--out", required=True)
+    p = sub.add_parser("sweep")
+    p.add_argument("--set", choices=sorted(SETS), required=True)
+    p.add_argument("--start", type=int, default=0)
+    p.add_argument("--count", type=int, default=64)
+    p.add_argument("--batch", type=int, default=64)
+    p.add_argument("--periods", type=int, default=300)
+    p.add_argument("--weight-scale", type=float, default=1.0)
+    p.add_argument("--capacity", type=int, default=1 << 20)
+    p.add_argument("--out", required=True)
+    p = sub.add_parser("train")
+    p.add_argument("--data", nargs="+", required=True)
+    p.add_argument("--steps", type=int, default=4000)
+    p.add_argument("--lr", type=float, default=1e-3)
+    p.add_argument("--batch", type=int, default=128)
+    p.add_argument("--out", required=True)
+    p = sub.add_parser("warm")
+    p.add_argument("--model", required=True)
+    p.add_argument("--cold", required=True)
+    p.add_argument("--periods", type=int, default=300)
+    p.add_argument("--weight-scale", type=float, default=1.0)
+    p.add_argument("--capacity", type=int, default=1 << 20)
+    p.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    dict(plain=cmd_plain, sweep=cmd_sweep, train=cmd_train, warm=cmd_warm)[a.cmd](a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -125,6 +125,14 @@ def gas_density(pressure_pa, temp_k=300.0):
     return pressure_pa / (K_BOLTZMANN * temp_k)
 
 
+# Real particles per m^2 per macroparticle of the argon RF runs, fixed by a
+# pilot run: a cold start of the 2.5 cm / 30 mTorr / 200 V discharge with
+# 3e8 settled at about 4.5e4 macros per species after 250 periods, so 6.75e7
+# gives about 2e5.  Sweeps use the same weight, so counts follow the physics.
+PILOT_WEIGHT = 6.75e7
+RF_DT = 1.0 / (13.56e6 * 1600)           # the time step of every RF run
+
+
 def argon_rf(gap=0.025, n_cells=400, pressure_mtorr=30.0, v_amp=200.0,
              freq=13.56e6, steps_per_period=1600, n_init=100000, weight=None,
              see_gamma=0.1, te_ev=2.0, seed=2, capacity=None, dt=None):
@@ -134,7 +142,7 @@ def argon_rf(gap=0.025, n_cells=400, pressure_mtorr=30.0, v_amp=200.0,
     if dt is None:
         dt = 1.0 / (freq * steps_per_period)
     if weight is None:
-        weight = 6.0e13 * gap / 0.025 / 2.0e5   # ~6e13 m^-2 of plasma for 2e5 macros
+        weight = PILOT_WEIGHT
     if capacity is None:
         capacity = max(8 * n_init, 1 << 20)
     vte = math.sqrt(te_ev * E_CHARGE / M_ELECTRON)
