@@ -213,8 +213,10 @@ class Sim:
     def step(self, n=1):
         self._check(_lib.pic_step(self.h, int(n)), "pic_step")
 
-    def sync(self):
-        self._check(_lib.pic_sync(self.h), "pic_sync")
+    def sync(self, check=True):
+        rc = _lib.pic_sync(self.h)
+        if check:
+            self._check(rc, "pic_sync")
 
     def config_tiles(self, ppt=4, threads=256, sort_every=0, compact_every=16):
         self._check(_lib.pic_config_tiles(self.h, ppt, threads, sort_every, compact_every), "pic_config_tiles")
@@ -279,9 +281,9 @@ class Sim:
     def flags(self, batch=0):
         return int(self.diag("FLAGS", 1, np.int64, batch)[0])
 
-    def avg(self, batch=0):
+    def avg(self, batch=0, check=True):
         n = self.n_nodes[batch]
-        o = self.diag("AVG", 1 + (self.S + 2) * n, batch=batch)
+        o = self.diag("AVG", 1 + (self.S + 2) * n, batch=batch, check=check)
         prof = o[1:].reshape(self.S + 2, n)
         return dict(samples=o[0], density=prof[: self.S], phi=prof[self.S], mean_energy=prof[self.S + 1])
 
@@ -290,8 +292,10 @@ class Sim:
         return dict(bulk=o[:EEPF_BINS], wall=o[EEPF_BINS:2 * EEPF_BINS],
                     bin_width=o[2 * EEPF_BINS], samples=o[2 * EEPF_BINS + 1])
 
-    def reset_avg(self, batch=0):
-        self._check(_lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0), "pic_diag(RESET_AVG)")
+    def reset_avg(self, batch=0, check=True):
+        rc = _lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0)
+        if check:
+            self._check(rc, "pic_diag(RESET_AVG)")
 
     def load_profiles(self, density, temp_ev, n, batch=0):
         """Restart discharge `batch` from profiles [S][m] (relative density,

@@ -29,11 +29,13 @@ def resample(y, npts=NPTS):
 
 def window(sim, batch=0, electron=0, ion=1):
     """The [3, NPTS] profiles (n_e, n_i, mean electron energy in eV) accumulated
-    since the last reset of discharge `batch`; then clears the accumulators."""
-    a = sim.avg(batch)
+    since the last reset of discharge `batch`; then clears the accumulators.
+    Latched device conditions are not raised here: the caller reads them
+    with the counts."""
+    a = sim.avg(batch, check=False)
     out = np.stack([resample(a["density"][electron]), resample(a["density"][ion]),
                     resample(a["mean_energy"])])
-    sim.reset_avg(batch)
+    sim.reset_avg(batch, check=False)
     return out
 
 

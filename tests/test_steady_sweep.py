@@ -56,7 +56,7 @@ class FakeSim:
     def set_diag(self, on):
         pass
 
-    def reset_avg(self, b):
+    def reset_avg(self, b, check=True):
         pass
 
     def counts(self, b):
@@ -67,14 +67,14 @@ class FakeSim:
         self.calls.append(n)
         self.step_no += n
 
-    def avg(self, b):
+    def avg(self, b, check=True):
         v = np.full(5, b * 1000.0 + self.step_no)
         return dict(density=np.stack([v, v]), phi=v, mean_energy=v, samples=1.0)
 
     def retire(self, b):
         self.retired.add(b)
 
-    def sync(self):
+    def sync(self, check=True):
         pass
 
 

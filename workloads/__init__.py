@@ -215,11 +215,11 @@ def sweep_draws(n=64, seed=4):
             for i in range(n)]
 
 
-def warm_draws(n, seed):
+def warm_draws(n, seed, f_range=(2e6, 60e6)):
     rng = np.random.default_rng(seed)
     p = np.exp(rng.uniform(np.log(10.0), np.log(200.0), n))
     v = rng.uniform(100.0, 400.0, n)
-    f = np.exp(rng.uniform(np.log(2e6), np.log(60e6), n))
+    f = np.exp(rng.uniform(np.log(f_range[0]), np.log(f_range[1]), n))
     gap = rng.uniform(0.015, 0.04, n)
     gamma = rng.uniform(0.0, 0.2, n)
     cells = np.rint(200 + 400 * (gap - 0.015) / 0.025).astype(int)
