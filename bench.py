@@ -65,6 +65,41 @@ def cpu_baseline(cfg, steps):
                        f"(load {t1 - t0:.1f} s not counted), single-threaded FP64 C oracle")
 
 
+def timed_rate(sim, torch, steps):
+    """particle-steps/s and us per step over `steps` graph-replayed steps"""
+    sim.step(64)
+    sim.sync()
+    n = sum(sum(sim.counts(b)["count"]) for b in range(sim.B))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return dict(particle_steps_per_s=n * steps / (ms * 1e-3), us_per_step=ms / steps * 1e3, particles=n)
+
+
+def secondary(P, W, torch, steps):
+    """The bounded, colliding path: one argon RF discharge (2.5 cm, 30 mTorr,
+    200 V, 13.56 MHz, 1600 steps per period) and the sweep of 64 such
+    discharges (10-200 mTorr, 100-400 V, 1.5-4 cm) in one batched step, each
+    after 3200 steps from its cold start."""
+    out = {}
+    sim = P.Sim(W.argon_rf(), W.argon_tables())
+    sim.step(3200)
+    out["argon_rf_single"] = timed_rate(sim, torch, steps)
+    sim.close()
+    draws = W.sweep_draws(64, seed=4)
+    cfgs = [W.argon_rf(gap=d["gap"], n_cells=d["n_cells"], pressure_mtorr=d["pressure_mtorr"], v_amp=d["v_amp"],
+                       seed=1000 + i, capacity=1 << 21) for i, d in enumerate(draws)]
+    sim = P.Sim(cfgs, W.argon_tables())
+    sim.step(3200)
+    out["argon_rf_batched_64"] = timed_rate(sim, torch, steps)
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +109,8 @@ def main():
     ap.add_argument("--threads", type=int, default=1024)
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the argon RF single and batched lines")
+    ap.add_argument("--secondary-steps", type=int, default=320)
     ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -154,6 +191,9 @@ def main():
                                   "finalize": float(tm["finalize_ms"]) / args.steps,
                                   "finalize_avg_launch_ms": float(tm["finalize_ms"] / max(tm["finalize_n"], 1))},
     }
+    if not args.no_secondary:
+        sim.close()
+        out["secondary"] = secondary(P, W, torch, args.secondary_steps)
     if not args.no_cpu:
         sim.close()
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

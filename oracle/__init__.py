@@ -75,6 +75,7 @@ def lib():
         L.orc_free.restype = None
         L.orc_load_xsec.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_int32, dp, dp]
         L.orc_load.argtypes = [P]
+        L.orc_get_moments.argtypes = [P, C.c_int32, dp, dp]
         L.orc_load_profiles.argtypes = [P, C.c_int32, dp, dp, C.POINTER(C.c_int64)]
         L.orc_set_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up, C.c_uint32]
         L.orc_get_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up,
@@ -193,6 +194,13 @@ class Oracle:
         temp = np.ascontiguousarray(temp_ev, dtype=np.float64)
         nn = (C.c_int64 * len(n))(*[int(v) for v in n])
         _check(lib().orc_load_profiles(self.h, dens.shape[1], _dp(dens), _dp(temp), nn), "orc_load_profiles")
+
+    def moments(self, s):
+        """(flux, x-momentum flux) densities of species s at the nodes."""
+        n = self.n_nodes
+        f, m = np.zeros(n), np.zeros(n)
+        _check(lib().orc_get_moments(self.h, s, _dp(f), _dp(m)), "orc_get_moments")
+        return f, m
 
     def refresh_field(self):
         _check(lib().orc_refresh_field(self.h), "orc_refresh_field")

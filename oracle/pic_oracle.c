@@ -921,6 +921,32 @@ int orc_get_density(const orc_sim* s, int32_t k, double* dens)
     return ORC_OK;
 }
 
+/* Velocity moments of species k at the nodes, with the weights of the charge
+ * deposit: flux[i] = w sum_p S_i(x_p) vx_p / V_i and mom[i] = w sum_p S_i(x_p)
+ * vx_p^2 / V_i (S_i the linear weight of node i, V_i its volume); with the
+ * field E[i] at the same nodes, q flux[i] E[i] is the power density the field
+ * gives the species. */
+int orc_get_moments(const orc_sim* s, int32_t k, double* flux, double* mom)
+{
+    if (!s || k < 0 || k >= s->c.n_species || !flux || !mom) return ORC_EINVAL;
+    int nn = s->nn;
+    for (int i = 0; i < nn; ++i) { flux[i] = 0.0; mom[i] = 0.0; }
+    for (int64_t p = 0; p < s->p[k].n; ++p) {
+        int64_t c, c1;
+        double f, vx = s->p[k].vx[p];
+        locate(s, s->p[k].x[p], &c, &c1, &f);
+        flux[c] += (1.0 - f) * vx;
+        flux[c1] += f * vx;
+        mom[c] += (1.0 - f) * vx * vx;
+        mom[c1] += f * vx * vx;
+    }
+    for (int i = 0; i < nn; ++i) {
+        flux[i] *= s->c.sp[k].weight / node_volume(s, i);
+        mom[i] *= s->c.sp[k].weight / node_volume(s, i);
+    }
+    return ORC_OK;
+}
+
 int orc_get_counters(const orc_sim* s, orc_counters* out)
 {
     if (!s || !out) return ORC_EINVAL;

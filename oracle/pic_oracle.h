@@ -73,6 +73,8 @@ int  orc_load_xsec(orc_sim* s, int32_t species, int32_t kind, double threshold_e
 /* Load particles (Philox draws at step 0xFFFFFFFF), deposit, solve at t = 0,
  * and take the backward half step of the leapfrog start. */
 int  orc_load(orc_sim* s);
+/* velocity moments of species k at the nodes (flux and x-momentum flux densities) */
+int  orc_get_moments(const orc_sim* s, int32_t k, double* flux, double* mom);
 /* start from density and temperature profiles at m points over [0, L]
  * (arrays [n_species][m]); n[k] particles of species k */
 int  orc_load_profiles(orc_sim* s, int32_t m, const double* density, const double* temp_ev,

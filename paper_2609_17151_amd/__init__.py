@@ -22,7 +22,7 @@ EEPF_BINS = 256
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
-            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14)
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15)
 
 
 class SpeciesCfg(C.Structure):
@@ -286,6 +286,14 @@ class Sim:
         o = self.diag("AVG", 1 + (self.S + 2) * n, batch=batch, check=check)
         prof = o[1:].reshape(self.S + 2, n)
         return dict(samples=o[0], density=prof[: self.S], phi=prof[self.S], mean_energy=prof[self.S + 1])
+
+    def power(self, batch=0):
+        """Time means per species: flux density, x-momentum flux density and
+        the power density q Gamma E the field gives the species."""
+        n = self.n_nodes[batch]
+        o = self.diag("POWER", 1 + 3 * self.S * n, batch=batch)
+        p = o[1:].reshape(self.S, 3, n)
+        return dict(samples=o[0], flux=p[:, 0], momentum=p[:, 1], power=p[:, 2])
 
     def eepf(self, batch=0):
         o = self.diag("EEPF", 2 * EEPF_BINS + 2, batch=batch)

@@ -1,0 +1,89 @@
+"""Autotuner of the step schedule: particles per thread, threads per
+workgroup, the interval of the sort by cell and the interval of the hole
+compaction.
+
+None of these changes the results: the deposit sums are exact integers, the
+random draws are keyed by particle id and step, and sorting and compaction
+keep the canonical order up to a permutation that the physics does not see.
+So the tuner times candidates on the live run itself (every timed step is a
+real step of the simulation), keeps the fastest, and remembers the choice in
+a JSON cache keyed by the shape of the workload.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+STREAMING = [(ppt, thr) for ppt, thr in ((4, 1024), (4, 512), (4, 256), (8, 256), (2, 256), (1, 256))]
+GENERAL = [(2, 256), (1, 256)]
+SORT_EVERY = (0, 32, 16)
+COMPACT_EVERY = (16, 32, 8)
+
+
+def signature(sim):
+    """Workload key: discharges, species, boundary, mesh and particle count
+    (to the nearest power of two), and whether the general kernel runs."""
+    cfg = sim.cfgs[0]
+    n = sum(sum(sim.counts(b)["count"]) for b in range(sim.B))
+    general = any(c["bc"] == 1 or c["gas_density"] > 0.0 for c in sim.cfgs)
+    cells = max(c["n_cells"] for c in sim.cfgs)
+    return "B%d-S%d-bc%d-cells%d-n2^%d-%s" % (sim.B, sim.S, cfg["bc"], cells, max(n, 1).bit_length(),
+                                              "general" if general else "streaming")
+
+
+def candidates(general):
+    shapes = GENERAL if general else STREAMING
+    out = []
+    for ppt, thr in shapes:
+        for srt in SORT_EVERY:
+            for cmp_ in (COMPACT_EVERY if general else (16,)):
+                out.append(dict(ppt=ppt, threads=thr, sort_every=srt, compact_every=cmp_))
+    return out
+
+
+def _time_steps(sim, n):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(n)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def tune(sim, steps=64, warm=32, cache=None, timer=None, verbose=False):
+    """Pick the fastest schedule for `sim`'s workload, apply it and return
+    (choice, table of ms per step).  With a cache file, a known workload is
+    applied without timing.  `timer(sim, n)` returns ms per step over n steps
+    (default: HIP events on the context's stream)."""
+    timer = timer or _time_steps
+    key = signature(sim)
+    store = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            store = json.load(f)
+        if key in store:
+            c = store[key]["choice"]
+            sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
+            return c, store[key]["table"]
+    general = key.endswith("general")
+    table = []
+    for c in candidates(general):
+        sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
+        if warm:
+            sim.step(warm)
+        ms = timer(sim, steps)
+        table.append(dict(c, ms_per_step=ms))
+        if verbose:
+            print("autotune", key, c, "%.4f ms/step" % ms, flush=True)
+    best = min(table, key=lambda r: r["ms_per_step"])
+    choice = {k: best[k] for k in ("ppt", "threads", "sort_every", "compact_every")}
+    sim.config_tiles(choice["ppt"], choice["threads"], choice["sort_every"], choice["compact_every"])
+    if cache:
+        store[key] = dict(choice=choice, table=table)
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(store, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return choice, table

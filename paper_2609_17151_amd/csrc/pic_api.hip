@@ -184,6 +184,11 @@ void bound(const pic_config& c, int s, SegHost& h)
     h.t32 = (uint32_t)t;
 }
 
+// velocity scale of the fixed-point moments: the speed of a 50 eV particle
+// of the species (|vx| up to ~2^15 of it stays exact in the int64 sums)
+constexpr double kMomentScale = 16777216.0;   // 2^24
+double moment_vref(const pic_config& c, int s) { return std::sqrt(100.0 * c.e_unit / c.species[s].mass); }
+
 void fill_push_consts(const pic_config& c, int s, SegConst& sc)
 {
     const pic_species_cfg& sp = c.species[s];
@@ -210,6 +215,8 @@ void fill_push_consts(const pic_config& c, int s, SegConst& sc)
     sc.half_m_over_e = (float)(0.5 * sp.mass / c.e_unit);
     sc.two_e_over_m = (float)(2.0 * c.e_unit / sp.mass);
     sc.two_e_over_me = (float)(2.0 * c.e_unit / c.species[0].mass);
+    sc.mscale1 = (float)(kMomentScale / moment_vref(c, s));
+    sc.mscale2 = (float)(kMomentScale / (moment_vref(c, s) * moment_vref(c, s)));
     sc.emits = (s >= 1 && sp.charge > 0.0 && c.see_gamma > 0.0 && c.bc == PIC_BC_DIRICHLET) ? 1 : 0;
     sc.see_k = (uint32_t)std::min(16777217.0, std::ceil(c.see_gamma * 16777216.0));
     sc.vsee = (float)std::sqrt(c.see_temp * c.e_unit / c.species[0].mass);
@@ -476,6 +483,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         for (int s = 0; s < S; ++s) {
             dc.dens_coef[s] = c.species[s].weight / dc.dx / kDepScale;
             dc.q[s] = c.species[s].charge;
+            dc.flux_coef[s] = c.species[s].weight / dc.dx / (kMomentScale / moment_vref(c, s));
+            dc.mom_coef[s] = c.species[s].weight / dc.dx / (kMomentScale / (moment_vref(c, s) * moment_vref(c, s)));
         }
         dc.key0 = (uint32_t)(c.seed & 0xffffffffu);
         dc.key1 = (uint32_t)(c.seed >> 32);
@@ -515,6 +524,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.acc = (unsigned long long*)A(8ull * B * S * kRep * nodes_max);
         d.cnt = (unsigned long long*)A(8ull * B * S * kRep * C_N);
         d.eacc = (unsigned long long*)A(8ull * B * nodes_max);
+        d.macc = (unsigned long long*)A(8ull * B * S * 2 * nodes_max);
+        d.pavg = (double*)A(8ull * B * S * 3 * nodes_max);
         d.rho = (double*)A(8ull * B * nodes_max);
         d.phi = (double*)A(8ull * B * nodes_max);
         d.ef = (double*)A(8ull * B * nodes_max);
@@ -553,6 +564,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.acc, 0, 8ull * B * S * kRep * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.cnt, 0, 8ull * B * S * kRep * C_N, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.macc, 0, 8ull * B * S * 2 * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.pavg, 0, 8ull * B * S * 3 * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.bcnt, 0, 4ull * tiles_max, st) == hipSuccess;
@@ -1208,10 +1221,26 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
         }
         case PIC_DIAG_RESET_AVG: {
             ok = hipMemset(ctx->d.avg + (size_t)batch * (S + 2) * nm, 0, 8ull * (S + 2) * nm) == hipSuccess;
+            ok = ok && hipMemset(ctx->d.pavg + (size_t)batch * S * 3 * nm, 0, 8ull * S * 3 * nm) == hipSuccess;
             ok = ok && hipMemset(ctx->d.eepf + (size_t)batch * 2 * kEepfBins, 0, 8ull * 2 * kEepfBins) == hipSuccess;
             ds.avg_samples = 0.0;
             ds.eepf_samples = 0.0;
             ok = ok && hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+            break;
+        }
+        case PIC_DIAG_POWER: {
+            if (!need(8ull * (1 + (size_t)3 * S * nn))) return PIC_EINVAL;
+            std::vector<double> pv((size_t)S * 3 * nm);
+            ok = d2h(pv.data(), ctx->d.pavg + (size_t)batch * S * 3 * nm, pv.size() * 8);
+            const double ns = ds.avg_samples;
+            double* o = (double*)out;
+            o[0] = ns;
+            for (int sp = 0; sp < S; ++sp)
+                for (int k = 0; k < 3; ++k)
+                    for (int i = 0; i < nn; ++i) {
+                        const double v = pv[((size_t)sp * 3 + k) * nm + i];
+                        o[1 + ((size_t)sp * 3 + k) * nn + i] = ns > 0.0 ? v / ns : 0.0;
+                    }
             break;
         }
         case PIC_DIAG_TIMING: {

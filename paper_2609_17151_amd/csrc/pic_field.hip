@@ -111,6 +111,17 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         const int io0 = s0.parity, io1 = S > 1 ? d.segs[b * S + 1].parity : 0;
         const int64_t cap0 = c0.cap, cap1 = S > 1 ? d.segc[b * S + 1].cap : 0;
         int64_t pos0 = slot0, pos1 = slot1;
+        // velocity moments of an appended birth (diagnostics), as in the push
+        auto moment_add = [&](int sp, int cell, float off, float vx) {
+            const SegConst& cs = d.segc[b * S + sp];
+            unsigned long long* ma = d.macc + ((size_t)b * S + sp) * 2 * d.nodes_max;
+            const int c1 = (periodic && cell + 1 == nc) ? 0 : cell + 1;
+            const float a1 = vx * cs.mscale1, a2 = vx * vx * cs.mscale2, w0 = 1.0f - off;
+            atomicAdd(&ma[cell], (unsigned long long)(long long)rintf(w0 * a1));
+            atomicAdd(&ma[c1], (unsigned long long)(long long)rintf(off * a1));
+            atomicAdd(&ma[d.nodes_max + cell], (unsigned long long)(long long)rintf(w0 * a2));
+            atomicAdd(&ma[d.nodes_max + c1], (unsigned long long)(long long)rintf(off * a2));
+        };
         for (int src = 0; src < S; ++src) {
             const int g = b * S + src;
             if (src > 0 && !d.segc[g].emits) continue;
@@ -140,6 +151,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                         c0.vy[io0][e] = bb.vy;
                         c0.vz[io0][e] = bb.vz;
                         c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
+                        if (a.diag) moment_add(0, bb.cell, bb.off, bb.vx);
                     }
                     if (pair) {
                         const SegConst& c1 = d.segc[b * S + 1];
@@ -151,6 +163,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                             c1.vy[io1][q] = bb.ivy;
                             c1.vz[io1][q] = bb.ivz;
                             c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
+                            if (a.diag) moment_add(1, bb.cell, bb.off, bb.ivx);
                         }
                     }
                 }
@@ -383,6 +396,19 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
             av[(size_t)(S + 1) * d.nodes_max + i] += (double)ea[i] * ecoef * wall;   // n_e <eps>
             ea[i] = 0ull;
+            // flux, momentum flux and the power the new field gives each species
+            const double e = efield(i);
+            for (int s = 0; s < S; ++s) {
+                unsigned long long* ma = d.macc + ((size_t)b * S + s) * 2 * d.nodes_max;
+                double* pv = d.pavg + ((size_t)b * S + s) * 3 * d.nodes_max;
+                const double G = (double)(long long)ma[i] * dc.flux_coef[s] * wall;
+                const double M = (double)(long long)ma[d.nodes_max + i] * dc.mom_coef[s] * wall;
+                ma[i] = 0ull;
+                ma[d.nodes_max + i] = 0ull;
+                pv[i] += G;
+                pv[d.nodes_max + i] += M;
+                pv[2 * (size_t)d.nodes_max + i] += dc.q[s] * G * e;
+            }
         }
     }
     __syncthreads();

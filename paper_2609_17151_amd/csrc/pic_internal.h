@@ -89,6 +89,9 @@ struct SegConst {
     float dtdx_e;           // dt/dx of the electron species (same mesh and dt)
     // electrons born here: speed from energy
     float two_e_over_me;
+    // velocity moments (diagnostics) in fixed point: per particle weight x
+    // vx x mscale1 and weight x vx^2 x mscale2, rounded to integers
+    float mscale1, mscale2;
 };
 
 struct DisConst {
@@ -100,6 +103,7 @@ struct DisConst {
     double wall_coef;          // dx / (2 eps0)
     double dens_coef[kMaxSpecies];   // weight / dx / 2^32 (interior node; twice at a wall node)
     double q[kMaxSpecies];     // species charge
+    double flux_coef[kMaxSpecies], mom_coef[kMaxSpecies];   // moment sums -> densities (interior node)
     uint32_t key0, key1;
 };
 
@@ -137,6 +141,8 @@ struct DevPtrs {
     unsigned long long* acc;     // [B][S][kRep][nodes_max] deposit sums (fixed point)
     unsigned long long* cnt;     // [B][S][kRep][C_N] event counters
     unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^24)
+    unsigned long long* macc;    // [B][S][2][nodes_max] flux and x-momentum flux sums of the step (fixed point)
+    double* pavg;                // [B][S][3][nodes_max] time sums of flux, momentum flux, power density
     double* rho;                 // [B][nodes_max]
     double* phi;
     double* ef;

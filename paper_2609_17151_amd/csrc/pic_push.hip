@@ -388,6 +388,19 @@ __device__ __forceinline__ void collide_particle(const DevPtrs& d, const SegCons
     }
 }
 
+// velocity moments of a particle at the nodes, fixed point (diagnostics)
+__device__ __forceinline__ void moment_diag(const SegConst& sc, unsigned long long* fh, unsigned long long* mh, int c,
+                                            float f, float ux, int nc, int periodic)
+{
+    const int c1 = (periodic && c + 1 == nc) ? 0 : c + 1;
+    const float a = ux * sc.mscale1, b2 = ux * ux * sc.mscale2;
+    const float w0 = 1.0f - f;
+    atomicAdd(&fh[c], (unsigned long long)(long long)rintf(w0 * a));
+    atomicAdd(&fh[c1], (unsigned long long)(long long)rintf(f * a));
+    atomicAdd(&mh[c], (unsigned long long)(long long)rintf(w0 * b2));
+    atomicAdd(&mh[c1], (unsigned long long)(long long)rintf(f * b2));
+}
+
 __device__ __forceinline__ void electron_diag(const SegConst& sc, const PushArgs& a, unsigned long long* ehist,
                                               unsigned int* eepf, int c, float f, float ux, float uy, float uz,
                                               int nc, int periodic)
@@ -475,11 +488,15 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     __syncthreads();
     const int32_t NT = s_pref[NS];
 
-    // LDS layout: deposit histogram, [energy histogram, EEPF], E pairs
+    // LDS layout: deposit histogram, [energy, flux and momentum-flux
+    // histograms, EEPF], E pairs
     const int nn_max = a.nodes_max_dyn;
+    const int dn = a.diag ? nn_max : 0;
     unsigned long long* hist = reinterpret_cast<unsigned long long*>(smem);
     unsigned long long* ehist = hist + nn_max;
-    unsigned int* eepf = reinterpret_cast<unsigned int*>(ehist + (a.diag ? nn_max : 0));
+    unsigned long long* fhist = ehist + dn;
+    unsigned long long* mhist = fhist + dn;
+    unsigned int* eepf = reinterpret_cast<unsigned int*>(mhist + dn);
     float2* ep = reinterpret_cast<float2*>(eepf + (a.diag ? kEepfBins : 0));
 
     int cur_g = -1, cur_b = -1;
@@ -501,6 +518,14 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         for (int i = tid; i < dcf.n_nodes; i += kBS) {
             const unsigned long long v = hist[i];
             if (v) atomicAdd(&acc_s[i], v);
+        }
+        if (a.diag) {
+            unsigned long long* ma = d.macc + (size_t)cg * 2 * d.nodes_max;
+            for (int i = tid; i < dcf.n_nodes; i += kBS) {
+                const unsigned long long v = fhist[i], w = mhist[i];
+                if (v) atomicAdd(&ma[i], v);
+                if (w) atomicAdd(&ma[d.nodes_max + i], w);
+            }
         }
         if (a.diag && cs == 0) {
             unsigned long long* ea = d.eacc + (size_t)cb * d.nodes_max;
@@ -549,6 +574,12 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 for (int i = tid; i < dc.n_cells; i += kBS) ep[i] = epg[i];
             }
             for (int i = tid; i < dc.n_nodes; i += kBS) hist[i] = 0ull;
+            if (a.diag) {
+                for (int i = tid; i < dc.n_nodes; i += kBS) {
+                    fhist[i] = 0ull;
+                    mhist[i] = 0ull;
+                }
+            }
             if (a.diag && s == 0) {
                 for (int i = tid; i < dc.n_nodes; i += kBS) ehist[i] = 0ull;
                 for (int i = tid; i < kEepfBins; i += kBS) eepf[i] = 0u;
@@ -615,8 +646,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                     e.uz = vz[j];
                     e.pid = pid[j];
                     s_q[q] = e;
-                } else if (a.diag && s == 0) {
-                    electron_diag(sc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
+                } else if (a.diag) {
+                    moment_diag(sc, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
+                    if (s == 0)
+                        electron_diag(sc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
                 }
             } else {
                 cell[j] = -1;                              // absorbed: leaves a hole
@@ -659,7 +692,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 sc.vx[io][slot] = e.ux;
                 sc.vy[io][slot] = e.uy;
                 sc.vz[io][slot] = e.uz;
-                if (a.diag && s == 0) electron_diag(sc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
+                if (a.diag) {
+                    moment_diag(sc, fhist, mhist, e.c, e.f, e.ux, nc, periodic);
+                    if (s == 0) electron_diag(sc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
+                }
             }
             __syncthreads();
             // the tile's births in the order of their parents' slots
@@ -706,7 +742,7 @@ PIC_KERNELS(PIC_INST)
 size_t push_lds_bytes(int n_nodes, int n_cells, int diag)
 {
     size_t b = (size_t)n_nodes * 8;
-    if (diag) b += (size_t)n_nodes * 8 + kEepfBins * 4;
+    if (diag) b += (size_t)n_nodes * 8 * 3 + kEepfBins * 4;
     b = (b + 15) & ~(size_t)15;
     b += (size_t)n_cells * 8;
     return b;

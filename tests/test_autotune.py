@@ -1,0 +1,75 @@
+"""The step-schedule autotuner: candidate sets, the choice of the fastest,
+the cache (host logic, on a stand-in context), and on the GPU that a tuned
+run reaches exactly the state of an untuned one."""
+import json
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2609_17151_amd import autotune
+
+
+class FakeSim:
+    def __init__(self, cfg):
+        self.cfgs, self.B, self.S = [cfg], 1, len(cfg["species"])
+        self.applied, self.stepped = [], 0
+
+    def counts(self, b):
+        return dict(count=[1000] * self.S, step=0, flags=0)
+
+    def config_tiles(self, ppt, threads, sort_every, compact_every):
+        self.applied.append((ppt, threads, sort_every, compact_every))
+
+    def step(self, n):
+        self.stepped += n
+
+
+def fake_timer(sim, n):
+    ppt, thr, srt, cmp_ = sim.applied[-1]
+    sim.stepped += n
+    return 1.0 + 0.1 * ppt + (0.0 if thr == 512 else 0.05) + 0.01 * srt + 0.001 * cmp_
+
+
+def test_candidates_by_kernel_mode():
+    g = autotune.candidates(True)
+    s = autotune.candidates(False)
+    assert all(c["threads"] == 256 and c["ppt"] <= 2 for c in g)
+    assert {c["compact_every"] for c in g} == set(autotune.COMPACT_EVERY)
+    assert {(c["ppt"], c["threads"]) for c in s} == set(autotune.STREAMING)
+
+
+def test_picks_fastest_and_caches(tmp_path):
+    cfg = W.langmuir(n_particles=4096)
+    sim = FakeSim(cfg)
+    cache = str(tmp_path / "tune.json")
+    choice, table = autotune.tune(sim, steps=8, warm=0, cache=cache, timer=fake_timer)
+    assert choice == dict(ppt=1, threads=256, sort_every=0, compact_every=16)
+    best = min(table, key=lambda r: r["ms_per_step"])
+    assert all(choice[k] == best[k] for k in choice)
+    assert sim.applied[-1] == (choice["ppt"], choice["threads"], choice["sort_every"], choice["compact_every"])
+    stored = json.load(open(cache))
+    assert autotune.signature(sim) in stored
+    # a known workload is applied from the cache without timing
+    sim2 = FakeSim(cfg)
+    c2, _ = autotune.tune(sim2, steps=8, warm=0, cache=cache, timer=fake_timer)
+    assert c2 == choice and sim2.stepped == 0 and len(sim2.applied) == 1
+
+
+@pytest.mark.gpu
+def test_tuned_run_reaches_the_untuned_state():
+    import paper_2609_17151_amd as P
+    from gpu_helpers import small_argon
+    cfg, tabs = small_argon(n_init=20000)
+    a = P.Sim(cfg, tabs)
+    choice, table = autotune.tune(a, steps=16, warm=8)
+    n = a.counts()["step"]
+    b = P.Sim(cfg, tabs)
+    b.step(n)
+    assert a.counts()["count"] == b.counts()["count"]
+    for s in range(2):
+        pa, pb = a.get_particles(s), b.get_particles(s)
+        ia, ib = np.argsort(pa["id"]), np.argsort(pb["id"])
+        for k in ("cell", "off", "vx", "vy", "vz", "id"):
+            assert np.array_equal(pa[k][ia], pb[k][ib]), k
+    np.testing.assert_array_equal(a.rho(), b.rho())

@@ -1,0 +1,57 @@
+"""Power-decomposition moments on the GPU (PIC_DIAG_POWER) against the
+oracle's moments of the same state: one diagnostic step from identical
+states, so the time mean is the single step's value."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import small_argon, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pic():
+    import paper_2609_17151_amd as P
+    return P
+
+
+def check(sim, o, cfg):
+    pw = sim.power()
+    assert pw["samples"] == 1.0
+    ef = o.field()[2]
+    for s in range(len(cfg["species"])):
+        fo, mo = o.moments(s)
+        dens = o.density(s)
+        vth = max(cfg["species"][s]["vth"], 1e-30)
+        scale_f = max(dens.max(), 1e-300) * vth * 10
+        scale_m = max(dens.max(), 1e-300) * vth * vth * 100
+        assert np.max(np.abs(pw["flux"][s] - fo)) <= 1e-5 * scale_f
+        assert np.max(np.abs(pw["momentum"][s] - mo)) <= 1e-5 * scale_m
+        po = cfg["species"][s]["charge"] * fo * ef
+        assert np.max(np.abs(pw["power"][s] - po)) <= 1e-4 * max(np.max(np.abs(po)), 1e-300) + \
+            1e-5 * scale_f * abs(cfg["species"][s]["charge"]) * np.max(np.abs(ef))
+
+
+def test_power_moments_bounded_with_collisions(pic):
+    cfg, tabs = small_argon(n_init=20000)
+    sim = pic.Sim(cfg, tabs)
+    sim.step(400)                                   # a developed, non-uniform state
+    o = to_oracle(sim, cfg, tabs)
+    sim.set_diag(True)
+    sim.reset_avg()
+    sim.step(1)
+    o.step(1)
+    check(sim, o, cfg)
+
+
+def test_power_moments_periodic_streaming(pic):
+    cfg = W.langmuir(n_particles=65536)
+    sim = pic.Sim(cfg)
+    sim.step(20)
+    o = to_oracle(sim, cfg)
+    sim.set_diag(True)
+    sim.reset_avg()
+    sim.step(1)
+    o.step(1)
+    check(sim, o, cfg)

@@ -277,3 +277,26 @@ def test_perturbed_loading_mode_amplitude():
     x = np.arange(o.n_nodes) * L / o.n_nodes
     amp = 2 / o.n_nodes * np.sum(n * np.cos(2 * np.pi * x / L))
     assert abs(amp - 0.01) < 5e-4
+
+
+def test_moments_of_a_drifting_beam():
+    """A cold beam of velocity vd: flux n vd and momentum flux n vd^2 at every
+    node (n the deposited density there), and volume integrals w N vd and
+    w N vd^2 (half-cell volumes at walls)."""
+    import oracle as O
+    for bc in (0, 1):
+        n, L, vd = 4096, 2.0, -0.37
+        sp = [W.species(-1.0, 1.0, 0.5, n, 0.0, drift=(vd, 0.0, 0.0), load=W.LOAD_STRATIFIED)]
+        cfg = W.base_config(n_cells=64, bc=bc, field_solve=0, length=L, species=sp)
+        o = O.Oracle(cfg)
+        flux, mom = o.moments(0)
+        # partition of unity: the volume integrals are w N vd and w N vd^2
+        dx = L / 64
+        vol = np.full(len(flux), dx)
+        if bc == 1:
+            vol[0] = vol[-1] = 0.5 * dx
+        assert np.sum(vol * flux) == pytest.approx(0.5 * n * vd, rel=1e-12)
+        assert np.sum(vol * mom) == pytest.approx(0.5 * n * vd * vd, rel=1e-12)
+        dens = o.density(0)
+        np.testing.assert_allclose(flux, dens * vd, rtol=1e-12)
+        np.testing.assert_allclose(mom, dens * vd * vd, rtol=1e-12)
