@@ -74,7 +74,7 @@ def cmd_plain(a):
                converged_window=i, converged_periods=per, seconds_to_converge=t_conv,
                seconds_total=sw.window_time[0][-1], steps=sw.window_step[0][-1],
                us_per_step=sw.window_time[0][-1] / sw.window_step[0][-1] * 1e6)
-    np.savez(a.out, windows=np.array(sw.windows[0], dtype=np.float32), ref=ref,
+    np.savez(a.out, dist=np.array([steady.distance(w, ref) for w in sw.windows[0]]), ref=ref,
              times=np.array(sw.window_time[0]), steps=np.array(sw.window_step[0]), x=warm.inputs(draw))
     print(json.dumps(out), flush=True)
 
@@ -84,9 +84,18 @@ def cmd_sweep(a):
     grouped by frequency; windows, references and timings per draw."""
     draws = SETS[a.set]()[a.start:a.start + a.count]
     order = sorted(range(len(draws)), key=lambda i: -draws[i].get("freq", 13.56e6))
-    X, REF, WIN, TIMES, STEPS, CONV = [], [], [], [], [], []
+    X, REF, DIST, TIMES, STEPS, CONV, CNT = [], [], [], [], [], [], []
     ids = []
     total = 0.0
+
+    def save():
+        # compact: the reference and each window's distance to it, not the windows
+        nw = max(len(t) for t in TIMES)
+        pad = lambda rows: np.array([np.pad(np.asarray(r, dtype=np.float64), (0, nw - len(r)),
+                                            constant_values=np.nan) for r in rows])
+        np.savez(a.out, ids=np.array(ids), x=np.array(X), y=np.array(REF), dist=pad(DIST), times=pad(TIMES),
+                 steps=pad(STEPS), conv=np.array(CONV), counts=np.array(CNT))
+
     for k in range(0, len(order), a.batch):
         grp = order[k:k + a.batch]
         cfgs = [warm.config(draws[i], weight=weight_of(draws[i], a), seed=1000 + a.start + i,
@@ -100,18 +109,18 @@ def cmd_sweep(a):
             ids.append(a.start + i)
             X.append(warm.inputs(draws[i]))
             REF.append(steady.to_features(ref))
-            WIN.append(np.array(sw.windows[j], dtype=np.float32))
-            TIMES.append(np.array(sw.window_time[j]))
-            STEPS.append(np.array(sw.window_step[j]))
+            DIST.append([steady.distance(w, ref) for w in sw.windows[j]])
+            TIMES.append(sw.window_time[j])
+            STEPS.append(sw.window_step[j])
             CONV.append(convergence(sw.windows[j], ref)[1] or -1)
+            CNT.append(sim.counts(j)["count"])
         cnt = [sim.counts(j)["count"] for j in range(len(grp))]
         flags = [sw.flags[j] for j in range(len(grp))]
         print(json.dumps(dict(batch=k // a.batch, discharges=len(grp), seconds=time.perf_counter() - t0,
                               flags=sorted(set(flags)), min_count=int(np.min(cnt)), max_count=int(np.max(cnt)),
                               total=int(np.sum(cnt)))), flush=True)
         sim.close()
-    np.savez(a.out, ids=np.array(ids), x=np.array(X), y=np.array(REF), windows=np.array(WIN, dtype=object),
-             times=np.array(TIMES, dtype=object), steps=np.array(STEPS, dtype=object), conv=np.array(CONV))
+        save()
     print(json.dumps(dict(kind="sweep", set=a.set, draws=len(draws), seconds=total,
                           converged=int(np.sum(np.array(CONV) > 0)),
                           mean_periods_to_converge=float(np.mean([c for c in CONV if c > 0])) if any(
@@ -174,7 +183,7 @@ def cmd_warm(a):
                    c > 0 for c in cold_conv) else None)
     np.savez(a.out, ids=np.array(ids), conv=np.array(conv), cold_conv=np.array(cold_conv),
              t_conv=np.array([t if t is not None else -1.0 for t in t_conv]),
-             windows=np.array([np.array(w, dtype=np.float32) for w in sw.windows], dtype=object))
+             dist0=np.array([steady.distance(sw.windows[j][0], ref_prof[j]) for j in range(len(ids))]))
     print(json.dumps(out), flush=True)
 
 

@@ -42,8 +42,12 @@ def window(sim, batch=0, electron=0, ion=1):
 def distance(w, ref):
     """Largest relative L2 distance over the three profiles."""
     w, ref = np.asarray(w), np.asarray(ref)
-    return max(float(np.linalg.norm(w[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-300))
-               for k in range(ref.shape[0]))
+    out = 0.0
+    for k in range(ref.shape[0]):
+        nr = float(np.linalg.norm(ref[k]))
+        nd = float(np.linalg.norm(w[k] - ref[k]))
+        out = max(out, nd / nr if nr > 0.0 else (0.0 if nd == 0.0 else float("inf")))
+    return out
 
 
 def converged_at(windows, ref, tol=TOL, nrun=NRUN):
