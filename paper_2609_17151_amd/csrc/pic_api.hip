@@ -735,7 +735,7 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.fa.mode = kFinStep;
     p.fa.diag = ctx->diag;
     p.fa.only_b = -1;
-    p.fa.births_per_tile = T / kBirthsDiv;
+    p.fa.births_per_tile = p.general ? T / kBirthsDiv : 0;
     mix((uint64_t)ctx->sort_every);
     mix((uint64_t)ctx->compact_every);
     p.key = key;

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     // order of their electrons.  All threads, one tile per thread per round.
     __shared__ int64_t s_app[kMaxSpecies], s_want[kMaxSpecies];
     __shared__ uint32_t s_scan[kWaves];
-    if (a.mode == kFinStep) {
+    if (a.mode == kFinStep && a.births_per_tile > 0) {
         const SegState& s0 = d.segs[b * S + 0];
         const SegConst& c0 = d.segc[b * S + 0];
         const int64_t slot0 = s0.count, slot1 = S > 1 ? d.segs[b * S + 1].count : 0;
@@ -204,7 +204,8 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     if (lane == 0) st.ke = acc_k;
                 }
                 if (lane == 0) {
-                    const int64_t app = s_app[s], want = s_want[s];
+                    const bool births = a.births_per_tile > 0;
+                    const int64_t app = births ? s_app[s] : 0, want = births ? s_want[s] : 0;
                     if (app < want) {
                         atomicOr(&ds.flags, kFlagCapacity);
                         d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(want - app);

@@ -24,7 +24,7 @@ struct FinArgs {
     int32_t mode;
     int32_t diag;
     int32_t only_b;               // -1: all discharges (grid = B), else this one (grid = 1)
-    int32_t births_per_tile;      // staging slots of a push tile
+    int32_t births_per_tile;      // staging slots of a push tile (0: the step cannot have births)
     double t_ext;
     const double* rho_ext;
     double* phi_out;

@@ -8,10 +8,10 @@ started from the learned warm start.
     python -m paper_2609_17151_amd.experiments warm    --model model.npz --cold cold.npz --out warm.npz
 
 Converged (steady): the 5-period windows stay within 2 % (relative L2, each
-of n_e, n_i, <eps> at 256 points) of the reference, the mean of the last 50
-periods of the cold run (periods 251-300 of a 300-period run), for 10
-windows in a row; the convergence time is the end of the first of those
-windows.  Every run prints one JSON line.
+of n_e, n_i, <eps> at 256 points; or three times the windows' own scatter
+when that is larger) of the reference, the mean of the last 50 periods of
+the cold run, for 10 windows in a row; the convergence time is the end of
+the first of those windows.  Every run prints one JSON line.
 """
 from __future__ import annotations
 
@@ -54,10 +54,15 @@ def weight_of(draw, a):
     return w
 
 
-def convergence(windows, ref, window_periods=5):
+def convergence(windows, ref, tol=steady.TOL, window_periods=5):
     """(first converged window, periods to convergence) or (None, None)."""
-    i = steady.converged_at(windows, ref)
+    i = steady.converged_at(windows, ref, tol=tol)
     return (None, None) if i is None else (i, (i + 1) * window_periods)
+
+
+def cold_tolerance(windows, ref):
+    """2 % or three times the scatter of the reference windows."""
+    return steady.noise_tolerance([steady.distance(w, ref) for w in windows])
 
 
 def cmd_plain(a):
@@ -68,9 +73,10 @@ def cmd_plain(a):
     sim = _sim([cfg])
     sw = Sweep(sim, [warm.steps_per_period(draw)], max_periods=a.periods).run()
     ref = sw.reference(0)
-    i, per = convergence(sw.windows[0], ref)
+    tol = cold_tolerance(sw.windows[0], ref)
+    i, per = convergence(sw.windows[0], ref, tol)
     t_conv = sw.window_time[0][i] if i is not None else None
-    out = dict(kind="plain", periods=a.periods, counts=sim.counts(0)["count"],
+    out = dict(kind="plain", periods=a.periods, counts=sim.counts(0)["count"], tolerance=tol,
                converged_window=i, converged_periods=per, seconds_to_converge=t_conv,
                seconds_total=sw.window_time[0][-1], steps=sw.window_step[0][-1],
                us_per_step=sw.window_time[0][-1] / sw.window_step[0][-1] * 1e6)
@@ -84,7 +90,7 @@ def cmd_sweep(a):
     grouped by frequency; windows, references and timings per draw."""
     draws = SETS[a.set]()[a.start:a.start + a.count]
     order = sorted(range(len(draws)), key=lambda i: -draws[i].get("freq", 13.56e6))
-    X, REF, DIST, TIMES, STEPS, CONV, CNT = [], [], [], [], [], [], []
+    X, REF, DIST, TIMES, STEPS, CONV, CNT, TOL = [], [], [], [], [], [], [], []
     ids = []
     total = 0.0
 
@@ -94,7 +100,7 @@ def cmd_sweep(a):
         pad = lambda rows: np.array([np.pad(np.asarray(r, dtype=np.float64), (0, nw - len(r)),
                                             constant_values=np.nan) for r in rows])
         np.savez(a.out, ids=np.array(ids), x=np.array(X), y=np.array(REF), dist=pad(DIST), times=pad(TIMES),
-                 steps=pad(STEPS), conv=np.array(CONV), counts=np.array(CNT))
+                 steps=pad(STEPS), conv=np.array(CONV), counts=np.array(CNT), tol=np.array(TOL))
 
     for k in range(0, len(order), a.batch):
         grp = order[k:k + a.batch]
@@ -112,7 +118,8 @@ def cmd_sweep(a):
             DIST.append([steady.distance(w, ref) for w in sw.windows[j]])
             TIMES.append(sw.window_time[j])
             STEPS.append(sw.window_step[j])
-            CONV.append(convergence(sw.windows[j], ref)[1] or -1)
+            TOL.append(steady.noise_tolerance(DIST[-1]))
+            CONV.append(convergence(sw.windows[j], ref, TOL[-1])[1] or -1)
             CNT.append(sim.counts(j)["count"])
         cnt = [sim.counts(j)["count"] for j in range(len(grp))]
         flags = [sw.flags[j] for j in range(len(grp))]
@@ -143,14 +150,35 @@ def cmd_train(a):
                           train_loss=m.loss(X[tr], Y[tr]), validation_loss=m.loss(X[va], Y[va]))), flush=True)
 
 
+def cold_summary(cold):
+    """Per cold draw: tolerance, periods to convergence and whether the
+    discharge survived (from the stored distances and counts)."""
+    out = []
+    for k in range(len(cold["ids"])):
+        d = cold["dist"][k]
+        d = d[np.isfinite(d)]
+        tol = steady.noise_tolerance(d)
+        ok = [x <= tol for x in d]
+        i = next((j for j in range(len(ok) - steady.NRUN + 1) if all(ok[j:j + steady.NRUN])), None)
+        alive = int(cold["counts"][k][0]) > 0 and int(cold["counts"][k][1]) > 0
+        t = cold["times"][k]
+        out.append(dict(tol=tol, periods=(i + 1) * 5 if i is not None else None, alive=alive,
+                        steps=int(cold["steps"][k][i]) if i is not None else None,
+                        batch_seconds=float(t[i]) if i is not None else None))
+    return out
+
+
 def cmd_warm(a):
     """Held-out draws started from the network, run together until each has
     converged to its cold run's reference (then retired)."""
-    cold = np.load(a.cold, allow_pickle=True)
+    cold = np.load(a.cold)
+    summ = cold_summary(cold)
     st = np.load(a.model)
     draws = SETS["heldout"]()
-    ids = [int(i) for i in cold["ids"]]
-    refs = {i: steady.from_features(y) for i, y in zip(ids, cold["y"])}
+    keep = [k for k in range(len(cold["ids"])) if summ[k]["alive"]]
+    ids = [int(cold["ids"][k]) for k in keep]
+    ref_prof = [steady.from_features(cold["y"][k]) for k in keep]
+    tols = [summ[k]["tol"] for k in keep]
     t0 = time.perf_counter()
     m = warm.Model(widths=tuple(int(w) for w in st["widths"]))
     m.set_state(st)
@@ -160,29 +188,34 @@ def cmd_warm(a):
     sim = _sim(cfgs)
     for j in range(len(ids)):
         warm.start_from_features(sim, j, cfgs[j], feats[j])
+    sim.sync()
     t_ready = time.perf_counter() - t0
-    # the reference is stored as features: back to profiles for the distance
-    ref_prof = [refs[i] for i in ids]
 
     def stop(j, sw):
-        return steady.converged_at(sw.windows[j], ref_prof[j]) is not None
+        return steady.converged_at(sw.windows[j], ref_prof[j], tol=tols[j]) is not None
 
     sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in ids], max_periods=a.periods).run(stop=stop)
-    conv, t_conv = [], []
+    conv, t_conv, steps_conv = [], [], []
     for j in range(len(ids)):
-        i, per = convergence(sw.windows[j], ref_prof[j])
+        i, per = convergence(sw.windows[j], ref_prof[j], tols[j])
         conv.append(per if per is not None else -1)
         t_conv.append(t_ready + sw.window_time[j][i] if i is not None else None)
+        steps_conv.append(sw.window_step[j][i] if i is not None else None)
     done = [t for t in t_conv if t is not None]
-    cold_conv = [int(c) for c in cold["conv"]]
-    out = dict(kind="warm", draws=len(ids), seconds_inference_and_load=t_ready,
-               converged=len(done), seconds_to_last_convergence=max(done) if done else None,
+    cold_periods = [summ[k]["periods"] for k in keep]
+    out = dict(kind="warm", draws=len(ids), seconds_inference_and_load=t_ready, converged=len(done),
+               seconds_to_last_convergence=max(done) if done else None,
                seconds_per_converged_discharge=(max(done) / len(ids)) if len(done) == len(ids) else None,
                mean_periods_warm=float(np.mean([c for c in conv if c > 0])) if done else None,
-               mean_periods_cold=float(np.mean([c for c in cold_conv if c > 0])) if any(
-                   c > 0 for c in cold_conv) else None)
-    np.savez(a.out, ids=np.array(ids), conv=np.array(conv), cold_conv=np.array(cold_conv),
+               median_periods_warm=float(np.median([c for c in conv if c > 0])) if done else None,
+               mean_periods_cold=float(np.mean([c for c in cold_periods if c])),
+               median_periods_cold=float(np.median([c for c in cold_periods if c])),
+               first_window_distance_median=float(np.median(
+                   [steady.distance(sw.windows[j][0], ref_prof[j]) for j in range(len(ids))])))
+    np.savez(a.out, ids=np.array(ids), conv=np.array(conv),
+             cold_conv=np.array([c if c else -1 for c in cold_periods]), tol=np.array(tols),
              t_conv=np.array([t if t is not None else -1.0 for t in t_conv]),
+             steps_conv=np.array([s if s is not None else -1 for s in steps_conv]),
              dist0=np.array([steady.distance(sw.windows[j][0], ref_prof[j]) for j in range(len(ids))]))
     print(json.dumps(out), flush=True)
 

@@ -7,9 +7,12 @@ the mesh nodes.  Every profile is resampled to NPTS points evenly spread over
 x / gap, so discharges with different meshes compare point by point.
 
 Converged: the reference state of a discharge is the mean of its windows over
-a late span of a cold run (for instance periods 251-300); a run has converged
-at the first window after which NRUN consecutive windows all lie within a
-relative L2 distance TOL of the reference, in each of the three profiles.
+a late span of a cold run (the last 50 periods); a run has converged at the
+first window after which NRUN consecutive windows all lie within a relative
+L2 distance of the reference, in each of the three profiles.  The distance
+allowed is 2 % or, when a window's own statistical scatter is larger, three
+times that scatter (the RMS distance of the reference span's windows to their
+mean), as profiles are held to 2 % or the run's statistical error.
 """
 from __future__ import annotations
 
@@ -48,6 +51,16 @@ def distance(w, ref):
         nd = float(np.linalg.norm(w[k] - ref[k]))
         out = max(out, nd / nr if nr > 0.0 else (0.0 if nd == 0.0 else float("inf")))
     return out
+
+
+def noise_tolerance(dists, span_windows=10, k=3.0, floor=TOL):
+    """Allowed distance: max(floor, k x RMS of the last `span_windows`
+    distances to the reference), the windows that make up the reference."""
+    d = np.asarray(dists, dtype=np.float64)
+    d = d[np.isfinite(d)][-span_windows:]
+    if d.size == 0:
+        return floor
+    return max(floor, k * float(np.sqrt(np.mean(d * d))))
 
 
 def converged_at(windows, ref, tol=TOL, nrun=NRUN):

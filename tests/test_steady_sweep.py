@@ -96,3 +96,11 @@ def test_sweep_early_stop_retires():
     assert len(sw.windows[0]) == 3 and len(sw.windows[1]) == 100
     with pytest.raises(ValueError):
         Sweep(FakeSim(2), [4], window_periods=1)
+
+
+def test_noise_tolerance():
+    assert steady.noise_tolerance([0.5] * 5 + [0.001] * 10) == steady.TOL
+    d = [0.3, 0.2] + [0.01, 0.03] * 5
+    rms = float(np.sqrt(np.mean(np.array([0.01, 0.03] * 5) ** 2)))
+    assert steady.noise_tolerance(d) == pytest.approx(3 * rms)
+    assert steady.noise_tolerance([float("nan")] * 3) == steady.TOL
