@@ -80,16 +80,19 @@ def timed_rate(sim, torch, steps):
     return dict(particle_steps_per_s=n * steps / (ms * 1e-3), us_per_step=ms / steps * 1e3, particles=n)
 
 
-def secondary(P, W, torch, steps):
+def secondary(P, W, torch, steps, only=None):
     """The bounded, colliding path: one argon RF discharge (2.5 cm, 30 mTorr,
     200 V, 13.56 MHz, 1600 steps per period) and the sweep of 64 such
     discharges (10-200 mTorr, 100-400 V, 1.5-4 cm) in one batched step, each
     after 3200 steps from its cold start."""
     out = {}
-    sim = P.Sim(W.argon_rf(), W.argon_tables())
-    sim.step(3200)
-    out["argon_rf_single"] = timed_rate(sim, torch, steps)
-    sim.close()
+    if only in (None, "argon_rf"):
+        sim = P.Sim(W.argon_rf(), W.argon_tables())
+        sim.step(3200)
+        out["argon_rf_single"] = timed_rate(sim, torch, steps)
+        sim.close()
+    if only not in (None, "argon_sweep"):
+        return out
     draws = W.sweep_draws(64, seed=4)
     cfgs = [W.argon_rf(gap=d["gap"], n_cells=d["n_cells"], pressure_mtorr=d["pressure_mtorr"], v_amp=d["v_amp"],
                        seed=1000 + i, capacity=1 << 21) for i, d in enumerate(draws)]
@@ -113,6 +116,8 @@ def main():
     ap.add_argument("--secondary-steps", type=int, default=320)
     ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
+    ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
+                    help="argon_rf / argon_sweep: only that secondary workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -134,6 +139,10 @@ def main():
     import paper_2609_17151_amd as P
 
     torch.cuda.set_device(0)
+    if args.workload != "exb":
+        r = secondary(P, W, torch, args.secondary_steps, only=args.workload)
+        print(json.dumps(dict(workload=args.workload, **r[next(iter(r))])), flush=True)
+        return
     cfg = W.exb()
     n = sum(sp["n_init"] for sp in cfg["species"])
     sim = P.Sim(cfg)

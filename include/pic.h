@@ -16,7 +16,7 @@
  *   - Work is queued on the HIP stream given to pic_init.  pic_step returns as
  *     soon as the work is queued; conditions met on the device (capacity
  *     overflow, non-finite values, a collision frequency above the bound, a
- *     cell out of range, a stalled tile chain) are latched in a flag word and
+ *     cell out of range) are latched in a flag word and
  *     returned by the next pic_sync or pic_diag.
  *   - A context is used by one host thread at a time.
  *
@@ -44,7 +44,7 @@ typedef int32_t pic_status;
 #define PIC_ECAPACITY (-4)   /* particle or birth capacity exceeded (births dropped) */
 #define PIC_ENUMERIC (-5)    /* non-finite particle state */
 #define PIC_ESTATE (-6)      /* call not valid in the current state */
-#define PIC_ESTALL (-7)      /* a tile waited too long for its predecessor */
+#define PIC_ESTALL (-7)      /* reserved: no kernel of the library waits on another workgroup */
 
 /* Boundary conditions of the 1D domain [0, L): periodic column or a gap
  * between two electrodes (Section 1: "between two electrodes", "closed on

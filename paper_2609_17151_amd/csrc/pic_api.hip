@@ -394,7 +394,7 @@ const char* pic_strerror(pic_status s)
         case PIC_ECAPACITY: return "particle capacity exceeded";
         case PIC_ENUMERIC: return "non-finite or out-of-range particle state";
         case PIC_ESTATE: return "invalid state";
-        case PIC_ESTALL: return "tile chain stalled";
+        case PIC_ESTALL: return "reserved status";
         default: return "unknown status";
     }
 }

@@ -1,9 +1,10 @@
 // Internal layout of the MI355X PIC-MCC library: constant and mutable state of
 // every (discharge, species) segment and of every discharge, and the kernel
 // argument blocks.  Device memory is structure-of-arrays: per segment, one
-// array per particle field (cell i32, in-cell offset f32, vx/vy/vz f32, id u32),
-// two copies when particles can leave (walls) so that survivors are compacted
-// into the other copy in their original order.
+// array per particle field (cell i32, in-cell offset f32, vx/vy/vz f32, id u32)
+// in two copies: the step updates one copy in place, and the compaction of
+// the holes left by absorbed particles (and the optional sort) writes the
+// other, preserving the order of the live particles.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
