@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic_mi355x.so")
+LIB_PATH = os.environ.get("PIC_MI355X_LIB", LIB_PATH)   # another build of the same library
 
 MAX_SPECIES = 4
 MAX_CHAN = 8
