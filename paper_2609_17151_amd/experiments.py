@@ -135,8 +135,15 @@ def cmd_sweep(a):
 
 
 def cmd_train(a):
-    X = np.concatenate([np.load(f, allow_pickle=True)["x"] for f in a.data])
-    Y = np.concatenate([np.load(f, allow_pickle=True)["y"] for f in a.data])
+    """Train on the references of the sustained discharges (a discharge that
+    died out has no steady profile to learn)."""
+    X, Y = [], []
+    for f in a.data:
+        d = np.load(f)
+        alive = np.all(d["counts"] > 0, axis=1)
+        X.append(d["x"][alive])
+        Y.append(d["y"][alive])
+    X, Y = np.concatenate(X), np.concatenate(Y)
     rng = np.random.default_rng(0)
     perm = rng.permutation(len(X))
     nv = max(1, len(X) // 10)
