@@ -1004,6 +1004,7 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     ss.count = n;
     ss.live = n;
     ss.dead = 0;
+    ss.staged = 0;
     ss.next_id = next_id;
     ss.ntiles = 0;
     ok = ok && hipMemcpy(ctx->d.segs + idx, &ss, sizeof(SegState), hipMemcpyHostToDevice) == hipSuccess;
@@ -1071,6 +1072,7 @@ pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const doubl
         ok = launch_profile_load(pa, st) == hipSuccess;
         ss[s].count = ss[s].live = n[s];
         ss[s].dead = 0;
+        ss[s].staged = 0;
         ss[s].next_id = (uint32_t)n[s];
         ss[s].ntiles = 0;
     }

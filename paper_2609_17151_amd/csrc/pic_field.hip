@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         for (int src = 0; src < S; ++src) {
             const int g = b * S + src;
             if (src > 0 && !d.segc[g].emits) continue;
+            if (d.segs[g].staged == 0) continue;          // no tile of this segment staged a birth
             const int64_t tf = d.segs[g].tile_first, nt = d.segs[g].ntiles;
             const bool pair = src == 0 && S > 1;            // ionization: an ion with every electron
             for (int64_t r0 = 0; r0 < nt; r0 += kFT) {
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     st.count += app;
                     st.live += app - st.dead;
                     st.dead = 0;
+                    st.staged = 0;
                     st.next_id += (uint32_t)app;
                     st.ntiles = 0;
                 }

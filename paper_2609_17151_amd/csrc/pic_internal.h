@@ -115,6 +115,7 @@ struct SegState {
     int64_t count;          // slots in use (live particles and holes)
     int64_t live;           // live particles
     int64_t dead;           // particles absorbed in the current step
+    int64_t staged;         // births staged by this segment's tiles in the current step
     int64_t tile_first, ntiles;  // tile range of the current step (tiles are numbered over all segments)
     uint32_t next_id;
     int32_t parity;         // which copy holds the particles

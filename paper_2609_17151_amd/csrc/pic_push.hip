@@ -707,7 +707,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 for (int i = 0; i < nb; ++i) rank += s_bkey[i] < k;
                 d.births[(size_t)t * kBirthsPerTile + rank] = s_bb[tid];
             }
-            if (tid == 0) d.bcnt[t] = nb;
+            if (tid == 0) {
+                d.bcnt[t] = nb;
+                if (nb) atomicAdd(reinterpret_cast<unsigned long long*>(&st.staged), (unsigned long long)nb);
+            }
         }
 
         if (tid == 0 && tin == ntiles - 1) {
