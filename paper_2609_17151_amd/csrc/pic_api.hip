@@ -493,18 +493,13 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
             const int64_t cap = pad_cap(c.species[s].capacity);
             sc.cap = c.species[s].capacity;
             ctx->grid_cap[s] += cap;
-            const int copies = 2;                 // compaction and the sort write the other copy
-            for (int k = 0; k < copies; ++k) {
+            for (int k = 0; k < 2; ++k) {        // the compaction and the sort write the other copy
                 sc.cell[k] = (int32_t*)A(cap * 4);
                 sc.off[k] = (float*)A(cap * 4);
                 sc.vx[k] = (float*)A(cap * 4);
                 sc.vy[k] = (float*)A(cap * 4);
                 sc.vz[k] = (float*)A(cap * 4);
                 sc.id[k] = (uint32_t*)A(cap * 4);
-            }
-            if (copies == 1) {
-                sc.cell[1] = sc.cell[0]; sc.off[1] = sc.off[0]; sc.vx[1] = sc.vx[0];
-                sc.vy[1] = sc.vy[0]; sc.vz[1] = sc.vz[0]; sc.id[1] = sc.id[0];
             }
             fill_push_consts(c, s, sc);
         }

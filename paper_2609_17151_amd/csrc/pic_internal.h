@@ -53,8 +53,8 @@ struct Birth {
 };
 
 struct SegConst {
-    // particle storage, [0] and [1] are the two copies (same pointer when the
-    // segment never compacts)
+    // particle storage, [0] and [1] are the two copies (SegState::parity
+    // says which holds the particles)
     int32_t* cell[2];
     float* off[2];
     float* vx[2];
