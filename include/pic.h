@@ -175,6 +175,8 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_DIAG_POWER 15       /* double[1 + 3 * S * n_nodes]: samples, then per species the time means of the particle flux density
                                    Gamma = n <vx> (m^-2 s^-1), the x-momentum flux density n <vx^2> and the power density q Gamma E (W/m^3)
                                    that the field gives the species (pic_set_diag; cleared with RESET_AVG) */
+#define PIC_DIAG_WALL_ENERGY 16 /* double[2 * S]: kinetic energy carried into each wall (x < 0, x >= L) per species since pic_init, J/m^2
+                                   (Section 1: walls; impact energies summed in 2^-20 eV fixed point) */
 #define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
 
 #define PIC_EEPF_BINS 256

@@ -55,7 +55,8 @@ class Counters(C.Structure):
     _fields_ = [("absorbed", (C.c_int64 * 2) * MAX_SPECIES), ("see_emitted", C.c_int64 * 2),
                 ("candidates", C.c_int64 * MAX_SPECIES), ("nulls", C.c_int64 * MAX_SPECIES),
                 ("coll", (C.c_int64 * MAX_CHAN) * MAX_SPECIES),
-                ("violations", C.c_int64 * MAX_SPECIES), ("dropped", C.c_int64)]
+                ("violations", C.c_int64 * MAX_SPECIES), ("dropped", C.c_int64),
+                ("wall_energy", (C.c_double * 2) * MAX_SPECIES)]
 
 
 _lib = None
@@ -253,7 +254,8 @@ class Oracle:
                     nulls=np.array([c.nulls[k] for k in range(ns)]),
                     coll=np.array([[c.coll[k][j] for j in range(MAX_CHAN)] for k in range(ns)]),
                     violations=np.array([c.violations[k] for k in range(ns)]),
-                    dropped=c.dropped)
+                    dropped=c.dropped,
+                    wall_energy=np.array([[c.wall_energy[k][w] for w in range(2)] for k in range(ns)]))
 
     def energy(self):
         ke = np.zeros(MAX_SPECIES)

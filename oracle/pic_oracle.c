@@ -855,6 +855,7 @@ static int one_step(orc_sim* s)
             } else if (x < 0.0 || x >= L) {
                 int wall = x < 0.0 ? 0 : 1;
                 s->cnt.absorbed[k][wall] += 1;
+                s->cnt.wall_energy[k][wall] += 0.5 * s->c.sp[k].mass * s->c.sp[k].weight * vnew2;
                 if (k > 0 && s->c.sp[k].charge > 0.0 && s->c.see_gamma > 0.0) {
                     int rc = emit_secondary(s, k, p->id[j], wall);
                     if (rc) return rc;

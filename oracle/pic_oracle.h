@@ -53,7 +53,8 @@ typedef struct {
     orc_species sp[ORC_MAX_SPECIES];
 } orc_config;
 
-/* Counters of one run, all integer-exact. */
+/* Counters of one run: event counts (integer-exact) and the kinetic energy
+ * carried into each wall (J per m^2 of electrode). */
 typedef struct {
     int64_t absorbed[ORC_MAX_SPECIES][2];   /* [species][wall 0 = x<0, 1 = x>=L] */
     int64_t see_emitted[2];
@@ -62,6 +63,7 @@ typedef struct {
     int64_t coll[ORC_MAX_SPECIES][ORC_MAX_CHAN];
     int64_t violations[ORC_MAX_SPECIES];
     int64_t dropped;
+    double wall_energy[ORC_MAX_SPECIES][2];  /* [species][wall]: sum of m w |v|^2 / 2 at impact */
 } orc_counters;
 
 typedef struct orc_sim orc_sim;

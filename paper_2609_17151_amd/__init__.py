@@ -23,7 +23,7 @@ EEPF_BINS = 256
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
-            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15)
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16)
 
 
 class SpeciesCfg(C.Structure):
@@ -287,6 +287,11 @@ class Sim:
         o = self.diag("AVG", 1 + (self.S + 2) * n, batch=batch, check=check)
         prof = o[1:].reshape(self.S + 2, n)
         return dict(samples=o[0], density=prof[: self.S], phi=prof[self.S], mean_energy=prof[self.S + 1])
+
+    def wall_energy(self, batch=0):
+        """Kinetic energy carried into each wall per species since start, J/m^2,
+        as [S][2] (wall at x < 0, wall at x >= L)."""
+        return self.diag("WALL_ENERGY", 2 * self.S, batch=batch).reshape(self.S, 2)
 
     def power(self, batch=0):
         """Time means per species: flux density, x-momentum flux density and

@@ -521,6 +521,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.eacc = (unsigned long long*)A(8ull * B * nodes_max);
         d.macc = (unsigned long long*)A(8ull * B * S * 2 * nodes_max);
         d.pavg = (double*)A(8ull * B * S * 3 * nodes_max);
+        d.wen = (unsigned long long*)A(8ull * B * S * 2);
         d.rho = (double*)A(8ull * B * nodes_max);
         d.phi = (double*)A(8ull * B * nodes_max);
         d.ef = (double*)A(8ull * B * nodes_max);
@@ -561,6 +562,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.macc, 0, 8ull * B * S * 2 * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.pavg, 0, 8ull * B * S * 3 * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.wen, 0, 8ull * B * S * 2, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.bcnt, 0, 4ull * tiles_max, st) == hipSuccess;
@@ -1223,6 +1225,17 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             ds.avg_samples = 0.0;
             ds.eepf_samples = 0.0;
             ok = ok && hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+            break;
+        }
+        case PIC_DIAG_WALL_ENERGY: {
+            if (!need(8ull * 2 * S)) return PIC_EINVAL;
+            std::vector<unsigned long long> we((size_t)S * 2);
+            ok = d2h(we.data(), ctx->d.wen + (size_t)batch * S * 2, 8ull * 2 * S);
+            const pic_config& c = ctx->cfg[batch];
+            double* o = (double*)out;
+            for (int sp = 0; sp < S; ++sp)
+                for (int w = 0; w < 2; ++w)
+                    o[2 * sp + w] = (double)we[2 * sp + w] / 1048576.0 * c.e_unit * c.species[sp].weight;
             break;
         }
         case PIC_DIAG_POWER: {

@@ -145,6 +145,7 @@ struct DevPtrs {
     unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^24)
     unsigned long long* macc;    // [B][S][2][nodes_max] flux and x-momentum flux sums of the step (fixed point)
     double* pavg;                // [B][S][3][nodes_max] time sums of flux, momentum flux, power density
+    unsigned long long* wen;     // [B][S][2] kinetic energy carried into each wall (eV, fixed point 2^20)
     double* rho;                 // [B][nodes_max]
     double* phi;
     double* ef;

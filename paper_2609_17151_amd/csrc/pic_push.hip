@@ -135,8 +135,8 @@ __device__ __forceinline__ bool stage_birth(const BirthSink& k, const Birth& x)
 template <bool GENERAL>
 __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, const DisConst& dc,
                                         const PushArgs& a, int s, int b, uint32_t step,
-                                        const float2* ep, unsigned int* s_cnt, int& c, float& f,
-                                        float& ux, float& uy, float& uz, uint32_t pid, float& ke_sum,
+                                        const float2* ep, unsigned int* s_cnt, unsigned long long* s_wen, int& c,
+                                        float& f, float& ux, float& uy, float& uz, uint32_t pid, float& ke_sum,
                                         const BirthSink& sink, bool& cand)
 {
     const int nc = dc.n_cells;
@@ -196,6 +196,7 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
     } else if (c < 0 || c >= nc) {
         const int wall = c < 0 ? 0 : 1;
         atomicAdd(&s_cnt[C_ABS0 + wall], 1u);
+        atomicAdd(&s_wen[wall], (unsigned long long)(sc.half_m_over_e * vnew2 * 1048576.0f));
         if (a.diag && s == 0) {
             const float eps = sc.half_m_over_e * vnew2;
             const int bin = (int)(eps * a.eepf_inv_bin);
@@ -446,6 +447,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_pref[kMaxSeg + 1];   // first tile of every segment (discharge-major)
     __shared__ unsigned int s_cnt[C_N];
+    __shared__ unsigned long long s_wen[2];   // energy carried into each wall by the run (eV, 2^20)
     __shared__ float s_red[kBS / 64];
     constexpr int kSink = GENERAL ? kBirthsPerTile : 1;
     __shared__ Birth s_bb[kSink];             // births of the current tile
@@ -481,6 +483,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
     }
     if (tid < C_N) s_cnt[tid] = 0;
+    if (tid < 2) s_wen[tid] = 0ull;
     if (tid < 2) {
         s_bn[tid] = 0u;
         s_nq[tid] = 0u;
@@ -548,6 +551,11 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                     atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[cg].dead), (unsigned long long)v);
             }
             s_cnt[tid] = 0;
+        }
+        if (tid < 2) {
+            const unsigned long long v = s_wen[tid];
+            if (v) atomicAdd(&d.wen[(size_t)cg * 2 + tid], v);
+            s_wen[tid] = 0ull;
         }
         if (a.diag) {
             const double kt = block_sum_f32<BS>(ke_run, s_red);
@@ -631,8 +639,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             if (GENERAL && cell[j] < 0) continue;          // a hole: absorbed earlier
             sink.pkey = (uint32_t)(tid * PPT + j);
             bool cand = false;
-            const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, cell[j], off[j], vx[j], vy[j],
-                                               vz[j], pid[j], ke_tile, sink, cand);
+            const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, s_wen, cell[j], off[j], vx[j],
+                                               vy[j], vz[j], pid[j], ke_tile, sink, cand);
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
                 if (GENERAL && cand) {

@@ -55,3 +55,27 @@ def test_power_moments_periodic_streaming(pic):
     sim.step(1)
     o.step(1)
     check(sim, o, cfg)
+
+
+def test_wall_energy_free_flight(pic):
+    """Free flight (no field, no gas) from identical states: counts and
+    energies per wall against the oracle."""
+    import oracle
+    n, L = 200_000, 0.02
+    sp = [W.species(-1.602176634e-19, 9.1093837e-31, 1e8, n, 1e6, load=W.LOAD_RANDOM),
+          W.species(1.602176634e-19, 6.6e-26, 1e8, n, 2e3, load=W.LOAD_RANDOM)]
+    cfg = W.base_config(n_cells=200, bc=1, field_solve=0, length=L, dt=1e-10, eps0=8.8541878128e-12,
+                        e_unit=1.602176634e-19, species=sp, seed=5)
+    sim = pic.Sim(cfg)
+    o = to_oracle(sim, cfg)
+    sim.step(100)
+    o.step(100)
+    we = sim.wall_energy()
+    c = o.counters()
+    absorbed = sim.wall()["absorbed"]
+    for s in range(2):
+        for w in range(2):
+            ref, k = c["wall_energy"][s][w], int(c["absorbed"][s][w])
+            # a particle within an FP32 rounding of the wall may land on either side
+            assert abs(int(absorbed[s][w]) - k) <= 2
+            assert abs(we[s][w] - ref) <= 1e-5 * ref + 3.0 * ref / max(k, 1)

@@ -300,3 +300,24 @@ def test_moments_of_a_drifting_beam():
         dens = o.density(0)
         np.testing.assert_allclose(flux, dens * vd, rtol=1e-12)
         np.testing.assert_allclose(mom, dens * vd * vd, rtol=1e-12)
+
+
+def test_wall_energy_bookkeeping():
+    """Free flight to the walls (no field, no gas): a particle reaches the
+    wall its velocity points to, after N steps iff x0 + N vx dt leaves
+    [0, L), carrying its own kinetic energy; each wall's energy is the sum of
+    m w v^2 / 2 over those particles."""
+    import oracle as O
+    n, L, dt, N = 3000, 1.0, 0.05, 400
+    sp = [W.species(-1.0, 2.0, 0.25, n, 1.0, load=W.LOAD_RANDOM)]
+    cfg = W.base_config(n_cells=32, bc=1, field_solve=0, length=L, dt=dt, species=sp)
+    o = O.Oracle(cfg)
+    p = o.get_particles(0)
+    e = 0.5 * 2.0 * 0.25 * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2)
+    xN = p["x"] + N * p["vx"] * dt
+    o.step(N)
+    c = o.counters()
+    assert c["absorbed"][0][0] == np.sum(xN < 0.0) and c["absorbed"][0][1] == np.sum(xN >= L)
+    assert c["wall_energy"][0][0] == pytest.approx(e[xN < 0.0].sum(), rel=1e-12)
+    assert c["wall_energy"][0][1] == pytest.approx(e[xN >= L].sum(), rel=1e-12)
+    assert len(o.get_particles(0)["x"]) == np.sum((xN >= 0.0) & (xN < L))
