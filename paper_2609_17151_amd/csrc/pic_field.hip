@@ -187,15 +187,13 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     if (tid >= kBook) {
         // ---- bookkeeping wave: counts, ids, kinetic energy --------------------
         if (a.mode == kFinStep) {
-#pragma unroll
-            for (int s = 0; s < kMaxSpecies; ++s) {
-                if (s >= S) break;
-                SegState& st = d.segs[b * S + s];
-                const int64_t tfirst = st.tile_first, ntl = st.ntiles;
-                if (a.diag) {
-                    // kinetic-energy partials of the step's runs (zeros
-                    // elsewhere), fixed order, cleared after reading
-                    double* kpp = d.ke_part + tfirst;
+            if (a.diag) {
+                // kinetic-energy partials of the step's runs (zeros elsewhere),
+                // fixed order, cleared after reading
+                for (int s = 0; s < S; ++s) {
+                    SegState& st = d.segs[b * S + s];
+                    double* kpp = d.ke_part + st.tile_first;
+                    const int64_t ntl = st.ntiles;
                     double acc_k = 0.0;
                     for (int64_t t = lane; t < ntl; t += 64) {
                         acc_k += kpp[t];
@@ -204,20 +202,22 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     acc_k = wave_sum_f64(acc_k);
                     if (lane == 0) st.ke = acc_k;
                 }
-                if (lane == 0) {
-                    const bool births = a.births_per_tile > 0;
-                    const int64_t app = births ? s_app[s] : 0, want = births ? s_want[s] : 0;
-                    if (app < want) {
-                        atomicOr(&ds.flags, kFlagCapacity);
-                        d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP] += (unsigned long long)(want - app);
-                    }
-                    st.count += app;
-                    st.live += app - st.dead;
-                    st.dead = 0;
-                    st.staged = 0;
-                    st.next_id += (uint32_t)app;
-                    st.ntiles = 0;
+            }
+            if (lane < S) {                             // one lane per species
+                const int s = lane;
+                SegState& st = d.segs[b * S + s];
+                const bool births = a.births_per_tile > 0;
+                const int64_t app = births ? s_app[s] : 0, want = births ? s_want[s] : 0;
+                if (app < want) {
+                    atomicOr(&ds.flags, kFlagCapacity);
+                    atomicAdd(&d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP], (unsigned long long)(want - app));
                 }
+                st.count += app;
+                st.live += app - st.dead;
+                st.dead = 0;
+                st.staged = 0;
+                st.next_id += (uint32_t)app;
+                st.ntiles = 0;
             }
         }
     } else {
