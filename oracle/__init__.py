@@ -19,6 +19,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MAX_SPECIES = 4
 MAX_CHAN = 8
+EEPF_BINS = 256
 
 
 def build(force=True):
@@ -93,6 +94,12 @@ def lib():
         L.orc_get_counters.argtypes = [P, C.POINTER(Counters)]
         L.orc_get_energy.argtypes = [P, dp, dp]
         L.orc_get_numax.argtypes = [P, C.c_int32, dp, up]
+        L.orc_set_diag.argtypes = [P, C.c_int32, C.c_double]
+        L.orc_set_wall_edf.argtypes = [P, C.c_int32, C.c_double]
+        L.orc_reset_avg.argtypes = [P]
+        L.orc_get_avg.argtypes = [P, dp]
+        L.orc_get_eepf.argtypes = [P, dp]
+        L.orc_get_wall_edf.argtypes = [P, dp]
         L.orc_philox4x32_10.argtypes = [up, up, up]
         L.orc_philox4x32_10.restype = None
         L.orc_u01.argtypes = [C.c_uint32]
@@ -256,6 +263,39 @@ class Oracle:
                     violations=np.array([c.violations[k] for k in range(ns)]),
                     dropped=c.dropped,
                     wall_energy=np.array([[c.wall_energy[k][w] for w in range(2)] for k in range(ns)]))
+
+    def set_diag(self, enable=True, eepf_emax=64.0):
+        _check(lib().orc_set_diag(self.h, int(enable), float(eepf_emax)), "orc_set_diag")
+
+    def set_wall_edf(self, s, emax):
+        _check(lib().orc_set_wall_edf(self.h, s, float(emax)), "orc_set_wall_edf")
+
+    def reset_avg(self):
+        _check(lib().orc_reset_avg(self.h), "orc_reset_avg")
+
+    def avg(self):
+        """Time means since the last reset: density per species, potential,
+        electron mean energy (eV) at the nodes, and the number of samples."""
+        S, n = self.n_species, self.n_nodes
+        o = np.zeros(1 + (S + 2) * n)
+        _check(lib().orc_get_avg(self.h, _dp(o)), "orc_get_avg")
+        return dict(samples=o[0], density=o[1:1 + S * n].reshape(S, n),
+                    phi=o[1 + S * n:1 + (S + 1) * n], mean_energy=o[1 + (S + 1) * n:])
+
+    def eepf(self):
+        o = np.zeros(2 * EEPF_BINS + 2)
+        _check(lib().orc_get_eepf(self.h, _dp(o)), "orc_get_eepf")
+        return dict(bulk=o[:EEPF_BINS], wall=o[EEPF_BINS:2 * EEPF_BINS],
+                    bin_width=o[2 * EEPF_BINS], samples=o[2 * EEPF_BINS + 1])
+
+    def wall_edf(self):
+        """Impact-energy histograms [species][wall][bin], bin widths (eV) per
+        species, samples."""
+        S = self.n_species
+        o = np.zeros(S * 2 * EEPF_BINS + S + 1)
+        _check(lib().orc_get_wall_edf(self.h, _dp(o)), "orc_get_wall_edf")
+        return dict(counts=o[:S * 2 * EEPF_BINS].reshape(S, 2, EEPF_BINS),
+                    bin_width=o[S * 2 * EEPF_BINS:S * 2 * EEPF_BINS + S], samples=o[-1])
 
     def energy(self):
         ke = np.zeros(MAX_SPECIES)

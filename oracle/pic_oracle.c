@@ -64,6 +64,14 @@ struct orc_sim {
     orc_counters cnt;
     double ke[ORC_MAX_SPECIES], fe;
     blist_t births[ORC_MAX_SPECIES];
+    /* time-accumulated diagnostics, sampled after every step while enabled */
+    int32_t diag;
+    double eepf_emax, wedf_emax[ORC_MAX_SPECIES];
+    double* av_dens[ORC_MAX_SPECIES];  /* sum over samples of the density per node */
+    double *av_phi, *av_neps;         /* potential; electron density times energy (eV) */
+    double av_samples;
+    int64_t eepf[2][ORC_EEPF_BINS];   /* electrons: bulk cells, wall impacts */
+    int64_t wedf[ORC_MAX_SPECIES][2][ORC_EEPF_BINS];
 };
 
 /* ------------------------------------------------------------------------ */
@@ -323,6 +331,15 @@ int orc_create(const orc_config* cfg, orc_sim** out)
     s->phi = calloc((size_t)s->nn, sizeof(double));
     s->ef = calloc((size_t)s->nn, sizeof(double));
     if (!s->rho || !s->phi || !s->ef) rc = ORC_ENOMEM;
+    for (int k = 0; k < cfg->n_species; ++k) {
+        s->av_dens[k] = calloc((size_t)s->nn, sizeof(double));
+        if (!s->av_dens[k]) rc = ORC_ENOMEM;
+        s->wedf_emax[k] = k == 0 ? 64.0 : 1024.0;
+    }
+    s->av_phi = calloc((size_t)s->nn, sizeof(double));
+    s->av_neps = calloc((size_t)s->nn, sizeof(double));
+    if (!s->av_phi || !s->av_neps) rc = ORC_ENOMEM;
+    s->eepf_emax = 64.0;
     if (rc != ORC_OK) { orc_free(s); return rc; }
     *out = s;
     return ORC_OK;
@@ -333,11 +350,11 @@ void orc_free(orc_sim* s)
     if (!s) return;
     for (int k = 0; k < ORC_MAX_SPECIES; ++k) {
         free(s->p[k].x); free(s->p[k].vx); free(s->p[k].vy); free(s->p[k].vz); free(s->p[k].id);
-        free(s->sum[k]); free(s->dens[k]);
+        free(s->sum[k]); free(s->dens[k]); free(s->av_dens[k]);
         free(s->births[k].b);
         for (int j = 0; j < ORC_MAX_CHAN; ++j) { free(s->ch[k][j].e); free(s->ch[k][j].s); }
     }
-    free(s->rho); free(s->phi); free(s->ef);
+    free(s->rho); free(s->phi); free(s->ef); free(s->av_phi); free(s->av_neps);
     free(s);
 }
 
@@ -824,6 +841,60 @@ static int emit_secondary(orc_sim* s, int k, uint32_t id, int wall)
     return push_birth(&s->births[0], x, vx, vsee * g0, vsee * g1);
 }
 
+/* Energy histograms: bin floor(eps / width) with width = emax / ORC_EEPF_BINS;
+ * energies at or above emax are not counted. */
+static void tally(int64_t* h, double eps, double emax)
+{
+    double b = floor(eps * (double)ORC_EEPF_BINS / emax);
+    if (b >= 0.0 && b < (double)ORC_EEPF_BINS) h[(int)b] += 1;
+}
+
+/* Cells whose electrons make up the bulk energy distribution: the whole
+ * domain when periodic, else the middle tenth of the gap, cells
+ * floor(0.45 N) .. max(that + 1, ceil(0.55 N)) - 1. */
+static void bulk_cells(const orc_sim* s, int64_t* lo, int64_t* hi)
+{
+    int64_t nc = s->c.n_cells;
+    if (is_periodic(s)) { *lo = 0; *hi = nc; return; }
+    *lo = (int64_t)floor(0.45 * (double)nc);
+    *hi = (int64_t)ceil(0.55 * (double)nc);
+    if (*hi < *lo + 1) *hi = *lo + 1;
+}
+
+/* One sample of the time-accumulated diagnostics, taken on the state at the
+ * end of a step (positions x^{n+1}, velocities v^{n+1/2} after collisions,
+ * births included): the densities and the potential at the nodes, the
+ * electron energy density sum_p S_i(x_p) eps_p w / V_i (its ratio to the
+ * electron density is the mean energy), and the bulk electron energy
+ * histogram. */
+static void sample_diagnostics(orc_sim* s)
+{
+    int nn = s->nn;
+    for (int k = 0; k < s->c.n_species; ++k)
+        for (int i = 0; i < nn; ++i) s->av_dens[k][i] += s->dens[k][i];
+    for (int i = 0; i < nn; ++i) s->av_phi[i] += s->phi[i];
+    const pop_t* e = &s->p[0];
+    double* ne = s->sum[0];             /* reused as the energy sums of this sample */
+    for (int i = 0; i < nn; ++i) ne[i] = 0.0;
+    int64_t lo, hi;
+    bulk_cells(s, &lo, &hi);
+    for (int64_t p = 0; p < e->n; ++p) {
+        double v2 = e->vx[p] * e->vx[p] + e->vy[p] * e->vy[p] + e->vz[p] * e->vz[p];
+        double eps = 0.5 * s->c.sp[0].mass * v2 / s->c.e_unit;
+        int64_t c, c1;
+        double f;
+        locate(s, e->x[p], &c, &c1, &f);
+        ne[c] += (1.0 - f) * eps;
+        ne[c1] += f * eps;
+        if (c >= lo && c < hi) tally(s->eepf[0], eps, s->eepf_emax);
+    }
+    for (int i = 0; i < nn; ++i) {
+        s->av_neps[i] += s->c.sp[0].weight * ne[i] / node_volume(s, i);
+        ne[i] = 0.0;
+    }
+    s->av_samples += 1.0;
+}
+
 /* One leapfrog step: for each species in order, each particle in index order:
  * gather E at x^n, Boris to v^{n+1/2}, move to x^{n+1}, wrap or absorb (with
  * secondary emission), collide.  Survivors keep their order; births follow,
@@ -856,6 +927,11 @@ static int one_step(orc_sim* s)
                 int wall = x < 0.0 ? 0 : 1;
                 s->cnt.absorbed[k][wall] += 1;
                 s->cnt.wall_energy[k][wall] += 0.5 * s->c.sp[k].mass * s->c.sp[k].weight * vnew2;
+                if (s->diag) {
+                    double eps = 0.5 * s->c.sp[k].mass * vnew2 / s->c.e_unit;
+                    tally(s->wedf[k][wall], eps, s->wedf_emax[k]);
+                    if (k == 0) tally(s->eepf[1], eps, s->eepf_emax);
+                }
                 if (k > 0 && s->c.sp[k].charge > 0.0 && s->c.see_gamma > 0.0) {
                     int rc = emit_secondary(s, k, p->id[j], wall);
                     if (rc) return rc;
@@ -889,6 +965,7 @@ static int one_step(orc_sim* s)
     deposit(s);
     int rs = solve(s, (double)s->step * dt, s->rho, s->phi, s->ef);
     s->fe = field_energy(s);
+    if (s->diag) sample_diagnostics(s);
     return rc != ORC_OK ? rc : rs;
 }
 
@@ -968,5 +1045,74 @@ int orc_get_numax(const orc_sim* s, int32_t k, double* numax, uint32_t* t32)
     if (!s || k < 0 || k >= s->c.n_species) return ORC_EINVAL;
     if (numax) *numax = s->numax[k];
     if (t32) *t32 = s->t32[k];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time-accumulated diagnostics (Section 1: densities, potential, mean
+ * energies and energy distributions in the bulk and at the walls). */
+int orc_set_diag(orc_sim* s, int32_t enable, double eepf_emax_ev)
+{
+    if (!s || !(eepf_emax_ev > 0.0)) return ORC_EINVAL;
+    s->diag = enable ? 1 : 0;
+    s->eepf_emax = eepf_emax_ev;
+    return ORC_OK;
+}
+
+int orc_set_wall_edf(orc_sim* s, int32_t k, double emax_ev)
+{
+    if (!s || k < 0 || k >= s->c.n_species || !(emax_ev > 0.0)) return ORC_EINVAL;
+    s->wedf_emax[k] = emax_ev;
+    return ORC_OK;
+}
+
+int orc_reset_avg(orc_sim* s)
+{
+    if (!s) return ORC_EINVAL;
+    for (int k = 0; k < s->c.n_species; ++k) memset(s->av_dens[k], 0, (size_t)s->nn * sizeof(double));
+    memset(s->av_phi, 0, (size_t)s->nn * sizeof(double));
+    memset(s->av_neps, 0, (size_t)s->nn * sizeof(double));
+    memset(s->eepf, 0, sizeof(s->eepf));
+    memset(s->wedf, 0, sizeof(s->wedf));
+    s->av_samples = 0.0;
+    return ORC_OK;
+}
+
+int orc_get_avg(const orc_sim* s, double* out)
+{
+    if (!s || !out) return ORC_EINVAL;
+    int nn = s->nn, S = s->c.n_species;
+    double ns = s->av_samples;
+    out[0] = ns;
+    for (int k = 0; k < S; ++k)
+        for (int i = 0; i < nn; ++i) out[1 + (size_t)k * nn + i] = ns > 0.0 ? s->av_dens[k][i] / ns : 0.0;
+    for (int i = 0; i < nn; ++i) {
+        out[1 + (size_t)S * nn + i] = ns > 0.0 ? s->av_phi[i] / ns : 0.0;
+        double n = s->av_dens[0][i];
+        out[1 + (size_t)(S + 1) * nn + i] = n > 0.0 ? s->av_neps[i] / n : 0.0;
+    }
+    return ORC_OK;
+}
+
+int orc_get_eepf(const orc_sim* s, double* out)
+{
+    if (!s || !out) return ORC_EINVAL;
+    for (int w = 0; w < 2; ++w)
+        for (int i = 0; i < ORC_EEPF_BINS; ++i) out[w * ORC_EEPF_BINS + i] = (double)s->eepf[w][i];
+    out[2 * ORC_EEPF_BINS] = s->eepf_emax / ORC_EEPF_BINS;
+    out[2 * ORC_EEPF_BINS + 1] = s->av_samples;
+    return ORC_OK;
+}
+
+int orc_get_wall_edf(const orc_sim* s, double* out)
+{
+    if (!s || !out) return ORC_EINVAL;
+    int S = s->c.n_species;
+    for (int k = 0; k < S; ++k)
+        for (int w = 0; w < 2; ++w)
+            for (int i = 0; i < ORC_EEPF_BINS; ++i)
+                out[((size_t)k * 2 + w) * ORC_EEPF_BINS + i] = (double)s->wedf[k][w][i];
+    for (int k = 0; k < S; ++k) out[(size_t)S * 2 * ORC_EEPF_BINS + k] = s->wedf_emax[k] / ORC_EEPF_BINS;
+    out[(size_t)S * 2 * ORC_EEPF_BINS + S] = s->av_samples;
     return ORC_OK;
 }

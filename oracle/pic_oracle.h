@@ -24,6 +24,7 @@ extern "C" {
 
 #define ORC_MAX_SPECIES 4
 #define ORC_MAX_CHAN 8
+#define ORC_EEPF_BINS 256
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ECAPACITY = -4,
        ORC_ENUMERIC = -5, ORC_ESTATE = -6 };
@@ -104,6 +105,22 @@ int  orc_get_counters(const orc_sim* s, orc_counters* out);
 /* Kinetic energy of each species at the last step (time-centred), field energy. */
 int  orc_get_energy(const orc_sim* s, double* ke_species, double* fe);
 int  orc_get_numax(const orc_sim* s, int32_t species, double* numax, uint32_t* t32);
+
+/* Time-accumulated diagnostics, sampled at the end of every step while
+ * enabled: mean density per species, mean potential and the electron mean
+ * energy at the nodes; electron energy histograms of the bulk cells and of
+ * the wall impacts over [0, eepf_emax); per species and wall, the histogram
+ * of impact energies over [0, emax_k) (64 eV for species 0, 1024 eV for the
+ * others unless set).  Layouts:
+ *   avg:      [samples, density[S][nn], phi[nn], mean electron energy (eV)[nn]]
+ *   eepf:     [bulk[BINS], wall[BINS], bin width (eV), samples]
+ *   wall edf: [counts[S][2][BINS], bin width per species (eV)[S], samples] */
+int  orc_set_diag(orc_sim* s, int32_t enable, double eepf_emax_ev);
+int  orc_set_wall_edf(orc_sim* s, int32_t species, double emax_ev);
+int  orc_reset_avg(orc_sim* s);
+int  orc_get_avg(const orc_sim* s, double* out);
+int  orc_get_eepf(const orc_sim* s, double* out);
+int  orc_get_wall_edf(const orc_sim* s, double* out);
 
 /* Building blocks exposed for the pins. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
