@@ -169,7 +169,7 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_DIAG_FLAGS 9        /* int64[1]: latched device flag bits (and clears them) */
 #define PIC_DIAG_AVG 10         /* double[1 + (S + 2) * n_nodes]: samples, then mean density per species, mean phi, mean electron energy (eV) */
 #define PIC_DIAG_EEPF 11        /* double[2 * PIC_EEPF_BINS + 2]: bulk and wall electron energy histograms, bin width eV, samples */
-#define PIC_DIAG_RESET_AVG 12   /* no output: clears AVG and EEPF accumulators */
+#define PIC_DIAG_RESET_AVG 12   /* no output: clears the AVG, EEPF, POWER and WALL_EDF accumulators */
 #define PIC_DIAG_CHARGE 13      /* double[2]: total charge per unit area on the mesh, and from particle counts */
 
 #define PIC_DIAG_POWER 15       /* double[1 + 3 * S * n_nodes]: samples, then per species the time means of the particle flux density
@@ -177,6 +177,10 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
                                    that the field gives the species (pic_set_diag; cleared with RESET_AVG) */
 #define PIC_DIAG_WALL_ENERGY 16 /* double[2 * S]: kinetic energy carried into each wall (x < 0, x >= L) per species since pic_init, J/m^2
                                    (Section 1: walls; impact energies summed in 2^-20 eV fixed point) */
+#define PIC_DIAG_WALL_EDF 17    /* double[S * 2 * PIC_EEPF_BINS + S + 1]: per species and wall (x < 0, x >= L) the
+                                   histogram of impact energies since the last reset (bin width emax / PIC_EEPF_BINS,
+                                   emax from pic_set_wall_edf), then the bin width (eV) per species, then the samples
+                                   of the time averages over the same interval */
 #define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
 
 #define PIC_EEPF_BINS 256
@@ -247,8 +251,21 @@ void pic_free(pic_ctx* ctx);
  * eepf_emax_eV / PIC_EEPF_BINS in the bulk (middle tenth of a bounded gap,
  * whole domain when periodic) and at the walls (PIC_DIAG_EEPF) (Section 1:
  * density and potential profiles, electron energy probability functions in
- * the bulk and at the walls). */
+ * the bulk and at the walls).  Samples are taken on the state at the end of
+ * each step (velocities after collisions, the step's births included); the
+ * mean energy at a node is sum(n eps) / sum(n) over the samples, with the
+ * linear weights of the charge deposit.  Species 0 is taken as the electrons.
+ * PIC_EINVAL when eepf_emax_eV is not positive and finite. */
 pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV);
+
+/* pic_set_wall_edf: energy range [0, emax_eV) of the histogram of the impact
+ * energies m |v|^2 / 2e of species `species` at each wall (PIC_DIAG_WALL_EDF;
+ * Section 1: wall diagnostics; for ions the ion flux-energy distribution at
+ * the electrodes), for every discharge of the context.  Defaults: 64 eV for
+ * species 0, 1024 eV for the others.  The histograms fill while pic_set_diag
+ * is enabled.  PIC_EINVAL for a species out of range or emax_eV not positive
+ * and finite.  Synchronous (waits for queued work). */
+pic_status pic_set_wall_edf(pic_ctx* ctx, int32_t species, double emax_eV);
 
 /* pic_profile: when enable is non-zero, pic_step records a pair of HIP
  * events on the context's stream around every kernel it launches and

@@ -23,7 +23,7 @@ EEPF_BINS = 256
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
-            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16)
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17)
 
 
 class SpeciesCfg(C.Structure):
@@ -101,6 +101,7 @@ def load_library():
         "pic_free": (None, [P]),
         "pic_config_tiles": (i32, [P, i32, i32, i32, i32]),
         "pic_set_diag": (i32, [P, i32, d]),
+        "pic_set_wall_edf": (i32, [P, i32, d]),
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
@@ -225,6 +226,10 @@ class Sim:
     def set_diag(self, enable=True, eepf_emax=64.0):
         self._check(_lib.pic_set_diag(self.h, int(enable), float(eepf_emax)), "pic_set_diag")
 
+    def set_wall_edf(self, species, emax):
+        """Energy range [0, emax) eV of species' wall impact-energy histograms."""
+        self._check(_lib.pic_set_wall_edf(self.h, int(species), float(emax)), "pic_set_wall_edf")
+
     def poisson(self, t, rho=None, batch=0):
         n = self.n_nodes[batch]
         phi, ef = np.zeros(n), np.zeros(n)
@@ -305,6 +310,15 @@ class Sim:
         o = self.diag("EEPF", 2 * EEPF_BINS + 2, batch=batch)
         return dict(bulk=o[:EEPF_BINS], wall=o[EEPF_BINS:2 * EEPF_BINS],
                     bin_width=o[2 * EEPF_BINS], samples=o[2 * EEPF_BINS + 1])
+
+    def wall_edf(self, batch=0):
+        """Impact-energy histograms [species][wall][bin] since the last reset
+        (wall 0 at x < 0, wall 1 at x >= L), bin width per species (eV), and
+        the samples of the time averages over the same interval."""
+        S = self.S
+        nv = S * 2 * EEPF_BINS
+        o = self.diag("WALL_EDF", nv + S + 1, batch=batch)
+        return dict(counts=o[:nv].reshape(S, 2, EEPF_BINS), bin_width=o[nv:nv + S], samples=o[nv + S])
 
     def reset_avg(self, batch=0, check=True):
         rc = _lib.pic_diag(self.h, batch, DIAG["RESET_AVG"], None, 0)

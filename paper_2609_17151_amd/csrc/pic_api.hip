@@ -56,6 +56,7 @@ struct pic_ctx {
     int64_t compact_tiles = 0;           // grid of the compaction passes
     int diag = 0;
     double eepf_emax = 64.0;
+    double wedf_emax[PIC_MAX_SPECIES] = {64.0, 1024.0, 1024.0, 1024.0};   // wall impact-energy ranges (eV)
     double* poisson_scratch = nullptr;   // rho, phi, e: 3 * nodes_max
     void* sort_scratch = nullptr;
     size_t sort_scratch_bytes = 0;
@@ -217,6 +218,7 @@ void fill_push_consts(const pic_config& c, int s, SegConst& sc)
     sc.two_e_over_me = (float)(2.0 * c.e_unit / c.species[0].mass);
     sc.mscale1 = (float)(kMomentScale / moment_vref(c, s));
     sc.mscale2 = (float)(kMomentScale / (moment_vref(c, s) * moment_vref(c, s)));
+    sc.wedf_inv_bin = (float)(kEepfBins / (s == 0 ? 64.0 : 1024.0));
     sc.emits = (s >= 1 && sp.charge > 0.0 && c.see_gamma > 0.0 && c.bc == PIC_BC_DIRICHLET) ? 1 : 0;
     sc.see_k = (uint32_t)std::min(16777217.0, std::ceil(c.see_gamma * 16777216.0));
     sc.vsee = (float)std::sqrt(c.see_temp * c.e_unit / c.species[0].mass);
@@ -478,6 +480,15 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         }
         dc.c2 = dc.dx * dc.dx / c.eps0;
         dc.inv_2dx = 1.0 / (2.0 * dc.dx);
+        // bulk electron energy distribution: the middle tenth of a bounded
+        // gap, every cell when periodic
+        if (c.bc == PIC_BC_PERIODIC) {
+            dc.bulk_lo = 0;
+            dc.bulk_hi = c.n_cells;
+        } else {
+            dc.bulk_lo = (int)std::floor(0.45 * c.n_cells);
+            dc.bulk_hi = std::max(dc.bulk_lo + 1, (int)std::ceil(0.55 * c.n_cells));
+        }
         dc.inv_dx = 1.0 / dc.dx;
         dc.wall_coef = dc.dx / (2.0 * c.eps0);
         for (int s = 0; s < S; ++s) {
@@ -529,6 +540,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.epair = (float2*)A(8ull * B * cells_max);
         d.avg = (double*)A(8ull * B * (S + 2) * nodes_max);
         d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
+        d.wedf = (unsigned long long*)A(8ull * B * S * 2 * kEepfBins);
         d.births = (Birth*)A(sizeof(Birth) * (size_t)tiles_max * kBirthsPerTileMin);
         d.bcnt = (int32_t*)A(4ull * tiles_max);
         d.ccnt = (uint32_t*)A(4ull * tiles_max);
@@ -565,6 +577,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.wen, 0, 8ull * B * S * 2, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.wedf, 0, 8ull * B * S * 2 * kEepfBins, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.bcnt, 0, 4ull * tiles_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * tiles_max, st) == hipSuccess;
@@ -661,10 +674,23 @@ pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t 
 
 pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV)
 {
-    if (!ctx || !(eepf_emax_eV > 0.0)) return PIC_EINVAL;
+    if (!ctx || !(eepf_emax_eV > 0.0) || !std::isfinite(eepf_emax_eV)) return PIC_EINVAL;
     ctx->diag = enable ? 1 : 0;
     ctx->eepf_emax = eepf_emax_eV;
     return PIC_OK;
+}
+
+pic_status pic_set_wall_edf(pic_ctx* ctx, int32_t species, double emax_eV)
+{
+    if (!ctx || species < 0 || species >= ctx->S || !(emax_eV > 0.0) || !std::isfinite(emax_eV))
+        return PIC_EINVAL;
+    pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
+    for (int b = 0; b < ctx->B && rc == PIC_OK; ++b) {
+        ctx->segc[b * ctx->S + species].wedf_inv_bin = (float)(kEepfBins / emax_eV);
+        rc = upload_segc(ctx, b * ctx->S + species);
+    }
+    if (rc == PIC_OK) ctx->wedf_emax[species] = emax_eV;
+    return rc;
 }
 
 namespace {
@@ -681,20 +707,10 @@ struct StepPlan {
 pic_status plan_step(pic_ctx* ctx, StepPlan& p)
 {
     const int S = ctx->S, B = ctx->B;
-    int nn_max = 0, nc_max = 0, bulk_lo = 0, bulk_hi = 0;
+    int nn_max = 0, nc_max = 0;
     for (int b = 0; b < B; ++b) {
         nn_max = std::max(nn_max, ctx->disc[b].n_nodes);
         nc_max = std::max(nc_max, ctx->disc[b].n_cells);
-    }
-    // bulk EEPF window: the middle tenth of the gap of discharge 0 (all cells
-    // when periodic)
-    const DisConst& d0 = ctx->disc[0];
-    if (d0.bc == PIC_BC_PERIODIC) {
-        bulk_lo = 0;
-        bulk_hi = d0.n_cells;
-    } else {
-        bulk_lo = (int)std::floor(0.45 * d0.n_cells);
-        bulk_hi = std::max(bulk_lo + 1, (int)std::ceil(0.55 * d0.n_cells));
     }
     // one launch for every segment: the general kernel as soon as any segment
     // can lose, gain or collide particles; tile shape; persistent grid
@@ -717,13 +733,16 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     pa.d = ctx->d;
     pa.diag = ctx->diag;
     pa.eepf_inv_bin = (float)(kEepfBins / ctx->eepf_emax);
-    pa.bulk_lo = bulk_lo;
-    pa.bulk_hi = bulk_hi;
     pa.nodes_max_dyn = nn_max;
     pa.cells_max_dyn = nc_max;
     uint64_t key = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
     mix((uint64_t)ctx->diag);
+    {
+        uint32_t bits;
+        std::memcpy(&bits, &pa.eepf_inv_bin, 4);
+        mix((uint64_t)bits);    // a captured step holds the bin width
+    }
     mix((uint64_t)p.ppt);
     mix((uint64_t)p.threads);
     mix((uint64_t)p.general);
@@ -733,6 +752,7 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.fa.diag = ctx->diag;
     p.fa.only_b = -1;
     p.fa.births_per_tile = p.general ? T / kBirthsDiv : 0;
+    p.fa.eepf_inv_bin = pa.eepf_inv_bin;
     mix((uint64_t)ctx->sort_every);
     mix((uint64_t)ctx->compact_every);
     p.key = key;
@@ -1222,9 +1242,22 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             ok = hipMemset(ctx->d.avg + (size_t)batch * (S + 2) * nm, 0, 8ull * (S + 2) * nm) == hipSuccess;
             ok = ok && hipMemset(ctx->d.pavg + (size_t)batch * S * 3 * nm, 0, 8ull * S * 3 * nm) == hipSuccess;
             ok = ok && hipMemset(ctx->d.eepf + (size_t)batch * 2 * kEepfBins, 0, 8ull * 2 * kEepfBins) == hipSuccess;
+            ok = ok && hipMemset(ctx->d.wedf + (size_t)batch * S * 2 * kEepfBins, 0, 8ull * S * 2 * kEepfBins) ==
+                           hipSuccess;
             ds.avg_samples = 0.0;
             ds.eepf_samples = 0.0;
             ok = ok && hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+            break;
+        }
+        case PIC_DIAG_WALL_EDF: {
+            const size_t nv = (size_t)S * 2 * kEepfBins;
+            if (!need(8ull * (nv + S + 1))) return PIC_EINVAL;
+            std::vector<unsigned long long> h(nv);
+            ok = d2h(h.data(), ctx->d.wedf + (size_t)batch * nv, nv * 8);
+            double* o = (double*)out;
+            for (size_t i = 0; i < nv; ++i) o[i] = (double)h[i];
+            for (int sp = 0; sp < S; ++sp) o[nv + sp] = ctx->wedf_emax[sp] / kEepfBins;
+            o[nv + S] = ds.avg_samples;
             break;
         }
         case PIC_DIAG_WALL_ENERGY: {

@@ -122,6 +122,19 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             atomicAdd(&ma[d.nodes_max + cell], (unsigned long long)(long long)rintf(w0 * a2));
             atomicAdd(&ma[d.nodes_max + c1], (unsigned long long)(long long)rintf(off * a2));
         };
+        // energy of an appended electron at its nodes and in the bulk energy
+        // distribution (diagnostics), as in the push
+        auto energy_add = [&](int cell, float off, float vx, float vy, float vz) {
+            const float eps = c0.half_m_over_e * (vx * vx + vy * vy + vz * vz);
+            const float w1 = off * eps, w0 = eps - w1;
+            const int c1 = (periodic && cell + 1 == nc) ? 0 : cell + 1;
+            atomicAdd(&d.eacc[nb + cell], (unsigned long long)(w0 * 1048576.0f));
+            atomicAdd(&d.eacc[nb + c1], (unsigned long long)(w1 * 1048576.0f));
+            if (cell >= dc.bulk_lo && cell < dc.bulk_hi) {
+                const int bin = (int)(eps * a.eepf_inv_bin);
+                if ((unsigned)bin < (unsigned)kEepfBins) atomicAdd(&d.eepf[(size_t)b * 2 * kEepfBins + bin], 1ull);
+            }
+        };
         for (int src = 0; src < S; ++src) {
             const int g = b * S + src;
             if (src > 0 && !d.segc[g].emits) continue;
@@ -152,7 +165,10 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                         c0.vy[io0][e] = bb.vy;
                         c0.vz[io0][e] = bb.vz;
                         c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
-                        if (a.diag) moment_add(0, bb.cell, bb.off, bb.vx);
+                        if (a.diag) {
+                            moment_add(0, bb.cell, bb.off, bb.vx);
+                            energy_add(bb.cell, bb.off, bb.vx, bb.vy, bb.vz);
+                        }
                     }
                     if (pair) {
                         const SegConst& c1 = d.segc[b * S + 1];

@@ -93,6 +93,7 @@ struct SegConst {
     // velocity moments (diagnostics) in fixed point: per particle weight x
     // vx x mscale1 and weight x vx^2 x mscale2, rounded to integers
     float mscale1, mscale2;
+    float wedf_inv_bin;     // wall impact-energy histogram: 1 / bin width (1/eV)
 };
 
 struct DisConst {
@@ -106,6 +107,7 @@ struct DisConst {
     double q[kMaxSpecies];     // species charge
     double flux_coef[kMaxSpecies], mom_coef[kMaxSpecies];   // moment sums -> densities (interior node)
     uint32_t key0, key1;
+    int32_t bulk_lo, bulk_hi;  // cells of the bulk electron energy distribution
 };
 
 // mutable, one per segment.  Slots [0, count) hold the particles in their
@@ -142,7 +144,7 @@ struct DevPtrs {
     DisState* diss;              // [B]
     unsigned long long* acc;     // [B][S][kRep][nodes_max] deposit sums (fixed point)
     unsigned long long* cnt;     // [B][S][kRep][C_N] event counters
-    unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^24)
+    unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^20)
     unsigned long long* macc;    // [B][S][2][nodes_max] flux and x-momentum flux sums of the step (fixed point)
     double* pavg;                // [B][S][3][nodes_max] time sums of flux, momentum flux, power density
     unsigned long long* wen;     // [B][S][2] kinetic energy carried into each wall (eV, fixed point 2^20)
@@ -153,6 +155,7 @@ struct DevPtrs {
     float2* epair;               // [B][cells_max] (E[c], E[c+1]) for the gather
     double* avg;                 // [B][(S+2)][nodes_max]
     unsigned long long* eepf;    // [B][2][bins]
+    unsigned long long* wedf;    // [B][S][2][bins] impact energies at each wall
     Birth* births;               // [tiles_max * kBirthsPerTileMin] births staged by tile, in particle order
     int32_t* bcnt;               // [tiles_max] births staged by each tile
     unsigned long long* tick;    // steps taken by the context

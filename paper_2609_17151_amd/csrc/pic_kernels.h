@@ -10,7 +10,6 @@ struct PushArgs {
     DevPtrs d;
     int32_t diag;                 // accumulate electron energy deposit and EEPF
     float eepf_inv_bin;           // 1 / bin width (eV)
-    int32_t bulk_lo, bulk_hi;     // cells of the bulk EEPF window
     int32_t nodes_max_dyn, cells_max_dyn;
 };
 
@@ -25,6 +24,7 @@ struct FinArgs {
     int32_t diag;
     int32_t only_b;               // -1: all discharges (grid = B), else this one (grid = 1)
     int32_t births_per_tile;      // staging slots of a push tile (0: the step cannot have births)
+    float eepf_inv_bin;           // 1 / bin width (eV) of the bulk electron energy distribution
     double t_ext;
     const double* rho_ext;
     double* phi_out;

@@ -197,10 +197,15 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
         const int wall = c < 0 ? 0 : 1;
         atomicAdd(&s_cnt[C_ABS0 + wall], 1u);
         atomicAdd(&s_wen[wall], (unsigned long long)(sc.half_m_over_e * vnew2 * 1048576.0f));
-        if (a.diag && s == 0) {
+        if (a.diag) {
+            // impact energy: this species' histogram at this wall, and for
+            // electrons the wall energy distribution
             const float eps = sc.half_m_over_e * vnew2;
+            const int wb = (int)(eps * sc.wedf_inv_bin);
+            if ((unsigned)wb < (unsigned)kEepfBins)
+                atomicAdd(&d.wedf[(((size_t)b * d.S + s) * 2 + wall) * kEepfBins + wb], 1ull);
             const int bin = (int)(eps * a.eepf_inv_bin);
-            if ((unsigned)bin < (unsigned)kEepfBins)
+            if (s == 0 && (unsigned)bin < (unsigned)kEepfBins)
                 atomicAdd(&d.eepf[((size_t)b * 2 + 1) * kEepfBins + bin], 1ull);
         }
         if (GENERAL && sc.emits) {
@@ -402,16 +407,16 @@ __device__ __forceinline__ void moment_diag(const SegConst& sc, unsigned long lo
     atomicAdd(&mh[c1], (unsigned long long)(long long)rintf(f * b2));
 }
 
-__device__ __forceinline__ void electron_diag(const SegConst& sc, const PushArgs& a, unsigned long long* ehist,
-                                              unsigned int* eepf, int c, float f, float ux, float uy, float uz,
-                                              int nc, int periodic)
+__device__ __forceinline__ void electron_diag(const SegConst& sc, const DisConst& dc, const PushArgs& a,
+                                              unsigned long long* ehist, unsigned int* eepf, int c, float f,
+                                              float ux, float uy, float uz, int nc, int periodic)
 {
     const float eps = sc.half_m_over_e * (ux * ux + uy * uy + uz * uz);
     const float w1 = f * eps, w0 = eps - w1;
     const int c1 = (periodic && c + 1 == nc) ? 0 : c + 1;
     atomicAdd(&ehist[c], (unsigned long long)(w0 * 1048576.0f));
     atomicAdd(&ehist[c1], (unsigned long long)(w1 * 1048576.0f));
-    if (c >= a.bulk_lo && c < a.bulk_hi) {
+    if (c >= dc.bulk_lo && c < dc.bulk_hi) {
         const int bin = (int)(eps * a.eepf_inv_bin);
         if ((unsigned)bin < (unsigned)kEepfBins) atomicAdd(&eepf[bin], 1u);
     }
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 } else if (a.diag) {
                     moment_diag(sc, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
                     if (s == 0)
-                        electron_diag(sc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
+                        electron_diag(sc, dc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
                 }
             } else {
                 cell[j] = -1;                              // absorbed: leaves a hole
@@ -702,7 +707,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 sc.vz[io][slot] = e.uz;
                 if (a.diag) {
                     moment_diag(sc, fhist, mhist, e.c, e.f, e.ux, nc, periodic);
-                    if (s == 0) electron_diag(sc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
+                    if (s == 0) electron_diag(sc, dc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
                 }
             }
             __syncthreads();
