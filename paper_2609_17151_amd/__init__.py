@@ -187,6 +187,8 @@ class Sim:
         self.h = h
         _live.append(weakref.ref(self))
         self.n_nodes = [c["n_cells"] + (1 if c["bc"] == 1 else 0) for c in self.cfgs]
+        self.tables = []            # every table loaded, in order (checkpoints replay them)
+        self.retired = set()
         for t in tables:
             self.load_xsec(t["species"], t["kind"], t["threshold"], t["energy"], t["sigma"],
                            batch=t.get("batch", -1))
@@ -211,6 +213,8 @@ class Sim:
         s = np.ascontiguousarray(sigma, dtype=np.float64)
         self._check(_lib.pic_load_xsec(self.h, batch, species, kind, threshold, len(e),
                                        _ptr(e, C.c_double), _ptr(s, C.c_double)), "pic_load_xsec")
+        self.tables.append(dict(species=int(species), kind=int(kind), threshold=float(threshold),
+                                energy=e.copy(), sigma=s.copy(), batch=int(batch)))
 
     def step(self, n=1):
         self._check(_lib.pic_step(self.h, int(n)), "pic_step")
@@ -338,6 +342,10 @@ class Sim:
 
     def retire(self, batch, retired=True):
         self._check(_lib.pic_retire(self.h, batch, int(retired)), "pic_retire")
+        if retired:
+            self.retired.add(int(batch))
+        else:
+            self.retired.discard(int(batch))
 
     def sort(self):
         self._check(_lib.pic_sort(self.h), "pic_sort")
