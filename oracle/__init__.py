@@ -49,7 +49,7 @@ class Config(C.Structure):
                 ("gas_mass", C.c_double), ("see_gamma", C.c_double),
                 ("see_temp", C.c_double), ("perturb_eps", C.c_double),
                 ("perturb_mode", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64),
-                ("sp", Species * MAX_SPECIES)]
+                ("sp", Species * MAX_SPECIES), ("renew_lz", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -57,7 +57,8 @@ class Counters(C.Structure):
                 ("candidates", C.c_int64 * MAX_SPECIES), ("nulls", C.c_int64 * MAX_SPECIES),
                 ("coll", (C.c_int64 * MAX_CHAN) * MAX_SPECIES),
                 ("violations", C.c_int64 * MAX_SPECIES), ("dropped", C.c_int64),
-                ("wall_energy", (C.c_double * 2) * MAX_SPECIES)]
+                ("wall_energy", (C.c_double * 2) * MAX_SPECIES),
+                ("renewed", C.c_int64 * MAX_SPECIES)]
 
 
 _lib = None
@@ -82,6 +83,8 @@ def lib():
         L.orc_set_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up, C.c_uint32]
         L.orc_get_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_uint32)]
+        L.orc_set_axial.argtypes = [P, C.c_int32, C.c_int64, dp]
+        L.orc_get_axial.argtypes = [P, C.c_int32, C.c_int64, dp]
         L.orc_set_step.argtypes = [P, C.c_uint64]
         L.orc_get_step.argtypes = [P]
         L.orc_get_step.restype = C.c_uint64
@@ -145,6 +148,7 @@ def make_config(cfg):
         c.b_ext[i] = cfg["b_ext"][i]
     c.perturb_mode = cfg["perturb_mode"]
     c.seed = cfg["seed"]
+    c.renew_lz = float(cfg.get("renew_lz", 0.0))
     for i, sp in enumerate(cfg["species"]):
         s = c.sp[i]
         s.charge, s.mass, s.weight = sp["charge"], sp["mass"], sp["weight"]
@@ -234,6 +238,17 @@ class Oracle:
         _check(lib().orc_set_particles(self.h, s, len(x), _dp(x), _dp(vx), _dp(vy), _dp(vz),
                                        _up(ids), next_id), "orc_set_particles")
 
+    def set_axial(self, s, z):
+        """Axial displacements of species s (one per particle, canonical order)."""
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        _check(lib().orc_set_axial(self.h, s, len(z), _dp(z)), "orc_set_axial")
+
+    def axial(self, s):
+        n = len(self.get_particles(s)["x"])
+        z = np.zeros(n)
+        _check(lib().orc_get_axial(self.h, s, n, _dp(z)), "orc_get_axial")
+        return z
+
     def field(self):
         n = self.n_nodes
         rho, phi, ef = np.zeros(n), np.zeros(n), np.zeros(n)
@@ -262,7 +277,8 @@ class Oracle:
                     coll=np.array([[c.coll[k][j] for j in range(MAX_CHAN)] for k in range(ns)]),
                     violations=np.array([c.violations[k] for k in range(ns)]),
                     dropped=c.dropped,
-                    wall_energy=np.array([[c.wall_energy[k][w] for w in range(2)] for k in range(ns)]))
+                    wall_energy=np.array([[c.wall_energy[k][w] for w in range(2)] for k in range(ns)]),
+                    renewed=np.array([c.renewed[k] for k in range(ns)]))
 
     def set_diag(self, enable=True, eepf_emax=64.0):
         _check(lib().orc_set_diag(self.h, int(enable), float(eepf_emax)), "orc_set_diag")

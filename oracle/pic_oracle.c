@@ -27,6 +27,7 @@
 
 typedef struct {
     double *x, *vx, *vy, *vz;
+    double* z;                        /* virtual axial displacement since the last renewal */
     uint32_t* id;
     int64_t n, cap;
     uint32_t next_id;
@@ -299,8 +300,9 @@ static int pop_alloc(pop_t* p, int64_t cap)
     p->vx = calloc(n, sizeof(double));
     p->vy = calloc(n, sizeof(double));
     p->vz = calloc(n, sizeof(double));
+    p->z = calloc(n, sizeof(double));
     p->id = calloc(n, sizeof(uint32_t));
-    return (p->x && p->vx && p->vy && p->vz && p->id) ? ORC_OK : ORC_ENOMEM;
+    return (p->x && p->vx && p->vy && p->vz && p->z && p->id) ? ORC_OK : ORC_ENOMEM;
 }
 
 int orc_create(const orc_config* cfg, orc_sim** out)
@@ -308,7 +310,8 @@ int orc_create(const orc_config* cfg, orc_sim** out)
     if (!cfg || !out) return ORC_EINVAL;
     if (cfg->n_cells < 2 || cfg->length <= 0.0 || cfg->dt <= 0.0 || cfg->eps0 <= 0.0 ||
         cfg->n_species < 1 || cfg->n_species > ORC_MAX_SPECIES ||
-        (cfg->bc != ORC_BC_PERIODIC && cfg->bc != ORC_BC_DIRICHLET))
+        (cfg->bc != ORC_BC_PERIODIC && cfg->bc != ORC_BC_DIRICHLET) ||
+        !(cfg->renew_lz >= 0.0 && cfg->renew_lz < 1e300))
         return ORC_EINVAL;
     for (int k = 0; k < cfg->n_species; ++k) {
         if (cfg->sp[k].mass <= 0.0 || cfg->sp[k].capacity < cfg->sp[k].n_init ||
@@ -350,6 +353,7 @@ void orc_free(orc_sim* s)
     if (!s) return;
     for (int k = 0; k < ORC_MAX_SPECIES; ++k) {
         free(s->p[k].x); free(s->p[k].vx); free(s->p[k].vy); free(s->p[k].vz); free(s->p[k].id);
+        free(s->p[k].z);
         free(s->sum[k]); free(s->dens[k]); free(s->av_dens[k]);
         free(s->births[k].b);
         for (int j = 0; j < ORC_MAX_CHAN; ++j) { free(s->ch[k][j].e); free(s->ch[k][j].s); }
@@ -551,6 +555,7 @@ int orc_load(orc_sim* s)
             box_muller(orc_u01(r1[0]), orc_u01(r1[1]), &g0, &g1);
             box_muller(orc_u01(r1[2]), orc_u01(r1[3]), &g2, &g3);
             p->x[j] = x;
+            p->z[j] = 0.0;
             p->vx[j] = sp->drift[0] + sp->vth * g0;
             p->vy[j] = sp->drift[1] + sp->vth * g1;
             p->vz[j] = sp->drift[2] + sp->vth * g2;
@@ -640,6 +645,7 @@ int orc_load_profiles(orc_sim* s, int32_t m, const double* dens, const double* t
             box_muller(orc_u01(r1[0]), orc_u01(r1[1]), &g0, &g1);
             box_muller(orc_u01(r1[2]), orc_u01(r1[3]), &g2, &g3);
             p->x[j] = x;
+            p->z[j] = 0.0;
             p->vx[j] = vth * g0;
             p->vy[j] = vth * g1;
             p->vz[j] = vth * g2;
@@ -677,9 +683,29 @@ int orc_set_particles(orc_sim* s, int32_t k, int64_t n, const double* x, const d
     for (int64_t j = 0; j < n; ++j) {
         p->x[j] = x[j]; p->vx[j] = vx[j]; p->vy[j] = vy[j]; p->vz[j] = vz[j];
         p->id[j] = id[j];
+        p->z[j] = 0.0;
     }
     p->n = n;
     p->next_id = next_id;
+    return ORC_OK;
+}
+
+/* Axial displacements of species k (renewal, Lafleur's method): replace the
+ * first n values (n = the species' count) or read them. */
+int orc_set_axial(orc_sim* s, int32_t k, int64_t n, const double* z)
+{
+    if (!s || k < 0 || k >= s->c.n_species || !z || n != s->p[k].n) return ORC_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!isfinite(z[j])) return ORC_ENUMERIC;
+        s->p[k].z[j] = z[j];
+    }
+    return ORC_OK;
+}
+
+int orc_get_axial(const orc_sim* s, int32_t k, int64_t cap, double* z)
+{
+    if (!s || k < 0 || k >= s->c.n_species || !z || cap < s->p[k].n) return ORC_EINVAL;
+    for (int64_t j = 0; j < s->p[k].n; ++j) z[j] = s->p[k].z[j];
     return ORC_OK;
 }
 
@@ -895,6 +921,29 @@ static void sample_diagnostics(orc_sim* s)
     s->av_samples += 1.0;
 }
 
+/* Axial renewal (Lafleur, Baalrud and Chabert): each particle carries the
+ * virtual displacement z along the imposed field's axis (the third velocity
+ * component) since its injection, advanced with the new velocity; once
+ * |z| >= L_z the particle is re-injected at the same x with a fresh velocity
+ * from the species' initial distribution (Maxwellian of scale vth plus the
+ * drift), drawn with call 6, and z = 0. */
+static void renew(orc_sim* s, int k, uint32_t id, double v[3], double* z)
+{
+    *z += v[2] * s->c.dt;
+    if (fabs(*z) < s->c.renew_lz) return;
+    uint32_t r[4];
+    draw(s, id, (uint32_t)s->step, k, 6u, r);
+    double g0, g1, g2, g3;
+    box_muller(orc_u01(r[0]), orc_u01(r[1]), &g0, &g1);
+    box_muller(orc_u01(r[2]), orc_u01(r[3]), &g2, &g3);
+    const orc_species* sp = &s->c.sp[k];
+    v[0] = sp->drift[0] + sp->vth * g0;
+    v[1] = sp->drift[1] + sp->vth * g1;
+    v[2] = sp->drift[2] + sp->vth * g2;
+    *z = 0.0;
+    s->cnt.renewed[k] += 1;
+}
+
 /* One leapfrog step: for each species in order, each particle in index order:
  * gather E at x^n, Boris to v^{n+1/2}, move to x^{n+1}, wrap or absorb (with
  * secondary emission), collide.  Survivors keep their order; births follow,
@@ -938,12 +987,15 @@ static int one_step(orc_sim* s)
                 }
                 continue;
             }
+            double z = p->z[j];
+            if (s->c.renew_lz > 0.0) renew(s, k, p->id[j], v, &z);
             if (s->nch[k] > 0) {
                 int rc = collide(s, k, p->id[j], x, v);
                 if (rc) return rc;
             }
             p->x[keep] = x;
             p->vx[keep] = v[0]; p->vy[keep] = v[1]; p->vz[keep] = v[2];
+            p->z[keep] = z;
             p->id[keep] = p->id[j];
             keep += 1;
         }
@@ -957,6 +1009,7 @@ static int one_step(orc_sim* s)
             if (p->n >= p->cap) { s->cnt.dropped += s->births[k].n - b; rc = ORC_ECAPACITY; break; }
             const birth_t* bb = &s->births[k].b[b];
             p->x[p->n] = bb->x; p->vx[p->n] = bb->vx; p->vy[p->n] = bb->vy; p->vz[p->n] = bb->vz;
+            p->z[p->n] = 0.0;
             p->id[p->n] = p->next_id++;
             p->n += 1;
         }

@@ -52,6 +52,7 @@ typedef struct {
     int32_t perturb_mode, pad;
     uint64_t seed;
     orc_species sp[ORC_MAX_SPECIES];
+    double renew_lz;                  /* axial renewal length (m); 0: no renewal */
 } orc_config;
 
 /* Counters of one run: event counts (integer-exact) and the kinetic energy
@@ -65,6 +66,7 @@ typedef struct {
     int64_t violations[ORC_MAX_SPECIES];
     int64_t dropped;
     double wall_energy[ORC_MAX_SPECIES][2];  /* [species][wall]: sum of m w |v|^2 / 2 at impact */
+    int64_t renewed[ORC_MAX_SPECIES];        /* axial renewals */
 } orc_counters;
 
 typedef struct orc_sim orc_sim;
@@ -86,6 +88,8 @@ int  orc_load_profiles(orc_sim* s, int32_t m, const double* density, const doubl
 int  orc_set_particles(orc_sim* s, int32_t species, int64_t n, const double* x,
                        const double* vx, const double* vy, const double* vz,
                        const uint32_t* id, uint32_t next_id);
+int  orc_set_axial(orc_sim* s, int32_t species, int64_t n, const double* z);
+int  orc_get_axial(const orc_sim* s, int32_t species, int64_t cap, double* z);
 int  orc_get_particles(const orc_sim* s, int32_t species, int64_t cap, double* x,
                        double* vx, double* vy, double* vz, uint32_t* id, int64_t* n,
                        uint32_t* next_id);

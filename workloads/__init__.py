@@ -61,7 +61,7 @@ def base_config(**kw):
                rho_bg=0.0, e_unit=1.0, v_amp=0.0, v_freq=0.0, v_phase=0.0,
                e_ext=[0.0, 0.0, 0.0], b_ext=[0.0, 0.0, 0.0], gas_density=0.0,
                gas_temp=300.0, gas_mass=0.0, see_gamma=0.0, see_temp=1.0,
-               perturb_eps=0.0, perturb_mode=0, seed=1, species=[])
+               perturb_eps=0.0, perturb_mode=0, seed=1, species=[], renew_lz=0.0)
     cfg.update(kw)
     return cfg
 
