@@ -101,6 +101,11 @@ typedef struct {
     int32_t perturb_mode, pad;
     uint64_t seed;                  /* Philox key */
     pic_species_cfg species[PIC_MAX_SPECIES];
+    double renew_lz;                /* axial renewal length L_z (m), 0 = off (Section 3.6, after Lafleur,
+                                       Baalrud and Chabert): every particle carries its displacement z along
+                                       the third axis since injection, z += vz dt; once |z| >= L_z it is
+                                       re-injected at the same x with velocities drawn from its species'
+                                       initial Maxwellian (vth, drift) and z = 0 */
 } pic_config;
 
 typedef struct {
@@ -181,6 +186,7 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
                                    histogram of impact energies since the last reset (bin width emax / PIC_EEPF_BINS,
                                    emax from pic_set_wall_edf), then the bin width (eV) per species, then the samples
                                    of the time averages over the same interval */
+#define PIC_DIAG_RENEWED 18     /* int64[S]: axial renewals per species since pic_init */
 #define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
 
 #define PIC_EEPF_BINS 256
@@ -235,6 +241,19 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
  */
 pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const double* density,
                              const double* temp_eV, const int64_t* n);
+
+/*
+ * pic_get_axial / pic_set_axial: the axial displacements z (m) of the
+ * particles of one species and discharge, in canonical order (one per
+ * particle of pic_get_particles), when the context renews particles
+ * (renew_lz > 0; Section 3.6).  pic_set_particles and pic_load_profiles set
+ * z = 0; pic_set_axial then replaces them (n must equal the species' count).
+ * PIC_EINVAL without renewal, for a size mismatch, or a non-finite value.
+ * get: *n_out receives the count; with cap below it (or z NULL) nothing is
+ * copied.  Synchronous.
+ */
+pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, float* z, int64_t* n_out);
+pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const float* z);
 
 /* pic_sync: wait for queued work; return a latched device error if any. */
 pic_status pic_sync(pic_ctx* ctx);

@@ -23,7 +23,7 @@ EEPF_BINS = 256
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
-            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17)
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17, RENEWED=18)
 
 
 class SpeciesCfg(C.Structure):
@@ -41,7 +41,7 @@ class PicConfig(C.Structure):
                 ("gas_density", C.c_double), ("gas_temp", C.c_double), ("gas_mass", C.c_double),
                 ("see_gamma", C.c_double), ("see_temp", C.c_double), ("perturb_eps", C.c_double),
                 ("perturb_mode", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64),
-                ("species", SpeciesCfg * MAX_SPECIES)]
+                ("species", SpeciesCfg * MAX_SPECIES), ("renew_lz", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -102,6 +102,8 @@ def load_library():
         "pic_config_tiles": (i32, [P, i32, i32, i32, i32]),
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_set_wall_edf": (i32, [P, i32, d]),
+        "pic_get_axial": (i32, [P, i32, i32, i64, fp, C.POINTER(i64)]),
+        "pic_set_axial": (i32, [P, i32, i32, i64, fp]),
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
@@ -135,6 +137,7 @@ def make_config(cfg):
     for i in range(3):
         c.e_ext[i], c.b_ext[i] = cfg["e_ext"][i], cfg["b_ext"][i]
     c.perturb_mode, c.seed = cfg["perturb_mode"], cfg["seed"]
+    c.renew_lz = float(cfg.get("renew_lz", 0.0))
     for i, sp in enumerate(cfg["species"]):
         s = c.species[i]
         s.charge, s.mass, s.weight = sp["charge"], sp["mass"], sp["weight"]
@@ -380,6 +383,24 @@ class Sim:
                                            _ptr(ids, C.c_uint32), C.byref(n), C.byref(nid)),
                     "pic_get_particles")
         return dict(cell=cell, off=off, vx=vx, vy=vy, vz=vz, id=ids, next_id=nid.value)
+
+    def renewed(self, batch=0):
+        """Axial renewals per species since the start."""
+        return self.diag("RENEWED", self.S, np.int64, batch).copy()
+
+    def axial(self, species, batch=0):
+        """Axial displacements (m) of a species, in the order of get_particles
+        (renewal only)."""
+        n = C.c_int64()
+        self._check(_lib.pic_get_axial(self.h, batch, species, 0, None, C.byref(n)), "pic_get_axial")
+        z = np.zeros(n.value, np.float32)
+        self._check(_lib.pic_get_axial(self.h, batch, species, n.value, _ptr(z, C.c_float), C.byref(n)),
+                    "pic_get_axial")
+        return z
+
+    def set_axial(self, species, z, batch=0):
+        z = np.ascontiguousarray(z, np.float32)
+        self._check(_lib.pic_set_axial(self.h, batch, species, len(z), _ptr(z, C.c_float)), "pic_set_axial")
 
     def set_particles(self, species, cell, off, vx, vy, vz, ids, next_id, step, batch=0):
         cell = np.ascontiguousarray(cell, np.int32)

@@ -6,16 +6,17 @@ velocities, ids), each species' next id, the step index, the configuration
 and the cross-section tables.  Random draws are keyed by (seed, id, step) and
 the deposit sums are exact integers, so a run resumed from a checkpoint
 continues bit for bit as the uninterrupted run would (the field is recomputed
-from the particles and equals the one the run held).  Not kept: counters,
-time averages and distributions (they restart from zero), the diagnostic and
-tile settings, and graphs.  All discharges of a context share one step index
+from the particles and equals the one the run held).  With axial renewal
+the axial displacements are kept too.  Not kept: counters, time averages
+and distributions (they restart from zero), the diagnostic and tile
+settings, and graphs.  All discharges of a context share one step index
 on resume; a retired discharge is restored retired.
 
 Format: one ``.npz`` file (numpy arrays only, readable with
 ``allow_pickle=False``): ``format``, ``configs`` and ``tables`` as JSON
 strings, ``steps`` [B], ``next_id`` [B, S], ``retired`` [B], the table
 arrays ``t{i}_energy`` / ``t{i}_sigma``, and per discharge and species
-``b{b}_s{s}_{cell,off,vx,vy,vz,id}``.
+``b{b}_s{s}_{cell,off,vx,vy,vz,id}`` (and ``b{b}_s{s}_z`` with renewal).
 """
 from __future__ import annotations
 
@@ -42,6 +43,8 @@ def save(sim, path):
             next_id[b, s] = p["next_id"]
             for k in FIELDS:
                 arrays["b%d_s%d_%s" % (b, s, k)] = p[k]
+            if sim.cfgs[b].get("renew_lz", 0.0) > 0.0:
+                arrays["b%d_s%d_z" % (b, s)] = sim.axial(s, b)
     live = [b for b in range(B) if b not in sim.retired]
     if len({int(steps[b]) for b in live}) > 1:
         raise ValueError("discharges at different steps cannot share one resumed step index")
@@ -72,7 +75,8 @@ def read(path):
             t["energy"] = z["t%d_energy" % i]
             t["sigma"] = z["t%d_sigma" % i]
         B, S = len(cfgs), len(cfgs[0]["species"])
-        parts = [[{k: z["b%d_s%d_%s" % (b, s, k)] for k in FIELDS} for s in range(S)] for b in range(B)]
+        parts = [[{k: z[f] for k in FIELDS + ("z",) for f in ["b%d_s%d_%s" % (b, s, k)] if f in z.files}
+                  for s in range(S)] for b in range(B)]
         return dict(configs=cfgs, tables=tabs, steps=z["steps"].copy(), next_id=z["next_id"].copy(),
                     retired=z["retired"].copy(), particles=parts)
 
@@ -102,6 +106,8 @@ def load(path, stream=None, make_sim=None):
             p = c["particles"][b][s]
             sim.set_particles(s, p["cell"], p["off"], p["vx"], p["vy"], p["vz"], p["id"],
                               int(c["next_id"][b, s]), step, batch=b)
+            if "z" in p:
+                sim.set_axial(s, p["z"], batch=b)
     for b in range(len(cfgs)):
         if c["retired"][b]:
             sim.retire(b)

@@ -117,6 +117,7 @@ pic_status check_cfg(const pic_config& c)
     if (!(c.length > 0.0) || !(c.dt > 0.0) || !(c.eps0 > 0.0) || !(c.e_unit > 0.0)) return PIC_EINVAL;
     if (c.n_species < 1 || c.n_species > PIC_MAX_SPECIES) return PIC_EINVAL;
     if (c.see_gamma < 0.0 || c.see_gamma > 1.0) return PIC_EINVAL;
+    if (!(c.renew_lz >= 0.0) || !std::isfinite(c.renew_lz)) return PIC_EINVAL;
     for (int s = 0; s < c.n_species; ++s)
         if (!valid_species(c.species[s])) return PIC_EINVAL;
     return PIC_OK;
@@ -219,6 +220,10 @@ void fill_push_consts(const pic_config& c, int s, SegConst& sc)
     sc.mscale1 = (float)(kMomentScale / moment_vref(c, s));
     sc.mscale2 = (float)(kMomentScale / (moment_vref(c, s) * moment_vref(c, s)));
     sc.wedf_inv_bin = (float)(kEepfBins / (s == 0 ? 64.0 : 1024.0));
+    sc.renew_lz = (float)c.renew_lz;
+    sc.dt_f = (float)c.dt;
+    sc.vth0 = (float)sp.vth;
+    for (int k = 0; k < 3; ++k) sc.drift0[k] = (float)sp.drift[k];
     sc.emits = (s >= 1 && sp.charge > 0.0 && c.see_gamma > 0.0 && c.bc == PIC_BC_DIRICHLET) ? 1 : 0;
     sc.see_k = (uint32_t)std::min(16777217.0, std::ceil(c.see_gamma * 16777216.0));
     sc.vsee = (float)std::sqrt(c.see_temp * c.e_unit / c.species[0].mass);
@@ -511,6 +516,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
                 sc.vy[k] = (float*)A(cap * 4);
                 sc.vz[k] = (float*)A(cap * 4);
                 sc.id[k] = (uint32_t*)A(cap * 4);
+                sc.z[k] = c.renew_lz > 0.0 ? (float*)A(cap * 4) : nullptr;
             }
             fill_push_consts(c, s, sc);
         }
@@ -578,6 +584,10 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.wedf, 0, 8ull * B * S * 2 * kEepfBins, st) == hipSuccess;
+    for (int g = 0; g < B * S && ok; ++g)
+        for (int k = 0; k < 2 && ok; ++k)
+            if (ctx->segc[g].z[k])
+                ok = hipMemsetAsync(ctx->segc[g].z[k], 0, 4ull * pad_cap(ctx->segc[g].cap), st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.bcnt, 0, 4ull * tiles_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * tiles_max, st) == hipSuccess;
@@ -721,7 +731,7 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.general = false;
     for (int g = 0; g < B * S; ++g) {
         const SegConst& sc = ctx->segc[g];
-        if (sc.compacts || sc.nch > 0 || sc.emits) p.general = true;
+        if (sc.compacts || sc.nch > 0 || sc.emits || sc.renew_lz > 0.0f) p.general = true;
     }
     push_shape(p.ppt, p.threads, p.general);
     const int T = p.threads * p.ppt;
@@ -956,6 +966,55 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
     return PIC_OK;
 }
 
+pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, float* z, int64_t* n_out)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S) return PIC_EINVAL;
+    const int idx = batch * ctx->S + species;
+    const SegConst& sc = ctx->segc[idx];
+    if (!sc.z[0]) return PIC_EINVAL;
+    int64_t n = 0;
+    uint32_t nid = 0;
+    // the particles' own read compacts the store first, so z is in canonical order
+    pic_status rc = pic_get_particles(ctx, batch, species, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                      nullptr, &n, &nid);
+    if (rc != PIC_OK) return rc;
+    if (n_out) *n_out = n;
+    if (!z || cap < n) return PIC_OK;
+    SegState ss;
+    if (hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+    if (ss.count != ss.live) {
+        if (launch_compact(ctx->d, ctx->compact_tiles, ctx->n_cu, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess ||
+            hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_EHIP;
+        if (ss.count != ss.live) return PIC_ESTATE;
+    }
+    return hip_st(hipMemcpy(z, sc.z[ss.parity], (size_t)ss.count * 4, hipMemcpyDeviceToHost));
+}
+
+pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const float* z)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S || n < 0) return PIC_EINVAL;
+    const int idx = batch * ctx->S + species;
+    const SegConst& sc = ctx->segc[idx];
+    if (!sc.z[0] || (n > 0 && !z)) return PIC_EINVAL;
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(z[k])) return PIC_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    SegState ss;
+    if (hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+    if (ss.count != ss.live) {
+        if (launch_compact(ctx->d, ctx->compact_tiles, ctx->n_cu, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess ||
+            hipMemcpy(&ss, ctx->d.segs + idx, sizeof(SegState), hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_EHIP;
+        if (ss.count != ss.live) return PIC_ESTATE;
+    }
+    if (n != ss.live) return PIC_EINVAL;
+    if (n == 0) return PIC_OK;
+    return hip_st(hipMemcpy(sc.z[ss.parity], z, (size_t)n * 4, hipMemcpyHostToDevice));
+}
+
 pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, int32_t* cell,
                              float* off, float* vx, float* vy, float* vz, uint32_t* id, int64_t* n_out,
                              uint32_t* next_id)
@@ -1017,6 +1076,7 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
         ok = ok && hipMemcpy(sc.vy[p], vy, nb, hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && hipMemcpy(sc.vz[p], vz, nb, hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && hipMemcpy(sc.id[p], id, nb, hipMemcpyHostToDevice) == hipSuccess;
+        if (sc.z[p]) ok = ok && hipMemset(sc.z[p], 0, nb) == hipSuccess;
     }
     ss.count = n;
     ss.live = n;
@@ -1087,6 +1147,9 @@ pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const doubl
         pa.temp = pa.cum + m;
         pa.e_over_m = c.e_unit / c.species[s].mass;
         ok = launch_profile_load(pa, st) == hipSuccess;
+        const SegConst& zc = ctx->segc[batch * S + s];
+        if (ok && zc.z[ss[s].parity] && n[s] > 0)
+            ok = hipMemsetAsync(zc.z[ss[s].parity], 0, 4ull * n[s], st) == hipSuccess;
         ss[s].count = ss[s].live = n[s];
         ss[s].dead = 0;
         ss[s].staged = 0;
@@ -1247,6 +1310,12 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             ds.avg_samples = 0.0;
             ds.eepf_samples = 0.0;
             ok = ok && hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+            break;
+        }
+        case PIC_DIAG_RENEWED: {
+            if (!need(8ull * S)) return PIC_EINVAL;
+            int64_t* o = (int64_t*)out;
+            for (int s = 0; s < S; ++s) o[s] = (int64_t)ev[(size_t)s * C_N + C_REN];
             break;
         }
         case PIC_DIAG_WALL_EDF: {

@@ -174,6 +174,7 @@ __global__ __launch_bounds__(kCT) void compact_scatter_kernel(DevPtrs d)
                     sc.vy[out][dst] = sc.vy[in][i];
                     sc.vz[out][dst] = sc.vz[in][i];
                     sc.id[out][dst] = sc.id[in][i];
+                    if (sc.z[0]) sc.z[out][dst] = sc.z[in][i];
                 } else {                           // cannot happen when the counts agree
                     atomicOr(&d.diss[g / d.S].flags, kFlagCell);
                 }

@@ -165,6 +165,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                         c0.vy[io0][e] = bb.vy;
                         c0.vz[io0][e] = bb.vz;
                         c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
+                        if (c0.z[0]) c0.z[io0][e] = 0.0f;
                         if (a.diag) {
                             moment_add(0, bb.cell, bb.off, bb.vx);
                             energy_add(bb.cell, bb.off, bb.vx, bb.vy, bb.vz);
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                             c1.vy[io1][q] = bb.ivy;
                             c1.vz[io1][q] = bb.ivz;
                             c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
+                            if (c1.z[0]) c1.z[io1][q] = 0.0f;
                             if (a.diag) moment_add(1, bb.cell, bb.off, bb.ivx);
                         }
                     }

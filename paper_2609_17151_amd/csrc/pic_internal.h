@@ -37,7 +37,7 @@ constexpr uint32_t kFlagStall = 1u << 4;
 // scope atomics on one address serialise); readers sum the copies.
 constexpr int kRep = 1;
 // event counters per segment
-enum { C_ABS0, C_ABS1, C_SEE0, C_SEE1, C_CAND, C_NULL, C_VIOL, C_DROP, C_COLL, C_N = C_COLL + kMaxChan };
+enum { C_ABS0, C_ABS1, C_SEE0, C_SEE1, C_CAND, C_NULL, C_VIOL, C_DROP, C_REN, C_COLL, C_N = C_COLL + kMaxChan };
 
 // Fixed-point scale of the deposit: a particle's weights (1-f, f) become the
 // integers 2^32 - q and q, q = f * 2^32, so sums are exact and independent of
@@ -61,6 +61,7 @@ struct SegConst {
     float* vy[2];
     float* vz[2];
     uint32_t* id[2];
+    float* z[2];            // axial displacement since injection (renewal only, else null)
     int64_t cap;
     // push
     float qmh;              // (q/m) dt/2
@@ -94,6 +95,9 @@ struct SegConst {
     // vx x mscale1 and weight x vx^2 x mscale2, rounded to integers
     float mscale1, mscale2;
     float wedf_inv_bin;     // wall impact-energy histogram: 1 / bin width (1/eV)
+    // axial renewal: length (0 = off), dt, the initial distribution
+    float renew_lz, dt_f, vth0;
+    float drift0[3];
 };
 
 struct DisConst {

@@ -646,6 +646,25 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             bool cand = false;
             const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, s_wen, cell[j], off[j], vx[j],
                                                vy[j], vz[j], pid[j], ke_tile, sink, cand);
+            if (GENERAL && keep && sc.renew_lz > 0.0f) {
+                // axial transit: displacement along the third axis since
+                // injection; past L_z, a fresh velocity from the species'
+                // initial distribution (call 6) at the same x
+                float* zp = sc.z[io] + base + j;
+                float zz = *zp + vz[j] * sc.dt_f;
+                if (fabsf(zz) >= sc.renew_lz) {
+                    const uint4 r6 = philox10(pid[j], step, ((uint32_t)s << 24) | 6u, 0u, dc.key0, dc.key1);
+                    float g0, g1, g2, g3;
+                    box_muller_f(u01f(r6.x), u01f(r6.y), g0, g1);
+                    box_muller_f(u01f(r6.z), u01f(r6.w), g2, g3);
+                    vx[j] = sc.drift0[0] + sc.vth0 * g0;
+                    vy[j] = sc.drift0[1] + sc.vth0 * g1;
+                    vz[j] = sc.drift0[2] + sc.vth0 * g2;
+                    zz = 0.0f;
+                    atomicAdd(&s_cnt[C_REN], 1u);
+                }
+                *zp = zz;
+            }
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
                 if (GENERAL && cand) {

@@ -278,6 +278,7 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(SortArgs a)
         sc.vy[out][dst] = sc.vy[in][idx];
         sc.vz[out][dst] = sc.vz[in][idx];
         sc.id[out][dst] = sc.id[in][idx];
+        if (sc.z[0]) sc.z[out][dst] = sc.z[in][idx];
     }
     (void)nc;
 }

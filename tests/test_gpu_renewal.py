@@ -1,0 +1,114 @@
+"""Axial renewal on the GPU (Section 3.6, Lafleur's method) against the
+oracle: one step from identical states (positions, velocities, ids and axial
+displacements) in an E x B box where many particles cross L_z, the ion
+transit time in the axial field, and a checkpoint resume of a renewing run."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import compare_species, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pic():
+    import paper_2609_17151_amd as P
+    return P
+
+
+def _box(n=200_000, lz=1e-3):
+    cfg = W.exb(n_per_species=n, n_cells=256, length=0.00178 * 4)
+    cfg["renew_lz"] = lz
+    return cfg
+
+
+def test_renewal_step_matches_oracle(pic):
+    cfg = _box()
+    sim = pic.Sim(cfg)
+    sim.step(3)
+    rng = np.random.default_rng(5)
+    lz = cfg["renew_lz"]
+    zs = []
+    dt = cfg["dt"]
+    for s in range(2):
+        vz = sim.get_particles(s)["vz"].astype(np.float64)
+        # within two steps' displacement of the L_z its velocity points to:
+        # about half of each species crosses in the next step
+        z = (np.sign(vz) * (lz - rng.uniform(0.0, 2.0, vz.size) * np.abs(vz) * dt)).astype(np.float32)
+        sim.set_axial(s, z)
+        zs.append(z)
+    o = to_oracle(sim, cfg)
+    for s in range(2):
+        o.set_axial(s, zs[s].astype(np.float64))
+    sim.step(1)
+    o.step(1)
+    ren_g, ren_o = sim.renewed(), o.counters()["renewed"]
+    for s in range(2):
+        assert ren_o[s] > 0.3 * len(zs[s])
+        # a displacement within rounding of L_z may decide either way
+        assert abs(int(ren_g[s]) - int(ren_o[s])) <= 2
+        pg, po = sim.get_particles(s), o.get_particles(s)
+        assert np.array_equal(pg["id"], po["id"])
+        r = compare_species(pg, po, cfg, cfg["species"][s]["vth"])
+        ok = (r["rel_v"] < 1e-5) & (r["dx"] < 1e-6 * cfg["length"])
+        assert ok.mean() >= 0.9999, (s, ok.mean())
+        zg, zo = sim.axial(s), o.axial(s)
+        close = np.abs(zg - zo) <= 1e-5 * lz
+        assert close.mean() >= 0.9999
+
+
+def test_ion_transit_time_on_gpu(pic):
+    # ions from rest, no magnetic field on them worth noting, axial field
+    # only: z after N steps = a dt^2 N^2 / 2, first renewal at the ceiling
+    q, m, e, dt, lz, n = 1.602176634e-19, 2.18e-25, 2e4, 5e-12, 2e-4, 4096
+    a = q * e / m
+    root = math.sqrt(2 * lz / (a * dt * dt))
+    nstar = math.ceil(root)
+    assert nstar - root > 0.05 and nstar - root < 0.95
+    sp = [W.species(q, m, 1e8, n, 0.0, capacity=n, load=W.LOAD_STRATIFIED)]
+    cfg = W.base_config(n_cells=64, bc=0, field_solve=0, length=0.01, dt=dt, eps0=8.8541878128e-12,
+                        e_unit=q, e_ext=[0.0, 0.0, e], species=sp, renew_lz=lz, seed=3)
+    sim = pic.Sim(cfg)
+    sim.step(nstar - 1)
+    assert sim.renewed()[0] == 0
+    np.testing.assert_allclose(sim.axial(0), a * dt * dt * (nstar - 1) ** 2 / 2, rtol=1e-4)
+    sim.step(1)
+    assert sim.renewed()[0] == n
+    assert np.all(sim.axial(0) == 0.0) and np.all(sim.get_particles(0)["vz"] == 0.0)
+
+
+def test_checkpoint_resume_with_renewal(pic, tmp_path):
+    from paper_2609_17151_amd import checkpoint as K
+    cfg = _box(n=100_000, lz=2e-4)
+    a = pic.Sim(cfg)
+    a.step(50)
+    assert a.renewed().sum() > 0
+    path = str(tmp_path / "ecdi.npz")
+    K.save(a, path)
+    a.step(37)
+    b = K.load(path)
+    b.step(37)
+    for s in range(2):
+        pa, pb = a.get_particles(s), b.get_particles(s)
+        for k in ("cell", "off", "vx", "vy", "vz", "id"):
+            assert np.array_equal(pa[k], pb[k]), (s, k)
+        assert np.array_equal(a.axial(s), b.axial(s))
+    b.close()
+
+
+def test_axial_access_rules(pic):
+    sim = pic.Sim(W.exb(n_per_species=4096, n_cells=64))
+    with pytest.raises(RuntimeError):
+        sim.axial(0)                     # no renewal: no axial coordinate
+    s2 = pic.Sim(_box(n=4096))
+    with pytest.raises(RuntimeError):
+        s2.set_axial(0, np.zeros(3, np.float32))
+    with pytest.raises(RuntimeError):
+        s2.set_axial(0, np.full(4096, np.nan, np.float32))
+    bad = _box(n=4096)
+    bad["renew_lz"] = -1.0
+    with pytest.raises(RuntimeError):
+        pic.Sim(bad)
