@@ -180,6 +180,25 @@ def exb(length=0.005, n_cells=1024, n_per_species=4_000_000, density=5e16,
 
 
 # --------------------------------------------------------------------------
+# Electron cyclotron drift instability box (Section 3.6): the E x B box with
+# the paper's reference fields and density, a whole number of resonant
+# wavelengths lambda_1 = 2 pi v_E / omega_ce along the drift, and axial
+# renewal after a virtual transit L_z.
+# --------------------------------------------------------------------------
+def lambda1(e_field=2e4, b_field=0.02):
+    v_e = e_field / b_field
+    return 2.0 * math.pi * v_e * M_ELECTRON / (E_CHARGE * b_field)
+
+
+def ecdi(n_lambda=15, n_cells=1024, n_per_species=4_000_000, density=1e17, te_ev=10.0, ti_ev=0.2,
+         e_field=2e4, b_field=0.02, lz=0.01, dt=5e-12, seed=11):
+    cfg = exb(length=n_lambda * lambda1(e_field, b_field), n_cells=n_cells, n_per_species=n_per_species,
+              density=density, te_ev=te_ev, ti_ev=ti_ev, e_field=e_field, b_field=b_field, dt=dt, seed=seed)
+    cfg["renew_lz"] = lz
+    return cfg
+
+
+# --------------------------------------------------------------------------
 # Maxwell-model swarm: electrons only, imposed uniform field, no Poisson,
 # sigma(eps) = nu0 / (n_g v(eps)) so the collision frequency is constant.
 # --------------------------------------------------------------------------
