@@ -299,7 +299,10 @@ pic_status pic_retire(pic_ctx* ctx, int32_t batch, int32_t retired);
 
 /* pic_sort: queue a stable sort of every species of every discharge by cell
  * index (particles with equal cells keep their order).  pic_config_tiles can
- * make pic_step do this every K steps.  Asynchronous. */
+ * make pic_step do this every K steps.  The canonical order changes, and
+ * with it the ids later births receive (in their parents' order): a run with
+ * births then draws other random numbers than an unsorted run.
+ * Asynchronous. */
 pic_status pic_sort(pic_ctx* ctx);
 
 /* pic_use_graphs: when enable is non-zero (the default), pic_step captures a

@@ -2,12 +2,16 @@
 workgroup, the interval of the sort by cell and the interval of the hole
 compaction.
 
-None of these changes the results: the deposit sums are exact integers, the
-random draws are keyed by particle id and step, and sorting and compaction
-keep the canonical order up to a permutation that the physics does not see.
-So the tuner times candidates on the live run itself (every timed step is a
-real step of the simulation), keeps the fastest, and remembers the choice in
-a JSON cache keyed by the shape of the workload.
+None of the choices it makes changes the results: the deposit sums are
+exact integers, the random draws are keyed by particle id and step, and the
+compaction keeps the canonical order.  Sorting permutes the particles, which
+the physics does not see as long as nothing is born: births take their ids
+in the order of their parents, so after a sort they would draw other random
+numbers.  The sort is therefore a candidate only where no particle can be
+born (the streaming kernel: periodic, no collisions).  The tuner times the
+candidates on the live run itself (every timed step is a real step of the
+simulation), keeps the fastest, and remembers the choice in a JSON cache
+keyed by the shape of the workload.
 """
 from __future__ import annotations
 
@@ -35,7 +39,7 @@ def candidates(general):
     shapes = GENERAL if general else STREAMING
     out = []
     for ppt, thr in shapes:
-        for srt in SORT_EVERY:
+        for srt in (SORT_EVERY if not general else (0,)):
             for cmp_ in (COMPACT_EVERY if general else (16,)):
                 out.append(dict(ppt=ppt, threads=thr, sort_every=srt, compact_every=cmp_))
     return out

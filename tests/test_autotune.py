@@ -37,6 +37,10 @@ def test_candidates_by_kernel_mode():
     assert all(c["threads"] == 256 and c["ppt"] <= 2 for c in g)
     assert {c["compact_every"] for c in g} == set(autotune.COMPACT_EVERY)
     assert {(c["ppt"], c["threads"]) for c in s} == set(autotune.STREAMING)
+    # births take ids in their parents' order, so a sort would change the
+    # random numbers of a run with births: no sort in the general kernel
+    assert {c["sort_every"] for c in g} == {0}
+    assert {c["sort_every"] for c in s} == set(autotune.SORT_EVERY)
 
 
 def test_picks_fastest_and_caches(tmp_path):
