@@ -376,7 +376,7 @@ int orc_load_xsec(orc_sim* s, int32_t sp, int32_t kind, double th, int32_t n,
     }
     if (s->nch[sp] > 0 && electron_kind(s->ch[sp][0].kind) != electron_kind(kind))
         return ORC_EINVAL;
-    if (kind == ORC_XS_IONIZATION && (sp != 0 || s->c.n_species < 2)) return ORC_EINVAL;
+    if (kind == ORC_XS_IONIZATION && sp != 0) return ORC_EINVAL;
     chan_t* ch = &s->ch[sp][s->nch[sp]];
     ch->e = malloc((size_t)n * sizeof(double));
     ch->s = malloc((size_t)n * sizeof(double));
@@ -822,8 +822,10 @@ static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
             double g0, g1, g2, g3, vt = sqrt(K_B * s->c.gas_temp / M);
             box_muller(orc_u01(r2[0]), orc_u01(r2[1]), &g0, &g1);
             box_muller(orc_u01(r2[2]), orc_u01(r2[3]), &g2, &g3);
-            rc = push_birth(&s->births[1], x, vt * g0, vt * g1, vt * g2);
-            if (rc) return rc;
+            if (s->c.n_species > 1) {   /* with electrons only (a swarm) the ion is not followed */
+                rc = push_birth(&s->births[1], x, vt * g0, vt * g1, vt * g2);
+                if (rc) return rc;
+            }
         }
         if (eps_new < 0.0) eps_new = 0.0;
         double vs = sqrt(2.0 * eps_new * eu / m);
