@@ -58,7 +58,7 @@ typedef int32_t pic_status;
  * from the gas Maxwellian. */
 #define PIC_XS_ELASTIC 0      /* isotropic, recoil loss 2m/M (1 - cos chi) */
 #define PIC_XS_EXCITATION 1   /* threshold energy removed, isotropic */
-#define PIC_XS_IONIZATION 2   /* threshold removed, uniform sharing, e-ion pair born */
+#define PIC_XS_IONIZATION 2   /* threshold removed, uniform sharing, e-ion pair born (the ion into species 1; with electrons only, as in a swarm, the ion is not followed) */
 #define PIC_XS_ION_CX 3       /* ion takes the neutral's velocity */
 #define PIC_XS_ION_ISO 4      /* isotropic scattering in the centre of mass */
 
@@ -136,7 +136,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
  * ln(energy), clamped outside the table, and zero below threshold_eV.
  * Processes are tried in the order they were added.  Recomputes the species'
  * maximum collision frequency.  Kinds may not mix electron-type and ion-type
- * within one species; ionization is accepted on species 0 with n_species >= 2.
+ * within one species; ionization is accepted on species 0 only (its ion goes
+ * to species 1 when the context has one).
  */
 pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t kind,
                          double threshold_eV, int32_t n, const double* energy_eV,

@@ -628,7 +628,7 @@ pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t k
             return PIC_EINVAL;
         if (i > 0 && !(energy[i] > energy[i - 1])) return PIC_EINVAL;
     }
-    if (kind == PIC_XS_IONIZATION && (species != 0 || ctx->S < 2)) return PIC_EINVAL;
+    if (kind == PIC_XS_IONIZATION && species != 0) return PIC_EINVAL;
     const int b0 = batch < 0 ? 0 : batch, b1 = batch < 0 ? ctx->B : batch + 1;
     for (int b = b0; b < b1; ++b) {
         const pic_config& c = ctx->cfg[b];

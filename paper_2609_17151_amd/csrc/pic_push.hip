@@ -134,7 +134,7 @@ struct BirthSink {
     uint32_t pkey;
     unsigned long long* hist;      // this segment's LDS histogram
     unsigned long long* acc_e;     // species 0 of the discharge
-    unsigned long long* acc_i;     // species 1 of the discharge
+    unsigned long long* acc_i;     // species 1 of the discharge (null with electrons only)
 };
 
 __device__ __forceinline__ bool stage_birth(const BirthSink& k, const Birth& x)
@@ -383,7 +383,7 @@ __device__ __forceinline__ void collide_particle(const DevPtrs& d, const SegCons
             x.ivz = sc.vt_gas * g2;
             if (stage_birth(sink, x)) {
                 lds_deposit(sink.hist, c, f, nc, periodic);
-                global_deposit(sink.acc_i, c, f, nc, periodic);
+                if (sink.acc_i) global_deposit(sink.acc_i, c, f, nc, periodic);   // no ions in a swarm
             } else {
                 atomicOr(&d.diss[b].flags, kFlagCapacity);
                 atomicAdd(&s_cnt[C_DROP], 1u);
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         sink.cap = kBirthsPerTile;
         sink.hist = hist;
         sink.acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
-        sink.acc_i = d.acc + ((size_t)b * S + (S > 1 ? 1 : 0)) * kRep * d.nodes_max;
+        sink.acc_i = S > 1 ? d.acc + ((size_t)b * S + 1) * kRep * d.nodes_max : nullptr;
         float ke_tile = 0.0f;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
