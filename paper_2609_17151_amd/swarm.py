@@ -146,3 +146,44 @@ class Swarm:
             out[k + "_err"] = v.std(axis=1, ddof=1) / math.sqrt(self.R) if self.R > 1 else np.zeros_like(out[k])
         return out
 
+
+
+def main(argv=None):
+    """python -m paper_2609_17151_amd.swarm --en 50,100,300,1000 --out swarm.npz"""
+    import argparse
+    import json
+    import sys
+    import time
+    ap = argparse.ArgumentParser(prog="swarm")
+    ap.add_argument("--en", default="50,100,200,500,1000", help="E/N values in Td")
+    ap.add_argument("--replicas", type=int, default=8)
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--relax", type=int, default=65536)
+    ap.add_argument("--sample", type=int, default=32768)
+    ap.add_argument("--every", type=int, default=512)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    en = [float(x) for x in a.en.split(",")]
+    t0 = time.time()
+    sw = Swarm(en, replicas=a.replicas, n=a.n)
+    last = [t0]
+
+    def progress(stage, i, n):
+        if time.time() - last[0] > 20.0:
+            last[0] = time.time()
+            print("swarm %s %d/%d %.0f s" % (stage, i, n, last[0] - t0), flush=True)
+
+    out = sw.run(a.relax, a.sample, every=a.every, progress=progress)
+    sw.sim.sync()
+    wall = time.time() - t0
+    np.savez(a.out, **{k: np.asarray(v) for k, v in out.items() if k != "per_replica"})
+    rows = [dict(e_over_n_td=en[i], W=float(out["W"][i]), W_err=float(out["W_err"][i]),
+                 energy_eV=float(out["energy"][i]), energy_err=float(out["energy_err"][i]),
+                 rates=[float(x) for x in out["rates"][i]], rates_err=[float(x) for x in out["rates_err"][i]])
+            for i in range(len(en))]
+    print(json.dumps(dict(metric="swarm_coefficients", kinds=out["kinds"], dt=out["dt"], replicas=a.replicas,
+                          electrons_per_replica=a.n, thinned=out["thinned"], wall_s=wall, rows=rows)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
