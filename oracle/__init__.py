@@ -49,7 +49,8 @@ class Config(C.Structure):
                 ("gas_mass", C.c_double), ("see_gamma", C.c_double),
                 ("see_temp", C.c_double), ("perturb_eps", C.c_double),
                 ("perturb_mode", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64),
-                ("sp", Species * MAX_SPECIES), ("renew_lz", C.c_double)]
+                ("sp", Species * MAX_SPECIES), ("renew_lz", C.c_double),
+                ("drive", C.c_int32), ("waveform", C.c_int32), ("cap", C.c_double), ("j_amp", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -84,6 +85,8 @@ def lib():
         L.orc_get_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, up,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_uint32)]
         L.orc_set_axial.argtypes = [P, C.c_int32, C.c_int64, dp]
+        L.orc_get_circuit.argtypes = [P, dp]
+        L.orc_set_circuit.argtypes = [P, C.c_double]
         L.orc_get_axial.argtypes = [P, C.c_int32, C.c_int64, dp]
         L.orc_set_step.argtypes = [P, C.c_uint64]
         L.orc_get_step.argtypes = [P]
@@ -149,6 +152,10 @@ def make_config(cfg):
     c.perturb_mode = cfg["perturb_mode"]
     c.seed = cfg["seed"]
     c.renew_lz = float(cfg.get("renew_lz", 0.0))
+    c.drive = int(cfg.get("drive", 0))
+    c.waveform = int(cfg.get("waveform", 0))
+    c.cap = float(cfg.get("cap", 0.0))
+    c.j_amp = float(cfg.get("j_amp", 0.0))
     for i, sp in enumerate(cfg["species"]):
         s = c.sp[i]
         s.charge, s.mass, s.weight = sp["charge"], sp["mass"], sp["weight"]
@@ -248,6 +255,15 @@ class Oracle:
         z = np.zeros(n)
         _check(lib().orc_get_axial(self.h, s, n, _dp(z)), "orc_get_axial")
         return z
+
+    def circuit(self):
+        """(electrode potential at the last solve, the conductor's charge per area)."""
+        o = np.zeros(2)
+        _check(lib().orc_get_circuit(self.h, _dp(o)), "orc_get_circuit")
+        return float(o[0]), float(o[1])
+
+    def set_circuit(self, q):
+        _check(lib().orc_set_circuit(self.h, float(q)), "orc_set_circuit")
 
     def field(self):
         n = self.n_nodes

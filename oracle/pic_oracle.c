@@ -63,6 +63,10 @@ struct orc_sim {
     double* dens[ORC_MAX_SPECIES];
     uint64_t step;
     orc_counters cnt;
+    /* external circuit: the conductor's charge is qbase + the source's charge
+     * since t = 0 + the charge collected from particles since the start */
+    double qbase;
+    int32_t circ_init;
     double ke[ORC_MAX_SPECIES], fe;
     blist_t births[ORC_MAX_SPECIES];
     /* time-accumulated diagnostics, sampled after every step while enabled */
@@ -217,10 +221,45 @@ static double gather(const orc_sim* s, double x)
     return (1.0 - f) * s->ef[c] + f * s->ef[c1];
 }
 
+/* The source waveform (Section 3.3 gives the two-harmonic form). */
+static double source(const orc_sim* s, double t)
+{
+    double w = TWO_PI * s->c.v_freq;
+    if (s->c.waveform == ORC_WAVE_TWO_HARMONIC)
+        return s->c.v_amp * (cos(w * t + s->c.v_phase) + cos(2.0 * w * t));
+    return s->c.v_amp * sin(w * t + s->c.v_phase);
+}
+
 static double voltage(const orc_sim* s, double t)
 {
     if (is_periodic(s)) return 0.0;
-    return s->c.v_amp * sin(TWO_PI * s->c.v_freq * t + s->c.v_phase);
+    return source(s, t);
+}
+
+static int circuit_mode(const orc_sim* s)
+{
+    return !is_periodic(s) && s->c.field_solve && s->c.drive != ORC_DRIVE_VOLTAGE;
+}
+
+/* Charge per area the particles have brought to the electrode at x = 0 since
+ * the start: absorbed particles bring their charge, each secondary electron
+ * it emits takes an electron's charge away. */
+static double q_collected(const orc_sim* s)
+{
+    double q = 0.0;
+    for (int k = 0; k < s->c.n_species; ++k)
+        q += s->c.sp[k].charge * s->c.sp[k].weight * (double)s->cnt.absorbed[k][0];
+    q -= s->c.sp[0].charge * s->c.sp[0].weight * (double)s->cnt.see_emitted[0];
+    return q;
+}
+
+/* Charge per area the current source has delivered since t = 0:
+ * integral of j_amp sin(w t + phase). */
+static double q_source(const orc_sim* s, double t)
+{
+    if (s->c.drive != ORC_DRIVE_CURRENT) return 0.0;
+    double w = TWO_PI * s->c.v_freq;
+    return s->c.j_amp / w * (cos(s->c.v_phase) - cos(w * t + s->c.v_phase));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -311,7 +350,11 @@ int orc_create(const orc_config* cfg, orc_sim** out)
     if (cfg->n_cells < 2 || cfg->length <= 0.0 || cfg->dt <= 0.0 || cfg->eps0 <= 0.0 ||
         cfg->n_species < 1 || cfg->n_species > ORC_MAX_SPECIES ||
         (cfg->bc != ORC_BC_PERIODIC && cfg->bc != ORC_BC_DIRICHLET) ||
-        !(cfg->renew_lz >= 0.0 && cfg->renew_lz < 1e300))
+        !(cfg->renew_lz >= 0.0 && cfg->renew_lz < 1e300) ||
+        cfg->drive < ORC_DRIVE_VOLTAGE || cfg->drive > ORC_DRIVE_CURRENT ||
+        (cfg->bc == ORC_BC_PERIODIC && cfg->drive != ORC_DRIVE_VOLTAGE) ||
+        (cfg->waveform != ORC_WAVE_SINE && cfg->waveform != ORC_WAVE_TWO_HARMONIC) ||
+        !(cfg->cap >= 0.0 && cfg->cap < 1e300) || !(fabs(cfg->j_amp) < 1e300))
         return ORC_EINVAL;
     for (int k = 0; k < cfg->n_species; ++k) {
         if (cfg->sp[k].mass <= 0.0 || cfg->sp[k].capacity < cfg->sp[k].n_init ||
@@ -423,7 +466,7 @@ static void deposit(orc_sim* s)
  * zero mean.  Field: central differences inside; at a wall node Gauss's law
  * over the half cell, E0 = -(phi1-phi0)/dx - rho0 dx/(2 eps0) and
  * EN = -(phiN-phiN-1)/dx + rhoN dx/(2 eps0). */
-static int solve(const orc_sim* s, double t, const double* rho, double* phi, double* ef)
+static int solve_dirichlet(const orc_sim* s, double left_bc, const double* rho, double* phi, double* ef)
 {
     int nn = s->nn;
     double dx = s->dx, e0 = s->c.eps0;
@@ -445,7 +488,7 @@ static int solve(const orc_sim* s, double t, const double* rho, double* phi, dou
         right = 0.0;
     } else {
         for (int i = 0; i < nn; ++i) g[i] = rho[i] * dx * dx / e0;
-        left = voltage(s, t);
+        left = left_bc;
         right = 0.0;
     }
     /* interior unknowns 1..m, m = (periodic ? nn-1 : nn-2); boundary values
@@ -489,6 +532,50 @@ static int solve(const orc_sim* s, double t, const double* rho, double* phi, dou
     return ORC_OK;
 }
 
+/* The field at time t.  Driven by a voltage, phi(0) is the source.  With an
+ * external circuit the electrode's potential follows from its conductor's
+ * charge q: the solution is linear in phi0, phi = psi + phi0 (1 - x/L) with
+ * psi the solution for phi0 = 0, so the field at the electrode's surface is
+ * E0 = E0[psi] + phi0 / L and Gauss's law, q = eps0 E0 + C (phi0 - V(t)),
+ * gives phi0 = (C V(t) + q - eps0 E0[psi]) / (C + eps0 / L) (C = 0 for a
+ * current source, whose V is zero). */
+static int solve(const orc_sim* s, double t, const double* rho, double* phi, double* ef)
+{
+    if (!circuit_mode(s)) return solve_dirichlet(s, voltage(s, t), rho, phi, ef);
+    int rc = solve_dirichlet(s, 0.0, rho, phi, ef);
+    if (rc) return rc;
+    int nn = s->nn;
+    double L = s->c.length, e0 = s->c.eps0;
+    double C = s->c.drive == ORC_DRIVE_CAPACITOR ? s->c.cap : 0.0;
+    double v = s->c.drive == ORC_DRIVE_CAPACITOR ? source(s, t) : 0.0;
+    double q = s->qbase + q_source(s, t) + q_collected(s);
+    double p0 = (C * v + q - e0 * ef[0]) / (C + e0 / L);
+    for (int i = 0; i < nn; ++i) {
+        phi[i] += p0 * (1.0 - (double)i / (double)(nn - 1));
+        ef[i] += p0 / L;
+    }
+    phi[nn - 1] = 0.0;
+    return ORC_OK;
+}
+
+/* The circuit's charge at the first solve: the electrode starts at the
+ * source's potential (capacitor uncharged), or at 0 for a current source. */
+static int circuit_start(orc_sim* s, double t)
+{
+    if (!circuit_mode(s) || s->circ_init) return ORC_OK;
+    int nn = s->nn;
+    double* phi = malloc((size_t)nn * sizeof(double));
+    double* ef = malloc((size_t)nn * sizeof(double));
+    if (!phi || !ef) { free(phi); free(ef); return ORC_ENOMEM; }
+    int rc = solve_dirichlet(s, 0.0, s->rho, phi, ef);
+    double v = s->c.drive == ORC_DRIVE_CAPACITOR ? source(s, t) : 0.0;
+    double q = s->c.eps0 * v / s->c.length + s->c.eps0 * ef[0];
+    s->qbase = q - q_source(s, t) - q_collected(s);
+    s->circ_init = 1;
+    free(phi); free(ef);
+    return rc;
+}
+
 static double field_energy(const orc_sim* s)
 {
     double fe = 0.0;
@@ -500,7 +587,9 @@ int orc_refresh_field(orc_sim* s)
 {
     if (!s) return ORC_EINVAL;
     deposit(s);
-    int rc = solve(s, (double)s->step * s->c.dt, s->rho, s->phi, s->ef);
+    int rc = circuit_start(s, (double)s->step * s->c.dt);
+    if (rc) return rc;
+    rc = solve(s, (double)s->step * s->c.dt, s->rho, s->phi, s->ef);
     s->fe = field_energy(s);
     return rc;
 }
@@ -1018,7 +1107,8 @@ static int one_step(orc_sim* s)
     }
     s->step += 1;
     deposit(s);
-    int rs = solve(s, (double)s->step * dt, s->rho, s->phi, s->ef);
+    int rs = circuit_start(s, (double)s->step * dt);
+    if (rs == ORC_OK) rs = solve(s, (double)s->step * dt, s->rho, s->phi, s->ef);
     s->fe = field_energy(s);
     if (s->diag) sample_diagnostics(s);
     return rc != ORC_OK ? rc : rs;
@@ -1169,5 +1259,21 @@ int orc_get_wall_edf(const orc_sim* s, double* out)
                 out[((size_t)k * 2 + w) * ORC_EEPF_BINS + i] = (double)s->wedf[k][w][i];
     for (int k = 0; k < S; ++k) out[(size_t)S * 2 * ORC_EEPF_BINS + k] = s->wedf_emax[k] / ORC_EEPF_BINS;
     out[(size_t)S * 2 * ORC_EEPF_BINS + S] = s->av_samples;
+    return ORC_OK;
+}
+
+int orc_get_circuit(const orc_sim* s, double out[2])
+{
+    if (!s || !out) return ORC_EINVAL;
+    out[0] = s->phi[0];
+    out[1] = s->qbase + q_source(s, (double)s->step * s->c.dt) + q_collected(s);
+    return ORC_OK;
+}
+
+int orc_set_circuit(orc_sim* s, double q)
+{
+    if (!s || !isfinite(q) || !circuit_mode(s)) return ORC_EINVAL;
+    s->qbase = q - q_source(s, (double)s->step * s->c.dt) - q_collected(s);
+    s->circ_init = 1;
     return ORC_OK;
 }

@@ -32,6 +32,11 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1 };
 enum { ORC_XS_ELASTIC = 0, ORC_XS_EXCITATION = 1, ORC_XS_IONIZATION = 2,
        ORC_XS_ION_CX = 3, ORC_XS_ION_ISO = 4 };
 enum { ORC_LOAD_STRATIFIED = 0, ORC_LOAD_RANDOM = 1, ORC_LOAD_NONE = 2 };
+/* drive of the electrode at x = 0 (bounded domains) */
+enum { ORC_DRIVE_VOLTAGE = 0, ORC_DRIVE_CAPACITOR = 1, ORC_DRIVE_CURRENT = 2 };
+/* source waveform: sine V sin(2 pi f t + phase); two harmonics
+ * V [cos(2 pi f t + phase) + cos(4 pi f t)] */
+enum { ORC_WAVE_SINE = 0, ORC_WAVE_TWO_HARMONIC = 1 };
 
 typedef struct {
     double charge, mass, weight;      /* C, kg, real particles per m^2 per macro */
@@ -53,6 +58,9 @@ typedef struct {
     uint64_t seed;
     orc_species sp[ORC_MAX_SPECIES];
     double renew_lz;                  /* axial renewal length (m); 0: no renewal */
+    int32_t drive, waveform;          /* ORC_DRIVE_*, ORC_WAVE_* */
+    double cap;                       /* series capacitance per area (F/m^2), capacitor drive */
+    double j_amp;                     /* current density amplitude (A/m^2), current drive */
 } orc_config;
 
 /* Counters of one run: event counts (integer-exact) and the kinetic energy
@@ -94,6 +102,12 @@ int  orc_get_particles(const orc_sim* s, int32_t species, int64_t cap, double* x
                        double* vx, double* vy, double* vz, uint32_t* id, int64_t* n,
                        uint32_t* next_id);
 int  orc_set_step(orc_sim* s, uint64_t step);
+/* External circuit of the electrode at x = 0: out[0] = its potential at the
+ * last solve, out[1] = q, the charge per area on the electrode's conductor
+ * (its surface facing the plasma plus the series capacitor's plate).  Set:
+ * replaces q (e.g. on resume). */
+int  orc_get_circuit(const orc_sim* s, double out[2]);
+int  orc_set_circuit(orc_sim* s, double q);
 uint64_t orc_get_step(const orc_sim* s);
 /* Deposit the current particles and solve the field at t = step*dt. */
 int  orc_refresh_field(orc_sim* s);

@@ -39,6 +39,11 @@ TORR = 133.322368421
 LOAD_STRATIFIED = 0
 LOAD_RANDOM = 1
 LOAD_NONE = 2
+DRIVE_VOLTAGE = 0
+DRIVE_CAPACITOR = 1
+DRIVE_CURRENT = 2
+WAVE_SINE = 0
+WAVE_TWO_HARMONIC = 1
 
 XS_ELASTIC = 0
 XS_EXCITATION = 1
@@ -61,7 +66,8 @@ def base_config(**kw):
                rho_bg=0.0, e_unit=1.0, v_amp=0.0, v_freq=0.0, v_phase=0.0,
                e_ext=[0.0, 0.0, 0.0], b_ext=[0.0, 0.0, 0.0], gas_density=0.0,
                gas_temp=300.0, gas_mass=0.0, see_gamma=0.0, see_temp=1.0,
-               perturb_eps=0.0, perturb_mode=0, seed=1, species=[], renew_lz=0.0)
+               perturb_eps=0.0, perturb_mode=0, seed=1, species=[], renew_lz=0.0,
+               drive=0, waveform=0, cap=0.0, j_amp=0.0)
     cfg.update(kw)
     return cfg
 
