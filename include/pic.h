@@ -68,6 +68,22 @@ typedef int32_t pic_status;
 #define PIC_LOAD_RANDOM 1     /* x_j = u L */
 #define PIC_LOAD_NONE 2       /* start empty; fill with pic_set_particles */
 
+/* Drive of the electrode at x = 0 (bounded gaps; Sections 3.2 and 3.3).  The
+ * electrode and whatever is wired to it form one conductor whose charge per
+ * area q changes only by the charge particles bring (absorbed particles
+ * bring theirs, each secondary electron emitted takes one away) and by a
+ * current source.  Gauss's law at the electrode's surface,
+ * q = eps0 E(0) + C (phi0 - V(t)), then fixes its potential phi0; the field
+ * is linear in phi0, so phi0 = (C V + q - eps0 E0[psi]) / (C + eps0 / L) with
+ * psi the solution for phi0 = 0. */
+#define PIC_DRIVE_VOLTAGE 0   /* phi0 = V(t) */
+#define PIC_DRIVE_CAPACITOR 1 /* V(t) behind a series capacitor of `cap` F/m^2 (0: a floating electrode);
+                                 the DC self-bias develops; starts uncharged, phi0 = V(0) */
+#define PIC_DRIVE_CURRENT 2   /* current source J(t) = j_amp sin(2 pi v_freq t + v_phase) A/m^2 into the
+                                 electrode; starts at phi0 = 0 */
+#define PIC_WAVE_SINE 0         /* V(t) = v_amp sin(2 pi v_freq t + v_phase) */
+#define PIC_WAVE_TWO_HARMONIC 1 /* V(t) = v_amp [cos(2 pi v_freq t + v_phase) + cos(4 pi v_freq t)] (Section 3.3) */
+
 typedef struct {
     double charge;      /* C (or normalised) */
     double mass;        /* kg */
@@ -106,6 +122,10 @@ typedef struct {
                                        the third axis since injection, z += vz dt; once |z| >= L_z it is
                                        re-injected at the same x with velocities drawn from its species'
                                        initial Maxwellian (vth, drift) and z = 0 */
+    int32_t drive;                  /* PIC_DRIVE_*; periodic domains take PIC_DRIVE_VOLTAGE */
+    int32_t waveform;               /* PIC_WAVE_* */
+    double cap;                     /* series capacitance per area, F/m^2 (PIC_DRIVE_CAPACITOR), >= 0 */
+    double j_amp;                   /* current density amplitude, A/m^2 (PIC_DRIVE_CURRENT) */
 } pic_config;
 
 typedef struct {
@@ -188,6 +208,8 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
                                    emax from pic_set_wall_edf), then the bin width (eV) per species, then the samples
                                    of the time averages over the same interval */
 #define PIC_DIAG_RENEWED 18     /* int64[S]: axial renewals per species since pic_init */
+#define PIC_DIAG_CIRCUIT 19     /* double[2]: potential of the electrode at x = 0 at the last field solve (V),
+                                   charge per area of its conductor now (C/m^2; 0 without a circuit) */
 #define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
 
 #define PIC_EEPF_BINS 256
@@ -255,6 +277,14 @@ pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const doubl
  */
 pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, float* z, int64_t* n_out);
 pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const float* z);
+
+/*
+ * pic_set_circuit: replace the charge per area q of the driven electrode's
+ * conductor of discharge `batch` (PIC_DRIVE_CAPACITOR or PIC_DRIVE_CURRENT;
+ * e.g. when resuming a run) and re-solve that discharge's field.  PIC_EINVAL
+ * without a circuit or for a non-finite q.  Synchronous.
+ */
+pic_status pic_set_circuit(pic_ctx* ctx, int32_t batch, double q);
 
 /* pic_sync: wait for queued work; return a latched device error if any. */
 pic_status pic_sync(pic_ctx* ctx);

@@ -23,7 +23,7 @@ EEPF_BINS = 256
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
-            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17, RENEWED=18)
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17, RENEWED=18, CIRCUIT=19)
 
 
 class SpeciesCfg(C.Structure):
@@ -41,7 +41,8 @@ class PicConfig(C.Structure):
                 ("gas_density", C.c_double), ("gas_temp", C.c_double), ("gas_mass", C.c_double),
                 ("see_gamma", C.c_double), ("see_temp", C.c_double), ("perturb_eps", C.c_double),
                 ("perturb_mode", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64),
-                ("species", SpeciesCfg * MAX_SPECIES), ("renew_lz", C.c_double)]
+                ("species", SpeciesCfg * MAX_SPECIES), ("renew_lz", C.c_double),
+                ("drive", C.c_int32), ("waveform", C.c_int32), ("cap", C.c_double), ("j_amp", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -104,6 +105,7 @@ def load_library():
         "pic_set_wall_edf": (i32, [P, i32, d]),
         "pic_get_axial": (i32, [P, i32, i32, i64, fp, C.POINTER(i64)]),
         "pic_set_axial": (i32, [P, i32, i32, i64, fp]),
+        "pic_set_circuit": (i32, [P, i32, d]),
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
@@ -138,6 +140,10 @@ def make_config(cfg):
         c.e_ext[i], c.b_ext[i] = cfg["e_ext"][i], cfg["b_ext"][i]
     c.perturb_mode, c.seed = cfg["perturb_mode"], cfg["seed"]
     c.renew_lz = float(cfg.get("renew_lz", 0.0))
+    c.drive = int(cfg.get("drive", 0))
+    c.waveform = int(cfg.get("waveform", 0))
+    c.cap = float(cfg.get("cap", 0.0))
+    c.j_amp = float(cfg.get("j_amp", 0.0))
     for i, sp in enumerate(cfg["species"]):
         s = c.species[i]
         s.charge, s.mass, s.weight = sp["charge"], sp["mass"], sp["weight"]
@@ -383,6 +389,15 @@ class Sim:
                                            _ptr(ids, C.c_uint32), C.byref(n), C.byref(nid)),
                     "pic_get_particles")
         return dict(cell=cell, off=off, vx=vx, vy=vy, vz=vz, id=ids, next_id=nid.value)
+
+    def circuit(self, batch=0):
+        """(potential of the electrode at x = 0 at the last solve, charge per
+        area of its conductor; 0 without a circuit)."""
+        o = self.diag("CIRCUIT", 2, batch=batch)
+        return float(o[0]), float(o[1])
+
+    def set_circuit(self, q, batch=0):
+        self._check(_lib.pic_set_circuit(self.h, batch, float(q)), "pic_set_circuit")
 
     def renewed(self, batch=0):
         """Axial renewals per species since the start."""

@@ -7,7 +7,8 @@ and the cross-section tables.  Random draws are keyed by (seed, id, step) and
 the deposit sums are exact integers, so a run resumed from a checkpoint
 continues bit for bit as the uninterrupted run would (the field is recomputed
 from the particles and equals the one the run held).  With axial renewal
-the axial displacements are kept too.  Not kept: counters, time averages
+the axial displacements are kept too, and with an external circuit the
+charge of the driven electrode's conductor.  Not kept: counters, time averages
 and distributions (they restart from zero), the diagnostic and tile
 settings, and graphs.  All discharges of a context share one step index
 on resume; a retired discharge is restored retired.
@@ -16,7 +17,8 @@ Format: one ``.npz`` file (numpy arrays only, readable with
 ``allow_pickle=False``): ``format``, ``configs`` and ``tables`` as JSON
 strings, ``steps`` [B], ``next_id`` [B, S], ``retired`` [B], the table
 arrays ``t{i}_energy`` / ``t{i}_sigma``, and per discharge and species
-``b{b}_s{s}_{cell,off,vx,vy,vz,id}`` (and ``b{b}_s{s}_z`` with renewal).
+``b{b}_s{s}_{cell,off,vx,vy,vz,id}`` (and ``b{b}_s{s}_z`` with renewal),
+``circuit`` [B] (NaN where the electrode is driven by a voltage).
 """
 from __future__ import annotations
 
@@ -27,6 +29,10 @@ import numpy as np
 
 FORMAT = "pic-mi355x-checkpoint-1"
 FIELDS = ("cell", "off", "vx", "vy", "vz", "id")
+
+
+def _has_circuit(cfg):
+    return cfg["bc"] == 1 and cfg["field_solve"] and cfg.get("drive", 0) != 0
 
 
 def save(sim, path):
@@ -59,6 +65,7 @@ def save(sim, path):
     arrays["steps"] = steps
     arrays["next_id"] = next_id
     arrays["retired"] = np.array([b in sim.retired for b in range(B)])
+    arrays["circuit"] = np.array([sim.circuit(b)[1] if _has_circuit(sim.cfgs[b]) else np.nan for b in range(B)])
     tmp = path + ".tmp.npz"
     np.savez(tmp, **arrays)
     os.replace(tmp, path)
@@ -77,8 +84,9 @@ def read(path):
         B, S = len(cfgs), len(cfgs[0]["species"])
         parts = [[{k: z[f] for k in FIELDS + ("z",) for f in ["b%d_s%d_%s" % (b, s, k)] if f in z.files}
                   for s in range(S)] for b in range(B)]
+        circ = z["circuit"].copy() if "circuit" in z.files else np.full(B, np.nan)
         return dict(configs=cfgs, tables=tabs, steps=z["steps"].copy(), next_id=z["next_id"].copy(),
-                    retired=z["retired"].copy(), particles=parts)
+                    retired=z["retired"].copy(), particles=parts, circuit=circ)
 
 
 def load(path, stream=None, make_sim=None):
@@ -109,6 +117,8 @@ def load(path, stream=None, make_sim=None):
             if "z" in p:
                 sim.set_axial(s, p["z"], batch=b)
     for b in range(len(cfgs)):
+        if np.isfinite(c["circuit"][b]):
+            sim.set_circuit(float(c["circuit"][b]), batch=b)
         if c["retired"][b]:
             sim.retire(b)
     # the saved configurations (with their load modes) stay the context's record

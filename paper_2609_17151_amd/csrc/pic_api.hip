@@ -118,6 +118,10 @@ pic_status check_cfg(const pic_config& c)
     if (c.n_species < 1 || c.n_species > PIC_MAX_SPECIES) return PIC_EINVAL;
     if (c.see_gamma < 0.0 || c.see_gamma > 1.0) return PIC_EINVAL;
     if (!(c.renew_lz >= 0.0) || !std::isfinite(c.renew_lz)) return PIC_EINVAL;
+    if (c.drive < PIC_DRIVE_VOLTAGE || c.drive > PIC_DRIVE_CURRENT) return PIC_EINVAL;
+    if (c.bc == PIC_BC_PERIODIC && c.drive != PIC_DRIVE_VOLTAGE) return PIC_EINVAL;
+    if (c.waveform != PIC_WAVE_SINE && c.waveform != PIC_WAVE_TWO_HARMONIC) return PIC_EINVAL;
+    if (!(c.cap >= 0.0) || !std::isfinite(c.cap) || !std::isfinite(c.j_amp)) return PIC_EINVAL;
     for (int s = 0; s < c.n_species; ++s)
         if (!valid_species(c.species[s])) return PIC_EINVAL;
     return PIC_OK;
@@ -485,6 +489,11 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         }
         dc.c2 = dc.dx * dc.dx / c.eps0;
         dc.inv_2dx = 1.0 / (2.0 * dc.dx);
+        dc.drive = c.drive;
+        dc.waveform = c.waveform;
+        dc.cap = c.cap;
+        dc.j_amp = c.j_amp;
+        for (int s = 0; s < c.n_species; ++s) dc.qw[s] = c.species[s].charge * c.species[s].weight;
         // bulk electron energy distribution: the middle tenth of a bounded
         // gap, every cell when periodic
         if (c.bc == PIC_BC_PERIODIC) {
@@ -966,6 +975,31 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
     return PIC_OK;
 }
 
+pic_status pic_set_circuit(pic_ctx* ctx, int32_t batch, double q)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || !std::isfinite(q)) return PIC_EINVAL;
+    const DisConst& dc = ctx->disc[batch];
+    if (dc.bc == PIC_BC_PERIODIC || !dc.field_solve || dc.drive == PIC_DRIVE_VOLTAGE) return PIC_EINVAL;
+    hipStream_t st = ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return PIC_EHIP;
+    const int S = ctx->S;
+    std::vector<unsigned long long> cr((size_t)S * kRep * C_N);
+    DisState ds;
+    if (hipMemcpy(cr.data(), ctx->d.cnt + (size_t)batch * S * kRep * C_N, cr.size() * 8, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(&ds, ctx->d.diss + batch, sizeof(DisState), hipMemcpyDeviceToHost) != hipSuccess)
+        return PIC_EHIP;
+    ds.qbase = q - source_charge(dc, (double)ds.step * dc.dt) - collected_charge(dc, cr.data(), S);
+    ds.circ_init = 1;
+    if (hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) != hipSuccess) return PIC_EHIP;
+    if (hipMemset(ctx->d.acc + (size_t)batch * S * kRep * ctx->d.nodes_max, 0, 8ull * S * kRep * ctx->d.nodes_max) !=
+        hipSuccess)
+        return PIC_EHIP;
+    pic_status rc = solve_after_deposit(ctx, batch);
+    if (rc != PIC_OK) return rc;
+    return hip_st(hipStreamSynchronize(st));
+}
+
 pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, float* z, int64_t* n_out)
 {
     if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S) return PIC_EINVAL;
@@ -1310,6 +1344,17 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             ds.avg_samples = 0.0;
             ds.eepf_samples = 0.0;
             ok = ok && hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+            break;
+        }
+        case PIC_DIAG_CIRCUIT: {
+            if (!need(16)) return PIC_EINVAL;
+            double* o = (double*)out;
+            ok = d2h(o, ctx->d.phi + (size_t)batch * nm, 8);
+            const DisConst& dc = ctx->disc[batch];
+            const bool circuit = dc.bc != PIC_BC_PERIODIC && dc.field_solve && dc.drive != PIC_DRIVE_VOLTAGE;
+            o[1] = circuit && ds.circ_init
+                       ? ds.qbase + source_charge(dc, (double)ds.step * dc.dt) + collected_charge(dc, cr.data(), S)
+                       : 0.0;
             break;
         }
         case PIC_DIAG_RENEWED: {

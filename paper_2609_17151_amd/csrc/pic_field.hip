@@ -270,6 +270,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     const double t = a.mode == kFinExternal ? a.t_ext
                    : (double)(ds.step + (a.mode == kFinStep ? 1 : 0)) * dc.dt;
     double phi[kNodesPerThread];
+    double circ_qbase = 0.0;                  // circuit: the conductor's base charge of this solve
     if (!periodic && tid == 0) {
         s_bc[0] = s_a[0];
         s_bc[1] = s_a[nn - 1];
@@ -330,9 +331,24 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         if (periodic) {
             phi0 = 0.0;
             d0 = totP / nc;                              // H = sum_{i<N} G[i]
-        } else {
-            phi0 = dc.v_amp * sin(6.283185307179586476925286766559 * dc.v_freq * t + dc.v_phase);
+        } else if (dc.drive == PIC_DRIVE_VOLTAGE) {
+            phi0 = source_voltage(dc, t);
             d0 = (totP - totS - phi0) / nc;              // H = P - G[N], phi[N] = 0
+        } else {
+            // external circuit: psi (phi0 = 0) has phi[1] = (P - G[N]) / N; its
+            // surface field at x = 0 by Gauss's law over the half cell; then
+            // q = eps0 (E0[psi] + phi0 / L) + C (phi0 - V) gives phi0
+            const double e0psi = -((totP - totS) / nc) * dc.inv_dx - s_bc[0] * dc.wall_coef;
+            const bool capd = dc.drive == PIC_DRIVE_CAPACITOR;
+            const double C = capd ? dc.cap : 0.0;
+            const double v = capd ? source_voltage(dc, t) : 0.0;
+            const double qc = collected_charge(dc, d.cnt + (size_t)b * S * kRep * C_N, S);
+            const double qs = source_charge(dc, t);
+            // first solve: the electrode starts at the source's potential
+            const double qb = ds.circ_init ? ds.qbase : dc.eps0 * (v / dc.L + e0psi) - qs - qc;
+            phi0 = (C * v + (qb + qs + qc) - dc.eps0 * e0psi) / (C + dc.eps0 / dc.L);
+            d0 = (totP - totS - phi0) / nc;
+            circ_qbase = qb;
         }
         double phis = 0.0;
 #pragma unroll
@@ -437,6 +453,10 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         double fe = 0.0;
         for (int w = 0; w < kWaves; ++w) fe += s_w[w];
         ds.fe = 0.5 * dc.eps0 * dc.dx * fe;
+        if (!periodic && dc.field_solve && dc.drive != PIC_DRIVE_VOLTAGE && !ds.circ_init) {
+            ds.qbase = circ_qbase;
+            ds.circ_init = 1;
+        }
         if (a.mode == kFinStep) {
             if (a.diag) {
                 ds.avg_samples += 1.0;

@@ -112,6 +112,10 @@ struct DisConst {
     double flux_coef[kMaxSpecies], mom_coef[kMaxSpecies];   // moment sums -> densities (interior node)
     uint32_t key0, key1;
     int32_t bulk_lo, bulk_hi;  // cells of the bulk electron energy distribution
+    // drive of the electrode at x = 0
+    int32_t drive, waveform;
+    double cap, j_amp;
+    double qw[kMaxSpecies];    // charge x weight of a macro-particle, C/m^2
 };
 
 // mutable, one per segment.  Slots [0, count) hold the particles in their
@@ -136,7 +140,44 @@ struct DisState {
     double fe;
     double avg_samples;
     double eepf_samples;
+    double qbase;           // circuit: conductor charge minus the source's and the particles' since the start
+    int32_t circ_init;      // circuit: qbase set
 };
+
+// The source of the electrode at x = 0: its voltage V(t), and the charge per
+// area a current source has delivered since t = 0 (the integral of
+// j_amp sin(w t + phase)).
+__host__ __device__ inline double source_voltage(const DisConst& dc, double t)
+{
+    const double w = 6.283185307179586476925286766559 * dc.v_freq;
+    if (dc.waveform == PIC_WAVE_TWO_HARMONIC) return dc.v_amp * (cos(w * t + dc.v_phase) + cos(2.0 * w * t));
+    return dc.v_amp * sin(w * t + dc.v_phase);
+}
+
+__host__ __device__ inline double source_charge(const DisConst& dc, double t)
+{
+    if (dc.drive != PIC_DRIVE_CURRENT) return 0.0;
+    const double w = 6.283185307179586476925286766559 * dc.v_freq;
+    return dc.j_amp / w * (cos(dc.v_phase) - cos(w * t + dc.v_phase));
+}
+
+// Charge per area particles have brought to the electrode at x = 0, from the
+// event counters [S][kRep][C_N] of one discharge: absorbed particles bring
+// theirs, each secondary electron emitted there takes one away.
+__host__ __device__ inline double collected_charge(const DisConst& dc, const unsigned long long* cnt, int S)
+{
+    double q = 0.0;
+    unsigned long long see = 0ull;
+    for (int s = 0; s < S; ++s) {
+        unsigned long long ab = 0ull;
+        for (int r = 0; r < kRep; ++r) {
+            ab += cnt[((size_t)s * kRep + r) * C_N + C_ABS0];
+            see += cnt[((size_t)s * kRep + r) * C_N + C_SEE0];
+        }
+        q += dc.qw[s] * (double)ab;
+    }
+    return q - dc.qw[0] * (double)see;
+}
 
 struct Ctx;  // host
 
