@@ -78,9 +78,12 @@ typedef int32_t pic_status;
  * psi the solution for phi0 = 0. */
 #define PIC_DRIVE_VOLTAGE 0   /* phi0 = V(t) */
 #define PIC_DRIVE_CAPACITOR 1 /* V(t) behind a series capacitor of `cap` F/m^2 (0: a floating electrode);
-                                 the DC self-bias develops; starts uncharged, phi0 = V(0) */
+                                 the DC self-bias develops; starts uncharged, phi0 = V(t) */
 #define PIC_DRIVE_CURRENT 2   /* current source J(t) = j_amp sin(2 pi v_freq t + v_phase) A/m^2 into the
                                  electrode; starts at phi0 = 0 */
+/* The circuit starts at the first field solve after pic_init, pic_set_particles
+ * or pic_load_profiles (new particles); pic_set_circuit then replaces its
+ * charge. */
 #define PIC_WAVE_SINE 0         /* V(t) = v_amp sin(2 pi v_freq t + v_phase) */
 #define PIC_WAVE_TWO_HARMONIC 1 /* V(t) = v_amp [cos(2 pi v_freq t + v_phase) + cos(4 pi v_freq t)] (Section 3.3) */
 

@@ -742,6 +742,7 @@ int orc_load_profiles(orc_sim* s, int32_t m, const double* dens, const double* t
         }
         free(cum);
         p->n = n[k];
+        s->circ_init = 0;
         p->next_id = (uint32_t)n[k];
     }
     int rc = orc_refresh_field(s);
@@ -776,6 +777,7 @@ int orc_set_particles(orc_sim* s, int32_t k, int64_t n, const double* x, const d
     }
     p->n = n;
     p->next_id = next_id;
+    s->circ_init = 0;   /* new particles: the circuit restarts at the next solve */
     return ORC_OK;
 }
 
@@ -1017,11 +1019,14 @@ static void sample_diagnostics(orc_sim* s)
  * component) since its injection, advanced with the new velocity; once
  * |z| >= L_z the particle is re-injected at the same x with a fresh velocity
  * from the species' initial distribution (Maxwellian of scale vth plus the
- * drift), drawn with call 6, and z = 0. */
+ * drift), drawn with call 6, and z = 0.  z decides an integer event and is
+ * held in binary32, the precision of the GPU's store, so both sides take the
+ * decision alike: a slow ion moves a few binary32 spacings of z per step. */
 static void renew(orc_sim* s, int k, uint32_t id, double v[3], double* z)
 {
-    *z += v[2] * s->c.dt;
-    if (fabs(*z) < s->c.renew_lz) return;
+    float zf = (float)*z + (float)v[2] * (float)s->c.dt;
+    *z = (double)zf;
+    if (fabsf(zf) < (float)s->c.renew_lz) return;
     uint32_t r[4];
     draw(s, id, (uint32_t)s->step, k, 6u, r);
     double g0, g1, g2, g3;

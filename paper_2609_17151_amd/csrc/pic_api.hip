@@ -1125,6 +1125,7 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
     if (hipMemcpy(ds.data(), ctx->d.diss, sizeof(DisState) * ctx->B, hipMemcpyDeviceToHost) != hipSuccess)
         return PIC_EHIP;
     for (auto& x : ds) x.step = step;
+    ds[batch].circ_init = 0;            // new particles: the circuit restarts at the next solve
     if (hipMemcpy(ctx->d.diss, ds.data(), sizeof(DisState) * ctx->B, hipMemcpyHostToDevice) != hipSuccess)
         return PIC_EHIP;
     if (hipMemset(ctx->d.acc + (size_t)batch * ctx->S * kRep * ctx->d.nodes_max, 0,
@@ -1192,6 +1193,12 @@ pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const doubl
     }
     ok = ok && hipMemcpy(ctx->d.segs + (size_t)batch * S, ss.data(), sizeof(SegState) * S, hipMemcpyHostToDevice) ==
                    hipSuccess;
+    {
+        DisState dsb;
+        ok = ok && hipMemcpy(&dsb, ctx->d.diss + batch, sizeof(DisState), hipMemcpyDeviceToHost) == hipSuccess;
+        dsb.circ_init = 0;              // new particles: the circuit restarts at the next solve
+        ok = ok && hipMemcpy(ctx->d.diss + batch, &dsb, sizeof(DisState), hipMemcpyHostToDevice) == hipSuccess;
+    }
     ok = ok && hipMemset(ctx->d.acc + (size_t)batch * S * kRep * ctx->d.nodes_max, 0,
                          8ull * S * kRep * ctx->d.nodes_max) == hipSuccess;
     ok = ok && solve_after_deposit(ctx, batch) == PIC_OK;

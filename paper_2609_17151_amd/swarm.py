@@ -75,7 +75,7 @@ class Swarm:
         self.dt = dt if dt else nu_dt / numax_estimate(self.tables, n_gas)
         self.control = float(control)
         self.cfgs = [config(en, n_gas, n, self.dt, seed + 1000 * i + r, te_ev=te_ev,
-                            capacity=int(math.ceil(control * n * 1.25)) + 4096, gas_mass=gas_mass,
+                            capacity=int(math.ceil(control * n * 4)) + 4096, gas_mass=gas_mass,
                             gas_temp=gas_temp)
                      for i, en in enumerate(self.en) for r in range(self.R)]
         self.sim = Sim(self.cfgs, self.tables, stream=stream)
@@ -96,9 +96,12 @@ class Swarm:
                               p["id"][keep], p["next_id"], c["step"], batch=b)
             self.thinned += 1
 
-    def run(self, relax_steps, sample_steps, every=256, eepf_emax=40.0, progress=None):
+    def run(self, relax_steps, sample_steps, every=128, eepf_emax=40.0, progress=None):
         """Relax, then sample; returns a dict of per-(E/N) means and errors
-        (standard error over replicas) and the per-replica values."""
+        (standard error over replicas) and the per-replica values.  Replicas
+        are thinned every `every` steps: at 1000 Td in argon the population
+        doubles in about 250 steps, and the store holds 4 x control x the
+        initial count."""
         sim = self.sim
         chunks = max(1, relax_steps // every)
         for i in range(chunks):
@@ -160,7 +163,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--relax", type=int, default=65536)
     ap.add_argument("--sample", type=int, default=32768)
-    ap.add_argument("--every", type=int, default=512)
+    ap.add_argument("--every", type=int, default=128)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     en = [float(x) for x in a.en.split(",")]

@@ -70,7 +70,7 @@ def test_maxwell_model_on_gpu(pic):
 def test_argon_coefficients_trend_with_e_over_n(pic):
     from paper_2609_17151_amd import swarm
     sw = swarm.Swarm([100.0, 300.0, 1000.0], replicas=4, n=50_000)
-    out = sw.run(32768, 8192, every=512)
+    out = sw.run(32768, 8192, every=128)
     w, eps, k = out["W"], out["energy"], out["rates"]
     assert np.all(np.diff(w) > 0) and np.all(np.diff(eps) > 0)
     assert np.all(w > 0)
