@@ -216,6 +216,7 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
 
 #define PIC_EEPF_BINS 256
+#define PIC_WINDOW_RING 64      /* completed RF windows kept per discharge (pic_get_windows) */
 
 /*
  * pic_diag: synchronise the stream, then copy diagnostic `what` of discharge
@@ -288,6 +289,29 @@ pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n
  * without a circuit or for a non-finite q.  Synchronous.
  */
 pic_status pic_set_circuit(pic_ctx* ctx, int32_t batch, double q);
+
+/*
+ * pic_set_windows: close a time-averaging window of discharge `batch` every
+ * `steps` steps from its current step (steps = 0: off).  At the end of each
+ * window the step itself moves the window's sums (the PIC_DIAG_AVG
+ * accumulators: densities, potential, electron energy) into a ring of
+ * PIC_WINDOW_RING completed windows on the device and restarts them, so a
+ * batch of discharges with different RF periods needs no host
+ * synchronisation per window (Section 1: periodic steady states are judged
+ * on RF-period averages).  Needs pic_set_diag enabled.  PIC_EINVAL for
+ * steps < 0.  Synchronous.
+ *
+ * pic_get_windows: copies the completed windows first .. first + count - 1
+ * of discharge `batch` to out, each 1 + (S + 2) n_nodes doubles in the
+ * layout of PIC_DIAG_AVG (samples, mean densities, mean potential, electron
+ * mean energy), and sets *n_done to the number of windows completed so far.
+ * count may be 0 (query).  PIC_EINVAL when a requested window is not
+ * completed yet or already overwritten (first < n_done - PIC_WINDOW_RING).
+ * Synchronous.
+ */
+pic_status pic_set_windows(pic_ctx* ctx, int32_t batch, int64_t steps);
+pic_status pic_get_windows(pic_ctx* ctx, int32_t batch, int64_t first, int32_t count, double* out,
+                           int64_t* n_done);
 
 /* pic_sync: wait for queued work; return a latched device error if any. */
 pic_status pic_sync(pic_ctx* ctx);

@@ -106,6 +106,8 @@ def load_library():
         "pic_get_axial": (i32, [P, i32, i32, i64, fp, C.POINTER(i64)]),
         "pic_set_axial": (i32, [P, i32, i32, i64, fp]),
         "pic_set_circuit": (i32, [P, i32, d]),
+        "pic_set_windows": (i32, [P, i32, i64]),
+        "pic_get_windows": (i32, [P, i32, i64, i32, dp, C.POINTER(i64)]),
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
@@ -398,6 +400,31 @@ class Sim:
 
     def set_circuit(self, q, batch=0):
         self._check(_lib.pic_set_circuit(self.h, batch, float(q)), "pic_set_circuit")
+
+    def set_windows(self, batch, steps):
+        """Close an averaging window of discharge `batch` every `steps` steps
+        on the device (0: off)."""
+        self._check(_lib.pic_set_windows(self.h, batch, int(steps)), "pic_set_windows")
+
+    def windows(self, batch=0, first=0, count=None):
+        """Completed windows first .. (all completed when count is None), each
+        a dict as avg()."""
+        n = C.c_int64()
+        self._check(_lib.pic_get_windows(self.h, batch, first, 0, None, C.byref(n)), "pic_get_windows")
+        cnt = n.value - first if count is None else count
+        if cnt <= 0:
+            return []
+        nn = self.n_nodes[batch]
+        row = 1 + (self.S + 2) * nn
+        o = np.zeros(cnt * row)
+        self._check(_lib.pic_get_windows(self.h, batch, first, cnt, _ptr(o, C.c_double), C.byref(n)),
+                    "pic_get_windows")
+        out = []
+        for k in range(cnt):
+            r = o[k * row:(k + 1) * row]
+            prof = r[1:].reshape(self.S + 2, nn)
+            out.append(dict(samples=r[0], density=prof[: self.S], phi=prof[self.S], mean_energy=prof[self.S + 1]))
+        return out
 
     def renewed(self, batch=0):
         """Axial renewals per species since the start."""

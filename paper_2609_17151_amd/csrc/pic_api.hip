@@ -556,6 +556,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.avg = (double*)A(8ull * B * (S + 2) * nodes_max);
         d.eepf = (unsigned long long*)A(8ull * B * 2 * kEepfBins);
         d.wedf = (unsigned long long*)A(8ull * B * S * 2 * kEepfBins);
+        d.wring = (double*)A(8ull * B * kWindowRing * (1 + (size_t)(S + 2) * nodes_max));
         d.births = (Birth*)A(sizeof(Birth) * (size_t)tiles_max * kBirthsPerTileMin);
         d.bcnt = (int32_t*)A(4ull * tiles_max);
         d.ccnt = (uint32_t*)A(4ull * tiles_max);
@@ -972,6 +973,59 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
         return PIC_EHIP;
     if (e_out && hipMemcpy(e_out, e_d, nn * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         return PIC_EHIP;
+    return PIC_OK;
+}
+
+pic_status pic_set_windows(pic_ctx* ctx, int32_t batch, int64_t steps)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || steps < 0) return PIC_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    DisState ds;
+    if (hipMemcpy(&ds, ctx->d.diss + batch, sizeof(DisState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+    ds.win_len = steps;
+    ds.win_start = (int64_t)ds.step;
+    ds.nwin = 0;
+    ds.avg_samples = 0.0;
+    const size_t nm = ctx->d.nodes_max;
+    if (hipMemset(ctx->d.avg + (size_t)batch * (ctx->S + 2) * nm, 0, 8ull * (ctx->S + 2) * nm) != hipSuccess)
+        return PIC_EHIP;
+    return hip_st(hipMemcpy(ctx->d.diss + batch, &ds, sizeof(DisState), hipMemcpyHostToDevice));
+}
+
+pic_status pic_get_windows(pic_ctx* ctx, int32_t batch, int64_t first, int32_t count, double* out,
+                           int64_t* n_done)
+{
+    if (!ctx || batch < 0 || batch >= ctx->B || first < 0 || count < 0 || (count > 0 && !out)) return PIC_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PIC_EHIP;
+    DisState ds;
+    if (hipMemcpy(&ds, ctx->d.diss + batch, sizeof(DisState), hipMemcpyDeviceToHost) != hipSuccess) return PIC_EHIP;
+    if (n_done) *n_done = ds.nwin;
+    if (count == 0) return PIC_OK;
+    if (first + count > ds.nwin || first < ds.nwin - kWindowRing) return PIC_EINVAL;
+    const int S = ctx->S;
+    const int nn = ctx->disc[batch].n_nodes;
+    const size_t nm = ctx->d.nodes_max, stride = 1 + (size_t)(S + 2) * nm;
+    std::vector<double> w(stride);
+    for (int32_t k = 0; k < count; ++k) {
+        const int64_t idx = first + k;
+        if (hipMemcpy(w.data(), ctx->d.wring + ((size_t)batch * kWindowRing + (size_t)(idx % kWindowRing)) * stride,
+                      stride * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_EHIP;
+        double* o = out + (size_t)k * (1 + (size_t)(S + 2) * nn);
+        const double ns = w[0];
+        o[0] = ns;
+        for (int r = 0; r < S + 2; ++r)
+            for (int i = 0; i < nn; ++i) {
+                double v = w[1 + (size_t)r * nm + i];
+                if (r == S + 1) {
+                    const double ne = w[1 + i];
+                    v = ne > 0.0 ? v / ne : 0.0;          // <eps> = sum(n eps) / sum(n)
+                } else if (ns > 0.0) {
+                    v /= ns;
+                }
+                o[1 + (size_t)r * nn + i] = v;
+            }
+    }
     return PIC_OK;
 }
 

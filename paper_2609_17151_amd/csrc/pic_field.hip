@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                    : (double)(ds.step + (a.mode == kFinStep ? 1 : 0)) * dc.dt;
     double phi[kNodesPerThread];
     double circ_qbase = 0.0;                  // circuit: the conductor's base charge of this solve
+    bool win_closed = false;                  // an RF window ended with this step
     if (!periodic && tid == 0) {
         s_bc[0] = s_a[0];
         s_bc[1] = s_a[nn - 1];
@@ -447,6 +448,19 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                 pv[2 * (size_t)d.nodes_max + i] += dc.q[s] * G * e;
             }
         }
+        // an RF window ends with this step: its sums go to the ring (each
+        // thread its own nodes, as above) and the accumulators restart
+        if (ds.win_len > 0 && (ds.step + 1 - ds.win_start) % ds.win_len == 0) {
+            const size_t stride = 1 + (size_t)(S + 2) * d.nodes_max;
+            double* w = d.wring + ((size_t)b * kWindowRing + (size_t)(ds.nwin % kWindowRing)) * stride;
+            for (int i = tid; i < nn; i += kFT)
+                for (int k = 0; k < S + 2; ++k) {
+                    w[1 + (size_t)k * d.nodes_max + i] = av[(size_t)k * d.nodes_max + i];
+                    av[(size_t)k * d.nodes_max + i] = 0.0;
+                }
+            if (tid == 0) w[0] = ds.avg_samples + 1.0;   // this step's sample included
+            win_closed = true;
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -461,6 +475,10 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             if (a.diag) {
                 ds.avg_samples += 1.0;
                 ds.eepf_samples += 1.0;
+                if (win_closed) {
+                    ds.avg_samples = 0.0;
+                    ds.nwin += 1;
+                }
             }
             ds.step += 1;
         }

@@ -19,6 +19,7 @@ constexpr int kMaxCells = 4096;
 constexpr int kFinThreads = 1024;          // finalize / field-solve workgroup (4 nodes per thread at most)
 constexpr int kNodesPerThread = 4;         // kFinThreads * 4 >= nodes of a bounded mesh
 constexpr int kEepfBins = PIC_EEPF_BINS;
+constexpr int kWindowRing = PIC_WINDOW_RING;
 constexpr int kMaxSeg = PIC_MAX_BATCH * PIC_MAX_SPECIES;   // (discharge, species) segments of a context
 constexpr int64_t kMaxTiles = 1ll << 30;                    // tile numbers fit in int32
 constexpr int kTileMin = 256;                               // smallest tile of the push (particles)
@@ -142,6 +143,7 @@ struct DisState {
     double eepf_samples;
     double qbase;           // circuit: conductor charge minus the source's and the particles' since the start
     int32_t circ_init;      // circuit: qbase set
+    int64_t win_len, win_start, nwin;   // RF windows: length in steps (0 = off), first step, windows done
 };
 
 // The source of the electrode at x = 0: its voltage V(t), and the charge per
@@ -200,6 +202,7 @@ struct DevPtrs {
     float2* epair;               // [B][cells_max] (E[c], E[c+1]) for the gather
     double* avg;                 // [B][(S+2)][nodes_max]
     unsigned long long* eepf;    // [B][2][bins]
+    double* wring;               // [B][kWindowRing][1 + (S+2) nodes_max] completed windows: samples, sums as avg
     unsigned long long* wedf;    // [B][S][2][bins] impact energies at each wall
     Birth* births;               // [tiles_max * kBirthsPerTileMin] births staged by tile, in particle order
     int32_t* bcnt;               // [tiles_max] births staged by each tile

@@ -1,13 +1,21 @@
 """Batched sweeps of RF discharges on one context, each with its own RF period.
 
 All discharges of a context advance together, one step at a time, but every
-discharge has its own number of steps per RF period.  The driver advances the
-batch to the next window boundary of any discharge (a window is a whole
-number of that discharge's periods), reads and clears that discharge's time
-averages (steady.window), and retires a discharge once it has run its
-periods or once a caller-supplied rule says it is done; retired discharges
-cost nothing in later steps.  A discharge whose device flags latch (capacity
-overflow, non-finite values, ...) is retired at once and its flags kept.
+discharge has its own number of steps per RF period; a window is a whole
+number of that discharge's periods.  A discharge is retired once it has run
+its periods or once a caller-supplied rule says it is done; retired
+discharges cost nothing in later steps.  A discharge whose device flags latch
+(capacity overflow, non-finite values, ...) is retired and its flags kept.
+
+Two ways to take the windows:
+  * chunk > 0 (default): every discharge's windows are closed on the device
+    by the step itself (pic_set_windows); the host steps the batch in chunks
+    of `chunk` steps and then reads the windows each running discharge has
+    completed, so nothing waits on the host between window ends.  A discharge
+    may run up to one chunk past its last window before it is retired.
+  * chunk = 0: the batch is advanced to the next window boundary of any
+    discharge and that discharge's averages are read and cleared there (one
+    host synchronisation per window).
 """
 from __future__ import annotations
 
@@ -20,8 +28,9 @@ from . import steady
 
 class Sweep:
     def __init__(self, sim, steps_per_period, window_periods=5, max_periods=300, electron=0, ion=1,
-                 progress=20.0):
+                 progress=20.0, chunk=2048):
         self.sim = sim
+        self.chunk = int(chunk)
         self.B = sim.B
         self.spp = [int(s) for s in steps_per_period]
         if len(self.spp) != self.B or min(self.spp) < 1:
@@ -44,6 +53,8 @@ class Sweep:
     def run(self, stop=None):
         """Advance until every discharge is done.  `stop(b, sweep)` is called
         after each window of discharge b; a true result retires it early."""
+        if self.chunk > 0:
+            return self._run_device(stop)
         sim = self.sim
         sim.set_diag(True)
         for b in range(self.B):
@@ -74,6 +85,58 @@ class Sweep:
                 if self.flags[b] or periods >= self.max_periods or (stop is not None and stop(b, self)):
                     sim.retire(b)
                     self.done[b] = True
+        sim.sync(check=False)
+        return self
+
+    def _window_done(self, b, w, step, wall, stop):
+        self.windows[b].append(np.stack([steady.resample(w["density"][self.electron]),
+                                         steady.resample(w["density"][self.ion]),
+                                         steady.resample(w["mean_energy"])]))
+        self.window_time[b].append(wall)
+        self.window_step[b].append(step)
+        periods = len(self.windows[b]) * self.window_periods
+        return periods >= self.max_periods or (stop is not None and stop(b, self))
+
+    def _run_device(self, stop):
+        sim = self.sim
+        sim.set_diag(True)
+        for b in range(self.B):
+            if self.chunk > 32 * self.window_steps(b):
+                raise ValueError("a chunk would span more windows than the device ring holds")
+            sim.set_windows(b, self.window_steps(b))
+        start = sim.counts(0)["step"]
+        self.t0 = time.perf_counter()
+        self.steps = start
+        last = self.t0
+        while not all(self.done):
+            t_a, s_a = time.perf_counter() - self.t0, self.steps
+            sim.step(self.chunk)
+            sim.sync(check=False)                       # the chunk's end in wall time
+            self.steps += self.chunk
+            t_b = time.perf_counter() - self.t0
+            for b in range(self.B):
+                if self.done[b]:
+                    continue
+                new = sim.windows(b, first=len(self.windows[b]))
+                retire = False
+                for w in new:
+                    k = len(self.windows[b])
+                    step = start + (k + 1) * self.window_steps(b)
+                    # the window's end, placed in the chunk's wall time
+                    wall = t_a + (t_b - t_a) * (step - s_a) / self.chunk
+                    if self._window_done(b, w, step, wall, stop):
+                        retire = True
+                        break
+                self.flags[b] = sim.counts(b)["flags"]
+                if retire or self.flags[b]:
+                    sim.retire(b)
+                    sim.set_windows(b, 0)
+                    self.done[b] = True
+            now = time.perf_counter()
+            if self.progress and now - last >= self.progress:
+                last = now
+                print("sweep: step %d, %d of %d discharges running, %.0f s"
+                      % (self.steps, self.done.count(False), self.B, now - self.t0), flush=True)
         sim.sync(check=False)
         return self
 

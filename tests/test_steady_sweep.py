@@ -81,7 +81,7 @@ class FakeSim:
 def test_sweep_windows_follow_each_period():
     sim = FakeSim(3)
     spp = [10, 7, 25]
-    sw = Sweep(sim, spp, window_periods=2, max_periods=6).run()
+    sw = Sweep(sim, spp, window_periods=2, max_periods=6, chunk=0).run()
     for b in range(3):
         assert sw.window_step[b] == [2 * spp[b] * k for k in (1, 2, 3)]
         assert [w[0][0] for w in sw.windows[b]] == [b * 1000.0 + s for s in sw.window_step[b]]
@@ -91,11 +91,11 @@ def test_sweep_windows_follow_each_period():
 
 def test_sweep_early_stop_retires():
     sim = FakeSim(2)
-    sw = Sweep(sim, [4, 4], window_periods=1, max_periods=100)
+    sw = Sweep(sim, [4, 4], window_periods=1, max_periods=100, chunk=0)
     sw.run(stop=lambda b, s: b == 0 and len(s.windows[0]) == 3)
     assert len(sw.windows[0]) == 3 and len(sw.windows[1]) == 100
     with pytest.raises(ValueError):
-        Sweep(FakeSim(2), [4], window_periods=1)
+        Sweep(FakeSim(2), [4], window_periods=1, chunk=0)
 
 
 def test_noise_tolerance():
@@ -104,3 +104,58 @@ def test_noise_tolerance():
     rms = float(np.sqrt(np.mean(np.array([0.01, 0.03] * 5) ** 2)))
     assert steady.noise_tolerance(d) == pytest.approx(3 * rms)
     assert steady.noise_tolerance([float("nan")] * 3) == steady.TOL
+
+
+class FakeWindowSim(FakeSim):
+    """Closes windows on its own as the device does: a window of discharge b
+    ends every `len` steps after set_windows, its mean is b * 1000 + the step
+    it ended at; retired discharges close no more windows."""
+
+    def __init__(self, B):
+        super().__init__(B)
+        self.win = {}
+
+    def set_windows(self, b, steps):
+        self.win[b] = (steps, self.step_no, [])
+
+    def step(self, n):
+        assert n > 0
+        self.calls.append(n)
+        for _ in range(n):
+            self.step_no += 1
+            for b, (ln, st, done) in self.win.items():
+                if ln and b not in self.retired and (self.step_no - st) % ln == 0:
+                    done.append(self.step_no)
+
+    def windows(self, b, first=0, count=None):
+        done = self.win[b][2]
+        out = []
+        for s in done[first:]:
+            v = np.full(5, b * 1000.0 + s)
+            out.append(dict(density=np.stack([v, v]), phi=v, mean_energy=v, samples=1.0))
+        return out
+
+
+def test_device_windows_follow_each_period_and_retire():
+    sim = FakeWindowSim(3)
+    spp = [10, 7, 25]
+    sw = Sweep(sim, spp, window_periods=2, max_periods=6, chunk=32).run()
+    for b in range(3):
+        assert sw.window_step[b] == [2 * spp[b] * k for k in (1, 2, 3)]
+        assert [w[0][0] for w in sw.windows[b]] == [b * 1000.0 + s for s in sw.window_step[b]]
+        times = sw.window_time[b]
+        assert all(t1 >= t0 for t0, t1 in zip(times, times[1:]))
+    assert sim.retired == {0, 1, 2}
+    assert all(c == 32 for c in sim.calls)
+    # the last discharge needed 150 steps: five chunks of 32
+    assert sim.step_no == 160
+
+
+def test_device_windows_early_stop():
+    sim = FakeWindowSim(2)
+    sw = Sweep(sim, [4, 4], window_periods=1, max_periods=100, chunk=16)
+    sw.run(stop=lambda b, s: b == 0 and len(s.windows[0]) == 3)
+    # windows after the stopping one are not kept, even inside the same chunk
+    assert len(sw.windows[0]) == 3 and len(sw.windows[1]) == 100
+    with pytest.raises(ValueError):
+        Sweep(FakeWindowSim(1), [1], window_periods=1, chunk=64).run()
