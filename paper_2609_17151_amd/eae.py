@@ -26,8 +26,8 @@ import numpy as np
 import workloads as W
 
 
-def config(theta, gap=0.067, n_cells=600, pressure_mtorr=20.0, v0=315.0, freq=13.56e6, cap=1e-8, weight=2e8,
-           n_init=100_000, capacity=2_000_000, seed=31):
+def config(theta, gap=0.067, n_cells=600, pressure_mtorr=20.0, v0=315.0, freq=13.56e6, cap=1e-8, weight=8e8,
+           n_init=100_000, capacity=4_000_000, seed=31):
     cfg = W.argon_rf(gap=gap, n_cells=n_cells, pressure_mtorr=pressure_mtorr, v_amp=v0, n_init=n_init,
                      weight=weight, capacity=capacity, seed=seed)
     cfg.update(v_phase=theta, v_freq=freq, waveform=W.WAVE_TWO_HARMONIC, drive=W.DRIVE_CAPACITOR, cap=cap)
@@ -38,7 +38,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(prog="eae")
     ap.add_argument("--periods", type=int, default=1500)
     ap.add_argument("--block", type=int, default=100, help="periods per self-bias block")
-    ap.add_argument("--weight", type=float, default=2e8)
+    ap.add_argument("--weight", type=float, default=8e8)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     from . import Sim
