@@ -62,7 +62,20 @@ def cpu_baseline(cfg, steps):
     n = sum(sp["n_init"] for sp in cfg["species"])
     return dict(value=n * steps / (t2 - t1), unit="particle-steps/s", cores=1, kind="oracle",
                 sample=f"full E x B box ({n} particles), {steps} steps after loading "
-                       f"(load {t1 - t0:.1f} s not counted), single-threaded FP64 C oracle")
+                       f"(load {t1 - t0:.1f} s not counted), single-threaded FP64 C oracle",
+                cpu=cpu_model(), host_cores=os.cpu_count())
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def timed_rate(sim, torch, steps):
