@@ -155,7 +155,6 @@ def main(argv=None):
     """python -m paper_2609_17151_amd.swarm --en 50,100,300,1000 --out swarm.npz"""
     import argparse
     import json
-    import sys
     import time
     ap = argparse.ArgumentParser(prog="swarm")
     ap.add_argument("--en", default="50,100,200,500,1000", help="E/N values in Td")

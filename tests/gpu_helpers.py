@@ -1,7 +1,5 @@
 """Shared helpers of the GPU parity tests: move a GPU state into the oracle and
 compare states element by element."""
-import math
-
 import numpy as np
 
 import oracle

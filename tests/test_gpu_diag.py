@@ -60,7 +60,6 @@ def test_power_moments_periodic_streaming(pic):
 def test_wall_energy_free_flight(pic):
     """Free flight (no field, no gas) from identical states: counts and
     energies per wall against the oracle."""
-    import oracle
     n, L = 200_000, 0.02
     sp = [W.species(-1.602176634e-19, 9.1093837e-31, 1e8, n, 1e6, load=W.LOAD_RANDOM),
           W.species(1.602176634e-19, 6.6e-26, 1e8, n, 2e3, load=W.LOAD_RANDOM)]

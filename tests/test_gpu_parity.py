@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_helpers import compare_species, dx_of, gpu_positions, small_argon, to_oracle
+from gpu_helpers import compare_species, small_argon, to_oracle
 
 pytestmark = pytest.mark.gpu
 

@@ -5,7 +5,6 @@ import numpy as np
 import pytest
 
 import oracle
-import workloads as W
 from gpu_helpers import compare_species, small_argon
 
 pytestmark = pytest.mark.gpu

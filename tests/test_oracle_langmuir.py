@@ -14,7 +14,6 @@ import multiprocessing as mp
 import os
 
 import numpy as np
-import pytest
 from scipy.optimize import curve_fit, fsolve
 from scipy.special import wofz
 

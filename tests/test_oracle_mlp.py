@@ -1,8 +1,6 @@
 """Pins of the FP64 warm-start network reference (oracle/mlp.py) against what
 mathematics fixes: finite differences, a library normal CDF, least squares and
 the closed form of Adam's first update."""
-import math
-
 import numpy as np
 import pytest
 from scipy.stats import norm
