@@ -119,8 +119,9 @@ def secondary(P, W, torch, steps, only=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=2000)
+    # the GPU's clocks settle over the first ~1000 steps (~0.1 s); warm up past that
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--ppt", type=int, default=4)
     ap.add_argument("--threads", type=int, default=1024)
     ap.add_argument("--sort-every", type=int, default=0)
