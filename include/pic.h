@@ -46,9 +46,9 @@ typedef int32_t pic_status;
 #define PIC_ESTATE (-6)      /* call not valid in the current state */
 #define PIC_ESTALL (-7)      /* reserved: no kernel of the library waits on another workgroup */
 
-/* Boundary conditions of the 1D domain [0, L): periodic column or a gap
- * between two electrodes (Section 1: "between two electrodes", "closed on
- * itself", Sections 3.5, 3.6). */
+/* Boundary conditions of the 1D domain [0, L): a column closed on itself
+ * (periodic) or a gap between two electrodes (Section 1; Sections 3.5 and
+ * 3.6 use the periodic form). */
 #define PIC_BC_PERIODIC 0
 #define PIC_BC_DIRICHLET 1
 
