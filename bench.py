@@ -93,15 +93,16 @@ def timed_rate(sim, torch, steps):
     return dict(particle_steps_per_s=n * steps / (ms * 1e-3), us_per_step=ms / steps * 1e3, particles=n)
 
 
-def secondary(P, W, torch, steps, only=None):
+def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True):
     """The bounded, colliding path: one argon RF discharge (2.5 cm, 30 mTorr,
     200 V, 13.56 MHz, 1600 steps per period) and the sweep of 64 such
     discharges (10-200 mTorr, 100-400 V, 1.5-4 cm) in one batched step, each
-    after 3200 steps from its cold start."""
+    after `warm` steps from its cold start."""
     out = {}
     if only in (None, "argon_rf"):
         sim = P.Sim(W.argon_rf(), W.argon_tables())
-        sim.step(3200)
+        sim.use_graphs(graphs)
+        sim.step(warm)
         out["argon_rf_single"] = timed_rate(sim, torch, steps)
         sim.close()
     if only not in (None, "argon_sweep"):
@@ -110,7 +111,8 @@ def secondary(P, W, torch, steps, only=None):
     cfgs = [W.argon_rf(gap=d["gap"], n_cells=d["n_cells"], pressure_mtorr=d["pressure_mtorr"], v_amp=d["v_amp"],
                        seed=1000 + i, capacity=1 << 21) for i, d in enumerate(draws)]
     sim = P.Sim(cfgs, W.argon_tables())
-    sim.step(3200)
+    sim.use_graphs(graphs)
+    sim.step(warm)
     out["argon_rf_batched_64"] = timed_rate(sim, torch, steps)
     sim.close()
     return out
@@ -128,6 +130,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the argon RF single and batched lines")
     ap.add_argument("--secondary-steps", type=int, default=320)
+    ap.add_argument("--secondary-warm", type=int, default=3200, help="steps before the argon lines are timed")
     ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
     ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
@@ -154,7 +157,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload != "exb":
-        r = secondary(P, W, torch, args.secondary_steps, only=args.workload)
+        r = secondary(P, W, torch, args.secondary_steps, only=args.workload, warm=args.secondary_warm,
+                      graphs=not args.no_graph)
         print(json.dumps(dict(workload=args.workload, **r[next(iter(r))])), flush=True)
         return
     cfg = W.exb()
@@ -216,7 +220,7 @@ def main():
     }
     if not args.no_secondary:
         sim.close()
-        out["secondary"] = secondary(P, W, torch, args.secondary_steps)
+        out["secondary"] = secondary(P, W, torch, args.secondary_steps, warm=args.secondary_warm, graphs=not args.no_graph)
     if not args.no_cpu:
         sim.close()
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
