@@ -23,17 +23,20 @@ constexpr int kFT = kFinThreads;          // finalize threads
 constexpr int kWaves = kFT / 64;
 constexpr int kBook = kFT - 64;           // first thread of the bookkeeping wave
 
-// Prefix state of a run of nodes for the two nested sums of the solve:
-// n nodes, S = sum of g, P = sum over the run of the running sums of g.
-// Appending run B after run A: n = nA + nB, S = SA + SB, P = PA + PB + nB SA.
-// The all-zero run is the identity.
+// Prefix state of a run of nodes for the nested sums of the solve: n nodes,
+// S = sum of g, P = sum over the run of the running sums of g, Q = sum over
+// the run of the running sums of those (Q gives the sum of phi, hence the
+// zero-mean gauge, without another reduction).  Appending run B after run A:
+// n = nA + nB, S = SA + SB, P = PA + PB + nB SA,
+// Q = QA + QB + nB PA + SA nB (nB + 1) / 2.  The all-zero run is the identity.
 struct Run {
-    double n, S, P;
+    double n, S, P, Q;
 };
 
 __device__ __forceinline__ Run run_combine(const Run& A, const Run& B)
 {
-    return Run{A.n + B.n, A.S + B.S, A.P + B.P + B.n * A.S};
+    return Run{A.n + B.n, A.S + B.S, A.P + B.P + B.n * A.S,
+               A.Q + B.Q + B.n * A.P + A.S * (0.5 * B.n * (B.n + 1.0))};
 }
 
 // DPP move of a double within a wave (zero where the source lane is invalid
@@ -54,6 +57,7 @@ __device__ __forceinline__ void run_step(Run& v)
     o.n = dpp_f64<CTRL, ROW_MASK>(v.n);
     o.S = dpp_f64<CTRL, ROW_MASK>(v.S);
     o.P = dpp_f64<CTRL, ROW_MASK>(v.P);
+    o.Q = dpp_f64<CTRL, ROW_MASK>(v.Q);
     v = run_combine(o, v);
 }
 
@@ -71,14 +75,33 @@ __device__ __forceinline__ Run wave_run_scan(Run v)
     return v;
 }
 
+// sum over a wave in a fixed order (the same row shifts and broadcasts; the
+// last lane ends with the total), returned to every lane.  The whole wave
+// must be active.
+__device__ __forceinline__ double wave_total_f64(double v)
+{
+    v += dpp_f64<0x111, 0xf>(v);
+    v += dpp_f64<0x112, 0xf>(v);
+    v += dpp_f64<0x114, 0xf>(v);
+    v += dpp_f64<0x118, 0xf>(v);
+    v += dpp_f64<0x142, 0xa>(v);
+    v += dpp_f64<0x143, 0xc>(v);
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 }  // namespace
 
 // One workgroup per discharge, one node per thread (up to four).  All threads
 // first append the step's births; then the last wave does the bookkeeping
 // (counts, ids, kinetic-energy partial sums) while the others turn the
-// deposit into densities and charge.  Poisson: every thread forms
-// the run of its node, a wave-level scan and one 16-entry scan across waves
-// give K[i] and G[i] at every node, and phi follows directly.
+// deposit into densities and charge (and their per-wave sums, for the mean
+// charge of a periodic mesh).  Poisson: every thread forms the run of its
+// node, a wave-level scan and one scan over the waves' totals give K[i] and
+// G[i] at every node, and phi follows directly; the totals also give the
+// mean of phi.
 __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
 {
     const DevPtrs& d = a.d;
@@ -204,6 +227,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
 
     if (tid >= kBook) {
         // ---- bookkeeping wave: counts, ids, kinetic energy --------------------
+        if (lane == 0) s_w[wid] = 0.0;                  // no share of the charge sum
         if (a.mode == kFinStep) {
             if (a.diag) {
                 // kinetic-energy partials of the step's runs (zeros elsewhere),
@@ -240,6 +264,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         }
     } else {
         // ---- densities and charge (into s_a) ------------------------------------
+        double rsum = 0.0;
         for (int i = tid; i < nn; i += kBook) {
             double r;
             if (a.mode == kFinExternal) {
@@ -262,6 +287,11 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                 d.rho[nb + i] = r;
             }
             s_a[i] = r;
+            rsum += r;
+        }
+        if (periodic && dc.field_solve) {               // the waves' shares of the total charge
+            const double w = wave_total_f64(rsum);
+            if (lane == 0) s_w[wid] = w;
         }
     }
     __syncthreads();
@@ -279,11 +309,6 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     if (dc.field_solve) {
         double mean = 0.0;
         if (periodic) {
-            double loc = 0.0;
-            for (int i = tid; i < nn; i += kFT) loc += s_a[i];
-            loc = wave_sum_f64(loc);
-            if (lane == 0) s_w[wid] = loc;
-            __syncthreads();
             double tot = 0.0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) tot += s_w[w];
@@ -294,40 +319,32 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         Run inc[kNodesPerThread];
 #pragma unroll
         for (int k = 0; k < kNodesPerThread; ++k) {
-            inc[k] = Run{0.0, 0.0, 0.0};
+            inc[k] = Run{0.0, 0.0, 0.0, 0.0};
             if (k * kFT >= nn) {                           // empty chunk (uniform)
                 if (lane == 63) s_run[k * kWaves + wid] = inc[k];
                 continue;
             }
             const int i = k * kFT + tid;
-            Run v{0.0, 0.0, 0.0};
+            Run v{0.0, 0.0, 0.0, 0.0};
             if (i < nn) {
                 const bool unknown = i >= 1 && (periodic ? i < nn : i < nn - 1);
                 const double g = unknown ? (s_a[i] - mean) * c2 : 0.0;
-                v = Run{1.0, g, g};
+                v = Run{1.0, g, g, g};
             }
             inc[k] = wave_run_scan(v);
             if (lane == 63) s_run[k * kWaves + wid] = inc[k];
         }
         __syncthreads();
-        // exclusive prefix of every wave of every chunk (chunks in order)
+        // inclusive prefix of every wave of every chunk (chunks in order), in
+        // place: the wave's reads are issued before its writes
+        static_assert(kWaves * kNodesPerThread == 64, "one entry per lane of a wave");
         if (tid < 64) {                                   // wave 0; each lane its own entry
-            const int nw = kWaves * kNodesPerThread;      // 64 entries: one wave
-            const Run v = tid < nw ? s_run[tid] : Run{0.0, 0.0, 0.0};
-            const Run vi = wave_run_scan(v);
-            Run ex;
-            ex.n = __shfl_up(vi.n, 1, 64);
-            ex.S = __shfl_up(vi.S, 1, 64);
-            ex.P = __shfl_up(vi.P, 1, 64);
-            if (tid == 0) ex = Run{0.0, 0.0, 0.0};
-            if (tid < nw) s_run[tid] = ex;
-            if (tid == 63) {
-                s_bc[2] = vi.S;                           // S and P over all nodes
-                s_bc[3] = vi.P;
-            }
+            const Run vi = wave_run_scan(s_run[tid]);
+            s_run[tid] = vi;
         }
         __syncthreads();
-        const double totS = s_bc[2], totP = s_bc[3];
+        const Run all = s_run[kWaves * kNodesPerThread - 1];
+        const double totS = all.S, totP = all.P;
         double phi0, d0;
         if (periodic) {
             phi0 = 0.0;
@@ -351,37 +368,33 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             d0 = (totP - totS - phi0) / nc;
             circ_qbase = qb;
         }
-        double phis = 0.0;
 #pragma unroll
         for (int k = 0; k < kNodesPerThread; ++k) {
             const int i = k * kFT + tid;
             phi[k] = 0.0;
             if (i >= nn) continue;
             // inclusive run through i; K[i] excludes node i: P_incl - G[i]
-            const Run full = run_combine(s_run[k * kWaves + wid], inc[k]);
+            const int e = k * kWaves + wid;
+            const Run full = e > 0 ? run_combine(s_run[e - 1], inc[k]) : inc[k];
             double ph = phi0 + (double)i * d0 - (full.P - full.S);
             if (!periodic && i == nn - 1) ph = 0.0;
             if (i == 0) ph = phi0;
             phi[k] = ph;
-            phis += ph;
         }
-        if (periodic) {                                  // zero-mean gauge
-            phis = wave_sum_f64(phis);
-            __syncthreads();
-            if (lane == 0) s_w[wid] = phis;
-            __syncthreads();
-            double tot = 0.0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) tot += s_w[w];
-            const double pm = tot / nn;
+        if (periodic) {
+            // zero-mean gauge: sum of phi[i] = d0 N (N - 1) / 2 - sum of K[i],
+            // and the K[i] = P_incl[i] - G[i] sum to Q - P over all nodes
+            const double sum_phi = d0 * (0.5 * (double)nn * (double)(nn - 1)) - (all.Q - all.P);
+            const double pm = sum_phi / nn;
 #pragma unroll
             for (int k = 0; k < kNodesPerThread; ++k) phi[k] -= pm;
         }
+        // every read of rho was before the barrier after the chunk scans
     } else {
 #pragma unroll
         for (int k = 0; k < kNodesPerThread; ++k) phi[k] = 0.0;
+        __syncthreads();                                 // the wall charges are read
     }
-    __syncthreads();                                     // every read of rho is done
 #pragma unroll
     for (int k = 0; k < kNodesPerThread; ++k) {
         const int i = k * kFT + tid;
@@ -419,7 +432,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         d.epair[(size_t)b * d.cells_max + c] = make_float2((float)efield(c), (float)efield(c1));
     }
     // field energy: per-wave sums, added in wave order
-    fe_loc = wave_sum_f64(fe_loc);
+    fe_loc = wave_total_f64(fe_loc);
     if (lane == 0) s_w[wid] = fe_loc;
 
     // ---- time averages -------------------------------------------------------
