@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     __shared__ double s_a[kMaxCells + 1];     // rho, then phi
     __shared__ double s_bc[4];                // rho at the walls
     __shared__ double s_w[kWaves];
-    __shared__ Run s_run[kWaves * kNodesPerThread];
+    __shared__ Run s_run[kWaves];
 
     // ---- births, appended after the last slot in the order of their tiles --
     // (and, inside a tile, of their parents): ionization electrons, then the
@@ -299,7 +299,6 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     // ---- Poisson: phi[i] = phi0 + i d0 - K[i] (file header) -------------------
     const double t = a.mode == kFinExternal ? a.t_ext
                    : (double)(ds.step + (a.mode == kFinStep ? 1 : 0)) * dc.dt;
-    double phi[kNodesPerThread];
     double circ_qbase = 0.0;                  // circuit: the conductor's base charge of this solve
     bool win_closed = false;                  // an RF window ended with this step
     if (!periodic && tid == 0) {
@@ -314,36 +313,42 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             for (int w = 0; w < kWaves; ++w) tot += s_w[w];
             mean = tot / nn;
         }
-        // node i = k * kFT + tid: chunk k of the nodes, one node per thread
+        // thread tid holds the consecutive nodes kNodesPerThread tid + j; only
+        // the waves that hold nodes take part (one per SIMD on meshes of up to
+        // 1024 nodes), each thread summing its own nodes in sequence
         const double c2 = dc.c2;
-        Run inc[kNodesPerThread];
+        const int i0 = tid * kNodesPerThread;
+        const bool active = wid * 64 * kNodesPerThread < nn;     // uniform over the wave
+        double g[kNodesPerThread];
+        Run inc{0.0, 0.0, 0.0, 0.0};
+        if (active) {
+            Run loc{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < kNodesPerThread; ++k) {
-            inc[k] = Run{0.0, 0.0, 0.0, 0.0};
-            if (k * kFT >= nn) {                           // empty chunk (uniform)
-                if (lane == 63) s_run[k * kWaves + wid] = inc[k];
-                continue;
+            for (int j = 0; j < kNodesPerThread; ++j) {
+                const int i = i0 + j;
+                g[j] = 0.0;
+                if (i < nn) {
+                    const bool unknown = i >= 1 && (periodic ? i < nn : i < nn - 1);
+                    g[j] = unknown ? (s_a[i] - mean) * c2 : 0.0;
+                    loc.n += 1.0;                          // one node appended
+                    loc.S += g[j];
+                    loc.P += loc.S;
+                    loc.Q += loc.P;
+                }
             }
-            const int i = k * kFT + tid;
-            Run v{0.0, 0.0, 0.0, 0.0};
-            if (i < nn) {
-                const bool unknown = i >= 1 && (periodic ? i < nn : i < nn - 1);
-                const double g = unknown ? (s_a[i] - mean) * c2 : 0.0;
-                v = Run{1.0, g, g, g};
-            }
-            inc[k] = wave_run_scan(v);
-            if (lane == 63) s_run[k * kWaves + wid] = inc[k];
+            inc = wave_run_scan(loc);
+            if (lane == 63) s_run[wid] = inc;
         }
         __syncthreads();
-        // inclusive prefix of every wave of every chunk (chunks in order), in
-        // place: the wave's reads are issued before its writes
-        static_assert(kWaves * kNodesPerThread == 64, "one entry per lane of a wave");
-        if (tid < 64) {                                   // wave 0; each lane its own entry
-            const Run vi = wave_run_scan(s_run[tid]);
-            s_run[tid] = vi;
+        // inclusive prefix over the waves, in place (the wave's reads are
+        // issued before its writes); waves without nodes count as empty runs
+        if (tid < 64) {
+            const Run v = (tid < kWaves && tid * 64 * kNodesPerThread < nn) ? s_run[tid] : Run{0.0, 0.0, 0.0, 0.0};
+            const Run vi = wave_run_scan(v);
+            if (tid < kWaves) s_run[tid] = vi;
         }
         __syncthreads();
-        const Run all = s_run[kWaves * kNodesPerThread - 1];
+        const Run all = s_run[kWaves - 1];
         const double totS = all.S, totP = all.P;
         double phi0, d0;
         if (periodic) {
@@ -368,37 +373,36 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             d0 = (totP - totS - phi0) / nc;
             circ_qbase = qb;
         }
+        // zero-mean gauge of a periodic mesh: the sum of phi[i] is
+        // d0 N (N - 1) / 2 minus the sum of K[i], and the K[i] = P_incl[i] - G[i]
+        // sum to Q - P over all nodes
+        const double pm = periodic ? (d0 * (0.5 * (double)nn * (double)(nn - 1)) - (all.Q - all.P)) / nn : 0.0;
+        if (active) {
+            // the runs before this thread: the waves before, then the lanes before
+            Run lx;
+            lx.n = __shfl_up(inc.n, 1, 64);
+            lx.S = __shfl_up(inc.S, 1, 64);
+            lx.P = __shfl_up(inc.P, 1, 64);
+            lx.Q = 0.0;
+            if (lane == 0) lx = Run{0.0, 0.0, 0.0, 0.0};
+            const Run ex = wid > 0 ? run_combine(s_run[wid - 1], lx) : lx;
+            // every read of rho was before the barrier after the wave scans
+            double G = ex.S, P = ex.P;
 #pragma unroll
-        for (int k = 0; k < kNodesPerThread; ++k) {
-            const int i = k * kFT + tid;
-            phi[k] = 0.0;
-            if (i >= nn) continue;
-            // inclusive run through i; K[i] excludes node i: P_incl - G[i]
-            const int e = k * kWaves + wid;
-            const Run full = e > 0 ? run_combine(s_run[e - 1], inc[k]) : inc[k];
-            double ph = phi0 + (double)i * d0 - (full.P - full.S);
-            if (!periodic && i == nn - 1) ph = 0.0;
-            if (i == 0) ph = phi0;
-            phi[k] = ph;
+            for (int j = 0; j < kNodesPerThread; ++j) {
+                const int i = i0 + j;
+                if (i >= nn) break;
+                G += g[j];
+                P += G;                                    // K[i] = P - G[i]
+                double ph = phi0 + (double)i * d0 - (P - G);
+                if (!periodic && i == nn - 1) ph = 0.0;
+                if (i == 0) ph = phi0;
+                s_a[i] = ph - pm;
+            }
         }
-        if (periodic) {
-            // zero-mean gauge: sum of phi[i] = d0 N (N - 1) / 2 - sum of K[i],
-            // and the K[i] = P_incl[i] - G[i] sum to Q - P over all nodes
-            const double sum_phi = d0 * (0.5 * (double)nn * (double)(nn - 1)) - (all.Q - all.P);
-            const double pm = sum_phi / nn;
-#pragma unroll
-            for (int k = 0; k < kNodesPerThread; ++k) phi[k] -= pm;
-        }
-        // every read of rho was before the barrier after the chunk scans
     } else {
-#pragma unroll
-        for (int k = 0; k < kNodesPerThread; ++k) phi[k] = 0.0;
         __syncthreads();                                 // the wall charges are read
-    }
-#pragma unroll
-    for (int k = 0; k < kNodesPerThread; ++k) {
-        const int i = k * kFT + tid;
-        if (i < nn) s_a[i] = phi[k];
+        for (int i = tid; i < nn; i += kFT) s_a[i] = 0.0;
     }
     __syncthreads();
 
