@@ -461,12 +461,17 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     __shared__ unsigned int s_cnt[C_N];
     __shared__ unsigned long long s_wen[2];   // energy carried into each wall by the run (eV, 2^20)
     __shared__ float s_red[kBS / 64];
+    // collisions and births of up to kPair tiles of one segment are handled
+    // in one round (fuller waves on the collision path); the counters
+    // alternate between rounds so that a round's reset never meets the next
+    // round's appends
+    constexpr int kPair = 2;
     constexpr int kSink = GENERAL ? kBirthsPerTile : 1;
-    __shared__ Birth s_bb[kSink];             // births of the current tile
-    __shared__ uint32_t s_bkey[kSink];
-    __shared__ unsigned int s_bn[2];          // their count, by parity of the tile
-    __shared__ CollQ s_q[GENERAL ? T : 1];    // collision candidates of the current tile
-    __shared__ unsigned int s_nq[2];          // their count, by parity of the tile
+    __shared__ Birth s_bb[kPair * kSink];     // births of the round's tiles, kSink per tile
+    __shared__ uint32_t s_bkey[kPair * kSink];
+    __shared__ unsigned int s_bn[2 * kPair];  // their counts: [round parity][tile of the round]
+    __shared__ CollQ s_q[GENERAL ? kPair * T : 1];   // collision candidates of the round
+    __shared__ unsigned int s_nq[2];          // their count, by round parity
 
     // ---- tiles per segment, prefix over the segments (up to 16 per lane) -----
     if (wid == 0) {
@@ -496,10 +501,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     }
     if (tid < C_N) s_cnt[tid] = 0;
     if (tid < 2) s_wen[tid] = 0ull;
-    if (tid < 2) {
-        s_bn[tid] = 0u;
-        s_nq[tid] = 0u;
-    }
+    if (tid < 2 * kPair) s_bn[tid] = 0u;
+    if (tid < 2) s_nq[tid] = 0u;
     __syncthreads();
     const int32_t NT = s_pref[NS];
 
@@ -516,6 +519,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 
     int cur_g = -1, cur_b = -1;
     int32_t run_first = 0;
+    int rp = 0, npend = 0;                    // round parity, tiles of the open round
+    int32_t pend_t0 = 0, pend_tin0 = 0;       // the round's first tile (global, in its segment)
     float ke_run = 0.0f;
     // a fixed contiguous range of tiles per workgroup
     const int32_t chunk = (NT + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
@@ -637,9 +642,9 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
 
         BirthSink sink;
-        sink.b = s_bb;
-        sink.key = s_bkey;
-        sink.n = &s_bn[t & 1];
+        sink.b = s_bb + npend * kSink;
+        sink.key = s_bkey + npend * kSink;
+        sink.n = &s_bn[rp * kPair + npend];
         sink.cap = kBirthsPerTile;
         sink.hist = hist;
         sink.acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
@@ -675,9 +680,9 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
                 if (GENERAL && cand) {
-                    const unsigned int q = atomicAdd(&s_nq[t & 1], 1u);
+                    const unsigned int q = atomicAdd(&s_nq[rp], 1u);
                     CollQ e;
-                    e.key = sink.pkey;
+                    e.key = sink.pkey | ((uint32_t)npend << 16);   // slot in the tile, tile of the round
                     e.c = cell[j];
                     e.f = off[j];
                     e.ux = vx[j];
@@ -715,52 +720,67 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 }
             }
         }
-        if (GENERAL) {
-            // the tile's collisions together, with full lanes (a candidate in
-            // the main loop would stall its whole wave on the collision path);
-            // the new velocities overwrite the ones stored above
-            __threadfence_block();
-            __syncthreads();
-            const unsigned int nq = s_nq[t & 1];
-            for (unsigned int q = tid; q < nq; q += kBS) {
-                CollQ e = s_q[q];
-                BirthSink qs = sink;
-                qs.pkey = e.key;
-                collide_particle(d, sc, dc, s, b, step, s_cnt, e.c, e.f, e.ux, e.uy, e.uz, e.pid, qs);
-                const int64_t slot = (int64_t)tin * T + e.key;
-                sc.vx[io][slot] = e.ux;
-                sc.vy[io][slot] = e.uy;
-                sc.vz[io][slot] = e.uz;
-                if (a.diag) {
-                    moment_diag(sc, fhist, mhist, e.c, e.f, e.ux, nc, periodic);
-                    if (s == 0) electron_diag(sc, dc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
-                }
-            }
-            __syncthreads();
-            // the tile's births in the order of their parents' slots
-            const unsigned int nst = s_bn[t & 1];
-            const int nb = nst < (unsigned)kBirthsPerTile ? (int)nst : kBirthsPerTile;
-            if (tid < nb) {
-                const uint32_t k = s_bkey[tid];
-                int rank = 0;
-                for (int i = 0; i < nb; ++i) rank += s_bkey[i] < k;
-                d.births[(size_t)t * kBirthsPerTile + rank] = s_bb[tid];
-            }
-            if (tid == 0) {
-                d.bcnt[t] = nb;
-                if (nb) atomicAdd(reinterpret_cast<unsigned long long*>(&st.staged), (unsigned long long)nb);
-            }
-        }
-
         if (tid == 0 && tin == ntiles - 1) {
             st.tile_first = tile_first;
             st.ntiles = ntiles;
         }
         if (GENERAL) {
-            __syncthreads();                      // the staged births are read
-            if (tid == 0) {                       // free for tile t + 2 (tile t + 1 counts in the other)
-                s_bn[t & 1] = 0u;
-                s_nq[t & 1] = 0u;
+            if (npend == 0) {
+                pend_t0 = t;
+                pend_tin0 = tin;
+            }
+            ++npend;
+            if (npend == kPair || tin == ntiles - 1 || t + 1 == t_end) {
+                // the round's collisions together, with full lanes (a
+                // candidate in the main loop would stall its whole wave on the
+                // collision path); the new velocities overwrite the ones
+                // stored above.  The round's tiles are consecutive.
+                __threadfence_block();
+                __syncthreads();
+                const unsigned int nq = s_nq[rp];
+                for (unsigned int q = tid; q < nq; q += kBS) {
+                    CollQ e = s_q[q];
+                    const int pos = (int)(e.key >> 16);
+                    BirthSink qs = sink;
+                    qs.b = s_bb + pos * kSink;
+                    qs.key = s_bkey + pos * kSink;
+                    qs.n = &s_bn[rp * kPair + pos];
+                    qs.pkey = e.key & 0xffffu;
+                    collide_particle(d, sc, dc, s, b, step, s_cnt, e.c, e.f, e.ux, e.uy, e.uz, e.pid, qs);
+                    const int64_t slot = (int64_t)(pend_tin0 + pos) * T + qs.pkey;
+                    sc.vx[io][slot] = e.ux;
+                    sc.vy[io][slot] = e.uy;
+                    sc.vz[io][slot] = e.uz;
+                    if (a.diag) {
+                        moment_diag(sc, fhist, mhist, e.c, e.f, e.ux, nc, periodic);
+                        if (s == 0) electron_diag(sc, dc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
+                    }
+                }
+                __syncthreads();
+                // each tile's births in the order of their parents' slots
+                for (int pos = 0; pos < npend; ++pos) {
+                    const unsigned int nst = s_bn[rp * kPair + pos];
+                    const int nb = nst < (unsigned)kBirthsPerTile ? (int)nst : kBirthsPerTile;
+                    const uint32_t* keys = s_bkey + pos * kSink;
+                    const int32_t tt = pend_t0 + pos;
+                    if (tid < nb) {
+                        const uint32_t k = keys[tid];
+                        int rank = 0;
+                        for (int i = 0; i < nb; ++i) rank += keys[i] < k;
+                        d.births[(size_t)tt * kBirthsPerTile + rank] = s_bb[pos * kSink + tid];
+                    }
+                    if (tid == 0) {
+                        d.bcnt[tt] = nb;
+                        if (nb) atomicAdd(reinterpret_cast<unsigned long long*>(&st.staged), (unsigned long long)nb);
+                    }
+                }
+                __syncthreads();                  // the staged births are read
+                if (tid == 0) {                   // free for the round after next
+                    for (int pos = 0; pos < kPair; ++pos) s_bn[rp * kPair + pos] = 0u;
+                    s_nq[rp] = 0u;
+                }
+                rp ^= 1;
+                npend = 0;
             }
         }
     }
