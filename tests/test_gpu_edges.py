@@ -143,3 +143,32 @@ def test_meshes_and_batches_refused(pic):
     mixed = [W.base_config(species=[sp]), W.base_config(species=[sp, dict(sp)])]
     with pytest.raises(RuntimeError):
         pic.Sim(mixed)                  # every discharge of a context has the same species count
+
+
+def test_dense_gas_many_collisions(pic):
+    # at 3 Torr three quarters of the electrons are collision candidates in
+    # every step and about a fifth collide (the queues of the collision
+    # rounds run full): one step from identical states against the oracle.
+    # Births, losses and order agree exactly; a collided electron's new
+    # velocity carries the FP32 rounding of its kinematics (the scattering
+    # rotation through sqrt(1 - cos^2) and sincos, the energy loss), a few
+    # 1e-6 and up to some 1e-5 relative, so every particle agrees to 1e-4 and
+    # all but those collided ones to 1e-6
+    cfg, tabs = small_argon(n_init=20000)
+    dense = W.argon_rf(n_init=20000, pressure_mtorr=3000.0, weight=cfg["species"][0]["weight"],
+                       capacity=cfg["species"][0]["capacity"])
+    sim = pic.Sim(dense, tabs)
+    sim.step(4)
+    o = to_oracle(sim, dense, tabs)
+    n0 = sim.counts()["count"][0]
+    c0 = sim.coll()["candidates"][0]
+    sim.step(1)
+    o.step(1)
+    assert (sim.coll()["candidates"][0] - c0) > 0.5 * n0
+    for s in range(2):
+        pg, po = sim.get_particles(s), o.get_particles(s)
+        assert np.array_equal(pg["id"], po["id"]), s
+        r = compare_species(pg, po, dense, dense["species"][s]["vth"] or 1.0)
+        assert r["cell_mismatch"] == 0 and r["max_dx_over_L"] < 1e-6, s
+        assert r["max_rel_v"] < 1e-4, (s, r["max_rel_v"])
+        assert np.mean(r["rel_v"] < 1e-6) >= 0.995, (s, np.mean(r["rel_v"] < 1e-6))
