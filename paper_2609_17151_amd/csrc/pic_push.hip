@@ -464,13 +464,15 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     // collisions and births of up to kPair tiles of one segment are handled
     // in one round (fuller waves on the collision path); the counters
     // alternate between rounds so that a round's reset never meets the next
-    // round's appends
-    constexpr int kPair = 2;
+    // round's appends.  The queue holds kQcap candidates (a few per cent of
+    // the particles are candidates); one past it collides where it is found.
+    constexpr int kPair = 8;
+    constexpr int kQcap = T;
     constexpr int kSink = GENERAL ? kBirthsPerTile : 1;
     __shared__ Birth s_bb[kPair * kSink];     // births of the round's tiles, kSink per tile
     __shared__ uint32_t s_bkey[kPair * kSink];
     __shared__ unsigned int s_bn[2 * kPair];  // their counts: [round parity][tile of the round]
-    __shared__ CollQ s_q[GENERAL ? kPair * T : 1];   // collision candidates of the round
+    __shared__ CollQ s_q[GENERAL ? kQcap : 1];       // collision candidates of the round
     __shared__ unsigned int s_nq[2];          // their count, by round parity
 
     // ---- tiles per segment, prefix over the segments (up to 16 per lane) -----
@@ -679,8 +681,18 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             }
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
-                if (GENERAL && cand) {
-                    const unsigned int q = atomicAdd(&s_nq[rp], 1u);
+                const unsigned int q = (GENERAL && cand) ? atomicAdd(&s_nq[rp], 1u) : 0u;
+                if (GENERAL && cand && q >= (unsigned)kQcap) {
+                    // the round's queue is full: the collision happens here
+                    collide_particle(d, sc, dc, s, b, step, s_cnt, cell[j], off[j], vx[j], vy[j], vz[j], pid[j],
+                                     sink);
+                    if (a.diag) {
+                        moment_diag(sc, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
+                        if (s == 0)
+                            electron_diag(sc, dc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc,
+                                          periodic);
+                    }
+                } else if (GENERAL && cand) {
                     CollQ e;
                     e.key = sink.pkey | ((uint32_t)npend << 16);   // slot in the tile, tile of the round
                     e.c = cell[j];
@@ -737,7 +749,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 // stored above.  The round's tiles are consecutive.
                 __threadfence_block();
                 __syncthreads();
-                const unsigned int nq = s_nq[rp];
+                const unsigned int nq = s_nq[rp] < (unsigned)kQcap ? s_nq[rp] : (unsigned)kQcap;
                 for (unsigned int q = tid; q < nq; q += kBS) {
                     CollQ e = s_q[q];
                     const int pos = (int)(e.key >> 16);
