@@ -21,7 +21,7 @@ import os
 STREAMING = [(ppt, thr) for ppt, thr in ((4, 1024), (4, 512), (4, 256), (8, 256), (2, 256), (1, 256))]
 GENERAL = [(2, 256), (1, 256)]
 SORT_EVERY = (0, 32, 16)
-COMPACT_EVERY = (16, 32, 8)
+COMPACT_EVERY = (16, 32, 64, 8)
 
 
 def signature(sim):
