@@ -1019,14 +1019,11 @@ static void sample_diagnostics(orc_sim* s)
  * component) since its injection, advanced with the new velocity; once
  * |z| >= L_z the particle is re-injected at the same x with a fresh velocity
  * from the species' initial distribution (Maxwellian of scale vth plus the
- * drift), drawn with call 6, and z = 0.  z decides an integer event and is
- * held in binary32, the precision of the GPU's store, so both sides take the
- * decision alike: a slow ion moves a few binary32 spacings of z per step. */
+ * drift), drawn with call 6, and z = 0. */
 static void renew(orc_sim* s, int k, uint32_t id, double v[3], double* z)
 {
-    float zf = (float)*z + (float)v[2] * (float)s->c.dt;
-    *z = (double)zf;
-    if (fabsf(zf) < (float)s->c.renew_lz) return;
+    *z += v[2] * s->c.dt;
+    if (fabs(*z) < s->c.renew_lz) return;
     uint32_t r[4];
     draw(s, id, (uint32_t)s->step, k, 6u, r);
     double g0, g1, g2, g3;

@@ -49,7 +49,7 @@ def test_free_flight_renewal_step_and_velocities():
     for j in range(n):
         if not hit[j]:
             assert p["vz"][j] == vz[j] and p["vx"][j] == 0.0
-            assert z[j] == pytest.approx(steps * vz[j] * dt, rel=1e-6)
+            assert z[j] == pytest.approx(steps * vz[j] * dt, rel=1e-12)
             continue
         r = oracle.philox([int(ids[j]), int(k[j]), 6, 0], [seed & 0xffffffff, seed >> 32])
         g0, g1 = _box_muller(oracle.u01(r[0]), oracle.u01(r[1]))
@@ -57,7 +57,7 @@ def test_free_flight_renewal_step_and_velocities():
         want = np.array([0.01 + 0.02 * g0, -0.02 + 0.02 * g1, 0.03 + 0.02 * g2])
         # renewed at the end of step index k_j, then free flight with the new velocity
         np.testing.assert_allclose([p["vx"][j], p["vy"][j], p["vz"][j]], want, rtol=1e-13, atol=1e-15)
-        assert z[j] == pytest.approx((steps - k[j] - 1) * want[2] * dt, rel=1e-6, abs=1e-12)
+        assert z[j] == pytest.approx((steps - k[j] - 1) * want[2] * dt, abs=1e-13)
     # positions never move along x before a renewal, and move with the new vx after
     xs = (x + np.where(hit, (steps - k - 1) * p["vx"] * dt, 0.0)) % 1.0
     np.testing.assert_allclose(p["x"], xs, atol=1e-12)
@@ -93,8 +93,7 @@ def test_ion_transit_time_in_the_axial_field():
     o.step(nstar - 1)
     assert o.counters()["renewed"][0] == 0
     z = o.axial(0)
-    # z is held in binary32 (it decides an integer event, as on the GPU)
-    np.testing.assert_allclose(z, a * dt * dt * (nstar - 1) ** 2 / 2, rtol=2e-6)
+    np.testing.assert_allclose(z, a * dt * dt * (nstar - 1) ** 2 / 2, rtol=1e-12)
     o.step(1)
     assert o.counters()["renewed"][0] == n
     assert np.all(o.get_particles(0)["vz"] == 0.0) and np.all(o.axial(0) == 0.0)
