@@ -213,7 +213,10 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_DIAG_RENEWED 18     /* int64[S]: axial renewals per species since pic_init */
 #define PIC_DIAG_CIRCUIT 19     /* double[2]: potential of the electrode at x = 0 at the last field solve (V),
                                    charge per area of its conductor now (C/m^2; 0 without a circuit) */
-#define PIC_DIAG_TIMING 14      /* double[4]: finalize launches, finalize ms, push launches, push ms (pic_profile; one push launch covers every species) */
+#define PIC_DIAG_GRAPHS 20      /* int64[2]: replays of captured step graphs since pic_init, and the steps they ran
+                                   (the other steps were launched directly) */
+#define PIC_DIAG_TIMING 14      /* double[6]: finalize launches, finalize ms, push launches, push ms, events launches, events ms
+                                   (pic_profile; one launch of each kernel covers every species) */
 
 #define PIC_EEPF_BINS 256
 #define PIC_WINDOW_RING 64      /* completed RF windows kept per discharge (pic_get_windows) */
@@ -279,8 +282,8 @@ pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const doubl
  * get: *n_out receives the count; with cap below it (or z NULL) nothing is
  * copied.  Synchronous.
  */
-pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, float* z, int64_t* n_out);
-pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const float* z);
+pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, double* z, int64_t* n_out);
+pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const double* z);
 
 /*
  * pic_set_circuit: replace the charge per area q of the driven electrode's
@@ -367,7 +370,11 @@ pic_status pic_sort(pic_ctx* ctx);
  * chunk of consecutive steps once into a HIP graph on a private stream and
  * replays it on the context's stream, which removes the host launch gaps
  * between kernels; all per-step state lives on the device, so one capture
- * serves any number of steps.  Profiling (pic_profile) uses direct launches. */
+ * serves any number of steps.  The chunk is the least multiple of 32 steps
+ * that the sort and compaction intervals divide (graphs are not used when
+ * that exceeds 1024 steps); steps short of a whole chunk are launched
+ * directly.  PIC_DIAG_GRAPHS counts the replays.  Profiling (pic_profile)
+ * uses direct launches. */
 pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable);
 
 /* pic_config_tiles: tile shape of the particle kernels (particles per thread
@@ -375,8 +382,8 @@ pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable);
  * shape is used), the interval in steps of the sort by cell (0 = never) and
  * the interval in steps of the compaction that removes the holes absorbed
  * particles leave (1 .. 1024, default 16; bounded runs only).  With graphs,
- * intervals that divide 32 keep the replayed chunk.  Takes effect at the next
- * pic_step. */
+ * the replayed chunk is the least multiple of 32 steps both intervals
+ * divide.  Takes effect at the next pic_step. */
 pic_status pic_config_tiles(pic_ctx* ctx, int32_t particles_per_thread,
                             int32_t threads_per_group, int32_t sort_every, int32_t compact_every);
 

@@ -23,7 +23,7 @@ EEPF_BINS = 256
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
-            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17, RENEWED=18, CIRCUIT=19)
+            FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17, RENEWED=18, CIRCUIT=19, GRAPHS=20)
 
 
 class SpeciesCfg(C.Structure):
@@ -103,8 +103,8 @@ def load_library():
         "pic_config_tiles": (i32, [P, i32, i32, i32, i32]),
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_set_wall_edf": (i32, [P, i32, d]),
-        "pic_get_axial": (i32, [P, i32, i32, i64, fp, C.POINTER(i64)]),
-        "pic_set_axial": (i32, [P, i32, i32, i64, fp]),
+        "pic_get_axial": (i32, [P, i32, i32, i64, dp, C.POINTER(i64)]),
+        "pic_set_axial": (i32, [P, i32, i32, i64, dp]),
         "pic_set_circuit": (i32, [P, i32, d]),
         "pic_set_windows": (i32, [P, i32, i64]),
         "pic_get_windows": (i32, [P, i32, i64, i32, dp, C.POINTER(i64)]),
@@ -367,10 +367,16 @@ class Sim:
     def profile(self, enable=True):
         self._check(_lib.pic_profile(self.h, int(enable)), "pic_profile")
 
+    def graphs(self):
+        """Replays of captured step graphs since the start, and the steps they ran."""
+        o = self.diag("GRAPHS", 2, np.int64)
+        return dict(replays=int(o[0]), steps=int(o[1]))
+
     def timing(self):
-        o = self.diag("TIMING", 4)
+        o = self.diag("TIMING", 6)
         return dict(finalize_n=float(o[0]), finalize_ms=float(o[1]),
-                    push_n=float(o[2]), push_ms=float(o[3]))
+                    push_n=float(o[2]), push_ms=float(o[3]),
+                    events_n=float(o[4]), events_ms=float(o[5]))
 
     def charge(self, batch=0):
         o = self.diag("CHARGE", 2, batch=batch)
@@ -435,14 +441,14 @@ class Sim:
         (renewal only)."""
         n = C.c_int64()
         self._check(_lib.pic_get_axial(self.h, batch, species, 0, None, C.byref(n)), "pic_get_axial")
-        z = np.zeros(n.value, np.float32)
-        self._check(_lib.pic_get_axial(self.h, batch, species, n.value, _ptr(z, C.c_float), C.byref(n)),
+        z = np.zeros(n.value, np.float64)
+        self._check(_lib.pic_get_axial(self.h, batch, species, n.value, _ptr(z, C.c_double), C.byref(n)),
                     "pic_get_axial")
         return z
 
     def set_axial(self, species, z, batch=0):
-        z = np.ascontiguousarray(z, np.float32)
-        self._check(_lib.pic_set_axial(self.h, batch, species, len(z), _ptr(z, C.c_float)), "pic_set_axial")
+        z = np.ascontiguousarray(z, np.float64)
+        self._check(_lib.pic_set_axial(self.h, batch, species, len(z), _ptr(z, C.c_double)), "pic_set_axial")
 
     def set_particles(self, species, cell, off, vx, vy, vz, ids, next_id, step, batch=0):
         cell = np.ascontiguousarray(cell, np.int32)

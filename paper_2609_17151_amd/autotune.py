@@ -19,9 +19,13 @@ import json
 import os
 
 STREAMING = [(ppt, thr) for ppt, thr in ((4, 1024), (4, 512), (4, 256), (8, 256), (2, 256), (1, 256))]
-GENERAL = [(2, 256), (1, 256)]
+GENERAL = [(4, 1024), (4, 512), (4, 256), (2, 256), (1, 256)]
 SORT_EVERY = (0, 32, 16)
-COMPACT_EVERY = (16, 32, 64, 8)
+# intervals that divide the 32-step chunk a captured graph replays
+COMPACT_EVERY = (16, 32, 8)
+# a compaction interval is accepted only if the slots in use (live particles,
+# holes and the births of the interval) stay below this share of the capacity
+HEADROOM = 0.9
 
 
 def signature(sim):
@@ -43,6 +47,34 @@ def candidates(general):
             for cmp_ in (COMPACT_EVERY if general else (16,)):
                 out.append(dict(ppt=ppt, threads=thr, sort_every=srt, compact_every=cmp_))
     return out
+
+
+def birth_rate(sim, steps=4):
+    """Births per step of every discharge and species, from the growth of
+    the id counters over `steps` real steps: {(b, s): rate}."""
+    before = {b: sim.counts(b)["next_id"] for b in range(sim.B)}
+    sim.step(steps)
+    out = {}
+    for b in range(sim.B):
+        after = sim.counts(b)["next_id"]
+        for s in range(sim.S):
+            out[(b, s)] = max(0, after[s] - before[b][s]) / steps
+    return out
+
+
+def fits(sim, compact_every, rate):
+    """Whether holes and births can pile up for `compact_every` steps: for
+    every discharge and species, the slots in use plus the interval's births
+    at twice the measured rate stay within HEADROOM of the capacity."""
+    for b in range(sim.B):
+        if b in getattr(sim, "retired", ()):
+            continue
+        c0 = sim.counts(b)
+        for s in range(sim.S):
+            cap = sim.cfgs[b]["species"][s]["capacity"]
+            if c0["count"][s] + 2.0 * rate[(b, s)] * compact_every > HEADROOM * cap:
+                return False
+    return True
 
 
 def _time_steps(sim, n):
@@ -72,8 +104,11 @@ def tune(sim, steps=64, warm=32, cache=None, timer=None, verbose=False):
             sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
             return c, store[key]["table"]
     general = key.endswith("general")
+    rate = birth_rate(sim) if general else None
     table = []
     for c in candidates(general):
+        if general and not fits(sim, c["compact_every"], rate):
+            continue
         sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
         if warm:
             sim.step(warm)

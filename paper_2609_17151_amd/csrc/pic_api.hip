@@ -69,11 +69,13 @@ struct pic_ctx {
     size_t ev_used = 0;
     double push_ms = 0.0, push_n = 0.0;
     double fin_ms = 0.0, fin_n = 0.0;
+    double ev_ms = 0.0, ev_n = 0.0;
     // replay of a captured chunk of steps
     int use_graph = 1;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     int g_steps = 0;
+    int64_t graph_replays = 0, graph_steps = 0;   // replays of captured chunks since pic_init, and their steps
     uint64_t g_key = 0;
 };
 
@@ -219,19 +221,19 @@ void fill_push_consts(const pic_config& c, int s, SegConst& sc)
     sc.mass = (float)sp.mass;
     sc.compacts = c.bc == PIC_BC_DIRICHLET ? 1 : 0;
     sc.half_m_over_e = (float)(0.5 * sp.mass / c.e_unit);
-    sc.two_e_over_m = (float)(2.0 * c.e_unit / sp.mass);
-    sc.two_e_over_me = (float)(2.0 * c.e_unit / c.species[0].mass);
+    sc.half_m_over_e_d = 0.5 * sp.mass / c.e_unit;
+    sc.two_e_over_m = 2.0 * c.e_unit / sp.mass;
     sc.mscale1 = (float)(kMomentScale / moment_vref(c, s));
     sc.mscale2 = (float)(kMomentScale / (moment_vref(c, s) * moment_vref(c, s)));
     sc.wedf_inv_bin = (float)(kEepfBins / (s == 0 ? 64.0 : 1024.0));
-    sc.renew_lz = (float)c.renew_lz;
-    sc.dt_f = (float)c.dt;
-    sc.vth0 = (float)sp.vth;
-    for (int k = 0; k < 3; ++k) sc.drift0[k] = (float)sp.drift[k];
+    sc.renew_lz = c.renew_lz;
+    sc.dt_d = c.dt;
+    sc.vth0 = sp.vth;
+    for (int k = 0; k < 3; ++k) sc.drift0[k] = sp.drift[k];
     sc.emits = (s >= 1 && sp.charge > 0.0 && c.see_gamma > 0.0 && c.bc == PIC_BC_DIRICHLET) ? 1 : 0;
     sc.see_k = (uint32_t)std::min(16777217.0, std::ceil(c.see_gamma * 16777216.0));
-    sc.vsee = (float)std::sqrt(c.see_temp * c.e_unit / c.species[0].mass);
-    sc.dtdx_e = (float)(c.dt / dx);
+    sc.vsee = std::sqrt(c.see_temp * c.e_unit / c.species[0].mass);
+    sc.dtdx_e = c.dt / dx;
 }
 
 // Collision constants of a segment from its host tables: the frequency bound,
@@ -265,7 +267,7 @@ pic_status build_xs(pic_ctx* ctx, int b, int s)
     }
     const int n = shared ? (int)e0.size() : 4096;
     const double l0 = std::log(elo), l1 = std::log(ehi);
-    std::vector<float> xs((size_t)n * nch);
+    std::vector<double> xs((size_t)n * nch);
     const double scale = c.gas_density / h.numax;
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < nch; ++k) {
@@ -281,31 +283,31 @@ pic_status build_xs(pic_ctx* ctx, int b, int s)
                 sig = sigma_of(tt, eps);
                 (void)keep_th;
             }
-            xs[(size_t)i * nch + k] = (float)(sig * scale);
+            xs[(size_t)i * nch + k] = sig * scale;
         }
     }
-    void* p = dev_alloc(ctx, xs.size() * sizeof(float));
+    void* p = dev_alloc(ctx, xs.size() * sizeof(double));
     if (!p) return PIC_ENOMEM;
-    if (hipMemcpy(p, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(p, xs.data(), xs.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return PIC_EHIP;
     if (h.xs_dev) dev_release(ctx, h.xs_dev);
     h.xs_dev = p;
-    sc.xs = (const float*)p;
+    sc.xs = (const double*)p;
     sc.xs_n = n;
-    sc.xs_ln0 = (float)l0;
-    sc.xs_inv_dln = (float)((double)(n - 1) / (l1 - l0));
+    sc.xs_ln0 = l0;
+    sc.xs_inv_dln = (double)(n - 1) / (l1 - l0);
     sc.nch = nch;
     sc.ion_type = electron_kind(h.tabs[0].kind) ? 0 : 1;
     sc.t32 = h.t32;
     for (int k = 0; k < nch; ++k) {
         sc.kind[k] = h.tabs[k].kind;
-        sc.th[k] = (float)h.tabs[k].th;
+        sc.th[k] = h.tabs[k].th;
     }
     const double m = c.species[s].mass, M = c.gas_mass;
-    sc.mr2 = (float)(2.0 * m / M);
-    sc.vt_gas = (float)std::sqrt(kBoltzmann * c.gas_temp / M);
-    sc.m_frac = (float)(m / (m + M));
-    sc.M_frac = (float)(M / (m + M));
+    sc.mr2 = 2.0 * m / M;
+    sc.vt_gas = std::sqrt(kBoltzmann * c.gas_temp / M);
+    sc.m_frac = m / (m + M);
+    sc.M_frac = M / (m + M);
     return PIC_OK;
 }
 
@@ -367,6 +369,9 @@ void prof_collect(pic_ctx* c)
         if (pr.first < 0) {
             c->fin_ms += ms;
             c->fin_n += 1.0;
+        } else if (pr.first == 1) {
+            c->ev_ms += ms;
+            c->ev_n += 1.0;
         } else {
             c->push_ms += ms;
             c->push_n += 1.0;
@@ -525,7 +530,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
                 sc.vy[k] = (float*)A(cap * 4);
                 sc.vz[k] = (float*)A(cap * 4);
                 sc.id[k] = (uint32_t*)A(cap * 4);
-                sc.z[k] = c.renew_lz > 0.0 ? (float*)A(cap * 4) : nullptr;
+                sc.z[k] = c.renew_lz > 0.0 ? (double*)A(cap * 8) : nullptr;
             }
             fill_push_consts(c, s, sc);
         }
@@ -559,6 +564,13 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.wring = (double*)A(8ull * B * kWindowRing * (1 + (size_t)(S + 2) * nodes_max));
         d.births = (Birth*)A(sizeof(Birth) * (size_t)tiles_max * kBirthsPerTileMin);
         d.bcnt = (int32_t*)A(4ull * tiles_max);
+        int64_t slots = 0;
+        for (int s = 0; s < S; ++s) slots += ctx->grid_cap[s];
+        d.ev = (uint32_t*)A(4ull * slots);
+        d.evc = (uint32_t*)A(4ull * (slots / 64 + 1));
+        d.evp = (uint32_t*)A(4ull * (slots / 64 + 1));
+        d.evidx = (uint32_t*)A(4ull * (slots / 64 + 1));
+        d.evg = (uint32_t*)A(4ull * kMaxPushGrid);
         d.ccnt = (uint32_t*)A(4ull * tiles_max);
         d.tick = (unsigned long long*)A(8);
         d.ke_part = (double*)A(8ull * tiles_max);
@@ -597,8 +609,9 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     for (int g = 0; g < B * S && ok; ++g)
         for (int k = 0; k < 2 && ok; ++k)
             if (ctx->segc[g].z[k])
-                ok = hipMemsetAsync(ctx->segc[g].z[k], 0, 4ull * pad_cap(ctx->segc[g].cap), st) == hipSuccess;
+                ok = hipMemsetAsync(ctx->segc[g].z[k], 0, 8ull * pad_cap(ctx->segc[g].cap), st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.bcnt, 0, 4ull * tiles_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.evg, 0, 4ull * kMaxPushGrid, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.tick, 0, 8, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.ke_part, 0, 8ull * tiles_max, st) == hipSuccess;
     for (int b = 0; b < B && ok; ++b)
@@ -720,6 +733,8 @@ struct StepPlan {
     int ppt = 4, threads = 256;
     bool general = false;
     int64_t grid = 1;
+    EvArgs ea{};
+    int64_t ev_grid = 1;
     FinArgs fa{};
     uint64_t key = 0;
 };
@@ -741,14 +756,14 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.general = false;
     for (int g = 0; g < B * S; ++g) {
         const SegConst& sc = ctx->segc[g];
-        if (sc.compacts || sc.nch > 0 || sc.emits || sc.renew_lz > 0.0f) p.general = true;
+        if (sc.compacts || sc.nch > 0 || sc.emits || sc.renew_lz > 0.0) p.general = true;
     }
     push_shape(p.ppt, p.threads, p.general);
     const int T = p.threads * p.ppt;
     int64_t tiles = 0;
     for (int g = 0; g < B * S; ++g) tiles += (pad_cap(ctx->segc[g].cap) + T - 1) / T;
     const int64_t resident = (int64_t)push_occupancy(p.ppt, p.threads, p.general, lds) * ctx->n_cu;
-    p.grid = std::max<int64_t>(1, std::min(tiles, resident));
+    p.grid = std::max<int64_t>(1, std::min(std::min(tiles, resident), (int64_t)kMaxPushGrid));
     PushArgs& pa = p.pa;
     pa.d = ctx->d;
     pa.diag = ctx->diag;
@@ -772,6 +787,16 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.fa.diag = ctx->diag;
     p.fa.only_b = -1;
     p.fa.births_per_tile = p.general ? T / kBirthsDiv : 0;
+    p.ea.d = ctx->d;
+    p.ea.T = T;
+    p.ea.ppt = p.ppt;
+    p.ea.waves = p.threads / 64;
+    p.ea.push_grid = (int32_t)p.grid;
+    p.ea.births_per_tile = T / kBirthsDiv;
+    p.ea.diag = ctx->diag;
+    p.ea.eepf_inv_bin = pa.eepf_inv_bin;
+    p.ev_grid = std::max<int64_t>(1, std::min(tiles, (int64_t)events_occupancy() * ctx->n_cu));
+    mix((uint64_t)p.ev_grid);
     p.fa.eepf_inv_bin = pa.eepf_inv_bin;
     mix((uint64_t)ctx->sort_every);
     mix((uint64_t)ctx->compact_every);
@@ -793,6 +818,11 @@ pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st,
         const int pp = prof ? prof_begin(ctx) : -1;
         if (launch_push(p.pa, p.ppt, p.threads, p.general, p.grid, st) != hipSuccess) return PIC_EHIP;
         prof_end(ctx, pp, 0);
+        if (p.general) {
+            const int pv = prof ? prof_begin(ctx) : -1;
+            if (launch_events(p.ea, p.ev_grid, st) != hipSuccess) return PIC_EHIP;
+            prof_end(ctx, pv, 1);
+        }
         const int pe = prof ? prof_begin(ctx) : -1;
         if (launch_finalize(p.fa, st) != hipSuccess) return PIC_EHIP;
         prof_end(ctx, pe, -1);
@@ -842,6 +872,28 @@ pic_status capture_steps(pic_ctx* ctx, const StepPlan& p, int n)
 }
 
 constexpr int kGraphSteps = 32;
+constexpr int kGraphMaxSteps = 1024;
+
+int64_t gcd64(int64_t a, int64_t b)
+{
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// steps of the captured chunk: a multiple of 32 that every periodic
+// interval (sort, compaction) divides, so each replay sorts and compacts at
+// the same steps; 0 when that would exceed kGraphMaxSteps
+int graph_chunk(const pic_ctx* ctx, const StepPlan& p)
+{
+    int64_t L = kGraphSteps;
+    if (ctx->sort_every > 0) L = L / gcd64(L, ctx->sort_every) * ctx->sort_every;
+    if (p.general) L = L / gcd64(L, ctx->compact_every) * ctx->compact_every;
+    return L <= kGraphMaxSteps ? (int)L : 0;
+}
 
 }  // namespace
 
@@ -860,23 +912,24 @@ pic_status pic_step(pic_ctx* ctx, int32_t n_steps)
         return (ctx->sort_every == 0 || ctx->steps_since_sort == 0) &&
                (!p.general || ctx->steps_since_compact == 0);
     };
-    const bool divides = (ctx->sort_every == 0 || kGraphSteps % ctx->sort_every == 0) &&
-                         (!p.general || kGraphSteps % ctx->compact_every == 0);
-    while (divides && !aligned() && left > 0) {
-        rc = enqueue_steps(ctx, p, 1, st, ctx->prof != 0);
+    const int chunk = graph_chunk(ctx, p);
+    while (chunk > 0 && ctx->use_graph && !ctx->prof && !aligned() && left > 0) {
+        rc = enqueue_steps(ctx, p, 1, st, false);
         if (rc != PIC_OK) return rc;
         --left;
     }
-    // replays of a captured chunk; the intervals must divide the chunk
-    const bool graph_ok = ctx->use_graph && !ctx->prof && divides && aligned();
-    if (graph_ok && left >= kGraphSteps) {
-        if (!ctx->gexec || ctx->g_key != p.key || ctx->g_steps != kGraphSteps) {
-            rc = capture_steps(ctx, p, kGraphSteps);
+    // replays of a captured chunk; the intervals divide the chunk
+    const bool graph_ok = ctx->use_graph && !ctx->prof && chunk > 0 && aligned();
+    if (graph_ok && left >= chunk) {
+        if (!ctx->gexec || ctx->g_key != p.key || ctx->g_steps != chunk) {
+            rc = capture_steps(ctx, p, chunk);
             if (rc != PIC_OK) return rc;
         }
-        while (left >= kGraphSteps) {
+        while (left >= chunk) {
             if (hipGraphLaunch(ctx->gexec, st) != hipSuccess) return PIC_EHIP;
-            left -= kGraphSteps;
+            left -= chunk;
+            ctx->graph_replays += 1;
+            ctx->graph_steps += chunk;
         }
     }
     return enqueue_steps(ctx, p, left, st, ctx->prof != 0);
@@ -928,6 +981,7 @@ pic_status pic_profile(pic_ctx* ctx, int32_t enable)
     if (enable) {
         ctx->push_ms = ctx->push_n = 0.0;
         ctx->fin_ms = ctx->fin_n = 0.0;
+        ctx->ev_ms = ctx->ev_n = 0.0;
     }
     return PIC_OK;
 }
@@ -1054,7 +1108,7 @@ pic_status pic_set_circuit(pic_ctx* ctx, int32_t batch, double q)
     return hip_st(hipStreamSynchronize(st));
 }
 
-pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, float* z, int64_t* n_out)
+pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, double* z, int64_t* n_out)
 {
     if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S) return PIC_EINVAL;
     const int idx = batch * ctx->S + species;
@@ -1077,10 +1131,10 @@ pic_status pic_get_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t c
             return PIC_EHIP;
         if (ss.count != ss.live) return PIC_ESTATE;
     }
-    return hip_st(hipMemcpy(z, sc.z[ss.parity], (size_t)ss.count * 4, hipMemcpyDeviceToHost));
+    return hip_st(hipMemcpy(z, sc.z[ss.parity], (size_t)ss.count * 8, hipMemcpyDeviceToHost));
 }
 
-pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const float* z)
+pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n, const double* z)
 {
     if (!ctx || batch < 0 || batch >= ctx->B || species < 0 || species >= ctx->S || n < 0) return PIC_EINVAL;
     const int idx = batch * ctx->S + species;
@@ -1100,7 +1154,7 @@ pic_status pic_set_axial(pic_ctx* ctx, int32_t batch, int32_t species, int64_t n
     }
     if (n != ss.live) return PIC_EINVAL;
     if (n == 0) return PIC_OK;
-    return hip_st(hipMemcpy(sc.z[ss.parity], z, (size_t)n * 4, hipMemcpyHostToDevice));
+    return hip_st(hipMemcpy(sc.z[ss.parity], z, (size_t)n * 8, hipMemcpyHostToDevice));
 }
 
 pic_status pic_get_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64_t cap, int32_t* cell,
@@ -1164,7 +1218,7 @@ pic_status pic_set_particles(pic_ctx* ctx, int32_t batch, int32_t species, int64
         ok = ok && hipMemcpy(sc.vy[p], vy, nb, hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && hipMemcpy(sc.vz[p], vz, nb, hipMemcpyHostToDevice) == hipSuccess;
         ok = ok && hipMemcpy(sc.id[p], id, nb, hipMemcpyHostToDevice) == hipSuccess;
-        if (sc.z[p]) ok = ok && hipMemset(sc.z[p], 0, nb) == hipSuccess;
+        if (sc.z[p]) ok = ok && hipMemset(sc.z[p], 0, 2 * nb) == hipSuccess;
     }
     ss.count = n;
     ss.live = n;
@@ -1238,7 +1292,7 @@ pic_status pic_load_profiles(pic_ctx* ctx, int32_t batch, int32_t m, const doubl
         ok = launch_profile_load(pa, st) == hipSuccess;
         const SegConst& zc = ctx->segc[batch * S + s];
         if (ok && zc.z[ss[s].parity] && n[s] > 0)
-            ok = hipMemsetAsync(zc.z[ss[s].parity], 0, 4ull * n[s], st) == hipSuccess;
+            ok = hipMemsetAsync(zc.z[ss[s].parity], 0, 8ull * n[s], st) == hipSuccess;
         ss[s].count = ss[s].live = n[s];
         ss[s].dead = 0;
         ss[s].staged = 0;
@@ -1418,6 +1472,13 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
                        : 0.0;
             break;
         }
+        case PIC_DIAG_GRAPHS: {
+            if (!need(16)) return PIC_EINVAL;
+            int64_t* o = (int64_t*)out;
+            o[0] = ctx->graph_replays;
+            o[1] = ctx->graph_steps;
+            break;
+        }
         case PIC_DIAG_RENEWED: {
             if (!need(8ull * S)) return PIC_EINVAL;
             int64_t* o = (int64_t*)out;
@@ -1462,13 +1523,15 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             break;
         }
         case PIC_DIAG_TIMING: {
-            if (!need(8ull * 4)) return PIC_EINVAL;
+            if (!need(8ull * 6)) return PIC_EINVAL;
             prof_collect(ctx);
             double* o = (double*)out;
             o[0] = ctx->fin_n;
             o[1] = ctx->fin_ms;
             o[2] = ctx->push_n;
             o[3] = ctx->push_ms;
+            o[4] = ctx->ev_n;
+            o[5] = ctx->ev_ms;
             break;
         }
         case PIC_DIAG_CHARGE: {

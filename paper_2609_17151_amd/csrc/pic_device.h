@@ -35,52 +35,44 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 // odd 24-bit integer 2*(x>>9)+1: the uniform below is this times 2^-24
 __device__ __forceinline__ uint32_t odd24(uint32_t x) { return ((x >> 9) << 1) | 1u; }
 
-// uniform in (0,1), exact in binary32 (and equal to the binary64 value)
-__device__ __forceinline__ float u01f(uint32_t x) { return (float)odd24(x) * 0x1p-24f; }
+// uniform in (0,1) with 23 random bits (exact in binary32 and binary64)
 __device__ __forceinline__ double u01d(uint32_t x) { return (double)odd24(x) * 0x1p-24; }
 
-__device__ __forceinline__ void box_muller_f(float ua, float ub, float& g0, float& g1)
-{
-    const float r = sqrtf(-2.0f * logf(ua));
-    float s, c;
-    sincosf(6.283185307179586f * ub, &s, &c);
-    g0 = r * c;
-    g1 = r * s;
-}
-
+// Box-Muller pair from two uniforms; the angle 2 pi ub as sincospi(2 ub),
+// whose argument 2 ub is exact (no argument reduction)
 __device__ __forceinline__ void box_muller_d(double ua, double ub, double& g0, double& g1)
 {
     const double r = sqrt(-2.0 * log(ua));
     double s, c;
-    sincos(6.283185307179586476925286766559 * ub, &s, &c);
+    sincospi(2.0 * ub, &s, &c);
     g0 = r * c;
     g1 = r * s;
 }
 
-// Direction after scattering by (chi, phi) about the unit direction d
-// (Vahedi & Surendra form with the x axis as reference; the y axis when d is
-// within 1e-6 of x).
-__device__ __forceinline__ void scatter_dir(float dx, float dy, float dz, float cos_chi, float phi,
-                                            float& ox, float& oy, float& oz)
+// Direction after scattering by (chi, phi = 2 pi u_phi) about the unit
+// direction d (Vahedi & Surendra form with the x axis as reference; the y
+// axis when d is within 1e-6 of x), in FP64: only the few particles that
+// collide in a step take this path, so its cost is small, and the new
+// velocity is rounded to binary32 once, at the end.
+__device__ __forceinline__ void scatter_dir_d(double dx, double dy, double dz, double cos_chi, double u_phi,
+                                              double& ox, double& oy, double& oz)
 {
-    const float sin_chi = sqrtf(fmaxf(0.0f, 1.0f - cos_chi * cos_chi));
-    float sp, cp;
-    sincosf(phi, &sp, &cp);
-    float a = dx, b = dy, c = dz;
-    float st = sqrtf(fmaxf(0.0f, 1.0f - a * a));
-    const bool alt = !(st > 1e-6f);
+    const double sin_chi = sqrt(fmax(0.0, 1.0 - cos_chi * cos_chi));
+    double sp, cp;
+    sincospi(2.0 * u_phi, &sp, &cp);
+    double a = dx, b = dy, c = dz;
+    double st = sqrt(fmax(0.0, 1.0 - a * a));
+    const bool alt = !(st > 1e-6);
     if (alt) {
         a = dy;
         b = dz;
         c = dx;
-        st = sqrtf(fmaxf(0.0f, 1.0f - a * a));
+        st = sqrt(fmax(0.0, 1.0 - a * a));
     }
-    const float A = sin_chi / st;
-    const float na = a * cos_chi + sin_chi * cp * st;
-    const float nb = b * cos_chi + A * (sp * c - cp * a * b);
-    const float nc = c * cos_chi - A * (sp * b + cp * a * c);
-    // undo the axis rotation with selects (a branch on the outputs becomes a
-    // dynamically indexed stack array)
+    const double A = sin_chi / st;
+    const double na = a * cos_chi + sin_chi * cp * st;
+    const double nb = b * cos_chi + A * (sp * c - cp * a * b);
+    const double nc = c * cos_chi - A * (sp * b + cp * a * c);
     ox = alt ? nc : na;
     oy = alt ? na : nb;
     oz = alt ? nb : nc;
@@ -93,17 +85,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ double wave_incl_scan_f64(double v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double o = __shfl_up(v, d, 64);
         if (lane >= d) v += o;
     }
     return v;

@@ -123,9 +123,14 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     // ---- births, appended after the last slot in the order of their tiles --
     // (and, inside a tile, of their parents): ionization electrons, then the
     // secondaries of each emitting ion species in turn; ionization ions in the
-    // order of their electrons.  All threads, one tile per thread per round.
+    // order of their electrons.  Rounds of up to kFT tiles: a block scan of
+    // the tiles' birth counts, then one birth per thread (its tile found by a
+    // binary search of the scan), so the copies of a round go out together.
+    // A tile's births are staged in any order; each carries its parent's
+    // slot, and its rank among the tile's keys is its place.
     __shared__ int64_t s_app[kMaxSpecies], s_want[kMaxSpecies];
     __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_tinc[kFT];         // inclusive prefix of the round's tiles' birth counts
     if (a.mode == kFinStep && a.births_per_tile > 0) {
         const SegState& s0 = d.segs[b * S + 0];
         const SegConst& c0 = d.segc[b * S + 0];
@@ -166,7 +171,9 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             const bool pair = src == 0 && S > 1;            // ionization: an ion with every electron
             for (int64_t r0 = 0; r0 < nt; r0 += kFT) {
                 const int64_t i = r0 + tid;
-                const uint32_t c = i < nt ? (uint32_t)d.bcnt[tf + i] : 0u;
+                const uint32_t bc = i < nt ? (uint32_t)d.bcnt[tf + i] : 0u;
+                const uint32_t bpt = (uint32_t)a.births_per_tile;
+                const uint32_t c = bc < bpt ? bc : bpt;   // more were counted as dropped
                 const uint32_t incl = wave_incl_scan_u32(c);
                 if (lane == 63) s_scan[wid] = incl;
                 __syncthreads();
@@ -176,11 +183,23 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     if (w < wid) wex += s_scan[w];
                     tot += s_scan[w];
                 }
-                const int64_t ex = (int64_t)(wex + incl - c);
-                const Birth* bs = d.births + (size_t)(tf + i) * a.births_per_tile;
-                for (uint32_t k = 0; k < c; ++k) {
-                    const Birth bb = bs[k];
-                    const int64_t e = pos0 + ex + k;
+                s_tinc[tid] = wex + incl;
+                __syncthreads();
+                const int64_t nr = nt - r0 < kFT ? nt - r0 : kFT;   // tiles in this round
+                for (uint32_t j = tid; j < tot; j += kFT) {
+                    // the tile of birth j: the first with an inclusive prefix above j
+                    int lo = 0, hi = (int)nr - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_tinc[mid] > j) hi = mid; else lo = mid + 1;
+                    }
+                    const uint32_t t0 = lo > 0 ? s_tinc[lo - 1] : 0u;
+                    const uint32_t k = j - t0, nk = s_tinc[lo] - t0;
+                    const Birth* tb = d.births + (size_t)(tf + r0 + lo) * a.births_per_tile;
+                    const Birth bb = tb[k];
+                    uint32_t rank = 0;
+                    for (uint32_t q = 0; q < nk; ++q) rank += tb[q].key < bb.key;
+                    const int64_t e = pos0 + t0 + rank;
                     if (e < cap0) {
                         c0.cell[io0][e] = bb.cell;
                         c0.off[io0][e] = bb.off;
@@ -188,7 +207,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                         c0.vy[io0][e] = bb.vy;
                         c0.vz[io0][e] = bb.vz;
                         c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
-                        if (c0.z[0]) c0.z[io0][e] = 0.0f;
+                        if (c0.z[0]) c0.z[io0][e] = 0.0;
                         if (a.diag) {
                             moment_add(0, bb.cell, bb.off, bb.vx);
                             energy_add(bb.cell, bb.off, bb.vx, bb.vy, bb.vz);
@@ -196,7 +215,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                     }
                     if (pair) {
                         const SegConst& c1 = d.segc[b * S + 1];
-                        const int64_t q = pos1 + ex + k;
+                        const int64_t q = pos1 + t0 + rank;
                         if (q < cap1) {
                             c1.cell[io1][q] = bb.cell;
                             c1.off[io1][q] = bb.off;
@@ -204,7 +223,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                             c1.vy[io1][q] = bb.ivy;
                             c1.vz[io1][q] = bb.ivz;
                             c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
-                            if (c1.z[0]) c1.z[io1][q] = 0.0f;
+                            if (c1.z[0]) c1.z[io1][q] = 0.0;
                             if (a.diag) moment_add(1, bb.cell, bb.off, bb.ivx);
                         }
                     }

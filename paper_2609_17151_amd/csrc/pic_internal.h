@@ -25,6 +25,7 @@ constexpr int64_t kMaxTiles = 1ll << 30;                    // tile numbers fit 
 constexpr int kTileMin = 256;                               // smallest tile of the push (particles)
 constexpr int kBirthsDiv = 16;                              // a tile stages up to T / 16 births per step
 constexpr int kBirthsPerTileMin = kTileMin / kBirthsDiv;
+constexpr int kMaxPushGrid = 4096;                          // workgroups of a push launch
 
 // latched device flags
 constexpr uint32_t kFlagCapacity = 1u << 0;
@@ -46,11 +47,13 @@ enum { C_ABS0, C_ABS1, C_SEE0, C_SEE1, C_CAND, C_NULL, C_VIOL, C_DROP, C_REN, C_
 constexpr double kDepScale = 4294967296.0;
 
 // a staged birth: the electron (ionization or secondary) and, for
-// ionization, the velocity of the ion born with it
+// ionization, the velocity of the ion born with it; key = the parent's slot
+// in its tile (births are staged in any order and ranked by key)
 struct Birth {
     int32_t cell;
     float off, vx, vy, vz;
     float ivx, ivy, ivz;
+    uint32_t key;
 };
 
 struct SegConst {
@@ -62,7 +65,7 @@ struct SegConst {
     float* vy[2];
     float* vz[2];
     uint32_t* id[2];
-    float* z[2];            // axial displacement since injection (renewal only, else null)
+    double* z[2];           // axial displacement since injection, FP64 (renewal only, else null)
     int64_t cap;
     // push
     float qmh;              // (q/m) dt/2
@@ -73,32 +76,33 @@ struct SegConst {
     double q, w, qm;
     float mass;
     int32_t compacts;       // 1 when particles can be absorbed (bounded domain)
-    // collisions
+    // collisions: the candidate test in the push, the rest (channel,
+    // kinematics, births) in the events kernel, in FP64
     int32_t nch, ion_type;
     uint32_t t32;
     int32_t xs_n;
-    float xs_ln0, xs_inv_dln;
-    const float* xs;        // [xs_n][nch] n_g sigma_k / nu_max on a uniform ln(eps) grid
+    double xs_ln0, xs_inv_dln;
+    const double* xs;       // [xs_n][nch] n_g sigma_k / nu_max on a uniform ln(eps) grid
     int32_t kind[kMaxChan];
-    float th[kMaxChan];
-    float half_m_over_e, two_e_over_m;
-    float mr2;              // 2 m / M_gas
-    float vt_gas;           // sqrt(k T_g / M_gas)
-    float m_frac, M_frac;   // m/(m+M), M/(m+M)
+    double th[kMaxChan];
+    float half_m_over_e;    // m / 2e in FP32 (wall energies, diagnostics)
+    double half_m_over_e_d, two_e_over_m;
+    double mr2;             // 2 m / M_gas
+    double vt_gas;          // sqrt(k T_g / M_gas)
+    double m_frac, M_frac;  // m/(m+M), M/(m+M)
     // secondary emission by this (ion) species
     int32_t emits;
     uint32_t see_k;         // emit iff (2*(x>>9)+1) < see_k
-    float vsee;             // sqrt(e T_see / m_e)
-    float dtdx_e;           // dt/dx of the electron species (same mesh and dt)
-    // electrons born here: speed from energy
-    float two_e_over_me;
+    double vsee;            // sqrt(e T_see / m_e)
+    double dtdx_e;          // dt/dx of the electron species (same mesh and dt)
     // velocity moments (diagnostics) in fixed point: per particle weight x
     // vx x mscale1 and weight x vx^2 x mscale2, rounded to integers
     float mscale1, mscale2;
     float wedf_inv_bin;     // wall impact-energy histogram: 1 / bin width (1/eV)
-    // axial renewal: length (0 = off), dt, the initial distribution
-    float renew_lz, dt_f, vth0;
-    float drift0[3];
+    // axial renewal: length (0 = off) and dt, the initial distribution
+    double renew_lz, dt_d;
+    double vth0;
+    double drift0[3];
 };
 
 struct DisConst {
@@ -206,6 +210,11 @@ struct DevPtrs {
     unsigned long long* wedf;    // [B][S][2][bins] impact energies at each wall
     Birth* births;               // [tiles_max * kBirthsPerTileMin] births staged by tile, in particle order
     int32_t* bcnt;               // [tiles_max] births staged by each tile
+    uint32_t* ev;                // [slots] events of the step: per tile, per wave, in slot order
+    uint32_t* evc;               // [slots / 64 + 1] events recorded by each wave of each tile (a "unit")
+    uint32_t* evp;               // [slots / 64 + 1] prefix of the units' events within their push workgroup's range
+    uint32_t* evidx;             // [slots / 64 + 1] per push range (from its first slot / 64): the unit holding event 64 k
+    uint32_t* evg;               // [kMaxPushGrid] events of each push workgroup's range
     unsigned long long* tick;    // steps taken by the context
     uint32_t* ccnt;              // [tiles_max] compaction: live particles of each tile, then their first slot
     double* ke_part;             // [tiles_max] kinetic-energy partial sums by tile

@@ -13,6 +13,18 @@ struct PushArgs {
     int32_t nodes_max_dyn, cells_max_dyn;
 };
 
+// The events kernel: the push's events of a step (collisions, renewals,
+// secondary emission) with the push's tile shape.
+constexpr int kEvThreads = 256;
+struct EvArgs {
+    DevPtrs d;
+    int32_t T, ppt, waves;        // the push's tile: particles, particles per thread, waves
+    int32_t push_grid;            // the push's workgroups (each indexed its own tile range's events)
+    int32_t births_per_tile;      // staging slots of a tile
+    int32_t diag;
+    float eepf_inv_bin;
+};
+
 // finalize modes
 constexpr int kFinStep = 0;       // append births, deposit -> field at t^{n+1}, step++
 constexpr int kFinSolve = 1;      // deposit -> field at t = step dt, no state change but the field
@@ -54,6 +66,8 @@ struct ProfileArgs {
 hipError_t launch_profile_load(const ProfileArgs& a, hipStream_t st);
 hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, int64_t grid, hipStream_t st);
 void push_shape(int& ppt, int& threads, bool general);
+hipError_t launch_events(const EvArgs& a, int64_t grid, hipStream_t st);
+int events_occupancy();
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
 hipError_t launch_load(const LoadArgs& a, hipStream_t st);
 hipError_t launch_deposit(const DevPtrs& d, int only_b, int64_t max_count, hipStream_t st);

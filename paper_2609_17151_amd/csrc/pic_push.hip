@@ -1,35 +1,44 @@
-// Fused particle kernel of one leapfrog step for every species of every
-// discharge of a context, in one launch (paper Section 1: explicit leapfrog,
-// Boris pusher, walls and secondary emission, null-collision Monte Carlo with
-// tabulated cross sections; the charge of the particles deposited on the mesh).
+// Particle kernels of one leapfrog step for every species of every discharge
+// of a context (paper Section 1: explicit leapfrog, Boris pusher, walls and
+// secondary emission, null-collision Monte Carlo with tabulated cross
+// sections; the charge of the particles deposited on the mesh).
 //
-// Work is cut into tiles of T = threads * PPT consecutive particle slots of
-// one (discharge, species) segment; tiles are numbered over all segments,
-// discharge-major, and every workgroup takes a fixed contiguous range of
-// tiles, so one launch covers the whole step with no waiting between
-// workgroups.  Each thread owns PPT consecutive slots and moves them with
-// 16-byte vector loads and stores, in place.  A workgroup stages the
+// The push is one launch over all segments.  Work is cut into tiles of
+// T = threads * PPT consecutive particle slots of one (discharge, species)
+// segment; tiles are numbered over all segments, discharge-major, and every
+// workgroup takes a fixed contiguous range of tiles, so no workgroup ever
+// waits for another.  Each thread owns PPT consecutive slots and moves them
+// with 16-byte vector loads and stores, in place.  A workgroup stages the
 // (E[c], E[c+1]) pairs of a discharge in LDS once per run of tiles of that
 // discharge, and zeroes and flushes its deposit histogram once per run of
 // tiles of one segment.
+//
+// Per particle the push does the gather (linear weighting), the Boris push in
+// the imposed B, the cell-relative move in FP32, the periodic wrap or the
+// absorption at a wall, and the null-collision candidate test (an integer
+// test on one Philox draw).  What only a few particles need per step is
+// recorded as an event instead: a collision candidate, an axial renewal, the
+// secondary-emission test of an absorbed ion.  Each wave writes its events in
+// slot order to its tile's list (ballots and lane counts: no barrier, no
+// queue), and the events kernel then does that work for all of them with full
+// waves, in FP64.
 //
 // Absorbed particles leave holes (cell = -1) that later steps skip; a stable
 // compaction every few steps removes them.  Holes do not change the order of
 // the live particles, and births are appended after the last slot in the
 // order of their parents, so the particle order after a compaction is the
 // order that compacting every step would give.  Births are staged per tile in
-// particle order (a block scan of the birth flags) and appended by the
+// the order of their parents' slots by the events kernel and appended by the
 // finalize in tile order, which also gives their ids.
 //
-// Per particle: gather E by linear weighting, Boris push in the imposed B,
-// cell-relative move in FP32, periodic wrap or absorption (with secondary
-// emission for ions), the null-collision test and, for candidates, the
-// collision.  Deposition: LDS histogram in 64-bit fixed point flushed with
-// integer atomics, so sums are exact and independent of the order of tiles and
-// runs are bit-reproducible without global float atomics.
+// Deposition: LDS histogram in 64-bit fixed point flushed with integer
+// atomics (births add theirs with integer atomics too), so sums are exact and
+// independent of the order of tiles and runs are bit-reproducible without
+// global float atomics.
 //
 // Streaming instances (GENERAL = false) serve periodic runs without
-// collisions, where nothing can be absorbed or born: no ids, holes or births.
+// collisions or renewal, where nothing can be absorbed or born: no ids,
+// holes or events.
 #include "pic_device.h"
 #include "pic_internal.h"
 #include "pic_kernels.h"
@@ -102,49 +111,24 @@ __device__ __forceinline__ void vstore(S* __restrict__ p, const S* in)
     }
 }
 
-// The births of a tile, staged in LDS as they happen; `pkey` is the slot of
-// the parent in the tile, so the tile's canonical order is the order of keys.
-// A staged birth is deposited at once: an ionization electron into the
-// workgroup's histogram and its ion into species 1, a secondary electron into
-// species 0.
-// a collision candidate waiting for the tile's collision pass
-struct CollQ {
-    uint32_t key;                  // slot in the tile
-    int32_t c;
-    float f, ux, uy, uz;
-    uint32_t pid;
-};
+// Events of the step, recorded by the push for the events kernel: the slot
+// of the particle in its tile and what happens to it there.
+constexpr uint32_t kEvSlot = 0xffffu;       // slot in the tile (tiles hold at most 4096 particles)
+constexpr uint32_t kEvCand = 1u << 16;      // collision candidate
+constexpr uint32_t kEvRenew = 1u << 17;     // axial renewal: a fresh velocity
+constexpr uint32_t kEvSee = 1u << 18;       // an emitting ion absorbed at a wall: secondary emission test
+constexpr uint32_t kEvWall1 = 1u << 19;     // ... at the wall x = L
 
-struct BirthSink {
-    Birth* b;
-    uint32_t* key;
-    unsigned int* n;
-    int cap;
-    uint32_t pkey;
-    unsigned long long* hist;      // this segment's LDS histogram
-    unsigned long long* acc_e;     // species 0 of the discharge
-    unsigned long long* acc_i;     // species 1 of the discharge (null with electrons only)
-};
-
-__device__ __forceinline__ bool stage_birth(const BirthSink& k, const Birth& x)
-{
-    const unsigned int i = atomicAdd(k.n, 1u);
-    if (i >= (unsigned)k.cap) return false;
-    k.b[i] = x;
-    k.key[i] = k.pkey;
-    return true;
-}
-
-// A particle's step up to the collision test.  Returns whether it stays;
-// secondary electrons go to `sink`; `cand` says whether it is a collision
-// candidate (the collision itself is collide_particle, run for the
-// candidates of a tile together).
+// A particle's step in the push: gather, Boris push, cell-relative move,
+// periodic wrap or absorption, and the collision test.  Returns whether the
+// particle stays; `ev` collects its event bits (the collision itself, the
+// secondary emission and the renewal are the events kernel's).
 template <bool GENERAL>
 __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, const DisConst& dc,
                                         const PushArgs& a, int s, int b, uint32_t step,
                                         const float2* ep, unsigned int* s_cnt, unsigned long long* s_wen, int& c,
                                         float& f, float& ux, float& uy, float& uz, uint32_t pid, float& ke_sum,
-                                        const BirthSink& sink, bool& cand)
+                                        uint32_t& ev)
 {
     const int nc = dc.n_cells;
     const int periodic = dc.bc == PIC_BC_PERIODIC;
@@ -215,193 +199,19 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
             if (s == 0 && (unsigned)bin < (unsigned)kEepfBins)
                 atomicAdd(&d.eepf[((size_t)b * 2 + 1) * kEepfBins + bin], 1ull);
         }
-        if (GENERAL && sc.emits) {
-            const uint4 r4 = philox10(pid, step, ((uint32_t)s << 24) | 4u, 0u, dc.key0, dc.key1);
-            if (odd24(r4.x) < sc.see_k) {
-                const uint4 r5 = philox10(pid, step, ((uint32_t)s << 24) | 5u, 0u, dc.key0, dc.key1);
-                const float vn = sc.vsee * sqrtf(-2.0f * logf(u01f(r4.y)));
-                const float adv = u01f(r4.z) * vn * sc.dtdx_e;   // cells
-                float g0, g1;
-                box_muller_f(u01f(r5.x), u01f(r5.y), g0, g1);
-                // placed u v_n dt into the gap from the wall it came from
-                int bc_ = -1;
-                float fr = 0.0f;
-                if (adv < (float)nc) {
-                    const float af = floorf(adv);
-                    fr = adv - af;
-                    if (wall == 0) {
-                        bc_ = (int)af;
-                    } else {
-                        bc_ = nc - 1 - (int)af;
-                        fr = 1.0f - fr;
-                        if (fr >= 1.0f) {
-                            fr -= 1.0f;
-                            bc_ += 1;
-                        }
-                    }
-                }
-                bool kept = false;
-                if (bc_ >= 0 && bc_ < nc) {
-                    Birth x;
-                    x.cell = bc_;
-                    x.off = fr;
-                    x.vx = wall == 0 ? vn : -vn;
-                    x.vy = sc.vsee * g0;
-                    x.vz = sc.vsee * g1;
-                    x.ivx = x.ivy = x.ivz = 0.0f;
-                    kept = stage_birth(sink, x);
-                    if (kept) {
-                        global_deposit(sink.acc_e, bc_, fr, nc, periodic);
-                        atomicAdd(&s_cnt[C_SEE0 + wall], 1u);
-                    } else {
-                        atomicOr(&d.diss[b].flags, kFlagCapacity);
-                    }
-                }
-                if (!kept) atomicAdd(&s_cnt[C_DROP], 1u);
-            }
-        }
+        if (GENERAL && sc.emits) ev = kEvSee | (wall ? kEvWall1 : 0u);
         return false;
     }
     if (!GENERAL || sc.nch == 0) return true;
     // null-collision Monte Carlo: integer candidate test on the first draw
     const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
-    cand = r.x < sc.t32;
+    if (r.x < sc.t32) ev |= kEvCand;
     return true;
 }
 
-// The collision of a candidate: the energy (electrons: target at rest; ions:
-// relative to a sampled neutral), the channel by the running sum of the
-// tabulated frequencies against the second word of the first draw, then the
-// kinematics of the channel; an ionization stages its pair in `sink`.
-__device__ __forceinline__ void collide_particle(const DevPtrs& d, const SegConst& sc, const DisConst& dc, int s,
-                                                 int b, uint32_t step, unsigned int* s_cnt, int c, float f,
-                                                 float& ux, float& uy, float& uz, uint32_t pid,
-                                                 const BirthSink& sink)
-{
-    const int nc = dc.n_cells;
-    const int periodic = dc.bc == PIC_BC_PERIODIC;
-    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
-    atomicAdd(&s_cnt[C_CAND], 1u);
-    float speed, eps;
-    float nvx = 0.0f, nvy = 0.0f, nvz = 0.0f;
-    if (!sc.ion_type) {
-        const float v2 = ux * ux + uy * uy + uz * uz;
-        speed = sqrtf(v2);
-        eps = sc.half_m_over_e * v2;
-    } else {
-        const uint4 r3 = philox10(pid, step, ((uint32_t)s << 24) | 3u, 0u, dc.key0, dc.key1);
-        float g0, g1, g2, g3;
-        box_muller_f(u01f(r3.x), u01f(r3.y), g0, g1);
-        box_muller_f(u01f(r3.z), u01f(r3.w), g2, g3);
-        nvx = sc.vt_gas * g0;
-        nvy = sc.vt_gas * g1;
-        nvz = sc.vt_gas * g2;
-        const float gx = ux - nvx, gy = uy - nvy, gz = uz - nvz;
-        const float g2s = gx * gx + gy * gy + gz * gz;
-        speed = sqrtf(g2s);
-        eps = sc.half_m_over_e * g2s;
-    }
-    // channel: the first k whose running sum of n_g sigma_k g / nu_max passes
-    // u1, one pass over the table row (the full sum checks the bound)
-    const float u1 = u01f(r.y);
-    float cum = 0.0f;
-    int ch = -1;
-    {
-        const float lx = (logf(fmaxf(eps, 1e-30f)) - sc.xs_ln0) * sc.xs_inv_dln;
-        int i;
-        float fr;
-        if (!(lx > 0.0f)) {
-            i = 0;
-            fr = 0.0f;
-        } else if (lx >= (float)(sc.xs_n - 1)) {
-            i = sc.xs_n - 2;
-            fr = 1.0f;
-        } else {
-            i = (int)lx;
-            if (i > sc.xs_n - 2) i = sc.xs_n - 2;
-            fr = lx - (float)i;
-        }
-        const float* r0 = sc.xs + (size_t)i * sc.nch;
-        const float* r1 = r0 + sc.nch;
-        for (int k = 0; k < sc.nch; ++k) {
-            const float v = r0[k] + fr * (r1[k] - r0[k]);
-            cum += ((eps < sc.th[k]) ? 0.0f : v) * speed;
-            if (ch < 0 && u1 < cum) ch = k;
-        }
-    }
-    if (cum > 1.0f) atomicAdd(&s_cnt[C_VIOL], 1u);
-    if (ch < 0) {
-        atomicAdd(&s_cnt[C_NULL], 1u);
-        return;
-    }
-    atomicAdd(&s_cnt[C_COLL + ch], 1u);
-    const float cos_chi = 1.0f - 2.0f * u01f(r.z);
-    const float phi = 6.283185307179586f * u01f(r.w);
-    const int kind = sc.kind[ch];
-    if (!sc.ion_type) {
-        const float inv = 1.0f / speed;
-        const float dx_ = ux * inv, dy_ = uy * inv, dz_ = uz * inv;
-        float ndx, ndy, ndz;
-        scatter_dir(dx_, dy_, dz_, cos_chi, phi, ndx, ndy, ndz);
-        float enew;
-        if (kind == PIC_XS_ELASTIC) {
-            enew = eps * (1.0f - sc.mr2 * (1.0f - cos_chi));
-        } else if (kind == PIC_XS_EXCITATION) {
-            enew = eps - sc.th[ch];
-        } else {
-            const uint4 r1 = philox10(pid, step, ((uint32_t)s << 24) | 1u, 0u, dc.key0, dc.key1);
-            const uint4 r2 = philox10(pid, step, ((uint32_t)s << 24) | 2u, 0u, dc.key0, dc.key1);
-            const float avail = eps - sc.th[ch];
-            const float eej = u01f(r1.x) * avail;
-            enew = avail - eej;
-            float edx, edy, edz;
-            scatter_dir(dx_, dy_, dz_, 1.0f - 2.0f * u01f(r1.y), 6.283185307179586f * u01f(r1.z), edx, edy,
-                        edz);
-            const float vej = sqrtf(sc.two_e_over_m * eej);
-            float g0, g1, g2, g3;
-            box_muller_f(u01f(r2.x), u01f(r2.y), g0, g1);
-            box_muller_f(u01f(r2.z), u01f(r2.w), g2, g3);
-            Birth x;
-            x.cell = c;
-            x.off = f;
-            x.vx = vej * edx;
-            x.vy = vej * edy;
-            x.vz = vej * edz;
-            x.ivx = sc.vt_gas * g0;
-            x.ivy = sc.vt_gas * g1;
-            x.ivz = sc.vt_gas * g2;
-            if (stage_birth(sink, x)) {
-                lds_deposit(sink.hist, c, f, nc, periodic);
-                if (sink.acc_i) global_deposit(sink.acc_i, c, f, nc, periodic);   // no ions in a swarm
-            } else {
-                atomicOr(&d.diss[b].flags, kFlagCapacity);
-                atomicAdd(&s_cnt[C_DROP], 1u);
-            }
-        }
-        enew = fmaxf(enew, 0.0f);
-        const float vs = sqrtf(sc.two_e_over_m * enew);
-        ux = vs * ndx;
-        uy = vs * ndy;
-        uz = vs * ndz;
-    } else if (kind == PIC_XS_ION_CX) {
-        ux = nvx;
-        uy = nvy;
-        uz = nvz;
-    } else {
-        const float cmx = sc.m_frac * ux + sc.M_frac * nvx;
-        const float cmy = sc.m_frac * uy + sc.M_frac * nvy;
-        const float cmz = sc.m_frac * uz + sc.M_frac * nvz;
-        const float st_ = sqrtf(fmaxf(0.0f, 1.0f - cos_chi * cos_chi));
-        float sp_, cp_;
-        sincosf(phi, &sp_, &cp_);
-        const float gg = sc.M_frac * speed;
-        ux = cmx + gg * cos_chi;
-        uy = cmy + gg * st_ * cp_;
-        uz = cmz + gg * st_ * sp_;
-    }
-}
-
-// velocity moments of a particle at the nodes, fixed point (diagnostics)
+// velocity moments of a particle at the nodes, fixed point (diagnostics);
+// fh and mh are LDS histograms in the push and the discharge's global sums
+// in the events kernel
 __device__ __forceinline__ void moment_diag(const SegConst& sc, unsigned long long* fh, unsigned long long* mh, int c,
                                             float f, float ux, int nc, int periodic)
 {
@@ -414,8 +224,11 @@ __device__ __forceinline__ void moment_diag(const SegConst& sc, unsigned long lo
     atomicAdd(&mh[c1], (unsigned long long)(long long)rintf(f * b2));
 }
 
-__device__ __forceinline__ void electron_diag(const SegConst& sc, const DisConst& dc, const PushArgs& a,
-                                              unsigned long long* ehist, unsigned int* eepf, int c, float f,
+// electron energy at the nodes and in the bulk distribution (diagnostics);
+// CT is the bin counter type (32-bit in LDS, 64-bit in global memory)
+template <typename CT>
+__device__ __forceinline__ void electron_diag(const SegConst& sc, const DisConst& dc, float eepf_inv_bin,
+                                              unsigned long long* ehist, CT* eepf, int c, float f,
                                               float ux, float uy, float uz, int nc, int periodic)
 {
     const float eps = sc.half_m_over_e * (ux * ux + uy * uy + uz * uz);
@@ -424,8 +237,8 @@ __device__ __forceinline__ void electron_diag(const SegConst& sc, const DisConst
     atomicAdd(&ehist[c], (unsigned long long)(w0 * 1048576.0f));
     atomicAdd(&ehist[c1], (unsigned long long)(w1 * 1048576.0f));
     if (c >= dc.bulk_lo && c < dc.bulk_hi) {
-        const int bin = (int)(eps * a.eepf_inv_bin);
-        if ((unsigned)bin < (unsigned)kEepfBins) atomicAdd(&eepf[bin], 1u);
+        const int bin = (int)(eps * eepf_inv_bin);
+        if ((unsigned)bin < (unsigned)kEepfBins) atomicAdd(&eepf[bin], (CT)1);
     }
 }
 
@@ -444,6 +257,56 @@ __device__ __forceinline__ double block_sum_f32(float v, float* s_w)
     return t;
 }
 
+// First tile of every (discharge, species) segment for tiles of T particles,
+// from the device-resident counts (retired discharges get none): s_pref[g]
+// is the first tile of segment g, s_pref[NS] the number of tiles.  Wave 0,
+// up to 16 segments per lane; the caller synchronises.
+__device__ __forceinline__ void tile_prefix(const DevPtrs& d, int T, int32_t* s_pref)
+{
+    const int S = d.S, NS = d.B * d.S;
+    const int lane = threadIdx.x & 63;
+    if ((threadIdx.x >> 6) != 0) return;
+    const int per = (NS + 63) >> 6;
+    const int g0 = lane * per;
+    int32_t run = 0;
+    for (int j = 0; j < per; ++j) {
+        const int g = g0 + j;
+        if (g < NS) {
+            const int64_t n = d.diss[g / S].retired ? 0 : d.segs[g].count;
+            run += (int32_t)((n + T - 1) / T);
+            s_pref[g + 1] = run;
+        }
+    }
+    int32_t incl = run;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        const int32_t o = __shfl_up(incl, dd, 64);
+        if (lane >= dd) incl += o;
+    }
+    const int32_t excl = incl - run;
+    if (lane == 0) s_pref[0] = 0;
+    for (int j = 0; j < per; ++j) {
+        const int g = g0 + j;
+        if (g < NS) s_pref[g + 1] += excl;
+    }
+}
+
+// the segment of tile t: the last g with s_pref[g] <= t
+__device__ __forceinline__ int tile_segment(const int32_t* s_pref, int NS, int32_t t)
+{
+    int lo = 0, hi = NS;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pref[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 }  // namespace
 
 template <int PPT, int BS, bool GENERAL>
@@ -451,7 +314,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 {
     constexpr int kBS = BS;
     constexpr int T = kBS * PPT;
-    constexpr int kBirthsPerTile = T / kBirthsDiv;
+    constexpr int kWavesPerTile = kBS / 64;
     const DevPtrs& d = a.d;
     const int S = d.S, NS = d.B * d.S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -461,50 +324,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     __shared__ unsigned int s_cnt[C_N];
     __shared__ unsigned long long s_wen[2];   // energy carried into each wall by the run (eV, 2^20)
     __shared__ float s_red[kBS / 64];
-    // collisions and births of up to kPair tiles of one segment are handled
-    // in one round (fuller waves on the collision path); the counters
-    // alternate between rounds so that a round's reset never meets the next
-    // round's appends.  The queue holds kQcap candidates (a few per cent of
-    // the particles are candidates); one past it collides where it is found.
-    constexpr int kPair = 8;
-    constexpr int kQcap = T;
-    constexpr int kSink = GENERAL ? kBirthsPerTile : 1;
-    __shared__ Birth s_bb[kPair * kSink];     // births of the round's tiles, kSink per tile
-    __shared__ uint32_t s_bkey[kPair * kSink];
-    __shared__ unsigned int s_bn[2 * kPair];  // their counts: [round parity][tile of the round]
-    __shared__ CollQ s_q[GENERAL ? kQcap : 1];       // collision candidates of the round
-    __shared__ unsigned int s_nq[2];          // their count, by round parity
 
-    // ---- tiles per segment, prefix over the segments (up to 16 per lane) -----
-    if (wid == 0) {
-        const int per = (NS + 63) >> 6;
-        const int g0 = lane * per;
-        int32_t run = 0;
-        for (int j = 0; j < per; ++j) {
-            const int g = g0 + j;
-            if (g < NS) {
-                const int64_t n = d.diss[g / S].retired ? 0 : d.segs[g].count;
-                run += (int32_t)((n + T - 1) / T);
-                s_pref[g + 1] = run;
-            }
-        }
-        int32_t incl = run;
-#pragma unroll
-        for (int dd = 1; dd < 64; dd <<= 1) {
-            const int32_t o = __shfl_up(incl, dd, 64);
-            if (lane >= dd) incl += o;
-        }
-        const int32_t excl = incl - run;
-        if (lane == 0) s_pref[0] = 0;
-        for (int j = 0; j < per; ++j) {
-            const int g = g0 + j;
-            if (g < NS) s_pref[g + 1] += excl;
-        }
-    }
+    tile_prefix(d, T, s_pref);
     if (tid < C_N) s_cnt[tid] = 0;
     if (tid < 2) s_wen[tid] = 0ull;
-    if (tid < 2 * kPair) s_bn[tid] = 0u;
-    if (tid < 2) s_nq[tid] = 0u;
     __syncthreads();
     const int32_t NT = s_pref[NS];
 
@@ -521,8 +344,6 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 
     int cur_g = -1, cur_b = -1;
     int32_t run_first = 0;
-    int rp = 0, npend = 0;                    // round parity, tiles of the open round
-    int32_t pend_t0 = 0, pend_tin0 = 0;       // the round's first tile (global, in its segment)
     float ke_run = 0.0f;
     // a fixed contiguous range of tiles per workgroup
     const int32_t chunk = (NT + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
@@ -584,13 +405,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     };
 
     for (int32_t t = t_begin; t < t_end; ++t) {
-        // segment of tile t: the last g with s_pref[g] <= t
-        int lo = 0, hi = NS;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_pref[mid] <= t) lo = mid; else hi = mid;
-        }
-        const int sg = lo;
+        const int sg = tile_segment(s_pref, NS, t);
         const int b = sg / S, s = sg - b * S;
         const DisConst& dc = d.disc[b];
         if (sg != cur_g) {
@@ -642,70 +457,46 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 #pragma unroll
             for (int j = 0; j < PPT; ++j) pid[j] = 0u;
         }
+        // axial renewal: the displacement along the third axis since
+        // injection, summed in FP64 (a slow ion adds only a few binary32
+        // spacings of z per step, so a binary32 sum would drift)
+        const bool renews = GENERAL && sc.renew_lz > 0.0;
+        double zax[PPT];
+        if (renews) {
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) zax[j] = sc.z[io][base + j];
+        }
 
-        BirthSink sink;
-        sink.b = s_bb + npend * kSink;
-        sink.key = s_bkey + npend * kSink;
-        sink.n = &s_bn[rp * kPair + npend];
-        sink.cap = kBirthsPerTile;
-        sink.hist = hist;
-        sink.acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
-        sink.acc_i = S > 1 ? d.acc + ((size_t)b * S + 1) * kRep * d.nodes_max : nullptr;
+        uint32_t evw[PPT];
         float ke_tile = 0.0f;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
+            evw[j] = 0u;
             if (base + j >= n) continue;
             if (GENERAL && cell[j] < 0) continue;          // a hole: absorbed earlier
-            sink.pkey = (uint32_t)(tid * PPT + j);
-            bool cand = false;
             const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, s_wen, cell[j], off[j], vx[j],
-                                               vy[j], vz[j], pid[j], ke_tile, sink, cand);
-            if (GENERAL && keep && sc.renew_lz > 0.0f) {
-                // axial transit: displacement along the third axis since
-                // injection; past L_z, a fresh velocity from the species'
-                // initial distribution (call 6) at the same x
-                float* zp = sc.z[io] + base + j;
-                float zz = *zp + vz[j] * sc.dt_f;
-                if (fabsf(zz) >= sc.renew_lz) {
-                    const uint4 r6 = philox10(pid[j], step, ((uint32_t)s << 24) | 6u, 0u, dc.key0, dc.key1);
-                    float g0, g1, g2, g3;
-                    box_muller_f(u01f(r6.x), u01f(r6.y), g0, g1);
-                    box_muller_f(u01f(r6.z), u01f(r6.w), g2, g3);
-                    vx[j] = sc.drift0[0] + sc.vth0 * g0;
-                    vy[j] = sc.drift0[1] + sc.vth0 * g1;
-                    vz[j] = sc.drift0[2] + sc.vth0 * g2;
-                    zz = 0.0f;
+                                               vy[j], vz[j], pid[j], ke_tile, evw[j]);
+            if (renews && keep) {
+                // past L_z the particle gets a fresh velocity from its
+                // species' initial distribution at the same x (events kernel)
+                const double zz = zax[j] + (double)vz[j] * sc.dt_d;
+                if (fabs(zz) >= sc.renew_lz) {
+                    evw[j] |= kEvRenew;
+                    zax[j] = 0.0;
                     atomicAdd(&s_cnt[C_REN], 1u);
+                } else {
+                    zax[j] = zz;
                 }
-                *zp = zz;
             }
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
-                const unsigned int q = (GENERAL && cand) ? atomicAdd(&s_nq[rp], 1u) : 0u;
-                if (GENERAL && cand && q >= (unsigned)kQcap) {
-                    // the round's queue is full: the collision happens here
-                    collide_particle(d, sc, dc, s, b, step, s_cnt, cell[j], off[j], vx[j], vy[j], vz[j], pid[j],
-                                     sink);
-                    if (a.diag) {
-                        moment_diag(sc, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
-                        if (s == 0)
-                            electron_diag(sc, dc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc,
-                                          periodic);
-                    }
-                } else if (GENERAL && cand) {
-                    CollQ e;
-                    e.key = sink.pkey | ((uint32_t)npend << 16);   // slot in the tile, tile of the round
-                    e.c = cell[j];
-                    e.f = off[j];
-                    e.ux = vx[j];
-                    e.uy = vy[j];
-                    e.uz = vz[j];
-                    e.pid = pid[j];
-                    s_q[q] = e;
-                } else if (a.diag) {
+                // a particle whose velocity the events kernel changes is
+                // sampled there
+                if (a.diag && !(evw[j] & (kEvCand | kEvRenew))) {
                     moment_diag(sc, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
                     if (s == 0)
-                        electron_diag(sc, dc, a, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j], nc, periodic);
+                        electron_diag(sc, dc, a.eepf_inv_bin, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j],
+                                      nc, periodic);
                 }
             } else {
                 cell[j] = -1;                              // absorbed: leaves a hole
@@ -732,71 +523,422 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 }
             }
         }
+        if (renews) {
+#pragma unroll
+            for (int j = 0; j < PPT; ++j)
+                if (base + j < n) sc.z[io][base + j] = zax[j];
+        }
+        if (GENERAL) {
+            // this wave's events, in slot order: lanes in order, a lane's
+            // particles in order (ballots and lane counts, no barrier)
+            uint32_t below = 0, total = 0;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const uint64_t m = __ballot(evw[j] != 0u);
+                below += lanes_below(m);
+                total += (uint32_t)__popcll(m);
+            }
+            uint32_t* evp = d.ev + (size_t)t * T + (size_t)wid * 64 * PPT;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                if (evw[j]) evp[below++] = evw[j] | (uint32_t)(tid * PPT + j);
+            }
+            if (lane == 0) d.evc[(size_t)t * kWavesPerTile + wid] = total;
+        }
         if (tid == 0 && tin == ntiles - 1) {
             st.tile_first = tile_first;
             st.ntiles = ntiles;
         }
-        if (GENERAL) {
-            if (npend == 0) {
-                pend_t0 = t;
-                pend_tin0 = tin;
-            }
-            ++npend;
-            if (npend == kPair || tin == ntiles - 1 || t + 1 == t_end) {
-                // the round's collisions together, with full lanes (a
-                // candidate in the main loop would stall its whole wave on the
-                // collision path); the new velocities overwrite the ones
-                // stored above.  The round's tiles are consecutive.
-                __threadfence_block();
-                __syncthreads();
-                const unsigned int nq = s_nq[rp] < (unsigned)kQcap ? s_nq[rp] : (unsigned)kQcap;
-                for (unsigned int q = tid; q < nq; q += kBS) {
-                    CollQ e = s_q[q];
-                    const int pos = (int)(e.key >> 16);
-                    BirthSink qs = sink;
-                    qs.b = s_bb + pos * kSink;
-                    qs.key = s_bkey + pos * kSink;
-                    qs.n = &s_bn[rp * kPair + pos];
-                    qs.pkey = e.key & 0xffffu;
-                    collide_particle(d, sc, dc, s, b, step, s_cnt, e.c, e.f, e.ux, e.uy, e.uz, e.pid, qs);
-                    const int64_t slot = (int64_t)(pend_tin0 + pos) * T + qs.pkey;
-                    sc.vx[io][slot] = e.ux;
-                    sc.vy[io][slot] = e.uy;
-                    sc.vz[io][slot] = e.uz;
-                    if (a.diag) {
-                        moment_diag(sc, fhist, mhist, e.c, e.f, e.ux, nc, periodic);
-                        if (s == 0) electron_diag(sc, dc, a, ehist, eepf, e.c, e.f, e.ux, e.uy, e.uz, nc, periodic);
-                    }
-                }
-                __syncthreads();
-                // each tile's births in the order of their parents' slots
-                for (int pos = 0; pos < npend; ++pos) {
-                    const unsigned int nst = s_bn[rp * kPair + pos];
-                    const int nb = nst < (unsigned)kBirthsPerTile ? (int)nst : kBirthsPerTile;
-                    const uint32_t* keys = s_bkey + pos * kSink;
-                    const int32_t tt = pend_t0 + pos;
-                    if (tid < nb) {
-                        const uint32_t k = keys[tid];
-                        int rank = 0;
-                        for (int i = 0; i < nb; ++i) rank += keys[i] < k;
-                        d.births[(size_t)tt * kBirthsPerTile + rank] = s_bb[pos * kSink + tid];
-                    }
-                    if (tid == 0) {
-                        d.bcnt[tt] = nb;
-                        if (nb) atomicAdd(reinterpret_cast<unsigned long long*>(&st.staged), (unsigned long long)nb);
-                    }
-                }
-                __syncthreads();                  // the staged births are read
-                if (tid == 0) {                   // free for the round after next
-                    for (int pos = 0; pos < kPair; ++pos) s_bn[rp * kPair + pos] = 0u;
-                    s_nq[rp] = 0u;
-                }
-                rp ^= 1;
-                npend = 0;
-            }
-        }
+        if (GENERAL && tid == 0) d.bcnt[t] = 0;   // the events kernel counts this tile's births
     }
     if (cur_g >= 0) flush(cur_g);
+    if (GENERAL) {
+        // the events of this workgroup's tile range, in unit order (a unit is
+        // one wave's list of one tile): each unit's exclusive prefix within the
+        // range, the unit holding every 64th event of the range, the range's
+        // total -- the events kernel's index, built where the counts are hot
+        __shared__ uint32_t s_sc[kBS / 64];
+        const int64_t u_begin = (int64_t)t_begin * kWavesPerTile;
+        const int64_t u_end = t_begin < t_end ? (int64_t)t_end * kWavesPerTile : u_begin;
+        uint32_t* ev_idx = d.evidx + (size_t)t_begin * T / 64;
+        uint32_t run = 0;
+        __syncthreads();                          // this workgroup's counts are written
+        for (int64_t r = u_begin; r < u_end; r += kBS) {
+            const int64_t u = r + tid;
+            const uint32_t c = u < u_end ? d.evc[u] : 0u;
+            const uint32_t incl = wave_incl_scan_u32(c);
+            if (lane == 63) s_sc[wid] = incl;
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
+#pragma unroll
+            for (int k = 0; k < kBS / 64; ++k) {
+                const uint32_t v = s_sc[k];
+                if (k < wid) before += v;
+                tot += v;
+            }
+            if (u < u_end) {
+                const uint32_t p0 = run + before + incl - c;
+                d.evp[u] = p0;
+                for (uint32_t k = (p0 + 63u) >> 6; c > 0 && (k << 6) < p0 + c; ++k) ev_idx[k] = (uint32_t)(u - u_begin);
+            }
+            run += tot;
+            __syncthreads();                      // s_sc is rewritten
+        }
+        if (tid == 0) d.evg[blockIdx.x] = run;
+    }
+}
+
+namespace {
+
+// The collision of a candidate, in FP64: the energy (electrons: target at
+// rest; ions: relative to a neutral drawn from the gas), the channel by the
+// running sum of the tabulated frequencies against the second word of the
+// first draw, then the kinematics of the channel.  Returns the channel (-1:
+// null collision); `viol` says whether the summed frequency exceeded the
+// bound, `born` whether an ionization filled `bb` (the ejected electron and
+// the new ion at the parent's position).
+__device__ __forceinline__ int collide_particle(const SegConst& sc, const DisConst& dc, int s, uint32_t step, int c,
+                                                float f, double& ux, double& uy, double& uz, uint32_t pid, Birth& bb,
+                                                bool& viol, bool& born)
+{
+    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
+    double speed, eps;
+    double nvx = 0.0, nvy = 0.0, nvz = 0.0;
+    if (!sc.ion_type) {
+        const double v2 = ux * ux + uy * uy + uz * uz;
+        speed = sqrt(v2);
+        eps = sc.half_m_over_e_d * v2;
+    } else {
+        const uint4 r3 = philox10(pid, step, ((uint32_t)s << 24) | 3u, 0u, dc.key0, dc.key1);
+        double g0, g1, g2, g3;
+        box_muller_d(u01d(r3.x), u01d(r3.y), g0, g1);
+        box_muller_d(u01d(r3.z), u01d(r3.w), g2, g3);
+        nvx = sc.vt_gas * g0;
+        nvy = sc.vt_gas * g1;
+        nvz = sc.vt_gas * g2;
+        const double gx = ux - nvx, gy = uy - nvy, gz = uz - nvz;
+        const double g2s = gx * gx + gy * gy + gz * gz;
+        speed = sqrt(g2s);
+        eps = sc.half_m_over_e_d * g2s;
+    }
+    // channel: the first k whose running sum of n_g sigma_k g / nu_max passes
+    // u1, one pass over the table row (the full sum checks the bound)
+    const double u1 = u01d(r.y);
+    double cum = 0.0;
+    int ch = -1;
+    {
+        const double lx = (log(fmax(eps, 1e-300)) - sc.xs_ln0) * sc.xs_inv_dln;
+        int i;
+        double fr;
+        if (!(lx > 0.0)) {
+            i = 0;
+            fr = 0.0;
+        } else if (lx >= (double)(sc.xs_n - 1)) {
+            i = sc.xs_n - 2;
+            fr = 1.0;
+        } else {
+            i = (int)lx;
+            if (i > sc.xs_n - 2) i = sc.xs_n - 2;
+            fr = lx - (double)i;
+        }
+        const double* r0 = sc.xs + (size_t)i * sc.nch;
+        const double* r1 = r0 + sc.nch;
+        for (int k = 0; k < sc.nch; ++k) {
+            const double v = r0[k] + fr * (r1[k] - r0[k]);
+            cum += ((eps < sc.th[k]) ? 0.0 : v) * speed;
+            if (ch < 0 && u1 < cum) ch = k;
+        }
+    }
+    viol = cum > 1.0;
+    born = false;
+    if (ch < 0) return -1;
+    const double cos_chi = 1.0 - 2.0 * u01d(r.z);
+    const double u_phi = u01d(r.w);           // azimuth 2 pi u_phi
+    const int kind = sc.kind[ch];
+    if (!sc.ion_type) {
+        const double inv = 1.0 / speed;
+        const double dx_ = ux * inv, dy_ = uy * inv, dz_ = uz * inv;
+        double ndx, ndy, ndz;
+        scatter_dir_d(dx_, dy_, dz_, cos_chi, u_phi, ndx, ndy, ndz);
+        double enew;
+        if (kind == PIC_XS_ELASTIC) {
+            enew = eps * (1.0 - sc.mr2 * (1.0 - cos_chi));
+        } else if (kind == PIC_XS_EXCITATION) {
+            enew = eps - sc.th[ch];
+        } else {
+            const uint4 r1 = philox10(pid, step, ((uint32_t)s << 24) | 1u, 0u, dc.key0, dc.key1);
+            const uint4 r2 = philox10(pid, step, ((uint32_t)s << 24) | 2u, 0u, dc.key0, dc.key1);
+            const double avail = eps - sc.th[ch];
+            const double eej = u01d(r1.x) * avail;
+            enew = avail - eej;
+            double edx, edy, edz;
+            scatter_dir_d(dx_, dy_, dz_, 1.0 - 2.0 * u01d(r1.y), u01d(r1.z), edx, edy, edz);
+            const double vej = sqrt(sc.two_e_over_m * eej);
+            double g0, g1, g2, g3;
+            box_muller_d(u01d(r2.x), u01d(r2.y), g0, g1);
+            box_muller_d(u01d(r2.z), u01d(r2.w), g2, g3);
+            bb.cell = c;
+            bb.off = f;
+            bb.vx = (float)(vej * edx);
+            bb.vy = (float)(vej * edy);
+            bb.vz = (float)(vej * edz);
+            bb.ivx = (float)(sc.vt_gas * g0);
+            bb.ivy = (float)(sc.vt_gas * g1);
+            bb.ivz = (float)(sc.vt_gas * g2);
+            born = true;
+        }
+        enew = fmax(enew, 0.0);
+        const double vs = sqrt(sc.two_e_over_m * enew);
+        ux = vs * ndx;
+        uy = vs * ndy;
+        uz = vs * ndz;
+    } else if (kind == PIC_XS_ION_CX) {
+        ux = nvx;
+        uy = nvy;
+        uz = nvz;
+    } else {
+        const double cmx = sc.m_frac * ux + sc.M_frac * nvx;
+        const double cmy = sc.m_frac * uy + sc.M_frac * nvy;
+        const double cmz = sc.m_frac * uz + sc.M_frac * nvz;
+        const double st_ = sqrt(fmax(0.0, 1.0 - cos_chi * cos_chi));
+        double sp_, cp_;
+        sincospi(2.0 * u_phi, &sp_, &cp_);
+        const double gg = sc.M_frac * speed;
+        ux = cmx + gg * cos_chi;
+        uy = cmy + gg * st_ * cp_;
+        uz = cmz + gg * st_ * sp_;
+    }
+    return ch;
+}
+
+// The secondary electron of an ion absorbed at `wall`, in FP64: emitted with
+// probability gamma (integer test on the draw), normal speed from the
+// flux-weighted half-Maxwellian, tangential components Maxwellian, placed
+// u v_n dt into the gap.  Returns 1 with `bb` filled when one is placed,
+// -1 when one is emitted but lands beyond the gap, 0 when none is emitted.
+__device__ __forceinline__ int secondary(const SegConst& sc, const DisConst& dc, int s, uint32_t step, int wall,
+                                         uint32_t pid, Birth& bb)
+{
+    const uint4 r4 = philox10(pid, step, ((uint32_t)s << 24) | 4u, 0u, dc.key0, dc.key1);
+    if (!(odd24(r4.x) < sc.see_k)) return 0;
+    const uint4 r5 = philox10(pid, step, ((uint32_t)s << 24) | 5u, 0u, dc.key0, dc.key1);
+    const int nc = dc.n_cells;
+    const double vn = sc.vsee * sqrt(-2.0 * log(u01d(r4.y)));
+    const double adv = u01d(r4.z) * vn * sc.dtdx_e;         // cells
+    double g0, g1;
+    box_muller_d(u01d(r5.x), u01d(r5.y), g0, g1);
+    if (!(adv < (double)nc)) return -1;
+    const double pos = wall == 0 ? adv : (double)nc - adv;   // cells from x = 0
+    const double cf = floor(pos);
+    int cell = (int)cf;
+    float off = (float)(pos - cf);
+    if (off >= 1.0f) {                   // the edge rule
+        off -= 1.0f;
+        cell += 1;
+    }
+    if (cell >= nc) {                    // within rounding of x = L: the last representable offset
+        cell = nc - 1;
+        off = 0x1.fffffep-1f;
+    }
+    if (cell < 0) return -1;
+    bb.cell = cell;
+    bb.off = off;
+    bb.vx = (float)(wall == 0 ? vn : -vn);
+    bb.vy = (float)(sc.vsee * g0);
+    bb.vz = (float)(sc.vsee * g1);
+    bb.ivx = bb.ivy = bb.ivz = 0.0f;
+    return 1;
+}
+
+__device__ __forceinline__ uint32_t popc_ballot(bool p) { return (uint32_t)__popcll(__ballot(p)); }
+
+}  // namespace
+
+// The events of a step, after the push: chunks of 64 consecutive events of
+// one push workgroup's range (in unit order: tiles, waves, slots), fully
+// packed but for the last of each range, strided over all the waves of the
+// grid.  Each lane one event: the renewal
+// (a fresh velocity from the species' initial distribution, call 6), the
+// collision of a candidate, or the secondary-emission test of an absorbed
+// ion, all in FP64, with the new velocity rounded to binary32 once and
+// written to the particle's slot, and the diagnostics of the particle's
+// final velocity.  A birth (ionization pair, secondary electron) claims a
+// slot of its tile's staging area with an atomic and carries its parent's
+// slot, by which the finalize orders the tile's births; its charge goes
+// straight into the discharge's fixed-point sums.  Counters come from
+// ballots, per segment of the chunk.
+template <int BS>
+__global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
+{
+    const DevPtrs& d = a.d;
+    const int S = d.S, NS = d.B * d.S;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int kW = BS / 64;
+    __shared__ int32_t s_pref[kMaxSeg + 1];
+    __shared__ uint32_t s_cp[kMaxPushGrid + 1];   // chunks of the push workgroups before each
+    __shared__ uint32_t s_w[kW];
+    tile_prefix(d, a.T, s_pref);
+    const int G = a.push_grid;
+    uint32_t run = 0;
+    for (int r = 0; r < G; r += BS) {
+        const int g = r + tid;
+        const uint32_t c = g < G ? (d.evg[g] + 63u) >> 6 : 0u;
+        const uint32_t incl = wave_incl_scan_u32(c);
+        if (lane == 63) s_w[wid] = incl;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) {
+            const uint32_t v = s_w[k];
+            if (k < wid) before += v;
+            tot += v;
+        }
+        if (g < G) s_cp[g] = run + before + incl - c;
+        run += tot;
+        __syncthreads();
+    }
+    if (tid == 0) s_cp[G] = run;
+    __syncthreads();
+    const int32_t NT = s_pref[NS];
+    const int32_t chunk_t = (NT + G - 1) / G;     // the push workgroups' tile ranges
+    const int W = a.waves;
+    const uint32_t bpt = (uint32_t)a.births_per_tile;
+    const uint32_t nchunk = s_cp[G];
+    const uint32_t stride = gridDim.x * kW;
+
+    for (uint32_t ck = blockIdx.x * kW + wid; ck < nchunk; ck += stride) {
+        // the push workgroup of chunk ck: the last g with s_cp[g] <= ck
+        int glo = 0, ghi = G;
+        while (ghi - glo > 1) {
+            const int mid = (glo + ghi) >> 1;
+            if (s_cp[mid] <= ck) glo = mid; else ghi = mid;
+        }
+        const int g = glo;
+        const uint32_t kc = ck - s_cp[g];
+        const uint32_t e = (kc << 6) + (uint32_t)lane;       // event of the range
+        const bool act = e < d.evg[g];
+        const int32_t t_begin = g * chunk_t;
+        const int32_t t_end = t_begin + chunk_t < NT ? t_begin + chunk_t : NT;
+        const int64_t u_end = (int64_t)t_end * W;
+        // the unit of event e: the last unit whose prefix is <= e, searched
+        // in windows of 64 units from the one holding the chunk's first event
+        int64_t ub = (int64_t)t_begin * W + d.evidx[(size_t)t_begin * a.T / 64 + kc];
+        int64_t unit = -1;
+        for (;;) {
+            const int64_t uj = ub + lane;
+            const uint32_t pj = uj < u_end ? d.evp[uj] : 0xffffffffu;
+            const uint32_t pend = ub + 64 < u_end ? d.evp[ub + 64] : 0xffffffffu;
+            // the last window entry <= e (lanes 0..63 hold the prefixes, in
+            // order; entry 0 is <= e), by binary lifting with whole-wave shuffles
+            int lo = 0;
+#pragma unroll
+            for (int h = 32; h >= 1; h >>= 1) {
+                const uint32_t pm = (uint32_t)__shfl((int)pj, lo + h, 64);
+                if (pm <= e) lo += h;
+            }
+            const bool found = !act || e < pend;
+            if (act && found && unit < 0) unit = ub + lo;
+            if (__ballot(!found) == 0ull) break;
+            ub += 64;                     // past 64 units that are all empty or earlier
+        }
+        bool hb = false, see = false, cand = false, viol = false, lost = false;
+        int wall = 0, ch = -1, sg = -1;
+        if (act) {
+            const int32_t t = (int32_t)(unit / W);
+            const int w = (int)(unit - (int64_t)t * W);
+            const uint32_t idx = e - d.evp[unit];   // both relative to the range
+            const uint32_t word = d.ev[(size_t)t * a.T + (size_t)w * 64 * a.ppt + idx];
+            sg = tile_segment(s_pref, NS, t);
+            const int b = sg / S, s = sg - b * S;
+            const DisConst& dc = d.disc[b];
+            const SegConst& sc = d.segc[sg];
+            const int32_t tin = t - s_pref[sg];
+            const int io = d.segs[sg].parity;
+            const uint32_t step = (uint32_t)d.diss[b].step;
+            const int nc = dc.n_cells;
+            const int periodic = dc.bc == PIC_BC_PERIODIC;
+            const uint32_t key = word & kEvSlot;
+            const int64_t slot = (int64_t)tin * a.T + key;
+            const uint32_t pid = sc.id[io][slot];
+            Birth bb;
+            if (word & kEvSee) {
+                see = true;
+                wall = (word & kEvWall1) ? 1 : 0;
+                const int r = secondary(sc, dc, s, step, wall, pid, bb);
+                hb = r > 0;
+                lost = r < 0;
+            } else {
+                const int c = sc.cell[io][slot];
+                const float f = sc.off[io][slot];
+                double ux = sc.vx[io][slot], uy = sc.vy[io][slot], uz = sc.vz[io][slot];
+                if (word & kEvRenew) {
+                    const uint4 r6 = philox10(pid, step, ((uint32_t)s << 24) | 6u, 0u, dc.key0, dc.key1);
+                    double g0, g1, g2, g3;
+                    box_muller_d(u01d(r6.x), u01d(r6.y), g0, g1);
+                    box_muller_d(u01d(r6.z), u01d(r6.w), g2, g3);
+                    ux = sc.drift0[0] + sc.vth0 * g0;
+                    uy = sc.drift0[1] + sc.vth0 * g1;
+                    uz = sc.drift0[2] + sc.vth0 * g2;
+                }
+                if (word & kEvCand) {
+                    cand = true;
+                    ch = collide_particle(sc, dc, s, step, c, f, ux, uy, uz, pid, bb, viol, hb);
+                }
+                const float fx = (float)ux, fy = (float)uy, fz = (float)uz;
+                sc.vx[io][slot] = fx;
+                sc.vy[io][slot] = fy;
+                sc.vz[io][slot] = fz;
+                if (a.diag) {
+                    unsigned long long* fh = d.macc + (size_t)sg * 2 * d.nodes_max;
+                    moment_diag(sc, fh, fh + d.nodes_max, c, f, fx, nc, periodic);
+                    if (s == 0)
+                        electron_diag(sc, dc, a.eepf_inv_bin, d.eacc + (size_t)b * d.nodes_max,
+                                      d.eepf + (size_t)b * 2 * kEepfBins, c, f, fx, fy, fz, nc, periodic);
+                }
+            }
+            if (hb) {
+                const uint32_t pos = atomicAdd(reinterpret_cast<uint32_t*>(&d.bcnt[t]), 1u);
+                if (pos < bpt) {
+                    bb.key = key;
+                    d.births[(size_t)t * bpt + pos] = bb;
+                    unsigned long long* acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
+                    global_deposit(acc_e, bb.cell, bb.off, nc, periodic);
+                    if (!see && S > 1)          // no ions in a swarm
+                        global_deposit(d.acc + ((size_t)b * S + 1) * kRep * d.nodes_max, bb.cell, bb.off, nc,
+                                       periodic);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[sg].staged), 1ull);
+                } else {
+                    hb = false;
+                    lost = true;
+                    atomicOr(&d.diss[b].flags, kFlagCapacity);
+                }
+            }
+        }
+        // counters of the chunk, one segment at a time (a chunk spans more
+        // than one only at a segment's end): lane i holds counter i
+        uint64_t todo = __ballot(act);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int lsg = __shfl(sg, leader, 64);
+            const bool mine = act && sg == lsg;
+            uint32_t cnt_lane = 0u;
+            auto count = [&](int i, bool p) {
+                const uint32_t v = popc_ballot(mine && p);
+                cnt_lane += lane == i ? v : 0u;
+            };
+            count(C_CAND, cand);
+            count(C_NULL, cand && ch < 0);
+            count(C_VIOL, viol);
+            const int nch = d.segc[lsg].nch;
+            for (int k = 0; k < nch; ++k) count(C_COLL + k, ch == k);
+            count(C_SEE0, hb && see && wall == 0);
+            count(C_SEE1, hb && see && wall == 1);
+            count(C_DROP, lost);
+            if (lane < C_N && cnt_lane)
+                atomicAdd(&d.cnt[((size_t)lsg * kRep) * C_N + lane], (unsigned long long)cnt_lane);
+            todo &= ~__ballot(mine);
+        }
+    }
 }
 
 #define PIC_KERNELS(X)   \
@@ -807,7 +949,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     X(4, 512, false)     \
     X(4, 1024, false)    \
     X(1, 256, true)      \
-    X(2, 256, true)
+    X(2, 256, true)      \
+    X(4, 256, true)      \
+    X(4, 512, true)      \
+    X(4, 1024, true)
 
 #define PIC_INST(P, B, G) template __global__ void push_kernel<P, B, G>(PushArgs);
 PIC_KERNELS(PIC_INST)
@@ -822,15 +967,10 @@ size_t push_lds_bytes(int n_nodes, int n_cells, int diag)
     return b;
 }
 
-// nearest instantiated shape: general kernels run 256 threads and PPT <= 2;
-// streaming kernels accept the shapes listed above
+// nearest instantiated shape (general kernels: up to four particles per
+// thread)
 void push_shape(int& ppt, int& threads, bool general)
 {
-    if (general) {                // the collision path holds many registers: two per thread at most
-        threads = 256;
-        ppt = ppt >= 2 ? 2 : 1;
-        return;
-    }
     if (threads >= 1024) {
         threads = 1024;
         ppt = 4;
@@ -840,6 +980,7 @@ void push_shape(int& ppt, int& threads, bool general)
     } else {
         threads = 256;
         ppt = ppt >= 8 ? 8 : (ppt >= 4 ? 4 : (ppt >= 2 ? 2 : 1));
+        if (general && ppt > 4) ppt = 4;
     }
 }
 
@@ -868,6 +1009,23 @@ int push_occupancy(int ppt, int threads, bool general, size_t lds)
     }
     PIC_KERNELS(PIC_OCC)
 #undef PIC_OCC
+    return nb > 0 ? nb : 1;
+}
+
+template __global__ void events_kernel<kEvThreads>(EvArgs);
+
+hipError_t launch_events(const EvArgs& a, int64_t grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((events_kernel<kEvThreads>), dim3((unsigned)grid), dim3(kEvThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+int events_occupancy()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(events_kernel<kEvThreads>),
+                                                     kEvThreads, 0) != hipSuccess)
+        nb = 0;
     return nb > 0 ? nb : 1;
 }
 

@@ -16,7 +16,7 @@ class FakeSim:
         self.applied, self.stepped = [], 0
 
     def counts(self, b):
-        return dict(count=[1000] * self.S, step=0, flags=0)
+        return dict(count=[1000] * self.S, step=0, flags=0, next_id=[1000 + 10 * self.stepped] * self.S)
 
     def config_tiles(self, ppt, threads, sort_every, compact_every):
         self.applied.append((ppt, threads, sort_every, compact_every))
@@ -34,8 +34,10 @@ def fake_timer(sim, n):
 def test_candidates_by_kernel_mode():
     g = autotune.candidates(True)
     s = autotune.candidates(False)
-    assert all(c["threads"] == 256 and c["ppt"] <= 2 for c in g)
+    assert {(c["ppt"], c["threads"]) for c in g} == set(autotune.GENERAL)
     assert {c["compact_every"] for c in g} == set(autotune.COMPACT_EVERY)
+    # a captured graph replays 32 steps: every compaction interval divides it
+    assert all(32 % c["compact_every"] == 0 for c in g)
     assert {(c["ppt"], c["threads"]) for c in s} == set(autotune.STREAMING)
     # births take ids in their parents' order, so a sort would change the
     # random numbers of a run with births: no sort in the general kernel
@@ -77,3 +79,20 @@ def test_tuned_run_reaches_the_untuned_state():
         for k in ("cell", "off", "vx", "vy", "vz", "id"):
             assert np.array_equal(pa[k][ia], pb[k][ib]), k
     np.testing.assert_array_equal(a.rho(), b.rho())
+
+
+def test_compaction_interval_needs_capacity_headroom():
+    # 1000 slots in use and 10 births per step: with capacity 1500 (90 %:
+    # 1350) a compaction every 8 or 16 steps fits (1160, 1320 slots at twice
+    # the birth rate), every 32 steps does not (1640)
+    cfg, _ = W.argon_rf(n_init=1000), None
+    for sp in cfg["species"]:
+        sp["capacity"] = 1500
+    sim = FakeSim(cfg)
+    rate = autotune.birth_rate(sim, steps=4)
+    assert rate[(0, 0)] == 10.0
+    assert autotune.fits(sim, 8, rate) and autotune.fits(sim, 16, rate)
+    assert not autotune.fits(sim, 32, rate)
+    choice, table = autotune.tune(sim, steps=4, warm=0, timer=fake_timer)
+    assert {r["compact_every"] for r in table} == {8, 16}
+    assert choice["compact_every"] in (8, 16)

@@ -68,25 +68,25 @@ def test_ragged_counts_every_tile_shape(pic, n):
 @pytest.mark.parametrize("n", [1, 301, 2049])
 def test_ragged_counts_general_kernel(pic, n):
     # the general kernel (walls, collisions, secondaries) with tiny and
-    # ragged counts, both of its tile shapes; births, losses and their order
-    # agree exactly, kinematics to binary32 rounding (at most one particle
-    # per species may differ by a collision decided on the other side of
-    # a rounding edge)
-    for ppt in (1, 2):
+    # ragged counts, every tile shape; births, losses and their order agree
+    # exactly, kinematics to binary32 rounding (at most one particle per
+    # species may differ by a collision decided on the other side of a
+    # rounding edge)
+    for ppt, thr in ((1, 256), (2, 256), (4, 256), (4, 512), (4, 1024)):
         cfg, tabs = small_argon(n_init=n)
         cfg["species"][0]["capacity"] = cfg["species"][1]["capacity"] = 8 * n + 64
         sim = pic.Sim(cfg, tabs)
-        sim.config_tiles(ppt, 256, 0)
+        sim.config_tiles(ppt, thr, 0)
         sim.step(5)
         o = to_oracle(sim, cfg, tabs)
         sim.step(1)
         o.step(1)
         for s in range(2):
             pg, po = sim.get_particles(s), o.get_particles(s)
-            assert np.array_equal(pg["id"], po["id"]), (n, ppt, s)
+            assert np.array_equal(pg["id"], po["id"]), (n, ppt, thr, s)
             r = compare_species(pg, po, cfg, cfg["species"][s]["vth"] or 1.0)
             bad = (r["rel_v"] >= 1e-6) | (r["dx"] >= 1e-6 * cfg["length"])
-            assert r["cell_mismatch"] <= 1 and bad.sum() <= 1, (n, ppt, s, int(bad.sum()))
+            assert r["cell_mismatch"] <= 1 and bad.sum() <= 1, (n, ppt, thr, s, int(bad.sum()))
         sim.close()
 
 
@@ -147,13 +147,10 @@ def test_meshes_and_batches_refused(pic):
 
 def test_dense_gas_many_collisions(pic):
     # at 3 Torr three quarters of the electrons are collision candidates in
-    # every step and about a fifth collide (the queues of the collision
-    # rounds run full): one step from identical states against the oracle.
-    # Births, losses and order agree exactly; a collided electron's new
-    # velocity carries the FP32 rounding of its kinematics (the scattering
-    # rotation through sqrt(1 - cos^2) and sincos, the energy loss), a few
-    # 1e-6 and up to some 1e-5 relative, so every particle agrees to 1e-4 and
-    # all but those collided ones to 1e-6
+    # every step and about a fifth collide: one step from identical states
+    # against the oracle.  Births, losses and order agree exactly; the
+    # collision kinematics run in FP64 and round once, so every particle,
+    # collided or not, agrees to 1e-6
     cfg, tabs = small_argon(n_init=20000)
     dense = W.argon_rf(n_init=20000, pressure_mtorr=3000.0, weight=cfg["species"][0]["weight"],
                        capacity=cfg["species"][0]["capacity"])
@@ -170,5 +167,5 @@ def test_dense_gas_many_collisions(pic):
         assert np.array_equal(pg["id"], po["id"]), s
         r = compare_species(pg, po, dense, dense["species"][s]["vth"] or 1.0)
         assert r["cell_mismatch"] == 0 and r["max_dx_over_L"] < 1e-6, s
-        assert r["max_rel_v"] < 1e-4, (s, r["max_rel_v"])
-        assert np.mean(r["rel_v"] < 1e-6) >= 0.995, (s, np.mean(r["rel_v"] < 1e-6))
+        print("dense gas, species %d: max relative velocity error %.3g" % (s, r["max_rel_v"]))
+        assert r["max_rel_v"] < 1e-6, (s, r["max_rel_v"])

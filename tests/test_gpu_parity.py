@@ -137,17 +137,37 @@ def test_argon_single_steps_collisions_walls(pic):
 
 
 def test_argon_counts_and_order_bit_exact(pic):
+    # steps from identical states: ids and order, the particles absorbed at
+    # each wall, the secondaries emitted and the collision candidates agree
+    # exactly (integer tests on identical draws, positions far from the
+    # walls' rounding); the channel of a real collision may differ only where
+    # u1 nu_max falls within rounding of a partial sum of the channel
+    # frequencies, which is counted (at most two over the run)
     cfg, tabs = small_argon(n_init=20000, seed=5)
     sim = pic.Sim(cfg, tabs)
     sim.step(10)
-    res, n_before, o = _argon_step_compare(sim, cfg, tabs)
-    cg = sim.wall()
-    co = o.counters()
-    # one step from an identical state: wall losses of that step agree exactly
-    for s in range(2):
-        pg, po = res[s]
-        assert len(pg["id"]) == len(po["id"])
-        assert np.array_equal(pg["id"], po["id"])
+    channel_ties = 0
+    n_coll = 0
+    for rep in range(8):
+        w0, k0 = sim.wall(), sim.coll()
+        res, n_before, o = _argon_step_compare(sim, cfg, tabs)
+        w1, k1 = sim.wall(), sim.coll()
+        co = o.counters()
+        for s in range(2):
+            pg, po = res[s]
+            assert len(pg["id"]) == len(po["id"])
+            assert np.array_equal(pg["id"], po["id"])
+        np.testing.assert_array_equal(w1["absorbed"] - w0["absorbed"], co["absorbed"])
+        np.testing.assert_array_equal(w1["see_emitted"] - w0["see_emitted"], co["see_emitted"])
+        np.testing.assert_array_equal(k1["candidates"] - k0["candidates"], co["candidates"])
+        dg = np.concatenate([(k1["coll"] - k0["coll"]), (k1["nulls"] - k0["nulls"])[:, None]], axis=1)
+        do = np.concatenate([co["coll"], co["nulls"][:, None]], axis=1)
+        channel_ties += int(np.abs(dg - do).sum()) // 2
+        n_coll += int(do.sum())
+        sim.step(3)
+    print("collision outcomes compared: %d, channel ties: %d" % (n_coll, channel_ties))
+    assert n_coll > 1000
+    assert channel_ties <= 2
 
 
 def test_numax_matches_oracle(pic):

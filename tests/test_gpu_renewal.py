@@ -26,38 +26,65 @@ def _box(n=200_000, lz=1e-3):
 
 
 def test_renewal_step_matches_oracle(pic):
+    # one step from identical states (positions, velocities, ids and FP64
+    # axial displacements) where about half of each species crosses L_z.
+    # Both sides sum z in FP64; the GPU's new v_z differs from the oracle's
+    # by the binary32 rounding of the push (at most 1e-6 of the speed), so
+    # its z differs by at most 1e-6 |v| dt plus FP64 rounding.  A renewal
+    # decision may differ only where the oracle's displacement lies within
+    # that bound of L_z: those particles (the tie band) are counted and
+    # excluded, every other decision must agree, and every other particle
+    # agrees to 1e-6.
     cfg = _box()
     sim = pic.Sim(cfg)
     sim.step(3)
     rng = np.random.default_rng(5)
     lz = cfg["renew_lz"]
-    zs = []
     dt = cfg["dt"]
+    zs = []
     for s in range(2):
         vz = sim.get_particles(s)["vz"].astype(np.float64)
-        # within two steps' displacement of the L_z its velocity points to:
-        # about half of each species crosses in the next step
-        z = (np.sign(vz) * (lz - rng.uniform(0.0, 2.0, vz.size) * np.abs(vz) * dt)).astype(np.float32)
+        # within two steps' displacement of the L_z its velocity points to
+        z = np.sign(vz) * (lz - rng.uniform(0.0, 2.0, vz.size) * np.abs(vz) * dt)
         sim.set_axial(s, z)
         zs.append(z)
     o = to_oracle(sim, cfg)
+    # the same state with renewal out of reach: the displacement each
+    # particle reaches in the step, before the oracle's decision
+    free = to_oracle(sim, dict(cfg, renew_lz=1e30))
     for s in range(2):
-        o.set_axial(s, zs[s].astype(np.float64))
+        o.set_axial(s, zs[s])
+        free.set_axial(s, zs[s])
+    ren0 = sim.renewed()
     sim.step(1)
     o.step(1)
-    ren_g, ren_o = sim.renewed(), o.counters()["renewed"]
+    free.step(1)
+    ren_g, ren_o = sim.renewed() - ren0, o.counters()["renewed"]
+    total_ties = 0
     for s in range(2):
-        assert ren_o[s] > 0.3 * len(zs[s])
-        # a displacement within rounding of L_z may decide either way
-        assert abs(int(ren_g[s]) - int(ren_o[s])) <= 2
+        zc = free.axial(s)
+        pf = free.get_particles(s)
+        vth = cfg["species"][s]["vth"]
+        vfree = np.maximum(np.sqrt(pf["vx"] ** 2 + pf["vy"] ** 2 + pf["vz"] ** 2), vth)
+        band = 1e-6 * vfree * dt + 4 * np.spacing(lz)
+        tie = np.abs(np.abs(zc) - lz) <= band
+        total_ties += int(tie.sum())
+        zg, zo = sim.axial(s), o.axial(s)
+        dec_g, dec_o = zg == 0.0, zo == 0.0
+        assert ren_o[s] > 0.3 * len(zo)
+        assert np.array_equal(dec_o, np.abs(zc) >= lz)          # the oracle's own rule
+        assert np.array_equal(dec_g[~tie], dec_o[~tie]), s
+        assert abs(int(ren_g[s]) - int(ren_o[s])) <= int(tie.sum())
         pg, po = sim.get_particles(s), o.get_particles(s)
         assert np.array_equal(pg["id"], po["id"])
-        r = compare_species(pg, po, cfg, cfg["species"][s]["vth"])
-        ok = (r["rel_v"] < 1e-5) & (r["dx"] < 1e-6 * cfg["length"])
-        assert ok.mean() >= 0.9999, (s, ok.mean())
-        zg, zo = sim.axial(s), o.axial(s)
-        close = np.abs(zg - zo) <= 1e-5 * lz
-        assert close.mean() >= 0.9999
+        r = compare_species(pg, po, cfg, vth)
+        keep = ~tie
+        assert r["max_dx_over_L"] < 1e-6
+        assert r["rel_v"][keep].max() < 1e-6, (s, float(r["rel_v"][keep].max()))
+        # displacements: the same sum in FP64 but for v_z's binary32 rounding
+        vref = np.maximum(np.sqrt(po["vx"] ** 2 + po["vy"] ** 2 + po["vz"] ** 2), vth)
+        assert np.all(np.abs(zg - zo)[keep] <= 1e-6 * vref[keep] * dt + 4 * np.spacing(lz))
+    print("renewal decisions within the rounding bound of L_z (excluded):", total_ties)
 
 
 def test_ion_transit_time_on_gpu(pic):
