@@ -45,6 +45,11 @@ typedef int32_t pic_status;
 #define PIC_ENUMERIC (-5)    /* non-finite particle state */
 #define PIC_ESTATE (-6)      /* call not valid in the current state */
 #define PIC_ESTALL (-7)      /* reserved: no kernel of the library waits on another workgroup */
+#define PIC_ESCRATCH (-8)    /* the work needs more than the fixed scratch of an allocation-free call */
+
+/* Size of the fixed device scratch the allocation-free calls share (one
+ * array per GPU the library runs on, held until the process ends). */
+#define PIC_NOALLOC_SCRATCH_BYTES (32u << 20)
 
 /* Boundary conditions of the 1D domain [0, L): a column closed on itself
  * (periodic) or a gap between two electrodes (Section 1; Sections 3.5 and
@@ -365,6 +370,20 @@ pic_status pic_retire(pic_ctx* ctx, int32_t batch, int32_t retired);
  * births then draws other random numbers than an unsorted run.
  * Asynchronous. */
 pic_status pic_sort(pic_ctx* ctx);
+
+/* pic_sort_noalloc: pic_sort for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, with their scratch (the
+ * per-tile cell histogram and the group sums) in a fixed device array of
+ * PIC_NOALLOC_SCRATCH_BYTES per GPU, resolved at pic_init, instead of the
+ * buffer pic_sort allocates at its first call.  Calls no allocating routine.
+ * Needs (tiles x cells + discharges x 64 x cells) x 4 bytes, tiles being the
+ * capacity of the largest species over 1024 (for example one species of up
+ * to 8.1e6 particles on 1024 cells); larger contexts get PIC_ESCRATCH with no
+ * work queued.  Every allocation-free call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads) race.  Asynchronous, on the context's stream. */
+pic_status pic_sort_noalloc(pic_ctx* ctx);
 
 /* pic_use_graphs: when enable is non-zero (the default), pic_step captures a
  * chunk of consecutive steps once into a HIP graph on a private stream and

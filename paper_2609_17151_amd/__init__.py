@@ -21,7 +21,7 @@ MAX_SPECIES = 4
 MAX_CHAN = 8
 EEPF_BINS = 256
 
-OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE, ESTALL, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8
 DIAG = dict(COUNTS=0, RHO=1, PHI=2, EFIELD=3, DENSITY=4, ENERGY=5, WALL=6, COLL=7, NUMAX=8,
             FLAGS=9, AVG=10, EEPF=11, RESET_AVG=12, CHARGE=13, TIMING=14, POWER=15, WALL_ENERGY=16, WALL_EDF=17, RENEWED=18, CIRCUIT=19, GRAPHS=20)
 
@@ -111,6 +111,7 @@ def load_library():
         "pic_profile": (i32, [P, i32]),
         "pic_use_graphs": (i32, [P, i32]),
         "pic_sort": (i32, [P]),
+        "pic_sort_noalloc": (i32, [P]),
         "pic_retire": (i32, [P, i32, i32]),
         "pic_load_profiles": (i32, [P, i32, i32, dp, dp, C.POINTER(i64)]),
         "pic_mlp_create": (i32, [ip, i32, i32, C.POINTER(PicAllocator), P, C.POINTER(P)]),
@@ -360,6 +361,10 @@ class Sim:
 
     def sort(self):
         self._check(_lib.pic_sort(self.h), "pic_sort")
+
+    def sort_noalloc(self):
+        """pic_sort with the library's fixed per-GPU scratch: no allocation."""
+        self._check(_lib.pic_sort_noalloc(self.h), "pic_sort_noalloc")
 
     def use_graphs(self, enable=True):
         self._check(_lib.pic_use_graphs(self.h, int(enable)), "pic_use_graphs")

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -49,6 +50,7 @@ struct pic_ctx {
     int ppt = 4;                          // particles per thread
     int threads = 1024;                   // threads per workgroup (streaming kernels)
     int n_cu = 256;
+    int device = 0;                       // the GPU current at pic_init
     int sort_every = 0;
     int64_t steps_since_sort = 0;
     int compact_every = 16;              // steps between compactions of the holes
@@ -398,6 +400,38 @@ namespace {
 void drop_graph(pic_ctx* ctx);
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free calls: one array per GPU, never freed.
+// Its name is a host-side stand-in in host code; the device address of each
+// GPU's copy is resolved once, with that GPU current, and kept here.
+static __device__ __align__(256) unsigned char scratch[PIC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+pic_status noalloc_scratch_init(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return PIC_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return PIC_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PIC_EHIP;
+    g_scratch_ptr[dev] = ptr;
+    return PIC_OK;
+}
+
+void* noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pic_strerror(pic_status s)
@@ -411,6 +445,7 @@ const char* pic_strerror(pic_status s)
         case PIC_ENUMERIC: return "non-finite or out-of-range particle state";
         case PIC_ESTATE: return "invalid state";
         case PIC_ESTALL: return "reserved status";
+        case PIC_ESCRATCH: return "work larger than the fixed scratch of an allocation-free call";
         default: return "unknown status";
     }
 }
@@ -443,6 +478,11 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         hipDeviceProp_t prop;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
             ctx->n_cu = prop.multiProcessorCount;
+        ctx->device = dev;
+        if (noalloc_scratch_init(dev) != PIC_OK) {
+            delete ctx;
+            return PIC_EHIP;
+        }
     }
     if (alloc && alloc->alloc && alloc->free) {
         ctx->alloc = *alloc;
@@ -962,6 +1002,23 @@ pic_status pic_sort(pic_ctx* ctx)
         if (launch_sort(ctx->d, s, ctx->sort_tiles, ctx->sort_scratch, ctx->sort_scratch_bytes, ctx->stream) !=
             hipSuccess)
             return PIC_EHIP;
+    return PIC_OK;
+}
+
+pic_status pic_sort_noalloc(pic_ctx* ctx)
+{
+    if (!ctx) return PIC_EINVAL;
+    void* ptr = noalloc_scratch(ctx->device);
+    if (!ptr) return PIC_ESTATE;
+    int64_t tiles = 0;
+    for (int s = 0; s < ctx->S; ++s) {
+        int64_t ts = 0;
+        for (int b = 0; b < ctx->B; ++b) ts += sort_tiles_for(pad_cap(ctx->segc[b * ctx->S + s].cap));
+        tiles = std::max(tiles, ts);
+    }
+    if (sort_scratch_bytes(tiles, ctx->B, ctx->d.cells_max) > (size_t)PIC_NOALLOC_SCRATCH_BYTES) return PIC_ESCRATCH;
+    for (int s = 0; s < ctx->S; ++s)
+        if (launch_sort(ctx->d, s, tiles, ptr, PIC_NOALLOC_SCRATCH_BYTES, ctx->stream) != hipSuccess) return PIC_EHIP;
     return PIC_OK;
 }
 
