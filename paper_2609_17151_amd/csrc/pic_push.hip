@@ -119,19 +119,58 @@ constexpr uint32_t kEvRenew = 1u << 17;     // axial renewal: a fresh velocity
 constexpr uint32_t kEvSee = 1u << 18;       // an emitting ion absorbed at a wall: secondary emission test
 constexpr uint32_t kEvWall1 = 1u << 19;     // ... at the wall x = L
 
+// The constants of a tile's segment that the particle loop reads, copied to
+// registers once per tile.  The segment index is made wave-uniform, so these
+// are scalar loads; read through the segment's structure instead, every
+// particle would reload them, since the loop's atomics could alias them.
+struct PushC {
+    int nc, periodic, emits, nch;
+    uint32_t t32, key0, key1;
+    float ex, ey, ez, qmh, tx, ty, tz, sx, sy, sz, dtdx, hme, wedf_inv_bin, mscale1, mscale2;
+    int bulk_lo, bulk_hi;
+};
+
+__device__ __forceinline__ PushC push_consts(const SegConst& sc, const DisConst& dc)
+{
+    PushC k;
+    k.nc = dc.n_cells;
+    k.periodic = dc.bc == PIC_BC_PERIODIC;
+    k.emits = sc.emits;
+    k.nch = sc.nch;
+    k.t32 = sc.t32;
+    k.key0 = dc.key0;
+    k.key1 = dc.key1;
+    k.ex = sc.eext[0];
+    k.ey = sc.eext[1];
+    k.ez = sc.eext[2];
+    k.qmh = sc.qmh;
+    k.tx = sc.tv[0];
+    k.ty = sc.tv[1];
+    k.tz = sc.tv[2];
+    k.sx = sc.sv[0];
+    k.sy = sc.sv[1];
+    k.sz = sc.sv[2];
+    k.dtdx = sc.dtdx;
+    k.hme = sc.half_m_over_e;
+    k.wedf_inv_bin = sc.wedf_inv_bin;
+    k.mscale1 = sc.mscale1;
+    k.mscale2 = sc.mscale2;
+    k.bulk_lo = dc.bulk_lo;
+    k.bulk_hi = dc.bulk_hi;
+    return k;
+}
+
 // A particle's step in the push: gather, Boris push, cell-relative move,
 // periodic wrap or absorption, and the collision test.  Returns whether the
 // particle stays; `ev` collects its event bits (the collision itself, the
 // secondary emission and the renewal are the events kernel's).
 template <bool GENERAL>
-__device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, const DisConst& dc,
-                                        const PushArgs& a, int s, int b, uint32_t step,
-                                        const float2* ep, unsigned int* s_cnt, unsigned long long* s_wen, int& c,
-                                        float& f, float& ux, float& uy, float& uz, uint32_t pid, float& ke_sum,
-                                        uint32_t& ev)
+__device__ __forceinline__ bool advance(const DevPtrs& d, const PushC& k, const PushArgs& a, int s, int b,
+                                        uint32_t step, const float2* ep, unsigned int* s_cnt,
+                                        unsigned long long* s_wen, int& c, float& f, float& ux, float& uy,
+                                        float& uz, uint32_t pid, float& ke_sum, uint32_t& ev)
 {
-    const int nc = dc.n_cells;
-    const int periodic = dc.bc == PIC_BC_PERIODIC;
+    const int nc = k.nc;
     if ((unsigned)c >= (unsigned)nc) {     // corrupt state: latch, park the particle
         atomicOr(&d.diss[b].flags, kFlagCell);
         c = 0;
@@ -139,12 +178,12 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
     }
     // gather
     const float2 e2 = ep[c];
-    const float ex = e2.x + f * (e2.y - e2.x) + sc.eext[0];
-    const float ey = sc.eext[1], ez = sc.eext[2];
+    const float ex = e2.x + f * (e2.y - e2.x) + k.ex;
+    const float ey = k.ey, ez = k.ez;
     // Boris: half kick, rotation, half kick
-    const float qmh = sc.qmh;
-    const float tx = sc.tv[0], ty = sc.tv[1], tz = sc.tv[2];
-    const float sx = sc.sv[0], sy = sc.sv[1], sz = sc.sv[2];
+    const float qmh = k.qmh;
+    const float tx = k.tx, ty = k.ty, tz = k.tz;
+    const float sx = k.sx, sy = k.sy, sz = k.sz;
     const float vold2 = ux * ux + uy * uy + uz * uz;
     ux += qmh * ex;
     uy += qmh * ey;
@@ -161,7 +200,7 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
     const float vnew2 = ux * ux + uy * uy + uz * uz;
     ke_sum += vold2 + vnew2;
     // move, relative to the cell
-    f += ux * sc.dtdx;
+    f += ux * k.dtdx;
     const float fl = floorf(f);
     c += (int)fl;
     f -= fl;
@@ -175,7 +214,7 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
         c = 0;
         ux = uy = uz = 0.0f;
     }
-    if (periodic) {
+    if (k.periodic) {
         if (c < 0) c += nc;
         else if (c >= nc) c -= nc;
         if ((unsigned)c >= (unsigned)nc) {                     // moved more than the domain
@@ -187,36 +226,36 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const SegConst& sc, co
     } else if (c < 0 || c >= nc) {
         const int wall = c < 0 ? 0 : 1;
         atomicAdd(&s_cnt[C_ABS0 + wall], 1u);
-        atomicAdd(&s_wen[wall], (unsigned long long)(sc.half_m_over_e * vnew2 * 1048576.0f));
+        atomicAdd(&s_wen[wall], (unsigned long long)(k.hme * vnew2 * 1048576.0f));
         if (a.diag) {
             // impact energy: this species' histogram at this wall, and for
             // electrons the wall energy distribution
-            const float eps = sc.half_m_over_e * vnew2;
-            const int wb = (int)(eps * sc.wedf_inv_bin);
+            const float eps = k.hme * vnew2;
+            const int wb = (int)(eps * k.wedf_inv_bin);
             if ((unsigned)wb < (unsigned)kEepfBins)
                 atomicAdd(&d.wedf[(((size_t)b * d.S + s) * 2 + wall) * kEepfBins + wb], 1ull);
             const int bin = (int)(eps * a.eepf_inv_bin);
             if (s == 0 && (unsigned)bin < (unsigned)kEepfBins)
                 atomicAdd(&d.eepf[((size_t)b * 2 + 1) * kEepfBins + bin], 1ull);
         }
-        if (GENERAL && sc.emits) ev = kEvSee | (wall ? kEvWall1 : 0u);
+        if (GENERAL && k.emits) ev = kEvSee | (wall ? kEvWall1 : 0u);
         return false;
     }
-    if (!GENERAL || sc.nch == 0) return true;
+    if (!GENERAL || k.nch == 0) return true;
     // null-collision Monte Carlo: integer candidate test on the first draw
-    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
-    if (r.x < sc.t32) ev |= kEvCand;
+    const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, k.key0, k.key1);
+    if (r.x < k.t32) ev |= kEvCand;
     return true;
 }
 
 // velocity moments of a particle at the nodes, fixed point (diagnostics);
 // fh and mh are LDS histograms in the push and the discharge's global sums
-// in the events kernel
-__device__ __forceinline__ void moment_diag(const SegConst& sc, unsigned long long* fh, unsigned long long* mh, int c,
-                                            float f, float ux, int nc, int periodic)
+// in the events kernel; ms1, ms2 the species' fixed-point scales
+__device__ __forceinline__ void moment_diag(float ms1, float ms2, unsigned long long* fh, unsigned long long* mh,
+                                            int c, float f, float ux, int nc, int periodic)
 {
     const int c1 = (periodic && c + 1 == nc) ? 0 : c + 1;
-    const float a = ux * sc.mscale1, b2 = ux * ux * sc.mscale2;
+    const float a = ux * ms1, b2 = ux * ux * ms2;
     const float w0 = 1.0f - f;
     atomicAdd(&fh[c], (unsigned long long)(long long)rintf(w0 * a));
     atomicAdd(&fh[c1], (unsigned long long)(long long)rintf(f * a));
@@ -225,18 +264,19 @@ __device__ __forceinline__ void moment_diag(const SegConst& sc, unsigned long lo
 }
 
 // electron energy at the nodes and in the bulk distribution (diagnostics);
-// CT is the bin counter type (32-bit in LDS, 64-bit in global memory)
+// CT is the bin counter type (32-bit in LDS, 64-bit in global memory); hme =
+// m / 2e, [lo, hi) the cells of the bulk distribution
 template <typename CT>
-__device__ __forceinline__ void electron_diag(const SegConst& sc, const DisConst& dc, float eepf_inv_bin,
+__device__ __forceinline__ void electron_diag(float hme, int lo, int hi, float eepf_inv_bin,
                                               unsigned long long* ehist, CT* eepf, int c, float f,
                                               float ux, float uy, float uz, int nc, int periodic)
 {
-    const float eps = sc.half_m_over_e * (ux * ux + uy * uy + uz * uz);
+    const float eps = hme * (ux * ux + uy * uy + uz * uz);
     const float w1 = f * eps, w0 = eps - w1;
     const int c1 = (periodic && c + 1 == nc) ? 0 : c + 1;
     atomicAdd(&ehist[c], (unsigned long long)(w0 * 1048576.0f));
     atomicAdd(&ehist[c1], (unsigned long long)(w1 * 1048576.0f));
-    if (c >= dc.bulk_lo && c < dc.bulk_hi) {
+    if (c >= lo && c < hi) {
         const int bin = (int)(eps * eepf_inv_bin);
         if ((unsigned)bin < (unsigned)kEepfBins) atomicAdd(&eepf[bin], (CT)1);
     }
@@ -345,6 +385,16 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     int cur_g = -1, cur_b = -1;
     int32_t run_first = 0;
     float ke_run = 0.0f;
+    // the current segment's particle arrays and counts, read when the segment
+    // changes, so that a tile's particle loads do not wait for them
+    int64_t n = 0;
+    uint32_t step = 0;
+    int32_t tile_first = 0, ntiles = 0;
+    int32_t* p_cell = nullptr;
+    float *p_off = nullptr, *p_vx = nullptr, *p_vy = nullptr, *p_vz = nullptr;
+    uint32_t* p_id = nullptr;
+    double* p_z = nullptr;
+    double renew_lz = 0.0, dt_d = 0.0;
     // a fixed contiguous range of tiles per workgroup
     const int32_t chunk = (NT + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
     const int32_t t_begin = (int32_t)blockIdx.x * chunk;
@@ -405,7 +455,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     };
 
     for (int32_t t = t_begin; t < t_end; ++t) {
-        const int sg = tile_segment(s_pref, NS, t);
+        // the tile's segment, wave-uniform (its constants become scalar loads)
+        const int sg = __builtin_amdgcn_readfirstlane(tile_segment(s_pref, NS, t));
         const int b = sg / S, s = sg - b * S;
         const DisConst& dc = d.disc[b];
         if (sg != cur_g) {
@@ -426,33 +477,43 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 for (int i = tid; i < dc.n_nodes; i += kBS) ehist[i] = 0ull;
                 for (int i = tid; i < kEepfBins; i += kBS) eepf[i] = 0u;
             }
-            __syncthreads();
             cur_g = sg;
             cur_b = b;
             run_first = t;
+            const SegConst& sc = d.segc[sg];
+            const SegState& st = d.segs[sg];
+            const int io = st.parity;             // updated in place
+            n = st.count;
+            step = (uint32_t)d.diss[b].step;
+            tile_first = __builtin_amdgcn_readfirstlane(s_pref[sg]);
+            ntiles = __builtin_amdgcn_readfirstlane(s_pref[sg + 1]) - tile_first;
+            p_cell = sc.cell[io];
+            p_off = sc.off[io];
+            p_vx = sc.vx[io];
+            p_vy = sc.vy[io];
+            p_vz = sc.vz[io];
+            p_id = sc.id[io];
+            p_z = sc.z[io];
+            renew_lz = sc.renew_lz;
+            dt_d = sc.dt_d;
+            __syncthreads();
         }
-        const int32_t tile_first = s_pref[sg];
-        const int32_t ntiles = s_pref[sg + 1] - tile_first;
         const int32_t tin = t - tile_first;
-        const SegConst& sc = d.segc[sg];
-        SegState& st = d.segs[sg];
-        const int64_t n = st.count;
-        const int nc = dc.n_cells;
-        const int periodic = dc.bc == PIC_BC_PERIODIC;
-        const uint32_t step = (uint32_t)d.diss[b].step;
-        const int io = st.parity;                 // updated in place
+        const PushC k = push_consts(d.segc[sg], dc);   // loads in flight with the particles'
+        const int nc = k.nc;
+        const int periodic = k.periodic;
         const int64_t base = (int64_t)tin * T + (int64_t)tid * PPT;
 
         int32_t cell[PPT];
         float off[PPT], vx[PPT], vy[PPT], vz[PPT];
         uint32_t pid[PPT];
-        vload<PPT, int4>(sc.cell[io] + base, cell);
-        vload<PPT, float4>(sc.off[io] + base, off);
-        vload<PPT, float4>(sc.vx[io] + base, vx);
-        vload<PPT, float4>(sc.vy[io] + base, vy);
-        vload<PPT, float4>(sc.vz[io] + base, vz);
+        vload<PPT, int4>(p_cell + base, cell);
+        vload<PPT, float4>(p_off + base, off);
+        vload<PPT, float4>(p_vx + base, vx);
+        vload<PPT, float4>(p_vy + base, vy);
+        vload<PPT, float4>(p_vz + base, vz);
         if (GENERAL) {
-            vload<PPT, uint4>(sc.id[io] + base, pid);
+            vload<PPT, uint4>(p_id + base, pid);
         } else {
 #pragma unroll
             for (int j = 0; j < PPT; ++j) pid[j] = 0u;
@@ -460,11 +521,11 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         // axial renewal: the displacement along the third axis since
         // injection, summed in FP64 (a slow ion adds only a few binary32
         // spacings of z per step, so a binary32 sum would drift)
-        const bool renews = GENERAL && sc.renew_lz > 0.0;
+        const bool renews = GENERAL && renew_lz > 0.0;
         double zax[PPT];
         if (renews) {
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) zax[j] = sc.z[io][base + j];
+            for (int j = 0; j < PPT; ++j) zax[j] = p_z[base + j];
         }
 
         uint32_t evw[PPT];
@@ -474,13 +535,13 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             evw[j] = 0u;
             if (base + j >= n) continue;
             if (GENERAL && cell[j] < 0) continue;          // a hole: absorbed earlier
-            const bool keep = advance<GENERAL>(d, sc, dc, a, s, b, step, ep, s_cnt, s_wen, cell[j], off[j], vx[j],
-                                               vy[j], vz[j], pid[j], ke_tile, evw[j]);
+            const bool keep = advance<GENERAL>(d, k, a, s, b, step, ep, s_cnt, s_wen, cell[j], off[j], vx[j], vy[j],
+                                               vz[j], pid[j], ke_tile, evw[j]);
             if (renews && keep) {
                 // past L_z the particle gets a fresh velocity from its
                 // species' initial distribution at the same x (events kernel)
-                const double zz = zax[j] + (double)vz[j] * sc.dt_d;
-                if (fabs(zz) >= sc.renew_lz) {
+                const double zz = zax[j] + (double)vz[j] * dt_d;
+                if (fabs(zz) >= renew_lz) {
                     evw[j] |= kEvRenew;
                     zax[j] = 0.0;
                     atomicAdd(&s_cnt[C_REN], 1u);
@@ -493,10 +554,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 // a particle whose velocity the events kernel changes is
                 // sampled there
                 if (a.diag && !(evw[j] & (kEvCand | kEvRenew))) {
-                    moment_diag(sc, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
+                    moment_diag(k.mscale1, k.mscale2, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
                     if (s == 0)
-                        electron_diag(sc, dc, a.eepf_inv_bin, ehist, eepf, cell[j], off[j], vx[j], vy[j], vz[j],
-                                      nc, periodic);
+                        electron_diag(k.hme, k.bulk_lo, k.bulk_hi, a.eepf_inv_bin, ehist, eepf, cell[j], off[j],
+                                      vx[j], vy[j], vz[j], nc, periodic);
                 }
             } else {
                 cell[j] = -1;                              // absorbed: leaves a hole
@@ -506,27 +567,27 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 
         // in place; every particle keeps its slot
         if (base + PPT <= n) {
-            vstore<PPT, int4>(sc.cell[io] + base, cell);
-            vstore<PPT, float4>(sc.off[io] + base, off);
-            vstore<PPT, float4>(sc.vx[io] + base, vx);
-            vstore<PPT, float4>(sc.vy[io] + base, vy);
-            vstore<PPT, float4>(sc.vz[io] + base, vz);
+            vstore<PPT, int4>(p_cell + base, cell);
+            vstore<PPT, float4>(p_off + base, off);
+            vstore<PPT, float4>(p_vx + base, vx);
+            vstore<PPT, float4>(p_vy + base, vy);
+            vstore<PPT, float4>(p_vz + base, vz);
         } else {
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 if (base + j < n) {
-                    sc.cell[io][base + j] = cell[j];
-                    sc.off[io][base + j] = off[j];
-                    sc.vx[io][base + j] = vx[j];
-                    sc.vy[io][base + j] = vy[j];
-                    sc.vz[io][base + j] = vz[j];
+                    p_cell[base + j] = cell[j];
+                    p_off[base + j] = off[j];
+                    p_vx[base + j] = vx[j];
+                    p_vy[base + j] = vy[j];
+                    p_vz[base + j] = vz[j];
                 }
             }
         }
         if (renews) {
 #pragma unroll
             for (int j = 0; j < PPT; ++j)
-                if (base + j < n) sc.z[io][base + j] = zax[j];
+                if (base + j < n) p_z[base + j] = zax[j];
         }
         if (GENERAL) {
             // this wave's events, in slot order: lanes in order, a lane's
@@ -546,8 +607,8 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             if (lane == 0) d.evc[(size_t)t * kWavesPerTile + wid] = total;
         }
         if (tid == 0 && tin == ntiles - 1) {
-            st.tile_first = tile_first;
-            st.ntiles = ntiles;
+            d.segs[sg].tile_first = tile_first;
+            d.segs[sg].ntiles = ntiles;
         }
         if (GENERAL && tid == 0) d.bcnt[t] = 0;   // the events kernel counts this tile's births
     }
@@ -890,9 +951,10 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
                 sc.vz[io][slot] = fz;
                 if (a.diag) {
                     unsigned long long* fh = d.macc + (size_t)sg * 2 * d.nodes_max;
-                    moment_diag(sc, fh, fh + d.nodes_max, c, f, fx, nc, periodic);
+                    moment_diag(sc.mscale1, sc.mscale2, fh, fh + d.nodes_max, c, f, fx, nc, periodic);
                     if (s == 0)
-                        electron_diag(sc, dc, a.eepf_inv_bin, d.eacc + (size_t)b * d.nodes_max,
+                        electron_diag(sc.half_m_over_e, dc.bulk_lo, dc.bulk_hi, a.eepf_inv_bin,
+                                      d.eacc + (size_t)b * d.nodes_max,
                                       d.eepf + (size_t)b * 2 * kEepfBins, c, f, fx, fy, fz, nc, periodic);
                 }
             }
