@@ -606,7 +606,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.bcnt = (int32_t*)A(4ull * tiles_max);
         int64_t slots = 0;
         for (int s = 0; s < S; ++s) slots += ctx->grid_cap[s];
-        d.ev = (uint32_t*)A(4ull * slots);
+        d.evr = (uint4*)A(16ull * slots);
+        d.evz = (float*)A(4ull * slots);
         d.evc = (uint32_t*)A(4ull * (slots / 64 + 1));
         d.evp = (uint32_t*)A(4ull * (slots / 64 + 1));
         d.evidx = (uint32_t*)A(4ull * (slots / 64 + 1));

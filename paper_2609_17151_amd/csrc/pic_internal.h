@@ -210,7 +210,9 @@ struct DevPtrs {
     unsigned long long* wedf;    // [B][S][2][bins] impact energies at each wall
     Birth* births;               // [tiles_max * kBirthsPerTileMin] births staged by tile, in particle order
     int32_t* bcnt;               // [tiles_max] births staged by each tile
-    uint32_t* ev;                // [slots] events of the step: per tile, per wave, in slot order
+    uint4* evr;                  // [slots] events of the step, per tile, per wave, in slot order:
+                                 // (slot | event bits, id, vx, vy) of the particle after the push
+    float* evz;                  // [slots] its vz
     uint32_t* evc;               // [slots / 64 + 1] events recorded by each wave of each tile (a "unit")
     uint32_t* evp;               // [slots / 64 + 1] prefix of the units' events within their push workgroup's range
     uint32_t* evidx;             // [slots / 64 + 1] per push range (from its first slot / 64): the unit holding event 64 k

@@ -599,10 +599,19 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 below += lanes_below(m);
                 total += (uint32_t)__popcll(m);
             }
-            uint32_t* evp = d.ev + (size_t)t * T + (size_t)wid * 64 * PPT;
+            // each event's record carries the particle's id and new velocity,
+            // so the events kernel reads records, not scattered particle slots
+            const size_t r0 = (size_t)t * T + (size_t)wid * 64 * PPT;
+            uint4* evr = d.evr + r0;
+            float* evz = d.evz + r0;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
-                if (evw[j]) evp[below++] = evw[j] | (uint32_t)(tid * PPT + j);
+                if (evw[j]) {
+                    evr[below] = make_uint4(evw[j] | (uint32_t)(tid * PPT + j), pid[j], __float_as_uint(vx[j]),
+                                            __float_as_uint(vy[j]));
+                    evz[below] = vz[j];
+                    ++below;
+                }
             }
             if (lane == 0) d.evc[(size_t)t * kWavesPerTile + wid] = total;
         }
@@ -656,10 +665,11 @@ namespace {
 // running sum of the tabulated frequencies against the second word of the
 // first draw, then the kinematics of the channel.  Returns the channel (-1:
 // null collision); `viol` says whether the summed frequency exceeded the
-// bound, `born` whether an ionization filled `bb` (the ejected electron and
-// the new ion at the parent's position).
-__device__ __forceinline__ int collide_particle(const SegConst& sc, const DisConst& dc, int s, uint32_t step, int c,
-                                                float f, double& ux, double& uy, double& uz, uint32_t pid, Birth& bb,
+// bound, `born` whether an ionization filled the velocities of `bb` (the
+// ejected electron and the new ion; the caller places them at the parent's
+// position).
+__device__ __forceinline__ int collide_particle(const SegConst& sc, const DisConst& dc, int s, uint32_t step,
+                                                double& ux, double& uy, double& uz, uint32_t pid, Birth& bb,
                                                 bool& viol, bool& born)
 {
     const uint4 r = philox10(pid, step, ((uint32_t)s << 24), 0u, dc.key0, dc.key1);
@@ -738,8 +748,6 @@ __device__ __forceinline__ int collide_particle(const SegConst& sc, const DisCon
             double g0, g1, g2, g3;
             box_muller_d(u01d(r2.x), u01d(r2.y), g0, g1);
             box_muller_d(u01d(r2.z), u01d(r2.w), g2, g3);
-            bb.cell = c;
-            bb.off = f;
             bb.vx = (float)(vej * edx);
             bb.vy = (float)(vej * edy);
             bb.vz = (float)(vej * edz);
@@ -908,7 +916,9 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
             const int32_t t = (int32_t)(unit / W);
             const int w = (int)(unit - (int64_t)t * W);
             const uint32_t idx = e - d.evp[unit];   // both relative to the range
-            const uint32_t word = d.ev[(size_t)t * a.T + (size_t)w * 64 * a.ppt + idx];
+            const size_t ri = (size_t)t * a.T + (size_t)w * 64 * a.ppt + idx;
+            const uint4 rec = d.evr[ri];
+            const uint32_t word = rec.x;
             sg = tile_segment(s_pref, NS, t);
             const int b = sg / S, s = sg - b * S;
             const DisConst& dc = d.disc[b];
@@ -920,7 +930,7 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
             const int periodic = dc.bc == PIC_BC_PERIODIC;
             const uint32_t key = word & kEvSlot;
             const int64_t slot = (int64_t)tin * a.T + key;
-            const uint32_t pid = sc.id[io][slot];
+            const uint32_t pid = rec.y;
             Birth bb;
             if (word & kEvSee) {
                 see = true;
@@ -929,9 +939,7 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
                 hb = r > 0;
                 lost = r < 0;
             } else {
-                const int c = sc.cell[io][slot];
-                const float f = sc.off[io][slot];
-                double ux = sc.vx[io][slot], uy = sc.vy[io][slot], uz = sc.vz[io][slot];
+                double ux = __uint_as_float(rec.z), uy = __uint_as_float(rec.w), uz = d.evz[ri];
                 if (word & kEvRenew) {
                     const uint4 r6 = philox10(pid, step, ((uint32_t)s << 24) | 6u, 0u, dc.key0, dc.key1);
                     double g0, g1, g2, g3;
@@ -943,7 +951,16 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
                 }
                 if (word & kEvCand) {
                     cand = true;
-                    ch = collide_particle(sc, dc, s, step, c, f, ux, uy, uz, pid, bb, viol, hb);
+                    ch = collide_particle(sc, dc, s, step, ux, uy, uz, pid, bb, viol, hb);
+                }
+                // the position: for an ionization's pair and the diagnostics
+                int c = 0;
+                float f = 0.0f;
+                if (hb || a.diag) {
+                    c = sc.cell[io][slot];
+                    f = sc.off[io][slot];
+                    bb.cell = c;
+                    bb.off = f;
                 }
                 const float fx = (float)ux, fy = (float)uy, fz = (float)uz;
                 sc.vx[io][slot] = fx;
