@@ -172,19 +172,28 @@ pic_status pic_load_xsec(pic_ctx* ctx, int32_t batch, int32_t species, int32_t k
                          const double* sigma_m2);
 
 /*
- * pic_step: queue n_steps >= 0 full steps of every discharge: gather, Boris
- * push, move, wall/periodic handling with secondary emission, null-collision
- * Monte Carlo, compaction and births, deposition, Poisson at t^{n+1}.
- * Asynchronous.
+ * pic_step: queue n_steps >= 0 full steps of every discharge of the
+ * context, each the explicit leapfrog step of Section 1 in order: the field
+ * gathered at the particles, the Boris push in the imposed magnetic field,
+ * the move, walls with absorption and ion-induced secondary emission (or
+ * the periodic wrap), collisions by the null-collision method against the
+ * tabulated cross sections, births after the survivors, the charge of the
+ * particles deposited on the mesh and the field solved at t^{n+1}.  Device
+ * conditions (capacity, non-finite state, frequency bound) are latched and
+ * reported by the next pic_diag or pic_sync.  n_steps < 0 gives PIC_EINVAL.
+ * Asynchronous, on the context's stream.
  */
 pic_status pic_step(pic_ctx* ctx, int32_t n_steps);
 
 /*
- * pic_poisson: solve the mesh problem of discharge `batch` at time t_s for
- * the charge density rho_in (host, n_nodes values; NULL: the last deposited
- * density) and copy phi and E at the nodes to phi_out / efield_out (host,
- * n_nodes doubles each; either may be NULL).  n_nodes = n_cells + 1 for
- * Dirichlet, n_cells for periodic.  Does not change the simulation state.
+ * pic_poisson: the field the particles' charge produces on the mesh
+ * (Section 1), with the electrode's voltage waveform or drive as the
+ * boundary: solve the discharge's 1D Poisson problem at time t_s, in FP64,
+ * for the charge density rho_in (host, n_nodes values in C/m^3; NULL: the
+ * last deposited density) and copy phi (V) and E (V/m) at the nodes to
+ * phi_out / efield_out (host, n_nodes doubles each; either may be NULL).
+ * n_nodes = n_cells + 1 for Dirichlet, n_cells for periodic.  Does not change
+ * the simulation state.  PIC_EINVAL for a bad batch or a non-finite density.
  * Synchronous.
  */
 pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rho_in,
@@ -227,9 +236,13 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_WINDOW_RING 64      /* completed RF windows kept per discharge (pic_get_windows) */
 
 /*
- * pic_diag: synchronise the stream, then copy diagnostic `what` of discharge
- * `batch` into out (host, out_bytes bytes).  Returns PIC_EINVAL if out_bytes
- * is too small, and any latched device error (after copying).
+ * pic_diag: the engine's diagnostics (Section 1 lists density, potential
+ * and field profiles, energies, electron energy distributions, wall fluxes
+ * and collision statistics; the selectors above say each layout).
+ * Synchronise the stream, then copy diagnostic `what` of discharge `batch`
+ * into out (host, out_bytes bytes, owned by the caller).  Returns PIC_EINVAL
+ * for an unknown selector or batch or if out_bytes is too small, and any
+ * latched device error (after copying).
  */
 pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t out_bytes);
 
