@@ -240,6 +240,28 @@ def sweep_draws(n=64, seed=4):
             for i in range(n)]
 
 
+# Steady-state particle counts of the argon configurations: about 2e5
+# macro-particles per species for the single discharge, and counts between
+# 5e4 and 2e6 per species (log-uniform, seeded) for the discharges of the
+# sweep.  The throughput lines start from these counts instead of a cold start.
+STEADY_COUNT_C2 = 200_000
+STEADY_COUNT_RANGE = (5e4, 2e6)
+
+
+def steady_counts(n, seed=40):
+    rng = np.random.default_rng(seed)
+    return np.rint(np.exp(rng.uniform(np.log(STEADY_COUNT_RANGE[0]), np.log(STEADY_COUNT_RANGE[1]), n))).astype(int)
+
+
+def discharge_profile(m=64, te_ev=3.0, ti_ev=0.026):
+    """Relative density and temperature (eV) of both species at m points over
+    the gap, for a start at steady-state counts: a half-sine density, flat
+    temperatures (electrons te_ev, ions at the gas temperature)."""
+    x = (np.arange(m) + 0.5) / m
+    dens = np.sin(np.pi * x)
+    return np.stack([dens, dens]), np.stack([np.full(m, te_ev), np.full(m, ti_ev)])
+
+
 def warm_draws(n, seed, f_range=(2e6, 60e6)):
     rng = np.random.default_rng(seed)
     p = np.exp(rng.uniform(np.log(10.0), np.log(200.0), n))
