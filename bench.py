@@ -84,17 +84,35 @@ def rocprof_entry(per_launch_bytes):
             "frac": gbs / HBM_PEAK_GBS}
 
 
-def cpu_baseline(cfg, steps):
+def host_threads():
+    """Threads the host gives this process (its CPU affinity), for the oracle."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(cfg, steps, steps_one):
+    """The FP64 oracle on the host: its parallel step (OpenMP, fixed chunks of
+    particles, the same result for every thread count) on every thread the
+    host gives, and its sequential step on one."""
     import oracle
+    n = sum(sp["n_init"] for sp in cfg["species"])
+    threads = host_threads()
     t0 = time.perf_counter()
     o = oracle.Oracle(cfg)
     t1 = time.perf_counter()
+    o.set_threads(threads)
     o.step(steps)
     t2 = time.perf_counter()
-    n = sum(sp["n_init"] for sp in cfg["species"])
-    return dict(value=n * steps / (t2 - t1), unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"full E x B box ({n} particles), {steps} steps after loading "
-                       f"(load {t1 - t0:.1f} s not counted), single-threaded FP64 C oracle",
+    o.set_threads(0)
+    o.step(steps_one)
+    t3 = time.perf_counter()
+    return dict(value=n * steps / (t2 - t1), unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"full E x B box ({n} particles): {steps} steps of the parallel FP64 C oracle on "
+                       f"{threads} threads, then {steps_one} steps of its sequential step on one "
+                       f"(load {t1 - t0:.1f} s not counted)",
+                single_thread=n * steps_one / (t3 - t2),
                 cpu=cpu_model(), host_cores=os.cpu_count())
 
 
@@ -185,7 +203,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the argon RF single and batched lines")
     ap.add_argument("--secondary-steps", type=int, default=320)
     ap.add_argument("--secondary-warm", type=int, default=3200, help="steps before the argon lines are timed")
-    ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps on all host threads")
+    ap.add_argument("--cpu-steps-one", type=int, default=60, help="oracle steps of the sequential step")
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
     ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
                     help="argon_rf / argon_sweep: only that secondary workload (profiling runs)")
@@ -281,7 +300,7 @@ def main():
         out["secondary"] = secondary(P, W, torch, args.secondary_steps, warm=args.secondary_warm, graphs=not args.no_graph)
     if not args.no_cpu:
         sim.close()
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps, args.cpu_steps_one)
     print(json.dumps(out), flush=True)
 
 

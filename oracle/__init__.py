@@ -27,7 +27,7 @@ def build(force=True):
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off",
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fopenmp",
                            "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB
@@ -89,6 +89,7 @@ def lib():
         L.orc_set_circuit.argtypes = [P, C.c_double]
         L.orc_get_axial.argtypes = [P, C.c_int32, C.c_int64, dp]
         L.orc_set_step.argtypes = [P, C.c_uint64]
+        L.orc_set_threads.argtypes = [P, C.c_int32]
         L.orc_get_step.argtypes = [P]
         L.orc_get_step.restype = C.c_uint64
         L.orc_refresh_field.argtypes = [P]
@@ -202,6 +203,11 @@ class Oracle:
 
     def set_step(self, n):
         _check(lib().orc_set_step(self.h, n), "orc_set_step")
+
+    def set_threads(self, n):
+        """0: the sequential step (default); n > 0: the parallel step on n
+        threads, the same result for every n."""
+        _check(lib().orc_set_threads(self.h, int(n)), "orc_set_threads")
 
     def step(self, n=1):
         _check(lib().orc_step(self.h, n), "orc_step")

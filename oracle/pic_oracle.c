@@ -14,7 +14,10 @@
  * exchange with a thermal neutral, a half-Maxwellian flux for secondaries,
  * Philox4x32-10 keyed by (seed, particle id, step)).
  *
- * Plain loops, sequential, FP64 throughout.
+ * Plain loops, FP64 throughout.  Sequential by default; orc_set_threads
+ * selects a parallel step (OpenMP over fixed chunks of particles, merged in
+ * chunk order) whose result does not depend on the thread count, for timing
+ * on the host's cores and for long statistical runs.
  */
 #include "pic_oracle.h"
 
@@ -49,6 +52,23 @@ typedef struct {
     int64_t n, cap;
 } blist_t;
 
+/* What a run of particles of one species adds in a step: counters, births
+ * (in the order they are made), the kinetic-energy sum, and the wall-impact
+ * histograms of the diagnostics.  The sequential step has one run per
+ * species; the parallel step one per chunk of ORC_CHUNK particles, merged in
+ * chunk order, so that its result does not depend on the thread count. */
+typedef struct {
+    orc_counters cnt;
+    blist_t births[ORC_MAX_SPECIES];
+    double ke;
+    int64_t eepf_wall[ORC_EEPF_BINS];  /* electrons: wall-impact energies */
+    int64_t wedf[2][ORC_EEPF_BINS];    /* this species: impact energies at each wall */
+    int64_t keep;                      /* survivors of the run */
+    int rc;                            /* first error of the run */
+} sink_t;
+
+#define ORC_CHUNK 4096
+
 struct orc_sim {
     orc_config c;
     double dx;
@@ -69,6 +89,14 @@ struct orc_sim {
     int32_t circ_init;
     double ke[ORC_MAX_SPECIES], fe;
     blist_t births[ORC_MAX_SPECIES];
+    /* the parallel step (threads > 0): its chunk runs, a second population to
+     * compact into, and per-chunk partial sums of the deposit */
+    int32_t threads;
+    sink_t* runs;
+    int64_t nruns;
+    pop_t spare[ORC_MAX_SPECIES];
+    double* part;
+    int64_t npart;
     /* time-accumulated diagnostics, sampled after every step while enabled */
     int32_t diag;
     double eepf_emax, wedf_emax[ORC_MAX_SPECIES];
@@ -400,7 +428,13 @@ void orc_free(orc_sim* s)
         free(s->sum[k]); free(s->dens[k]); free(s->av_dens[k]);
         free(s->births[k].b);
         for (int j = 0; j < ORC_MAX_CHAN; ++j) { free(s->ch[k][j].e); free(s->ch[k][j].s); }
+        free(s->spare[k].x); free(s->spare[k].vx); free(s->spare[k].vy); free(s->spare[k].vz);
+        free(s->spare[k].z); free(s->spare[k].id);
     }
+    for (int64_t r = 0; r < s->nruns; ++r)
+        for (int k = 0; k < ORC_MAX_SPECIES; ++k) free(s->runs[r].births[k].b);
+    free(s->runs);
+    free(s->part);
     free(s->rho); free(s->phi); free(s->ef); free(s->av_phi); free(s->av_neps);
     free(s);
 }
@@ -841,13 +875,13 @@ static int push_birth(blist_t* l, double x, double vx, double vy, double vz)
  * test x0 < T32, picks the channel with u1 nu_max against the running sum of
  * nu_k = n_g sigma_k v, and gives the scattering angles cos(chi) = 1 - 2 u2,
  * phi = 2 pi u3. */
-static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
+static int collide(const orc_sim* s, sink_t* o, int k, uint32_t id, double x, double v[3])
 {
     int nch = s->nch[k];
     uint32_t r[4];
     draw(s, id, (uint32_t)s->step, k, 0u, r);
     if (r[0] >= s->t32[k]) return ORC_OK;
-    s->cnt.candidates[k] += 1;
+    o->cnt.candidates[k] += 1;
     double m = s->c.sp[k].mass, M = s->c.gas_mass, ng = s->c.gas_density;
     double eu = s->c.e_unit;
     int ion = !electron_kind(s->ch[k][0].kind);
@@ -875,7 +909,7 @@ static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
         nu[c] = ng * sigma_at(&s->ch[k][c], eps) * speed;
         total += nu[c];
     }
-    if (total > s->numax[k]) s->cnt.violations[k] += 1;
+    if (total > s->numax[k]) o->cnt.violations[k] += 1;
     double u1 = orc_u01(r[1]);
     double target = u1 * s->numax[k];
     double cum = 0.0;
@@ -884,8 +918,8 @@ static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
         cum += nu[c];
         if (target < cum) { chosen = c; break; }
     }
-    if (chosen < 0) { s->cnt.nulls[k] += 1; return ORC_OK; }
-    s->cnt.coll[k][chosen] += 1;
+    if (chosen < 0) { o->cnt.nulls[k] += 1; return ORC_OK; }
+    o->cnt.coll[k][chosen] += 1;
     double cos_chi = 1.0 - 2.0 * orc_u01(r[2]);
     double phi = TWO_PI * orc_u01(r[3]);
     const chan_t* ch = &s->ch[k][chosen];
@@ -908,13 +942,13 @@ static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
             double ed[3];
             orc_rotate(d, 1.0 - 2.0 * orc_u01(r1[1]), TWO_PI * orc_u01(r1[2]), ed);
             double vej = sqrt(2.0 * eps_ej * eu / m);
-            int rc = push_birth(&s->births[0], x, vej * ed[0], vej * ed[1], vej * ed[2]);
+            int rc = push_birth(&o->births[0], x, vej * ed[0], vej * ed[1], vej * ed[2]);
             if (rc) return rc;
             double g0, g1, g2, g3, vt = sqrt(K_B * s->c.gas_temp / M);
             box_muller(orc_u01(r2[0]), orc_u01(r2[1]), &g0, &g1);
             box_muller(orc_u01(r2[2]), orc_u01(r2[3]), &g2, &g3);
             if (s->c.n_species > 1) {   /* with electrons only (a swarm) the ion is not followed */
-                rc = push_birth(&s->births[1], x, vt * g0, vt * g1, vt * g2);
+                rc = push_birth(&o->births[1], x, vt * g0, vt * g1, vt * g2);
                 if (rc) return rc;
             }
         }
@@ -941,7 +975,7 @@ static int collide(orc_sim* s, int k, uint32_t id, double x, double v[3])
  * emitted with probability gamma; normal speed from the flux-weighted
  * half-Maxwellian v_see sqrt(-2 ln u), tangential components Maxwellian,
  * advanced into the gap by u v_n dt. */
-static int emit_secondary(orc_sim* s, int k, uint32_t id, int wall)
+static int emit_secondary(const orc_sim* s, sink_t* o, int k, uint32_t id, int wall)
 {
     uint32_t r4[4], r5[4];
     draw(s, id, (uint32_t)s->step, k, 4u, r4);
@@ -952,12 +986,12 @@ static int emit_secondary(orc_sim* s, int k, uint32_t id, int wall)
     double adv = orc_u01(r4[2]) * vn * s->c.dt;
     double g0, g1;
     box_muller(orc_u01(r5[0]), orc_u01(r5[1]), &g0, &g1);
-    if (adv >= s->c.length) { s->cnt.dropped += 1; return ORC_OK; }
+    if (adv >= s->c.length) { o->cnt.dropped += 1; return ORC_OK; }
     double x = wall == 0 ? adv : s->c.length - adv;
     double vx = wall == 0 ? vn : -vn;
-    if (!(x >= 0.0 && x < s->c.length)) { s->cnt.dropped += 1; return ORC_OK; }
-    s->cnt.see_emitted[wall] += 1;
-    return push_birth(&s->births[0], x, vx, vsee * g0, vsee * g1);
+    if (!(x >= 0.0 && x < s->c.length)) { o->cnt.dropped += 1; return ORC_OK; }
+    o->cnt.see_emitted[wall] += 1;
+    return push_birth(&o->births[0], x, vx, vsee * g0, vsee * g1);
 }
 
 /* Energy histograms: bin floor(eps / width) with width = emax / ORC_EEPF_BINS;
@@ -1020,7 +1054,7 @@ static void sample_diagnostics(orc_sim* s)
  * |z| >= L_z the particle is re-injected at the same x with a fresh velocity
  * from the species' initial distribution (Maxwellian of scale vth plus the
  * drift), drawn with call 6, and z = 0. */
-static void renew(orc_sim* s, int k, uint32_t id, double v[3], double* z)
+static void renew(const orc_sim* s, sink_t* o, int k, uint32_t id, double v[3], double* z)
 {
     *z += v[2] * s->c.dt;
     if (fabs(*z) < s->c.renew_lz) return;
@@ -1034,67 +1068,104 @@ static void renew(orc_sim* s, int k, uint32_t id, double v[3], double* z)
     v[1] = sp->drift[1] + sp->vth * g1;
     v[2] = sp->drift[2] + sp->vth * g2;
     *z = 0.0;
-    s->cnt.renewed[k] += 1;
+    o->cnt.renewed[k] += 1;
 }
 
-/* One leapfrog step: for each species in order, each particle in index order:
- * gather E at x^n, Boris to v^{n+1/2}, move to x^{n+1}, wrap or absorb (with
- * secondary emission), collide.  Survivors keep their order; births follow,
- * in the order they were made, with ids from the species counter.  Then the
- * deposit, and the field at t^{n+1}. */
-static int one_step(orc_sim* s)
+/* One particle's step: gather E at x^n, Boris to v^{n+1/2}, move to x^{n+1},
+ * wrap or absorb (with secondary emission), renew, collide.  Returns 1 when
+ * the particle stays (x, v, z updated), 0 when it is absorbed; side effects
+ * go to the run's sink o. */
+static int step_particle(const orc_sim* s, sink_t* o, int k, uint32_t id, double* xp, double v[3], double* z)
 {
     double L = s->c.length, dt = s->c.dt;
-    int periodic = is_periodic(s);
-    for (int k = 0; k < s->c.n_species; ++k) s->births[k].n = 0;
-    for (int k = 0; k < s->c.n_species; ++k) {
-        pop_t* p = &s->p[k];
-        double qm = s->c.sp[k].charge / s->c.sp[k].mass;
-        double half_mw = 0.5 * s->c.sp[k].mass * s->c.sp[k].weight;
-        double ke = 0.0;
-        int64_t keep = 0;
-        for (int64_t j = 0; j < p->n; ++j) {
-            double x = p->x[j];
-            double v[3] = {p->vx[j], p->vy[j], p->vz[j]};
-            double vold2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-            double e[3] = {gather(s, x) + s->c.e_ext[0], s->c.e_ext[1], s->c.e_ext[2]};
-            orc_boris(v, e, s->c.b_ext, qm, dt);
-            double vnew2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-            ke += half_mw * 0.5 * (vold2 + vnew2);
-            x += v[0] * dt;
-            if (periodic) {
-                if (x < 0.0) x += L;
-                if (x >= L) x -= L;
-            } else if (x < 0.0 || x >= L) {
-                int wall = x < 0.0 ? 0 : 1;
-                s->cnt.absorbed[k][wall] += 1;
-                s->cnt.wall_energy[k][wall] += 0.5 * s->c.sp[k].mass * s->c.sp[k].weight * vnew2;
-                if (s->diag) {
-                    double eps = 0.5 * s->c.sp[k].mass * vnew2 / s->c.e_unit;
-                    tally(s->wedf[k][wall], eps, s->wedf_emax[k]);
-                    if (k == 0) tally(s->eepf[1], eps, s->eepf_emax);
-                }
-                if (k > 0 && s->c.sp[k].charge > 0.0 && s->c.see_gamma > 0.0) {
-                    int rc = emit_secondary(s, k, p->id[j], wall);
-                    if (rc) return rc;
-                }
-                continue;
-            }
-            double z = p->z[j];
-            if (s->c.renew_lz > 0.0) renew(s, k, p->id[j], v, &z);
-            if (s->nch[k] > 0) {
-                int rc = collide(s, k, p->id[j], x, v);
-                if (rc) return rc;
-            }
-            p->x[keep] = x;
-            p->vx[keep] = v[0]; p->vy[keep] = v[1]; p->vz[keep] = v[2];
-            p->z[keep] = z;
-            p->id[keep] = p->id[j];
-            keep += 1;
+    double qm = s->c.sp[k].charge / s->c.sp[k].mass;
+    double half_mw = 0.5 * s->c.sp[k].mass * s->c.sp[k].weight;
+    double x = *xp;
+    double vold2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double e[3] = {gather(s, x) + s->c.e_ext[0], s->c.e_ext[1], s->c.e_ext[2]};
+    orc_boris(v, e, s->c.b_ext, qm, dt);
+    double vnew2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    o->ke += half_mw * 0.5 * (vold2 + vnew2);
+    x += v[0] * dt;
+    if (is_periodic(s)) {
+        if (x < 0.0) x += L;
+        if (x >= L) x -= L;
+    } else if (x < 0.0 || x >= L) {
+        int wall = x < 0.0 ? 0 : 1;
+        o->cnt.absorbed[k][wall] += 1;
+        o->cnt.wall_energy[k][wall] += half_mw * vnew2;
+        if (s->diag) {
+            double eps = 0.5 * s->c.sp[k].mass * vnew2 / s->c.e_unit;
+            tally(o->wedf[wall], eps, s->wedf_emax[k]);
+            if (k == 0) tally(o->eepf_wall, eps, s->eepf_emax);
         }
-        p->n = keep;
-        s->ke[k] = ke;
+        if (k > 0 && s->c.sp[k].charge > 0.0 && s->c.see_gamma > 0.0) {
+            int rc = emit_secondary(s, o, k, id, wall);
+            if (rc && !o->rc) o->rc = rc;
+        }
+        return 0;
     }
+    if (s->c.renew_lz > 0.0) renew(s, o, k, id, v, z);
+    if (s->nch[k] > 0) {
+        int rc = collide(s, o, k, id, x, v);
+        if (rc && !o->rc) o->rc = rc;
+    }
+    *xp = x;
+    return 1;
+}
+
+static void run_reset(const orc_sim* s, sink_t* o)
+{
+    memset(&o->cnt, 0, sizeof(o->cnt));
+    for (int k = 0; k < ORC_MAX_SPECIES; ++k) o->births[k].n = 0;
+    o->ke = 0.0;
+    if (s->diag) {
+        memset(o->eepf_wall, 0, sizeof(o->eepf_wall));
+        memset(o->wedf, 0, sizeof(o->wedf));
+    }
+    o->keep = 0;
+    o->rc = ORC_OK;
+}
+
+/* Add a run of species k to the step's totals: counters, kinetic energy,
+ * histograms, and its births after the ones already made this step. */
+static int run_merge(orc_sim* s, int k, const sink_t* o)
+{
+    orc_counters* c = &s->cnt;
+    for (int q = 0; q < ORC_MAX_SPECIES; ++q) {
+        for (int w = 0; w < 2; ++w) {
+            c->absorbed[q][w] += o->cnt.absorbed[q][w];
+            c->wall_energy[q][w] += o->cnt.wall_energy[q][w];
+        }
+        c->candidates[q] += o->cnt.candidates[q];
+        c->nulls[q] += o->cnt.nulls[q];
+        for (int j = 0; j < ORC_MAX_CHAN; ++j) c->coll[q][j] += o->cnt.coll[q][j];
+        c->violations[q] += o->cnt.violations[q];
+        c->renewed[q] += o->cnt.renewed[q];
+    }
+    for (int w = 0; w < 2; ++w) c->see_emitted[w] += o->cnt.see_emitted[w];
+    c->dropped += o->cnt.dropped;
+    s->ke[k] += o->ke;
+    if (s->diag) {
+        for (int i = 0; i < ORC_EEPF_BINS; ++i) {
+            s->eepf[1][i] += o->eepf_wall[i];
+            s->wedf[k][0][i] += o->wedf[0][i];
+            s->wedf[k][1][i] += o->wedf[1][i];
+        }
+    }
+    for (int q = 0; q < ORC_MAX_SPECIES; ++q)
+        for (int64_t b = 0; b < o->births[q].n; ++b) {
+            const birth_t* bb = &o->births[q].b[b];
+            int rc = push_birth(&s->births[q], bb->x, bb->vx, bb->vy, bb->vz);
+            if (rc) return rc;
+        }
+    return o->rc;
+}
+
+/* The step's births appended after the survivors, in the order they were
+ * made, with ids from the species counter. */
+static int append_births(orc_sim* s)
+{
     int rc = ORC_OK;
     for (int k = 0; k < s->c.n_species; ++k) {
         pop_t* p = &s->p[k];
@@ -1107,13 +1178,230 @@ static int one_step(orc_sim* s)
             p->n += 1;
         }
     }
+    return rc;
+}
+
+static int grow_runs(orc_sim* s, int64_t n)
+{
+    if (n <= s->nruns) return ORC_OK;
+    sink_t* r = realloc(s->runs, (size_t)n * sizeof(sink_t));
+    if (!r) return ORC_ENOMEM;
+    memset(r + s->nruns, 0, (size_t)(n - s->nruns) * sizeof(sink_t));
+    s->runs = r;
+    s->nruns = n;
+    return ORC_OK;
+}
+
+static void deposit_chunks(orc_sim* s);
+static void sample_diagnostics_chunks(orc_sim* s);
+
+/* One leapfrog step: for each species in order, each particle in index order
+ * (step_particle).  Survivors keep their order; births follow, in the order
+ * they were made, with ids from the species counter.  Then the deposit, and
+ * the field at t^{n+1}.
+ *
+ * Sequential (threads == 0): one run per species, plain loops.  Parallel
+ * (threads > 0, OpenMP): the particles of a species in chunks of ORC_CHUNK,
+ * each its own run, survivors written to a second population and moved back
+ * in chunk order, runs merged in chunk order, the deposit and the sampled
+ * diagnostics summed per chunk and then over chunks in order; the result is
+ * the same for every thread count, and differs from the sequential one only
+ * in the rounding of those sums. */
+static int one_step(orc_sim* s)
+{
+    double dt = s->c.dt;
+    for (int k = 0; k < s->c.n_species; ++k) s->births[k].n = 0;
+    int rc = grow_runs(s, 1);
+    if (rc) return rc;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        pop_t* p = &s->p[k];
+        s->ke[k] = 0.0;
+        if (s->threads <= 0) {
+            sink_t* o = &s->runs[0];
+            run_reset(s, o);
+            int64_t keep = 0;
+            for (int64_t j = 0; j < p->n; ++j) {
+                double x = p->x[j];
+                double v[3] = {p->vx[j], p->vy[j], p->vz[j]};
+                double z = p->z[j];
+                if (!step_particle(s, o, k, p->id[j], &x, v, &z)) continue;
+                p->x[keep] = x;
+                p->vx[keep] = v[0]; p->vy[keep] = v[1]; p->vz[keep] = v[2];
+                p->z[keep] = z;
+                p->id[keep] = p->id[j];
+                keep += 1;
+            }
+            p->n = keep;
+            rc = run_merge(s, k, o);
+            if (rc) return rc;
+            continue;
+        }
+        int64_t nchunk = (p->n + ORC_CHUNK - 1) / ORC_CHUNK;
+        rc = grow_runs(s, nchunk);
+        if (rc) return rc;
+        pop_t* q = &s->spare[k];
+        if (q->cap < p->cap) {
+            free(q->x); free(q->vx); free(q->vy); free(q->vz); free(q->z); free(q->id);
+            rc = pop_alloc(q, p->cap);
+            if (rc) return rc;
+        }
+        #pragma omp parallel for schedule(dynamic, 1) num_threads(s->threads)
+        for (int64_t ck = 0; ck < nchunk; ++ck) {
+            sink_t* o = &s->runs[ck];
+            run_reset(s, o);
+            int64_t j0 = ck * ORC_CHUNK, j1 = j0 + ORC_CHUNK < p->n ? j0 + ORC_CHUNK : p->n;
+            for (int64_t j = j0; j < j1; ++j) {
+                double x = p->x[j];
+                double v[3] = {p->vx[j], p->vy[j], p->vz[j]};
+                double z = p->z[j];
+                if (!step_particle(s, o, k, p->id[j], &x, v, &z)) continue;
+                int64_t d = j0 + o->keep++;
+                q->x[d] = x;
+                q->vx[d] = v[0]; q->vy[d] = v[1]; q->vz[d] = v[2];
+                q->z[d] = z;
+                q->id[d] = p->id[j];
+            }
+        }
+        /* survivors back in chunk order */
+        int64_t keep = 0;
+        for (int64_t ck = 0; ck < nchunk; ++ck) {
+            int64_t kc = s->runs[ck].keep;
+            s->runs[ck].keep = keep;         /* now: the chunk's first survivor slot */
+            keep += kc;
+        }
+        #pragma omp parallel for schedule(static) num_threads(s->threads)
+        for (int64_t ck = 0; ck < nchunk; ++ck) {
+            int64_t d = s->runs[ck].keep, src = ck * ORC_CHUNK;
+            int64_t kc = (ck + 1 < nchunk ? s->runs[ck + 1].keep : keep) - d;
+            memcpy(p->x + d, q->x + src, (size_t)kc * sizeof(double));
+            memcpy(p->vx + d, q->vx + src, (size_t)kc * sizeof(double));
+            memcpy(p->vy + d, q->vy + src, (size_t)kc * sizeof(double));
+            memcpy(p->vz + d, q->vz + src, (size_t)kc * sizeof(double));
+            memcpy(p->z + d, q->z + src, (size_t)kc * sizeof(double));
+            memcpy(p->id + d, q->id + src, (size_t)kc * sizeof(uint32_t));
+        }
+        p->n = keep;
+        for (int64_t ck = 0; ck < nchunk; ++ck) {
+            rc = run_merge(s, k, &s->runs[ck]);
+            if (rc) return rc;
+        }
+    }
+    rc = append_births(s);
     s->step += 1;
-    deposit(s);
+    if (s->threads <= 0) deposit(s); else deposit_chunks(s);
     int rs = circuit_start(s, (double)s->step * dt);
     if (rs == ORC_OK) rs = solve(s, (double)s->step * dt, s->rho, s->phi, s->ef);
     s->fe = field_energy(s);
-    if (s->diag) sample_diagnostics(s);
+    if (s->diag) {
+        if (s->threads <= 0) sample_diagnostics(s); else sample_diagnostics_chunks(s);
+    }
     return rc != ORC_OK ? rc : rs;
+}
+
+/* The deposit of the parallel step: per chunk of particles, the sums of the
+ * linear weights at the nodes; then, node by node, the sum over chunks in
+ * chunk order. */
+static int grow_part(orc_sim* s, int64_t n)
+{
+    if (n <= s->npart) return ORC_OK;
+    double* p = realloc(s->part, (size_t)n * sizeof(double));
+    if (!p) return ORC_ENOMEM;
+    s->part = p;
+    s->npart = n;
+    return ORC_OK;
+}
+
+static void deposit_chunks(orc_sim* s)
+{
+    int nn = s->nn;
+    for (int i = 0; i < nn; ++i) s->rho[i] = s->c.rho_bg;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        const pop_t* p = &s->p[k];
+        double* S = s->sum[k];
+        int64_t nchunk = (p->n + ORC_CHUNK - 1) / ORC_CHUNK;
+        if (grow_part(s, nchunk * nn) != ORC_OK) { deposit(s); return; }
+        double* part = s->part;
+        #pragma omp parallel for schedule(static) num_threads(s->threads)
+        for (int64_t ck = 0; ck < nchunk; ++ck) {
+            double* P = part + ck * nn;
+            for (int i = 0; i < nn; ++i) P[i] = 0.0;
+            int64_t j1 = (ck + 1) * ORC_CHUNK < p->n ? (ck + 1) * ORC_CHUNK : p->n;
+            for (int64_t j = ck * ORC_CHUNK; j < j1; ++j) {
+                int64_t c, c1;
+                double f;
+                locate(s, p->x[j], &c, &c1, &f);
+                P[c] += 1.0 - f;
+                P[c1] += f;
+            }
+        }
+        #pragma omp parallel for schedule(static) num_threads(s->threads)
+        for (int i = 0; i < nn; ++i) {
+            double t = 0.0;
+            for (int64_t ck = 0; ck < nchunk; ++ck) t += part[ck * nn + i];
+            S[i] = t;
+        }
+        for (int i = 0; i < nn; ++i) {
+            s->dens[k][i] = s->c.sp[k].weight * S[i] / node_volume(s, i);
+            s->rho[i] += s->c.sp[k].charge * s->dens[k][i];
+        }
+    }
+}
+
+/* The sampled diagnostics of the parallel step: the electron energy at the
+ * nodes summed per chunk and over chunks in order, the bulk histogram per
+ * chunk (integers). */
+static void sample_diagnostics_chunks(orc_sim* s)
+{
+    int nn = s->nn;
+    for (int k = 0; k < s->c.n_species; ++k)
+        for (int i = 0; i < nn; ++i) s->av_dens[k][i] += s->dens[k][i];
+    for (int i = 0; i < nn; ++i) s->av_phi[i] += s->phi[i];
+    const pop_t* e = &s->p[0];
+    int64_t nchunk = (e->n + ORC_CHUNK - 1) / ORC_CHUNK;
+    if (grow_part(s, nchunk * nn) != ORC_OK || grow_runs(s, nchunk) != ORC_OK) {
+        /* no room for the chunk sums: undo this sample's fields, take it sequentially */
+        for (int k = 0; k < s->c.n_species; ++k)
+            for (int i = 0; i < nn; ++i) s->av_dens[k][i] -= s->dens[k][i];
+        for (int i = 0; i < nn; ++i) s->av_phi[i] -= s->phi[i];
+        sample_diagnostics(s);
+        return;
+    }
+    double* part = s->part;
+    int64_t lo, hi;
+    bulk_cells(s, &lo, &hi);
+    #pragma omp parallel for schedule(static) num_threads(s->threads)
+    for (int64_t ck = 0; ck < nchunk; ++ck) {
+        double* P = part + ck * nn;
+        int64_t* H = s->runs[ck].eepf_wall;          /* reused as this chunk's bulk histogram */
+        for (int i = 0; i < nn; ++i) P[i] = 0.0;
+        for (int i = 0; i < ORC_EEPF_BINS; ++i) H[i] = 0;
+        int64_t j1 = (ck + 1) * ORC_CHUNK < e->n ? (ck + 1) * ORC_CHUNK : e->n;
+        for (int64_t p = ck * ORC_CHUNK; p < j1; ++p) {
+            double v2 = e->vx[p] * e->vx[p] + e->vy[p] * e->vy[p] + e->vz[p] * e->vz[p];
+            double eps = 0.5 * s->c.sp[0].mass * v2 / s->c.e_unit;
+            int64_t c, c1;
+            double f;
+            locate(s, e->x[p], &c, &c1, &f);
+            P[c] += (1.0 - f) * eps;
+            P[c1] += f * eps;
+            if (c >= lo && c < hi) tally(H, eps, s->eepf_emax);
+        }
+    }
+    for (int i = 0; i < nn; ++i) {
+        double t = 0.0;
+        for (int64_t ck = 0; ck < nchunk; ++ck) t += part[ck * nn + i];
+        s->av_neps[i] += s->c.sp[0].weight * t / node_volume(s, i);
+    }
+    for (int64_t ck = 0; ck < nchunk; ++ck)
+        for (int i = 0; i < ORC_EEPF_BINS; ++i) s->eepf[0][i] += s->runs[ck].eepf_wall[i];
+    s->av_samples += 1.0;
+}
+
+int orc_set_threads(orc_sim* s, int32_t threads)
+{
+    if (!s || threads < 0) return ORC_EINVAL;
+    s->threads = threads;
+    return ORC_OK;
 }
 
 int orc_step(orc_sim* s, int32_t n)

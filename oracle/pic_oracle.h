@@ -120,6 +120,12 @@ int  orc_n_nodes(const orc_sim* s);
 int  orc_get_field(const orc_sim* s, double* rho, double* phi, double* efield);
 int  orc_get_density(const orc_sim* s, int32_t species, double* dens);
 int  orc_get_counters(const orc_sim* s, orc_counters* out);
+/* 0 (the default): the sequential step; n > 0: the parallel step on n OpenMP
+ * threads (fixed chunks of particles merged in chunk order: the same result
+ * for every n; only the order of the floating-point sums of the deposit,
+ * the kinetic energy, the wall energies and the sampled energy profile
+ * differs from the sequential step). */
+int  orc_set_threads(orc_sim* s, int32_t threads);
 /* Kinetic energy of each species at the last step (time-centred), field energy. */
 int  orc_get_energy(const orc_sim* s, double* ke_species, double* fe);
 int  orc_get_numax(const orc_sim* s, int32_t species, double* numax, uint32_t* t32);
