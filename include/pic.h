@@ -215,9 +215,14 @@ pic_status pic_poisson(pic_ctx* ctx, int32_t batch, double t_s, const double* rh
 #define PIC_DIAG_RESET_AVG 12   /* no output: clears the AVG, EEPF, POWER and WALL_EDF accumulators */
 #define PIC_DIAG_CHARGE 13      /* double[2]: total charge per unit area on the mesh, and from particle counts */
 
-#define PIC_DIAG_POWER 15       /* double[1 + 3 * S * n_nodes]: samples, then per species the time means of the particle flux density
-                                   Gamma = n <vx> (m^-2 s^-1), the x-momentum flux density n <vx^2> and the power density q Gamma E (W/m^3)
-                                   that the field gives the species (pic_set_diag; cleared with RESET_AVG) */
+#define PIC_DIAG_POWER 15       /* double[1 + 5 * S * n_nodes]: samples, then per species the time means of the particle flux density
+                                   Gamma = n <vx> (m^-2 s^-1), the x-momentum flux density n <vx^2>, the power density q Gamma E (W/m^3)
+                                   that the field (mesh and imposed) gives the species, and two terms of its decomposition (Section 1 names the power
+                                   terms; the momentum balance m dGamma/dt + d(m n <vx^2>)/dx = q n E + R times u = Gamma/n): the
+                                   inertia term u (m dGamma/dt + d(m Gamma^2/n)/dx) and the pressure term u dp/dx, p =
+                                   m (n <vx^2> - Gamma^2/n); the ohmic term is q Gamma E minus both.  dGamma/dt from the previous step's
+                                   flux when that step was sampled (else 0); gradients central, one-sided at a wall node
+                                   (pic_set_diag; cleared with RESET_AVG) */
 #define PIC_DIAG_WALL_ENERGY 16 /* double[2 * S]: kinetic energy carried into each wall (x < 0, x >= L) per species since pic_init, J/m^2
                                    (Section 1: walls; impact energies summed in 2^-20 eV fixed point) */
 #define PIC_DIAG_WALL_EDF 17    /* double[S * 2 * PIC_EEPF_BINS + S + 1]: per species and wall (x < 0, x >= L) the

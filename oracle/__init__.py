@@ -89,6 +89,7 @@ def lib():
         L.orc_set_circuit.argtypes = [P, C.c_double]
         L.orc_get_axial.argtypes = [P, C.c_int32, C.c_int64, dp]
         L.orc_set_step.argtypes = [P, C.c_uint64]
+        L.orc_get_power.argtypes = [P, C.c_int32, dp]
         L.orc_set_threads.argtypes = [P, C.c_int32]
         L.orc_get_step.argtypes = [P]
         L.orc_get_step.restype = C.c_uint64
@@ -304,6 +305,16 @@ class Oracle:
 
     def set_diag(self, enable=True, eepf_emax=64.0):
         _check(lib().orc_set_diag(self.h, int(enable), float(eepf_emax)), "orc_set_diag")
+
+    def power(self, s):
+        """Time means of species s's power terms at the nodes: flux, momentum
+        flux, q Gamma E, inertia, pressure, and the ohmic rest."""
+        n = self.n_nodes
+        o = np.zeros(5 * n)
+        _check(lib().orc_get_power(self.h, s, _dp(o)), "orc_get_power")
+        o = o.reshape(5, n)
+        return dict(flux=o[0], momentum=o[1], power=o[2], inertia=o[3], pressure=o[4],
+                    ohmic=o[2] - o[3] - o[4])
 
     def set_wall_edf(self, s, emax):
         _check(lib().orc_set_wall_edf(self.h, s, float(emax)), "orc_set_wall_edf")

@@ -104,6 +104,12 @@ struct orc_sim {
     double *av_phi, *av_neps;         /* potential; electron density times energy (eV) */
     double av_samples;
     int64_t eepf[2][ORC_EEPF_BINS];   /* electrons: bulk cells, wall impacts */
+    /* power decomposition: per species the time sums of flux, x-momentum
+     * flux, q Gamma E, inertia and pressure terms; the last sampled flux */
+    double* av_pw[ORC_MAX_SPECIES];    /* [5][nn] */
+    double* gprev[ORC_MAX_SPECIES];
+    double* pw_tmp;                    /* [4][nn]: Gamma, n <vx^2>, m Gamma^2 / n, p */
+    uint64_t pw_next;                  /* the step whose previous flux is stored (else none) */
     int64_t wedf[ORC_MAX_SPECIES][2][ORC_EEPF_BINS];
 };
 
@@ -407,9 +413,14 @@ int orc_create(const orc_config* cfg, orc_sim** out)
     if (!s->rho || !s->phi || !s->ef) rc = ORC_ENOMEM;
     for (int k = 0; k < cfg->n_species; ++k) {
         s->av_dens[k] = calloc((size_t)s->nn, sizeof(double));
-        if (!s->av_dens[k]) rc = ORC_ENOMEM;
+        s->av_pw[k] = calloc((size_t)5 * s->nn, sizeof(double));
+        s->gprev[k] = calloc((size_t)s->nn, sizeof(double));
+        if (!s->av_dens[k] || !s->av_pw[k] || !s->gprev[k]) rc = ORC_ENOMEM;
         s->wedf_emax[k] = k == 0 ? 64.0 : 1024.0;
     }
+    s->pw_tmp = calloc((size_t)4 * s->nn, sizeof(double));
+    if (!s->pw_tmp) rc = ORC_ENOMEM;
+    s->pw_next = UINT64_MAX;
     s->av_phi = calloc((size_t)s->nn, sizeof(double));
     s->av_neps = calloc((size_t)s->nn, sizeof(double));
     if (!s->av_phi || !s->av_neps) rc = ORC_ENOMEM;
@@ -426,6 +437,7 @@ void orc_free(orc_sim* s)
         free(s->p[k].x); free(s->p[k].vx); free(s->p[k].vy); free(s->p[k].vz); free(s->p[k].id);
         free(s->p[k].z);
         free(s->sum[k]); free(s->dens[k]); free(s->av_dens[k]);
+        free(s->av_pw[k]); free(s->gprev[k]);
         free(s->births[k].b);
         for (int j = 0; j < ORC_MAX_CHAN; ++j) { free(s->ch[k][j].e); free(s->ch[k][j].s); }
         free(s->spare[k].x); free(s->spare[k].vx); free(s->spare[k].vy); free(s->spare[k].vz);
@@ -435,6 +447,7 @@ void orc_free(orc_sim* s)
         for (int k = 0; k < ORC_MAX_SPECIES; ++k) free(s->runs[r].births[k].b);
     free(s->runs);
     free(s->part);
+    free(s->pw_tmp);
     free(s->rho); free(s->phi); free(s->ef); free(s->av_phi); free(s->av_neps);
     free(s);
 }
@@ -1048,6 +1061,123 @@ static void sample_diagnostics(orc_sim* s)
     s->av_samples += 1.0;
 }
 
+/* The power the field gives each species, and its decomposition (the paper
+ * names the power terms without formulas; the reading is the momentum
+ * balance of the species, m dGamma/dt + d(m n <vx^2>)/dx = q n E + R, times
+ * its mean velocity u = Gamma / n):
+ *   q Gamma E = u (m dGamma/dt + d(m Gamma^2/n)/dx)   inertia
+ *             + u dp/dx,  p = m (n <vx^2> - Gamma^2/n)  pressure
+ *             + ohmic (the rest: -u R, the momentum lost in collisions).
+ * Gamma = w sum_p S_i(x_p) vx_p / V_i and n <vx^2> likewise, at the state
+ * the step ends with; dGamma/dt by the flux of the previous step when that
+ * step was sampled, else 0; gradients central inside, one-sided at a wall
+ * node; E is the mesh field plus the imposed one.  Accumulated per node:
+ * Gamma, n <vx^2>, q Gamma E, inertia, pressure.  flux and mom hold species
+ * k's Gamma and n <vx^2>. */
+static void sample_power(orc_sim* s, int k, const double* flux, const double* mom, int prev)
+{
+    int nn = s->nn, periodic = is_periodic(s);
+    double m = s->c.sp[k].mass, dt = s->c.dt;
+    double* kt = s->pw_tmp + 2 * nn;
+    double* pt = s->pw_tmp + 3 * nn;
+    for (int i = 0; i < nn; ++i) {
+        double n = s->dens[k][i];
+        kt[i] = n > 0.0 ? m * flux[i] * flux[i] / n : 0.0;
+        pt[i] = m * mom[i] - kt[i];
+    }
+    double* av = s->av_pw[k];
+    for (int i = 0; i < nn; ++i) {
+        int il, ir;
+        double h;
+        if (periodic) {
+            il = i == 0 ? nn - 1 : i - 1;
+            ir = i == nn - 1 ? 0 : i + 1;
+            h = 2.0 * s->dx;
+        } else {
+            il = i > 0 ? i - 1 : i;
+            ir = i < nn - 1 ? i + 1 : i;
+            h = (double)(ir - il) * s->dx;
+        }
+        double n = s->dens[k][i];
+        double u = n > 0.0 ? flux[i] / n : 0.0;
+        double dgdt = prev ? (flux[i] - s->gprev[k][i]) / dt : 0.0;
+        av[i] += flux[i];
+        av[nn + i] += mom[i];
+        av[2 * nn + i] += s->c.sp[k].charge * flux[i] * (s->ef[i] + s->c.e_ext[0]);
+        av[3 * nn + i] += u * (m * dgdt + (kt[ir] - kt[il]) / h);
+        av[4 * nn + i] += u * (pt[ir] - pt[il]) / h;
+        s->gprev[k][i] = flux[i];
+    }
+}
+
+static int grow_part(orc_sim* s, int64_t n);
+
+/* The sequential sample of every species' power terms. */
+static void sample_power_all(orc_sim* s)
+{
+    int prev = s->pw_next == s->step;
+    double* flux = s->pw_tmp;
+    double* mom = s->pw_tmp + s->nn;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        orc_get_moments(s, k, flux, mom);
+        sample_power(s, k, flux, mom, prev);
+    }
+    s->pw_next = s->step + 1;
+}
+
+/* The same with the moments summed per chunk of particles and over chunks
+ * in order (the parallel step). */
+static void sample_power_chunks(orc_sim* s)
+{
+    int nn = s->nn, prev = s->pw_next == s->step;
+    double* flux = s->pw_tmp;
+    double* mom = s->pw_tmp + nn;
+    for (int k = 0; k < s->c.n_species; ++k) {
+        const pop_t* p = &s->p[k];
+        int64_t nchunk = (p->n + ORC_CHUNK - 1) / ORC_CHUNK;
+        if (grow_part(s, nchunk * 2 * nn) != ORC_OK) {
+            orc_get_moments(s, k, flux, mom);
+            sample_power(s, k, flux, mom, prev);
+            continue;
+        }
+        double* part = s->part;
+        #pragma omp parallel for schedule(static) num_threads(s->threads)
+        for (int64_t ck = 0; ck < nchunk; ++ck) {
+            double* F = part + ck * 2 * nn;
+            double* M = F + nn;
+            for (int i = 0; i < 2 * nn; ++i) F[i] = 0.0;
+            int64_t j1 = (ck + 1) * ORC_CHUNK < p->n ? (ck + 1) * ORC_CHUNK : p->n;
+            for (int64_t j = ck * ORC_CHUNK; j < j1; ++j) {
+                int64_t c, c1;
+                double f, vx = p->vx[j];
+                locate(s, p->x[j], &c, &c1, &f);
+                F[c] += (1.0 - f) * vx;
+                F[c1] += f * vx;
+                M[c] += (1.0 - f) * vx * vx;
+                M[c1] += f * vx * vx;
+            }
+        }
+        for (int i = 0; i < nn; ++i) {
+            double a = 0.0, b = 0.0;
+            for (int64_t ck = 0; ck < nchunk; ++ck) {
+                a += part[ck * 2 * nn + i];
+                b += part[ck * 2 * nn + nn + i];
+            }
+            flux[i] = a * s->c.sp[k].weight / node_volume(s, i);
+            mom[i] = b * s->c.sp[k].weight / node_volume(s, i);
+        }
+        sample_power(s, k, flux, mom, prev);
+    }
+    s->pw_next = s->step + 1;
+}
+
+int orc_get_power(const orc_sim* s, int32_t k, double* out)
+{
+    if (!s || k < 0 || k >= s->c.n_species || !out) return ORC_EINVAL;
+    for (int i = 0; i < 5 * s->nn; ++i) out[i] = s->av_samples > 0.0 ? s->av_pw[k][i] / s->av_samples : 0.0;
+    return ORC_OK;
+}
+
 /* Axial renewal (Lafleur, Baalrud and Chabert): each particle carries the
  * virtual displacement z along the imposed field's axis (the third velocity
  * component) since its injection, advanced with the new velocity; once
@@ -1293,7 +1423,13 @@ static int one_step(orc_sim* s)
     if (rs == ORC_OK) rs = solve(s, (double)s->step * dt, s->rho, s->phi, s->ef);
     s->fe = field_energy(s);
     if (s->diag) {
-        if (s->threads <= 0) sample_diagnostics(s); else sample_diagnostics_chunks(s);
+        if (s->threads <= 0) {
+            sample_power_all(s);
+            sample_diagnostics(s);
+        } else {
+            sample_power_chunks(s);
+            sample_diagnostics_chunks(s);
+        }
     }
     return rc != ORC_OK ? rc : rs;
 }
@@ -1504,7 +1640,10 @@ int orc_set_wall_edf(orc_sim* s, int32_t k, double emax_ev)
 int orc_reset_avg(orc_sim* s)
 {
     if (!s) return ORC_EINVAL;
-    for (int k = 0; k < s->c.n_species; ++k) memset(s->av_dens[k], 0, (size_t)s->nn * sizeof(double));
+    for (int k = 0; k < s->c.n_species; ++k) {
+        memset(s->av_dens[k], 0, (size_t)s->nn * sizeof(double));
+        memset(s->av_pw[k], 0, (size_t)5 * s->nn * sizeof(double));
+    }
     memset(s->av_phi, 0, (size_t)s->nn * sizeof(double));
     memset(s->av_neps, 0, (size_t)s->nn * sizeof(double));
     memset(s->eepf, 0, sizeof(s->eepf));

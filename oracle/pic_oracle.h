@@ -126,6 +126,11 @@ int  orc_get_counters(const orc_sim* s, orc_counters* out);
  * the kinetic energy, the wall energies and the sampled energy profile
  * differs from the sequential step). */
 int  orc_set_threads(orc_sim* s, int32_t threads);
+/* Time means (since the last reset) of species k's power terms at the
+ * nodes, [5][n_nodes]: flux Gamma, x-momentum flux n <vx^2>, q Gamma E, the
+ * inertia term and the pressure term (the ohmic term is q Gamma E minus
+ * both). */
+int  orc_get_power(const orc_sim* s, int32_t k, double* out);
 /* Kinetic energy of each species at the last step (time-centred), field energy. */
 int  orc_get_energy(const orc_sim* s, double* ke_species, double* fe);
 int  orc_get_numax(const orc_sim* s, int32_t species, double* numax, uint32_t* t32);

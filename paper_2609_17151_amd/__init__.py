@@ -315,12 +315,14 @@ class Sim:
         return self.diag("WALL_ENERGY", 2 * self.S, batch=batch).reshape(self.S, 2)
 
     def power(self, batch=0):
-        """Time means per species: flux density, x-momentum flux density and
-        the power density q Gamma E the field gives the species."""
+        """Time means per species: flux density, x-momentum flux density, the
+        power density q Gamma E the field gives the species and its
+        decomposition into inertia, pressure and the ohmic rest."""
         n = self.n_nodes[batch]
-        o = self.diag("POWER", 1 + 3 * self.S * n, batch=batch)
-        p = o[1:].reshape(self.S, 3, n)
-        return dict(samples=o[0], flux=p[:, 0], momentum=p[:, 1], power=p[:, 2])
+        o = self.diag("POWER", 1 + 5 * self.S * n, batch=batch)
+        p = o[1:].reshape(self.S, 5, n)
+        return dict(samples=o[0], flux=p[:, 0], momentum=p[:, 1], power=p[:, 2], inertia=p[:, 3],
+                    pressure=p[:, 4], ohmic=p[:, 2] - p[:, 3] - p[:, 4])
 
     def eepf(self, batch=0):
         o = self.diag("EEPF", 2 * EEPF_BINS + 2, batch=batch)

@@ -553,6 +553,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         for (int s = 0; s < S; ++s) {
             dc.dens_coef[s] = c.species[s].weight / dc.dx / kDepScale;
             dc.q[s] = c.species[s].charge;
+            dc.mass[s] = c.species[s].mass;
             dc.flux_coef[s] = c.species[s].weight / dc.dx / (kMomentScale / moment_vref(c, s));
             dc.mom_coef[s] = c.species[s].weight / dc.dx / (kMomentScale / (moment_vref(c, s) * moment_vref(c, s)));
         }
@@ -591,7 +592,9 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         d.cnt = (unsigned long long*)A(8ull * B * S * kRep * C_N);
         d.eacc = (unsigned long long*)A(8ull * B * nodes_max);
         d.macc = (unsigned long long*)A(8ull * B * S * 2 * nodes_max);
-        d.pavg = (double*)A(8ull * B * S * 3 * nodes_max);
+        d.pavg = (double*)A(8ull * B * S * kPow * nodes_max);
+        d.gprev = (double*)A(8ull * B * S * nodes_max);
+        d.ptmp = (double*)A(8ull * B * 2 * nodes_max);
         d.wen = (unsigned long long*)A(8ull * B * S * 2);
         d.rho = (double*)A(8ull * B * nodes_max);
         d.phi = (double*)A(8ull * B * nodes_max);
@@ -633,6 +636,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         }
     std::vector<DisState> ds(B);
     std::memset(ds.data(), 0, ds.size() * sizeof(DisState));
+    for (int b = 0; b < B; ++b) ds[b].pw_next = ~0ull;     // no flux sampled yet
     hipStream_t st = ctx->stream;
     bool ok = hipMemcpy(d.segc, ctx->segc.data(), sizeof(SegConst) * B * S, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(d.segs, ss.data(), sizeof(SegState) * B * S, hipMemcpyHostToDevice) == hipSuccess;
@@ -642,7 +646,8 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
     ok = ok && hipMemsetAsync(d.cnt, 0, 8ull * B * S * kRep * C_N, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eacc, 0, 8ull * B * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.macc, 0, 8ull * B * S * 2 * nodes_max, st) == hipSuccess;
-    ok = ok && hipMemsetAsync(d.pavg, 0, 8ull * B * S * 3 * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.pavg, 0, 8ull * B * S * kPow * nodes_max, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.gprev, 0, 8ull * B * S * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.wen, 0, 8ull * B * S * 2, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.avg, 0, 8ull * B * (S + 2) * nodes_max, st) == hipSuccess;
     ok = ok && hipMemsetAsync(d.eepf, 0, 8ull * B * 2 * kEepfBins, st) == hipSuccess;
@@ -1510,7 +1515,7 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
         }
         case PIC_DIAG_RESET_AVG: {
             ok = hipMemset(ctx->d.avg + (size_t)batch * (S + 2) * nm, 0, 8ull * (S + 2) * nm) == hipSuccess;
-            ok = ok && hipMemset(ctx->d.pavg + (size_t)batch * S * 3 * nm, 0, 8ull * S * 3 * nm) == hipSuccess;
+            ok = ok && hipMemset(ctx->d.pavg + (size_t)batch * S * kPow * nm, 0, 8ull * S * kPow * nm) == hipSuccess;
             ok = ok && hipMemset(ctx->d.eepf + (size_t)batch * 2 * kEepfBins, 0, 8ull * 2 * kEepfBins) == hipSuccess;
             ok = ok && hipMemset(ctx->d.wedf + (size_t)batch * S * 2 * kEepfBins, 0, 8ull * S * 2 * kEepfBins) ==
                            hipSuccess;
@@ -1566,17 +1571,17 @@ pic_status pic_diag(pic_ctx* ctx, int32_t batch, int32_t what, void* out, size_t
             break;
         }
         case PIC_DIAG_POWER: {
-            if (!need(8ull * (1 + (size_t)3 * S * nn))) return PIC_EINVAL;
-            std::vector<double> pv((size_t)S * 3 * nm);
-            ok = d2h(pv.data(), ctx->d.pavg + (size_t)batch * S * 3 * nm, pv.size() * 8);
+            if (!need(8ull * (1 + (size_t)kPow * S * nn))) return PIC_EINVAL;
+            std::vector<double> pv((size_t)S * kPow * nm);
+            ok = d2h(pv.data(), ctx->d.pavg + (size_t)batch * S * kPow * nm, pv.size() * 8);
             const double ns = ds.avg_samples;
             double* o = (double*)out;
             o[0] = ns;
             for (int sp = 0; sp < S; ++sp)
-                for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < kPow; ++k)
                     for (int i = 0; i < nn; ++i) {
-                        const double v = pv[((size_t)sp * 3 + k) * nm + i];
-                        o[1 + ((size_t)sp * 3 + k) * nn + i] = ns > 0.0 ? v / ns : 0.0;
+                        const double v = pv[((size_t)sp * kPow + k) * nm + i];
+                        o[1 + ((size_t)sp * kPow + k) * nn + i] = ns > 0.0 ? v / ns : 0.0;
                     }
             break;
         }

@@ -470,18 +470,64 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
             av[(size_t)(S + 1) * d.nodes_max + i] += (double)ea[i] * ecoef * wall;   // n_e <eps>
             ea[i] = 0ull;
-            // flux, momentum flux and the power the new field gives each species
-            const double e = efield(i);
-            for (int s = 0; s < S; ++s) {
-                unsigned long long* ma = d.macc + ((size_t)b * S + s) * 2 * d.nodes_max;
-                double* pv = d.pavg + ((size_t)b * S + s) * 3 * d.nodes_max;
+        }
+        // flux, momentum flux and the power the new field gives each species,
+        // and the power decomposition of the electron (and ion) momentum
+        // balance, m dGamma/dt + d(m n <vx^2>)/dx = q n E + R, multiplied by
+        // u = Gamma / n: inertia u (m dGamma/dt + d(m Gamma^2 / n)/dx),
+        // pressure u dp/dx with p = m (n <vx^2> - Gamma^2 / n), and the ohmic
+        // part q Gamma E - inertia - pressure (formed by the reader).  The time
+        // derivative uses the flux of the previous step when that step was
+        // sampled; gradients are central inside, one-sided at a wall node.
+        const bool prev = ds.pw_next == ds.step;
+        double* kt = d.ptmp + (size_t)b * 2 * d.nodes_max;    // m Gamma^2 / n and p at the nodes
+        double* pt = kt + d.nodes_max;
+        for (int s = 0; s < S; ++s) {
+            unsigned long long* ma = d.macc + ((size_t)b * S + s) * 2 * d.nodes_max;
+            double* pv = d.pavg + ((size_t)b * S + s) * kPow * d.nodes_max;
+            const double* dn = d.dens + ((size_t)b * S + s) * d.nodes_max;
+            double* gp = d.gprev + ((size_t)b * S + s) * d.nodes_max;
+            const double m = dc.mass[s];
+            __syncthreads();                             // the previous species' gradients are read
+            for (int i = tid; i < nn; i += kFT) {
+                const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
+                const double G = (double)(long long)ma[i] * dc.flux_coef[s] * wall;
+                const double M = (double)(long long)ma[d.nodes_max + i] * dc.mom_coef[s] * wall;
+                const double nd = dn[i];
+                const double K = nd > 0.0 ? m * G * G / nd : 0.0;
+                kt[i] = K;
+                pt[i] = m * M - K;
+            }
+            __threadfence_block();
+            __syncthreads();
+            for (int i = tid; i < nn; i += kFT) {
+                const double wall = (!periodic && (i == 0 || i == nn - 1)) ? 2.0 : 1.0;
                 const double G = (double)(long long)ma[i] * dc.flux_coef[s] * wall;
                 const double M = (double)(long long)ma[d.nodes_max + i] * dc.mom_coef[s] * wall;
                 ma[i] = 0ull;
                 ma[d.nodes_max + i] = 0ull;
+                const double e = efield(i) + dc.e_ext[0];   // the mesh field and the imposed one
+                const double nd = dn[i];
+                const double u = nd > 0.0 ? G / nd : 0.0;
+                int il, ir;
+                double h;
+                if (periodic) {
+                    il = i == 0 ? nn - 1 : i - 1;
+                    ir = i == nn - 1 ? 0 : i + 1;
+                    h = 2.0 * dc.dx;
+                } else {
+                    il = i > 0 ? i - 1 : i;
+                    ir = i < nn - 1 ? i + 1 : i;
+                    h = (double)(ir - il) * dc.dx;
+                }
+                const double dk = (kt[ir] - kt[il]) / h, dp = (pt[ir] - pt[il]) / h;
+                const double dgdt = prev ? (G - gp[i]) / dc.dt : 0.0;
                 pv[i] += G;
-                pv[d.nodes_max + i] += M;
+                pv[(size_t)d.nodes_max + i] += M;
                 pv[2 * (size_t)d.nodes_max + i] += dc.q[s] * G * e;
+                pv[3 * (size_t)d.nodes_max + i] += u * (m * dgdt + dk);
+                pv[4 * (size_t)d.nodes_max + i] += u * dp;
+                gp[i] = G;
             }
         }
         // an RF window ends with this step: its sums go to the ring (each
@@ -509,6 +555,7 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         }
         if (a.mode == kFinStep) {
             if (a.diag) {
+                ds.pw_next = ds.step + 1;                // this step's flux is stored
                 ds.avg_samples += 1.0;
                 ds.eepf_samples += 1.0;
                 if (win_closed) {

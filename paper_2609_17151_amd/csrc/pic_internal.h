@@ -26,6 +26,7 @@ constexpr int kTileMin = 256;                               // smallest tile of 
 constexpr int kBirthsDiv = 16;                              // a tile stages up to T / 16 births per step
 constexpr int kBirthsPerTileMin = kTileMin / kBirthsDiv;
 constexpr int kMaxPushGrid = 4096;                          // workgroups of a push launch
+constexpr int kPow = 5;                                     // power time sums per species and node
 
 // latched device flags
 constexpr uint32_t kFlagCapacity = 1u << 0;
@@ -115,6 +116,7 @@ struct DisConst {
     double dens_coef[kMaxSpecies];   // weight / dx / 2^32 (interior node; twice at a wall node)
     double q[kMaxSpecies];     // species charge
     double flux_coef[kMaxSpecies], mom_coef[kMaxSpecies];   // moment sums -> densities (interior node)
+    double mass[kMaxSpecies];  // species mass (power decomposition)
     uint32_t key0, key1;
     int32_t bulk_lo, bulk_hi;  // cells of the bulk electron energy distribution
     // drive of the electrode at x = 0
@@ -148,6 +150,7 @@ struct DisState {
     double qbase;           // circuit: conductor charge minus the source's and the particles' since the start
     int32_t circ_init;      // circuit: qbase set
     int64_t win_len, win_start, nwin;   // RF windows: length in steps (0 = off), first step, windows done
+    uint64_t pw_next;       // power decomposition: the step whose previous flux is stored (else none)
 };
 
 // The source of the electrode at x = 0: its voltage V(t), and the charge per
@@ -197,7 +200,10 @@ struct DevPtrs {
     unsigned long long* cnt;     // [B][S][kRep][C_N] event counters
     unsigned long long* eacc;    // [B][nodes_max] electron energy deposit (eV, fixed point 2^20)
     unsigned long long* macc;    // [B][S][2][nodes_max] flux and x-momentum flux sums of the step (fixed point)
-    double* pavg;                // [B][S][3][nodes_max] time sums of flux, momentum flux, power density
+    double* pavg;                // [B][S][kPow][nodes_max] time sums: flux, momentum flux, power density,
+                                 // inertia and pressure terms of the power decomposition
+    double* gprev;               // [B][S][nodes_max] the flux of the last sampled step
+    double* ptmp;                // [B][2][nodes_max] node scratch of the decomposition's gradients
     unsigned long long* wen;     // [B][S][2] kinetic energy carried into each wall (eV, fixed point 2^20)
     double* rho;                 // [B][nodes_max]
     double* phi;

@@ -187,3 +187,38 @@ def test_wall_edf_rejects_bad_ranges(pic):
     for s, e in ((2, 10.0), (-1, 10.0), (0, 0.0), (1, float("nan")), (0, float("inf"))):
         with pytest.raises(RuntimeError):
             sim.set_wall_edf(s, e)
+
+
+def test_power_decomposition_matches_oracle(pic):
+    """The decomposition of q Gamma E into inertia, pressure and the ohmic
+    rest (momentum balance times Gamma / n), GPU against oracle: from
+    identical states one sampled step stores the flux, then one more gives a
+    sample with the time derivative.  Compared where the species' density is
+    at least 5 % of its maximum (the terms divide by n)."""
+    cfg, tabs = small_argon(n_init=20000)
+    sim = pic.Sim(cfg, tabs)
+    sim.step(400)
+    o = to_oracle(sim, cfg, tabs)
+    sim.set_diag(True)
+    o.set_diag(True)
+    sim.step(1)
+    o.step(1)
+    sim.reset_avg()
+    o.reset_avg()
+    sim.step(1)
+    o.step(1)
+    pw = sim.power()
+    assert pw["samples"] == 1.0
+    for s in range(2):
+        po = o.power(s)
+        dens = o.density(s)
+        keep = dens >= 0.05 * dens.max()
+        for what in ("power", "inertia", "pressure", "ohmic"):
+            g, r = pw[what][s], po[what]
+            scale = np.max(np.abs(po["power"][keep]))
+            err = np.max(np.abs(g - r)[keep]) / scale
+            print("species %d %-8s max |GPU - oracle| / max|q Gamma E| = %.3g" % (s, what, err), flush=True)
+            assert err <= 1e-4, (s, what, err)
+        # the closure holds on each side
+        np.testing.assert_allclose(pw["inertia"][s] + pw["pressure"][s] + pw["ohmic"][s], pw["power"][s],
+                                   rtol=1e-12, atol=1e-12 * np.max(np.abs(pw["power"][s])))
