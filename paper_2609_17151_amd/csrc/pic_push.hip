@@ -27,9 +27,11 @@
 // compaction every few steps removes them.  Holes do not change the order of
 // the live particles, and births are appended after the last slot in the
 // order of their parents, so the particle order after a compaction is the
-// order that compacting every step would give.  Births are staged per tile in
-// the order of their parents' slots by the events kernel and appended by the
-// finalize in tile order, which also gives their ids.
+// order that compacting every step would give.  The events kernel stages a
+// tile's births in any order, each with a key made of its parent's slot and
+// its rank among that parent's births; the finalize writes each birth at the
+// rank of its key within its tile, the tiles in order, which also gives their
+// ids.
 //
 // Deposition: LDS histogram in 64-bit fixed point flushed with integer
 // atomics (births add theirs with integer atomics too), so sums are exact and

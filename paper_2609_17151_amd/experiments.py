@@ -6,6 +6,7 @@ started from the learned warm start.
     python -m paper_2609_17151_amd.experiments train   --data t0.npz t1.npz ... --out model.npz
     python -m paper_2609_17151_amd.experiments sweep   --set heldout --out cold.npz
     python -m paper_2609_17151_amd.experiments warm    --model model.npz --cold cold.npz --out warm.npz
+    python -m paper_2609_17151_amd.experiments plainset --cold cold.npz --warm warm.npz --out plain.npz
 
 Converged (steady): the 5-period windows stay within 2 % (relative L2, each
 of n_e, n_i, <eps> at 256 points; or three times the windows' own scatter
@@ -226,6 +227,49 @@ def cmd_warm(a):
     print(json.dumps(out), flush=True)
 
 
+def cmd_plainset(a):
+    """The plain method for the held-out draws: each draw alone in its own
+    context (one discharge, cold start, the seed of its cold batched run, so
+    the same discharge), stepped until it has converged to its cold run's
+    reference under the same rule, or for --periods; the wall time of each.
+    With --warm, only the draws that converged warm (the comparison's set)."""
+    cold = np.load(a.cold)
+    summ = cold_summary(cold)
+    draws = SETS["heldout"]()
+    keep = [k for k in range(len(cold["ids"])) if summ[k]["alive"]]
+    if a.warm:
+        w = np.load(a.warm)
+        done = {int(i) for i, c in zip(w["ids"], w["conv"]) if c > 0}
+        keep = [k for k in keep if int(cold["ids"][k]) in done]
+    keep = keep[a.first:a.first + a.count] if a.count else keep[a.first:]
+    ids, secs, per, steps = [], [], [], []
+    for k in keep:
+        i = int(cold["ids"][k])
+        ref = steady.from_features(cold["y"][k])
+        tol = summ[k]["tol"]
+        cfg = warm.config(draws[i], weight=weight_of(draws[i], a), seed=1000 + i, capacity=a.capacity)
+        sim = _sim([cfg])
+        t0 = time.perf_counter()
+
+        def stop(j, sw):
+            return steady.converged_at(sw.windows[j], ref, tol=tol) is not None
+
+        sw = Sweep(sim, [warm.steps_per_period(draws[i])], max_periods=a.periods, progress=0.0).run(stop=stop)
+        wall = time.perf_counter() - t0
+        c, p_ = convergence(sw.windows[0], ref, tol)
+        ids.append(i)
+        per.append(p_ if p_ is not None else -1)
+        secs.append(sw.window_time[0][c] if c is not None else -1.0)
+        steps.append(sw.window_step[0][c] if c is not None else -1)
+        print(json.dumps(dict(draw=i, periods=per[-1], cold_periods=summ[k]["periods"], seconds=secs[-1],
+                              wall=wall, counts=sim.counts(0)["count"])), flush=True)
+        sim.close()
+        np.savez(a.out, ids=np.array(ids), periods=np.array(per), seconds=np.array(secs), steps=np.array(steps))
+    done = [s for s in secs if s > 0]
+    print(json.dumps(dict(kind="plainset", draws=len(ids), converged=len(done), seconds=float(np.sum(done)),
+                          seconds_per_converged_discharge=float(np.mean(done)) if done else None)), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="experiments")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -258,8 +302,18 @@ def main(argv=None):
     p.add_argument("--weight-law", choices=["fixed", "f2"], default="fixed")
     p.add_argument("--capacity", type=int, default=1 << 20)
     p.add_argument("--out", required=True)
+    p = sub.add_parser("plainset")
+    p.add_argument("--cold", required=True)
+    p.add_argument("--warm", default=None)
+    p.add_argument("--first", type=int, default=0)
+    p.add_argument("--count", type=int, default=0)
+    p.add_argument("--periods", type=int, default=1200)
+    p.add_argument("--weight-scale", type=float, default=1.0)
+    p.add_argument("--weight-law", choices=["fixed", "f2"], default="fixed")
+    p.add_argument("--capacity", type=int, default=1 << 20)
+    p.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    dict(plain=cmd_plain, sweep=cmd_sweep, train=cmd_train, warm=cmd_warm)[a.cmd](a)
+    dict(plain=cmd_plain, sweep=cmd_sweep, train=cmd_train, warm=cmd_warm, plainset=cmd_plainset)[a.cmd](a)
 
 
 if __name__ == "__main__":
