@@ -156,14 +156,26 @@ def timed_rate(sim, torch, steps):
                 kernel_us={"push": per("push"), "events": per("events"), "finalize": per("finalize")})
 
 
-def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True):
+def tuned(sim, tune):
+    """The autotuner's schedule for the workload (timed on the live run), or
+    the default one; returns what ran: the choice and each candidate's time."""
+    if not tune:
+        return dict(choice="default")
+    from paper_2609_17151_amd import autotune
+    choice, table = autotune.tune(sim, steps=32, warm=16)
+    return dict(choice=choice, us_per_step={"%d/%d/%d" % (r["ppt"], r["threads"], r["compact_every"]):
+                                            round(1e3 * r["ms_per_step"], 2) for r in table})
+
+
+def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True):
     """The bounded, colliding path at steady-state counts: one argon RF
     discharge (2.5 cm, 30 mTorr, 200 V, 13.56 MHz, 1600 steps per period,
     2e5 macro-particles per species) and the sweep of 64 such discharges
     (10-200 mTorr, 100-400 V, 1.5-4 cm; 5e4-2e6 per species, seeded) in one
     batched step.  Each discharge starts from a half-sine density at those
     counts (electrons 3 eV, ions at the gas temperature) and runs `warm`
-    steps before it is timed."""
+    steps before it is timed; with `tune` the autotuner then picks the step
+    schedule (tile shape and compaction interval) on the live run."""
     out = {}
     dens, temp = W.discharge_profile()
     if only in (None, "argon_rf"):
@@ -172,7 +184,8 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True):
         sim.use_graphs(graphs)
         sim.load_profiles(dens, temp, [n, n])
         sim.step(warm)
-        out["argon_rf_single"] = timed_rate(sim, torch, steps)
+        sched = tuned(sim, tune)
+        out["argon_rf_single"] = dict(timed_rate(sim, torch, steps), schedule=sched)
         sim.close()
     if only not in (None, "argon_sweep"):
         return out
@@ -185,7 +198,8 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True):
     for b in range(64):
         sim.load_profiles(dens, temp, [counts[b], counts[b]], batch=b)
     sim.step(warm)
-    out["argon_rf_batched_64"] = timed_rate(sim, torch, steps)
+    sched = tuned(sim, tune)
+    out["argon_rf_batched_64"] = dict(timed_rate(sim, torch, steps), schedule=sched)
     sim.close()
     return out
 
@@ -206,6 +220,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps on all host threads")
     ap.add_argument("--cpu-steps-one", type=int, default=60, help="oracle steps of the sequential step")
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
+    ap.add_argument("--no-tune", action="store_true", help="argon lines: the default schedule, no autotuning")
     ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
                     help="argon_rf / argon_sweep: only that secondary workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -231,7 +246,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "exb":
         r = secondary(P, W, torch, args.secondary_steps, only=args.workload, warm=args.secondary_warm,
-                      graphs=not args.no_graph)
+                      graphs=not args.no_graph, tune=not args.no_tune)
         print(json.dumps(dict(workload=args.workload, **r[next(iter(r))])), flush=True)
         return
     cfg = W.exb()
@@ -297,7 +312,8 @@ def main():
     }
     if not args.no_secondary:
         sim.close()
-        out["secondary"] = secondary(P, W, torch, args.secondary_steps, warm=args.secondary_warm, graphs=not args.no_graph)
+        out["secondary"] = secondary(P, W, torch, args.secondary_steps, warm=args.secondary_warm,
+                                     graphs=not args.no_graph, tune=not args.no_tune)
     if not args.no_cpu:
         sim.close()
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps, args.cpu_steps_one)

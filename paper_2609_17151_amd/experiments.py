@@ -60,6 +60,12 @@ def convergence(windows, ref, tol=steady.TOL, window_periods=5):
     return (None, None) if i is None else (i, (i + 1) * window_periods)
 
 
+def _tuning(a):
+    """--tune: the autotuner picks each batch's step schedule first (its
+    choices cached in --tune-cache, keyed by the workload's shape)."""
+    return dict(tune=a.tune, tune_cache=a.tune_cache)
+
+
 def cold_tolerance(windows, ref):
     """2 % or three times the scatter of the reference windows."""
     return steady.noise_tolerance([steady.distance(w, ref) for w in windows])
@@ -71,7 +77,7 @@ def cmd_plain(a):
     draw = dict(pressure_mtorr=30.0, v_amp=200.0, freq=13.56e6, gap=0.025, n_cells=400, see_gamma=0.1)
     cfg = warm.config(draw, weight=weight_of(draw, a), seed=2)
     sim = _sim([cfg])
-    sw = Sweep(sim, [warm.steps_per_period(draw)], max_periods=a.periods).run()
+    sw = Sweep(sim, [warm.steps_per_period(draw)], max_periods=a.periods, **_tuning(a)).run()
     ref = sw.reference(0)
     tol = cold_tolerance(sw.windows[0], ref)
     i, per = convergence(sw.windows[0], ref, tol)
@@ -108,7 +114,8 @@ def cmd_sweep(a):
                             capacity=a.capacity) for i in grp]
         sim = _sim(cfgs)
         t0 = time.perf_counter()
-        sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in grp], max_periods=a.periods).run()
+        sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in grp], max_periods=a.periods,
+                   **_tuning(a)).run()
         total += time.perf_counter() - t0
         for j, i in enumerate(grp):
             ref = sw.reference(j)
@@ -125,7 +132,7 @@ def cmd_sweep(a):
         flags = [sw.flags[j] for j in range(len(grp))]
         print(json.dumps(dict(batch=k // a.batch, discharges=len(grp), seconds=time.perf_counter() - t0,
                               flags=sorted(set(flags)), min_count=int(np.min(cnt)), max_count=int(np.max(cnt)),
-                              total=int(np.sum(cnt)))), flush=True)
+                              total=int(np.sum(cnt)), schedule=sw.schedule)), flush=True)
         sim.close()
         save()
     print(json.dumps(dict(kind="sweep", set=a.set, draws=len(draws), seconds=total,
@@ -201,7 +208,8 @@ def cmd_warm(a):
     def stop(j, sw):
         return steady.converged_at(sw.windows[j], ref_prof[j], tol=tols[j]) is not None
 
-    sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in ids], max_periods=a.periods).run(stop=stop)
+    sw = Sweep(sim, [warm.steps_per_period(draws[i]) for i in ids], max_periods=a.periods,
+               **_tuning(a)).run(stop=stop)
     conv, t_conv, steps_conv = [], [], []
     for j in range(len(ids)):
         i, per = convergence(sw.windows[j], ref_prof[j], tols[j])
@@ -211,6 +219,7 @@ def cmd_warm(a):
     done = [t for t in t_conv if t is not None]
     cold_periods = [summ[k]["periods"] for k in keep]
     out = dict(kind="warm", draws=len(ids), seconds_inference_and_load=t_ready, converged=len(done),
+               schedule=sw.schedule,
                seconds_to_last_convergence=max(done) if done else None,
                seconds_per_converged_discharge=(max(done) / len(ids)) if len(done) == len(ids) else None,
                mean_periods_warm=float(np.mean([c for c in conv if c > 0])) if done else None,
@@ -254,7 +263,8 @@ def cmd_plainset(a):
         def stop(j, sw):
             return steady.converged_at(sw.windows[j], ref, tol=tol) is not None
 
-        sw = Sweep(sim, [warm.steps_per_period(draws[i])], max_periods=a.periods, progress=0.0).run(stop=stop)
+        sw = Sweep(sim, [warm.steps_per_period(draws[i])], max_periods=a.periods, progress=0.0,
+                   **_tuning(a)).run(stop=stop)
         wall = time.perf_counter() - t0
         c, p_ = convergence(sw.windows[0], ref, tol)
         ids.append(i)
@@ -312,6 +322,10 @@ def main(argv=None):
     p.add_argument("--weight-law", choices=["fixed", "f2"], default="fixed")
     p.add_argument("--capacity", type=int, default=1 << 20)
     p.add_argument("--out", required=True)
+    for name in ("plain", "sweep", "warm", "plainset"):
+        p = sub.choices[name]
+        p.add_argument("--tune", action="store_true", help="autotune each batch's step schedule first")
+        p.add_argument("--tune-cache", default=None, help="JSON cache of the autotuner's choices")
     a = ap.parse_args(argv)
     dict(plain=cmd_plain, sweep=cmd_sweep, train=cmd_train, warm=cmd_warm, plainset=cmd_plainset)[a.cmd](a)
 

@@ -28,8 +28,11 @@ from . import steady
 
 class Sweep:
     def __init__(self, sim, steps_per_period, window_periods=5, max_periods=300, electron=0, ion=1,
-                 progress=20.0, chunk=2048):
+                 progress=20.0, chunk=2048, tune=False, tune_cache=None):
         self.sim = sim
+        self.tune = bool(tune)
+        self.tune_cache = tune_cache
+        self.schedule = None                            # the autotuner's choice, when tuned
         self.chunk = int(chunk)
         self.B = sim.B
         self.spp = [int(s) for s in steps_per_period]
@@ -50,10 +53,22 @@ class Sweep:
     def window_steps(self, b):
         return self.window_periods * self.spp[b]
 
+    def _tune(self):
+        """Time the step schedules on the batch itself (real steps: the
+        windows start after them) and apply the fastest."""
+        from . import autotune
+        self.schedule, _ = autotune.tune(self.sim, steps=16, warm=8, cache=self.tune_cache)
+
     def run(self, stop=None):
         """Advance until every discharge is done.  `stop(b, sweep)` is called
-        after each window of discharge b; a true result retires it early."""
+        after each window of discharge b; a true result retires it early.
+        With tune=True the autotuner first picks the step schedule on the
+        batch (its steps come before the first window, inside the wall time)."""
+        t_start = time.perf_counter()
+        if self.tune:
+            self._tune()
         if self.chunk > 0:
+            return self._run_device(stop, t_start)
             return self._run_device(stop)
         sim = self.sim
         sim.set_diag(True)
@@ -61,7 +76,7 @@ class Sweep:
             sim.reset_avg(b)
         start = sim.counts(0)["step"]
         nxt = [start + self.window_steps(b) for b in range(self.B)]
-        self.t0 = time.perf_counter()
+        self.t0 = t_start
         self.steps = start
         last = self.t0
         while not all(self.done):
@@ -97,7 +112,7 @@ class Sweep:
         periods = len(self.windows[b]) * self.window_periods
         return periods >= self.max_periods or (stop is not None and stop(b, self))
 
-    def _run_device(self, stop):
+    def _run_device(self, stop, t_start):
         sim = self.sim
         sim.set_diag(True)
         for b in range(self.B):
@@ -105,9 +120,9 @@ class Sweep:
                 raise ValueError("a chunk would span more windows than the device ring holds")
             sim.set_windows(b, self.window_steps(b))
         start = sim.counts(0)["step"]
-        self.t0 = time.perf_counter()
+        self.t0 = t_start
         self.steps = start
-        last = self.t0
+        last = time.perf_counter()
         while not all(self.done):
             t_a, s_a = time.perf_counter() - self.t0, self.steps
             sim.step(self.chunk)

@@ -13,7 +13,22 @@ prints one JSON line per quantity and a closing summary line.  Quantities:
   * the Langmuir wave over 1000 steps: total-energy drift of each side, and
     the measured frequency against the kinetic root;
   * densities and charge of an argon RF state, and the charge balance;
-  * the warm-start network: BF16 outputs and gradients against FP64.
+  * the warm-start network: BF16 outputs and gradients against FP64;
+  * swarm coefficients (Section 4): drift velocity, mean energy and rate
+    coefficients from the same procedure (replicas with the same seeds,
+    relaxation, sampling, thinning) on both sides, in combined standard
+    errors over the replicas;
+  * the electrical asymmetry effect (Section 3.3): from the GPU's state after
+    a relaxation, both sides run the same RF periods; the self-bias of each
+    phase and the mean ion impact energy at each electrode;
+  * the electron cyclotron drift instability (Section 3.6): from the GPU's
+    state during the growth, both sides run the same steps; the ion-density
+    amplitude of the resonant mode and the dominant mode, and the field
+    energy.
+
+Statistical parity of time-averaged profiles at the argon RF configuration's
+steady state and of sampled discharges of a batched sweep is a test of its
+own (tests/test_gpu_steady_parity.py).
 """
 from __future__ import annotations
 
@@ -135,16 +150,195 @@ def network():
          gradient_cosine=float(np.dot(g, g_ref) / (np.linalg.norm(g) * np.linalg.norm(g_ref))), bar="2e-2")
 
 
+def _threads(fns):
+    """Run oracle calls side by side (the C library runs without the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(len(fns)) as ex:
+        return list(ex.map(lambda f: f(), fns))
+
+
+def _host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _se_diff(g, o):
+    """Difference of the replica means of g and o [replicas] in combined
+    standard errors, and relative to the oracle's mean."""
+    g, o = np.asarray(g, np.float64), np.asarray(o, np.float64)
+    se = math.sqrt(g.var(ddof=1) / len(g) + o.var(ddof=1) / len(o))
+    d = float(g.mean() - o.mean())
+    return dict(gpu=float(g.mean()), oracle=float(o.mean()), diff_in_standard_errors=abs(d) / max(se, 1e-300),
+                rel=abs(d) / max(abs(float(o.mean())), 1e-300))
+
+
+def swarm_vs_oracle(en=(100.0, 500.0), replicas=4, n=20000, relax=8192, sample=8192, every=128):
+    from paper_2609_17151_amd import swarm as SW
+    sw = SW.Swarm(en, replicas=replicas, n=n)
+    g = sw.run(relax, sample, every=every)
+    nch = len(sw.tables)
+    threads = max(1, _host_threads() // sw.B)
+
+    def one(b):
+        cfg = sw.cfgs[b]
+        o = oracle.Oracle(cfg, sw.tables)
+        o.set_threads(threads)
+        rng = np.random.default_rng(7000 + b)
+
+        def count():
+            return len(o.get_particles(0)["id"])
+
+        def thin():
+            p = o.get_particles(0)
+            if len(p["id"]) <= sw.control * n:
+                return
+            keep = np.sort(rng.choice(len(p["id"]), n, replace=False))
+            o.set_particles(0, p["x"][keep], p["vx"][keep], p["vy"][keep], p["vz"][keep], p["id"][keep],
+                            p["next_id"])
+
+        for _ in range(max(1, relax // every)):
+            o.step(every)
+            thin()
+        o.set_diag(True, 40.0)
+        o.reset_avg()
+        c0 = o.counters()["coll"][0][:nch].astype(np.float64)
+        n_dt = 0.0
+        for _ in range(max(1, sample // every)):
+            nb = count()
+            o.step(every)
+            n_dt += math.sqrt(nb * count()) * every * sw.dt
+            thin()
+        a = o.avg()
+        dens = a["density"][0]
+        ex = cfg["e_ext"][0]
+        W_ = -np.sign(ex) * np.sum(o.power(0)["flux"]) / np.sum(dens)
+        eps = np.sum(dens * a["mean_energy"]) / np.sum(dens)
+        rates = (o.counters()["coll"][0][:nch].astype(np.float64) - c0) / (sw.n_gas * n_dt)
+        return W_, eps, rates
+
+    res = _threads([lambda b=b: one(b) for b in range(sw.B)])
+    per = g["per_replica"]
+    for i, e in enumerate(en):
+        bs = range(i * replicas, (i + 1) * replicas)
+        row = dict(e_over_n_td=e, replicas=replicas, electrons=n, relax_steps=relax, sample_steps=sample,
+                   W=_se_diff([per["W"][b] for b in bs], [res[b][0] for b in bs]),
+                   mean_energy=_se_diff([per["energy"][b] for b in bs], [res[b][1] for b in bs]))
+        for j, kind in enumerate(g["kinds"]):
+            og = [res[b][2][j] for b in bs]
+            if max(og) > 0.0:
+                row["k_%s" % kind] = _se_diff([per["rates"][b][j] for b in bs], og)
+        emit("swarm_coefficients", **row, bar="statistics")
+
+
+def eae_vs_oracle(relax_periods=200, periods=3, weight=8e8):
+    from paper_2609_17151_amd import eae
+    cfgs = [eae.config(0.0, weight=weight), eae.config(0.5 * math.pi, weight=weight)]
+    tabs = W.argon_tables()
+    sim = Sim(cfgs, tabs)
+    spp = int(round(1.0 / (cfgs[0]["v_freq"] * cfgs[0]["dt"])))
+    sim.step(spp * relax_periods)
+    orcs = []
+    for b in range(2):
+        o = to_oracle(sim, cfgs[b], tabs, batch=b)
+        o.set_circuit(sim.circuit(b)[1])
+        o.refresh_field()
+        o.set_diag(True, 40.0)
+        o.set_wall_edf(1, 600.0)
+        o.set_threads(max(1, _host_threads() // 2))
+        orcs.append(o)
+    sim.set_diag(True, 40.0)
+    sim.set_wall_edf(1, 600.0)
+    counts = [sum(sim.counts(b)["count"]) for b in range(2)]
+
+    def ion_means(edf):
+        h, wdt = edf["counts"][1], edf["bin_width"][1]
+        e = (np.arange(h.shape[1]) + 0.5) * wdt
+        return [float((h[w] * e).sum() / max(h[w].sum(), 1.0)) for w in range(2)]
+
+    bias_g, ion_g = [[], []], [[], []]
+    for _ in range(periods):
+        for b in range(2):
+            sim.reset_avg(b)
+        sim.step(spp)
+        for b in range(2):
+            bias_g[b].append(float(sim.avg(b)["phi"][0]))
+            ion_g[b].append(ion_means(sim.wall_edf(b)))
+
+    def run(o):
+        bias, ion = [], []
+        for _ in range(periods):
+            o.reset_avg()
+            o.step(spp)
+            bias.append(float(o.avg()["phi"][0]))
+            ion.append(ion_means(o.wall_edf()))
+        return bias, ion
+
+    res = _threads([lambda o=o: run(o) for o in orcs])
+    for b, theta in enumerate((0, 90)):
+        bo, io = res[b]
+        ig, io_ = np.array(ion_g[b]), np.array(io)
+        emit("eae_self_bias", theta_deg=theta, relax_periods=relax_periods, periods=periods,
+             particles=int(counts[b]), self_bias=_se_diff(bias_g[b], bo),
+             ion_mean_energy_powered=_se_diff(ig[:, 0], io_[:, 0]),
+             ion_mean_energy_grounded=_se_diff(ig[:, 1], io_[:, 1]), bar="statistics")
+
+
+def ecdi_vs_oracle(n=1_000_000, relax_us=0.8, chunks=8, every=500):
+    cfg = W.ecdi(n_per_species=n)
+    sim = Sim(cfg)
+    sim.step(int(round(relax_us * 1e-6 / cfg["dt"])))
+    o = to_oracle(sim, cfg)
+    for s in range(2):
+        o.set_axial(s, sim.axial(s))
+    o.refresh_field()
+    o.set_threads(_host_threads())
+    m = 15                                  # the box holds 15 resonant wavelengths
+
+    def modes(d):
+        # amplitude of each spatial mode of the periodic density, over its mean
+        return np.abs(np.fft.rfft(d - d.mean())) / (len(d) * d.mean())
+
+    rows = []
+    for k in range(chunks):
+        sim.step(every)
+        o.step(every)
+        ag, ao = modes(sim.density()[1]), modes(o.density(1))
+        _, feg = sim.energy()
+        _, feo = o.energy()
+        rows.append(dict(steps=(k + 1) * every, mode_gpu=int(np.argmax(ag[1:]) + 1),
+                         mode_oracle=int(np.argmax(ao[1:]) + 1), amp_gpu=float(ag[m]), amp_oracle=float(ao[m]),
+                         field_energy_rel=float(abs(feg - feo) / max(feo, 1e-300))))
+    emit("ecdi_growth", particles_per_species=n, relax_us=relax_us, resonant_mode=m,
+         amp_rel_max=max(abs(r["amp_gpu"] - r["amp_oracle"]) / r["amp_oracle"] for r in rows),
+         field_energy_rel_max=max(r["field_energy_rel"] for r in rows), rows=rows, bar="statistics")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="smaller E x B runs")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated subset of exb,langmuir,argon,network,swarm,eae,ecdi")
     a = ap.parse_args(argv)
+    want = set(a.only.split(",")) if a.only else None
+    on = lambda k: want is None or k in want
     n = 500_000 if a.quick else 4_000_000
-    exb_single_step(n)
-    exb_run(200_000 if a.quick else 1_000_000, 200)
-    langmuir_energy(1000)
-    argon_state()
-    network()
+    if on("exb"):
+        exb_single_step(n)
+        exb_run(200_000 if a.quick else 1_000_000, 200)
+    if on("langmuir"):
+        langmuir_energy(1000)
+    if on("argon"):
+        argon_state()
+    if on("network"):
+        network()
+    if on("swarm"):
+        swarm_vs_oracle()
+    if on("eae"):
+        eae_vs_oracle()
+    if on("ecdi"):
+        ecdi_vs_oracle()
     emit("done")
 
 

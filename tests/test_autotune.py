@@ -69,6 +69,10 @@ def test_tuned_run_reaches_the_untuned_state():
     cfg, tabs = small_argon(n_init=20000)
     a = P.Sim(cfg, tabs)
     choice, table = autotune.tune(a, steps=16, warm=8)
+    # the chosen schedule replays captured step graphs
+    g0 = a.graphs()["steps"]
+    a.step(64)
+    assert a.graphs()["steps"] - g0 >= 32, (choice, a.graphs())
     n = a.counts()["step"]
     b = P.Sim(cfg, tabs)
     b.step(n)

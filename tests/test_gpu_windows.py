@@ -70,3 +70,22 @@ def test_sweep_device_mode_matches_host_mode(pic):
         assert out[0].window_step[b] == out[1].window_step[b]
         for w0, w1 in zip(out[0].windows[b], out[1].windows[b]):
             assert np.array_equal(w0, w1)
+
+
+def test_tuned_sweep_matches_untuned(pic):
+    # the autotuner's steps come before the first window and change no
+    # result: an untuned batch stepped as far first closes the same windows
+    from paper_2609_17151_amd.sweep import Sweep
+    cfgs, tabs = _batch(), W.argon_tables()
+    sim_t = pic.Sim(cfgs, tabs)
+    sw_t = Sweep(sim_t, [48, 40], window_periods=2, max_periods=6, chunk=64, progress=0, tune=True).run()
+    assert sw_t.schedule is not None
+    start = sw_t.window_step[0][0] - sw_t.window_steps(0)
+    assert start > 0
+    sim_u = pic.Sim(cfgs, tabs)
+    sim_u.step(start)
+    sw_u = Sweep(sim_u, [48, 40], window_periods=2, max_periods=6, chunk=64, progress=0).run()
+    for b in range(2):
+        assert sw_t.window_step[b] == sw_u.window_step[b]
+        for w0, w1 in zip(sw_t.windows[b], sw_u.windows[b]):
+            assert np.array_equal(w0, w1)
