@@ -163,7 +163,7 @@ def tuned(sim, tune):
         return dict(choice="default")
     from paper_2609_17151_amd import autotune
     choice, table = autotune.tune(sim, steps=32, warm=16)
-    return dict(choice=choice, us_per_step={"%d/%d/%d" % (r["ppt"], r["threads"], r["compact_every"]):
+    return dict(choice=choice, us_per_step={"%d/%d/%d/%d" % (r["ppt"], r["threads"], r["compact_every"], r["fuse"]):
                                             round(1e3 * r["ms_per_step"], 2) for r in table})
 
 

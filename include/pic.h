@@ -414,6 +414,19 @@ pic_status pic_sort_noalloc(pic_ctx* ctx);
  * uses direct launches. */
 pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable);
 
+/* pic_config_events: where the step's events (collision candidates, axial
+ * renewals, ions absorbed at an emitting wall: the few particles per step
+ * that need the null-collision Monte Carlo of Section 1, the renewal or
+ * the secondary emission) are processed.  in_push = 0 (the default): one
+ * events kernel after the push, its waves packed over all events of the
+ * step.  in_push = 1: each push workgroup processes the events of its own
+ * tiles after its push, with no further launch, which shortens the step of
+ * a workload too small to fill the GPU; this applies to tiles of 256
+ * threads (other shapes keep the events kernel).  The results are the same
+ * either way, bit for bit.  PIC_EINVAL for another value.  Synchronous;
+ * takes effect at the next pic_step. */
+pic_status pic_config_events(pic_ctx* ctx, int32_t in_push);
+
 /* pic_config_tiles: tile shape of the particle kernels (particles per thread
  * 1, 2, 4 or 8; threads per workgroup 256, 512 or 1024; the nearest built
  * shape is used), the interval in steps of the sort by cell (0 = never) and

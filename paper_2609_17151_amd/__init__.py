@@ -101,6 +101,7 @@ def load_library():
         "pic_strerror": (C.c_char_p, [i32]),
         "pic_free": (None, [P]),
         "pic_config_tiles": (i32, [P, i32, i32, i32, i32]),
+        "pic_config_events": (i32, [P, i32]),
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_set_wall_edf": (i32, [P, i32, d]),
         "pic_get_axial": (i32, [P, i32, i32, i64, dp, C.POINTER(i64)]),
@@ -238,6 +239,11 @@ class Sim:
 
     def config_tiles(self, ppt=4, threads=256, sort_every=0, compact_every=16):
         self._check(_lib.pic_config_tiles(self.h, ppt, threads, sort_every, compact_every), "pic_config_tiles")
+
+    def config_events(self, in_push=False):
+        """Events (collisions, renewals, secondary emission) in the push
+        workgroups of a 256-thread tile (True) or in the events kernel."""
+        self._check(_lib.pic_config_events(self.h, int(bool(in_push))), "pic_config_events")
 
     def set_diag(self, enable=True, eepf_emax=64.0):
         self._check(_lib.pic_set_diag(self.h, int(enable), float(eepf_emax)), "pic_set_diag")

@@ -1,6 +1,8 @@
 """Autotuner of the step schedule: particles per thread, threads per
-workgroup, the interval of the sort by cell and the interval of the hole
-compaction.
+workgroup, the interval of the sort by cell, the interval of the hole
+compaction and, for 256-thread tiles of the general kernel, whether the push
+workgroups process their own events (collisions, renewals, secondary
+emission) instead of the events kernel.
 
 None of the choices it makes changes the results: the deposit sums are
 exact integers, the random draws are keyed by particle id and step, and the
@@ -45,8 +47,15 @@ def candidates(general):
     for ppt, thr in shapes:
         for srt in (SORT_EVERY if not general else (0,)):
             for cmp_ in (COMPACT_EVERY if general else (16,)):
-                out.append(dict(ppt=ppt, threads=thr, sort_every=srt, compact_every=cmp_))
+                for fuse in ((0, 1) if general and thr == 256 else (0,)):
+                    out.append(dict(ppt=ppt, threads=thr, sort_every=srt, compact_every=cmp_, fuse=fuse))
     return out
+
+
+def apply(sim, c):
+    """Apply a schedule (a candidate or a cached choice)."""
+    sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
+    sim.config_events(bool(c.get("fuse", 0)))
 
 
 def birth_rate(sim, steps=4):
@@ -101,7 +110,7 @@ def tune(sim, steps=64, warm=32, cache=None, timer=None, verbose=False):
             store = json.load(f)
         if key in store:
             c = store[key]["choice"]
-            sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
+            apply(sim, c)
             return c, store[key]["table"]
     general = key.endswith("general")
     rate = birth_rate(sim) if general else None
@@ -109,7 +118,7 @@ def tune(sim, steps=64, warm=32, cache=None, timer=None, verbose=False):
     for c in candidates(general):
         if general and not fits(sim, c["compact_every"], rate):
             continue
-        sim.config_tiles(c["ppt"], c["threads"], c["sort_every"], c["compact_every"])
+        apply(sim, c)
         if warm:
             sim.step(warm)
         ms = timer(sim, steps)
@@ -117,8 +126,8 @@ def tune(sim, steps=64, warm=32, cache=None, timer=None, verbose=False):
         if verbose:
             print("autotune", key, c, "%.4f ms/step" % ms, flush=True)
     best = min(table, key=lambda r: r["ms_per_step"])
-    choice = {k: best[k] for k in ("ppt", "threads", "sort_every", "compact_every")}
-    sim.config_tiles(choice["ppt"], choice["threads"], choice["sort_every"], choice["compact_every"])
+    choice = {k: best[k] for k in ("ppt", "threads", "sort_every", "compact_every", "fuse")}
+    apply(sim, choice)
     if cache:
         store[key] = dict(choice=choice, table=table)
         tmp = cache + ".tmp"

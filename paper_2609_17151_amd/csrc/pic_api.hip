@@ -54,6 +54,7 @@ struct pic_ctx {
     int sort_every = 0;
     int64_t steps_since_sort = 0;
     int compact_every = 16;              // steps between compactions of the holes
+    int events_in_push = 0;              // 256-thread general pushes do their own events
     int64_t steps_since_compact = 0;
     int64_t compact_tiles = 0;           // grid of the compaction passes
     int diag = 0;
@@ -610,10 +611,7 @@ pic_status pic_init(const pic_config* cfg, int32_t n_batch, const pic_allocator*
         int64_t slots = 0;
         for (int s = 0; s < S; ++s) slots += ctx->grid_cap[s];
         d.evr = (uint4*)A(16ull * slots);
-        d.evz = (float*)A(4ull * slots);
-        d.evc = (uint32_t*)A(4ull * (slots / 64 + 1));
-        d.evp = (uint32_t*)A(4ull * (slots / 64 + 1));
-        d.evidx = (uint32_t*)A(4ull * (slots / 64 + 1));
+        d.evq = (uint4*)A(16ull * slots);
         d.evg = (uint32_t*)A(4ull * kMaxPushGrid);
         d.ccnt = (uint32_t*)A(4ull * tiles_max);
         d.tick = (unsigned long long*)A(8);
@@ -751,6 +749,15 @@ pic_status pic_config_tiles(pic_ctx* ctx, int32_t ppt, int32_t threads, int32_t 
     return rc;
 }
 
+pic_status pic_config_events(pic_ctx* ctx, int32_t in_push)
+{
+    if (!ctx || (in_push != 0 && in_push != 1)) return PIC_EINVAL;
+    pic_status rc = hip_st(hipStreamSynchronize(ctx->stream));
+    if (rc != PIC_OK) return rc;
+    ctx->events_in_push = in_push;
+    return rc;
+}
+
 pic_status pic_set_diag(pic_ctx* ctx, int32_t enable, double eepf_emax_eV)
 {
     if (!ctx || !(eepf_emax_eV > 0.0) || !std::isfinite(eepf_emax_eV)) return PIC_EINVAL;
@@ -778,6 +785,7 @@ struct StepPlan {
     PushArgs pa{};
     int ppt = 4, threads = 256;
     bool general = false;
+    bool fuse = false;                   // the push does the events (no events launch)
     int64_t grid = 1;
     EvArgs ea{};
     int64_t ev_grid = 1;
@@ -805,10 +813,11 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
         if (sc.compacts || sc.nch > 0 || sc.emits || sc.renew_lz > 0.0) p.general = true;
     }
     push_shape(p.ppt, p.threads, p.general);
+    p.fuse = ctx->events_in_push && push_fusable(p.threads, p.general);
     const int T = p.threads * p.ppt;
     int64_t tiles = 0;
     for (int g = 0; g < B * S; ++g) tiles += (pad_cap(ctx->segc[g].cap) + T - 1) / T;
-    const int64_t resident = (int64_t)push_occupancy(p.ppt, p.threads, p.general, lds) * ctx->n_cu;
+    const int64_t resident = (int64_t)push_occupancy(p.ppt, p.threads, p.general, p.fuse, lds) * ctx->n_cu;
     p.grid = std::max<int64_t>(1, std::min(std::min(tiles, resident), (int64_t)kMaxPushGrid));
     PushArgs& pa = p.pa;
     pa.d = ctx->d;
@@ -827,6 +836,7 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     mix((uint64_t)p.ppt);
     mix((uint64_t)p.threads);
     mix((uint64_t)p.general);
+    mix((uint64_t)p.fuse);
     mix((uint64_t)p.grid);
     p.fa.d = ctx->d;
     p.fa.mode = kFinStep;
@@ -835,8 +845,6 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
     p.fa.births_per_tile = p.general ? T / kBirthsDiv : 0;
     p.ea.d = ctx->d;
     p.ea.T = T;
-    p.ea.ppt = p.ppt;
-    p.ea.waves = p.threads / 64;
     p.ea.push_grid = (int32_t)p.grid;
     p.ea.births_per_tile = T / kBirthsDiv;
     p.ea.diag = ctx->diag;
@@ -862,9 +870,9 @@ pic_status enqueue_steps(pic_ctx* ctx, const StepPlan& p, int n, hipStream_t st,
                     return PIC_EHIP;
         }
         const int pp = prof ? prof_begin(ctx) : -1;
-        if (launch_push(p.pa, p.ppt, p.threads, p.general, p.grid, st) != hipSuccess) return PIC_EHIP;
+        if (launch_push(p.pa, p.ppt, p.threads, p.general, p.fuse, p.grid, st) != hipSuccess) return PIC_EHIP;
         prof_end(ctx, pp, 0);
-        if (p.general) {
+        if (p.general && !p.fuse) {
             const int pv = prof ? prof_begin(ctx) : -1;
             if (launch_events(p.ea, p.ev_grid, st) != hipSuccess) return PIC_EHIP;
             prof_end(ctx, pv, 1);

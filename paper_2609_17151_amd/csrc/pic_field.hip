@@ -94,18 +94,23 @@ __device__ __forceinline__ double wave_total_f64(double v)
 
 }  // namespace
 
-// One workgroup per discharge, one node per thread (up to four).  All threads
-// first append the step's births; then the last wave does the bookkeeping
-// (counts, ids, kinetic-energy partial sums) while the others turn the
-// deposit into densities and charge (and their per-wave sums, for the mean
-// charge of a periodic mesh).  Poisson: every thread forms the run of its
+// A step that can have births takes two workgroups per discharge that run side
+// by side: the first appends the step's births and then does the bookkeeping
+// (counts, ids, kinetic-energy partial sums); the second, one node per thread
+// (up to four), turns the deposit into densities and charge (and their
+// per-wave sums, for the mean charge of a periodic mesh), solves for the field
+// and adds the time averages.  The two share nothing of this step: the births'
+// charge and diagnostics were deposited when they were staged.  Otherwise one
+// workgroup does it all, its last wave the bookkeeping.  Poisson: every thread forms the run of its
 // node, a wave-level scan and one scan over the waves' totals give K[i] and
 // G[i] at every node, and phi follows directly; the totals also give the
 // mean of phi.
 __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
 {
     const DevPtrs& d = a.d;
-    const int b = a.only_b >= 0 ? a.only_b : (int)blockIdx.x;
+    const bool split = a.mode == kFinStep && a.births_per_tile > 0;   // a births workgroup per discharge
+    const bool births_wg = split && (blockIdx.x & 1u) == 0u;
+    const int b = a.only_b >= 0 ? a.only_b : (int)(split ? blockIdx.x >> 1 : blockIdx.x);
     const int S = d.S, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const DisConst& dc = d.disc[b];
     DisState& ds = d.diss[b];
@@ -131,7 +136,41 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     __shared__ int64_t s_app[kMaxSpecies], s_want[kMaxSpecies];
     __shared__ uint32_t s_scan[kWaves];
     __shared__ uint32_t s_tinc[kFT];         // inclusive prefix of the round's tiles' birth counts
-    if (a.mode == kFinStep && a.births_per_tile > 0) {
+    // the bookkeeping of a step, by one wave: counts, ids, kinetic energy
+    auto bookkeeping = [&](bool births) {
+        if (a.diag) {
+            // kinetic-energy partials of the step's runs (zeros elsewhere),
+            // fixed order, cleared after reading
+            for (int s = 0; s < S; ++s) {
+                SegState& st = d.segs[b * S + s];
+                double* kpp = d.ke_part + st.tile_first;
+                const int64_t ntl = st.ntiles;
+                double acc_k = 0.0;
+                for (int64_t t = lane; t < ntl; t += 64) {
+                    acc_k += kpp[t];
+                    kpp[t] = 0.0;
+                }
+                acc_k = wave_sum_f64(acc_k);
+                if (lane == 0) st.ke = acc_k;
+            }
+        }
+        if (lane < S) {                                 // one lane per species
+            const int s = lane;
+            SegState& st = d.segs[b * S + s];
+            const int64_t app = births ? s_app[s] : 0, want = births ? s_want[s] : 0;
+            if (app < want) {
+                atomicOr(&ds.flags, kFlagCapacity);
+                atomicAdd(&d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP], (unsigned long long)(want - app));
+            }
+            st.count += app;
+            st.live += app - st.dead;
+            st.dead = 0;
+            st.staged = 0;
+            st.next_id += (uint32_t)app;
+            st.ntiles = 0;
+        }
+    };
+    if (births_wg) {
         const SegState& s0 = d.segs[b * S + 0];
         const SegConst& c0 = d.segc[b * S + 0];
         const int64_t slot0 = s0.count, slot1 = S > 1 ? d.segs[b * S + 1].count : 0;
@@ -139,30 +178,6 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
         const int io0 = s0.parity, io1 = S > 1 ? d.segs[b * S + 1].parity : 0;
         const int64_t cap0 = c0.cap, cap1 = S > 1 ? d.segc[b * S + 1].cap : 0;
         int64_t pos0 = slot0, pos1 = slot1;
-        // velocity moments of an appended birth (diagnostics), as in the push
-        auto moment_add = [&](int sp, int cell, float off, float vx) {
-            const SegConst& cs = d.segc[b * S + sp];
-            unsigned long long* ma = d.macc + ((size_t)b * S + sp) * 2 * d.nodes_max;
-            const int c1 = (periodic && cell + 1 == nc) ? 0 : cell + 1;
-            const float a1 = vx * cs.mscale1, a2 = vx * vx * cs.mscale2, w0 = 1.0f - off;
-            atomicAdd(&ma[cell], (unsigned long long)(long long)rintf(w0 * a1));
-            atomicAdd(&ma[c1], (unsigned long long)(long long)rintf(off * a1));
-            atomicAdd(&ma[d.nodes_max + cell], (unsigned long long)(long long)rintf(w0 * a2));
-            atomicAdd(&ma[d.nodes_max + c1], (unsigned long long)(long long)rintf(off * a2));
-        };
-        // energy of an appended electron at its nodes and in the bulk energy
-        // distribution (diagnostics), as in the push
-        auto energy_add = [&](int cell, float off, float vx, float vy, float vz) {
-            const float eps = c0.half_m_over_e * (vx * vx + vy * vy + vz * vz);
-            const float w1 = off * eps, w0 = eps - w1;
-            const int c1 = (periodic && cell + 1 == nc) ? 0 : cell + 1;
-            atomicAdd(&d.eacc[nb + cell], (unsigned long long)(w0 * 1048576.0f));
-            atomicAdd(&d.eacc[nb + c1], (unsigned long long)(w1 * 1048576.0f));
-            if (cell >= dc.bulk_lo && cell < dc.bulk_hi) {
-                const int bin = (int)(eps * a.eepf_inv_bin);
-                if ((unsigned)bin < (unsigned)kEepfBins) atomicAdd(&d.eepf[(size_t)b * 2 * kEepfBins + bin], 1ull);
-            }
-        };
         for (int src = 0; src < S; ++src) {
             const int g = b * S + src;
             if (src > 0 && !d.segc[g].emits) continue;
@@ -208,10 +223,6 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                         c0.vz[io0][e] = bb.vz;
                         c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
                         if (c0.z[0]) c0.z[io0][e] = 0.0;
-                        if (a.diag) {
-                            moment_add(0, bb.cell, bb.off, bb.vx);
-                            energy_add(bb.cell, bb.off, bb.vx, bb.vy, bb.vz);
-                        }
                     }
                     if (pair) {
                         const SegConst& c1 = d.segc[b * S + 1];
@@ -224,7 +235,6 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
                             c1.vz[io1][q] = bb.ivz;
                             c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
                             if (c1.z[0]) c1.z[io1][q] = 0.0;
-                            if (a.diag) moment_add(1, bb.cell, bb.off, bb.ivx);
                         }
                     }
                 }
@@ -242,45 +252,13 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             if (S > 1) s_app[1] = (pos1 < cap1 ? pos1 : cap1) - slot1;
         }
         __syncthreads();
+        if (wid == 0) bookkeeping(true);
+        return;
     }
 
     if (tid >= kBook) {
-        // ---- bookkeeping wave: counts, ids, kinetic energy --------------------
         if (lane == 0) s_w[wid] = 0.0;                  // no share of the charge sum
-        if (a.mode == kFinStep) {
-            if (a.diag) {
-                // kinetic-energy partials of the step's runs (zeros elsewhere),
-                // fixed order, cleared after reading
-                for (int s = 0; s < S; ++s) {
-                    SegState& st = d.segs[b * S + s];
-                    double* kpp = d.ke_part + st.tile_first;
-                    const int64_t ntl = st.ntiles;
-                    double acc_k = 0.0;
-                    for (int64_t t = lane; t < ntl; t += 64) {
-                        acc_k += kpp[t];
-                        kpp[t] = 0.0;
-                    }
-                    acc_k = wave_sum_f64(acc_k);
-                    if (lane == 0) st.ke = acc_k;
-                }
-            }
-            if (lane < S) {                             // one lane per species
-                const int s = lane;
-                SegState& st = d.segs[b * S + s];
-                const bool births = a.births_per_tile > 0;
-                const int64_t app = births ? s_app[s] : 0, want = births ? s_want[s] : 0;
-                if (app < want) {
-                    atomicOr(&ds.flags, kFlagCapacity);
-                    atomicAdd(&d.cnt[(((size_t)b * S + s) * kRep) * C_N + C_DROP], (unsigned long long)(want - app));
-                }
-                st.count += app;
-                st.live += app - st.dead;
-                st.dead = 0;
-                st.staged = 0;
-                st.next_id += (uint32_t)app;
-                st.ntiles = 0;
-            }
-        }
+        if (a.mode == kFinStep && !split) bookkeeping(false);
     } else {
         // ---- densities and charge (into s_a) ------------------------------------
         double rsum = 0.0;
@@ -570,7 +548,8 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st)
 {
-    const unsigned g = a.only_b >= 0 ? 1u : (unsigned)a.d.B;
+    const unsigned per = (a.mode == kFinStep && a.births_per_tile > 0) ? 2u : 1u;   // births workgroup
+    const unsigned g = (a.only_b >= 0 ? 1u : (unsigned)a.d.B) * per;
     hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(kFT), 0, st, a);
     return hipGetLastError();
 }

@@ -216,12 +216,10 @@ struct DevPtrs {
     unsigned long long* wedf;    // [B][S][2][bins] impact energies at each wall
     Birth* births;               // [tiles_max * kBirthsPerTileMin] births staged by tile, in particle order
     int32_t* bcnt;               // [tiles_max] births staged by each tile
-    uint4* evr;                  // [slots] events of the step, per tile, per wave, in slot order:
-                                 // (slot | event bits, id, vx, vy) of the particle after the push
-    float* evz;                  // [slots] its vz
-    uint32_t* evc;               // [slots / 64 + 1] events recorded by each wave of each tile (a "unit")
-    uint32_t* evp;               // [slots / 64 + 1] prefix of the units' events within their push workgroup's range
-    uint32_t* evidx;             // [slots / 64 + 1] per push range (from its first slot / 64): the unit holding event 64 k
+    uint4* evr;                  // [slots] events of the step, packed per push workgroup from the first slot
+                                 // of its tile range, in any order: (slot in tile | event bits, id, vx, vy)
+                                 // of the particle after the push
+    uint4* evq;                  // [slots] the same events' (vz, cell, offset, tile)
     uint32_t* evg;               // [kMaxPushGrid] events of each push workgroup's range
     unsigned long long* tick;    // steps taken by the context
     uint32_t* ccnt;              // [tiles_max] compaction: live particles of each tile, then their first slot

@@ -18,8 +18,8 @@ struct PushArgs {
 constexpr int kEvThreads = 256;
 struct EvArgs {
     DevPtrs d;
-    int32_t T, ppt, waves;        // the push's tile: particles, particles per thread, waves
-    int32_t push_grid;            // the push's workgroups (each indexed its own tile range's events)
+    int32_t T;                    // particles of the push's tile
+    int32_t push_grid;            // the push's workgroups (each recorded its own tile range's events)
     int32_t births_per_tile;      // staging slots of a tile
     int32_t diag;
     float eepf_inv_bin;
@@ -64,7 +64,10 @@ struct ProfileArgs {
 };
 
 hipError_t launch_profile_load(const ProfileArgs& a, hipStream_t st);
-hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, int64_t grid, hipStream_t st);
+hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, bool fuse, int64_t grid,
+                       hipStream_t st);
+// whether a push of this shape can do its workgroups' own events
+bool push_fusable(int threads, bool general);
 void push_shape(int& ppt, int& threads, bool general);
 hipError_t launch_events(const EvArgs& a, int64_t grid, hipStream_t st);
 int events_occupancy();
@@ -79,6 +82,6 @@ int64_t compact_tiles_for(int64_t padded_count);
 size_t sort_scratch_bytes(int64_t max_tiles, int B, int cells_max);
 int64_t sort_tiles_for(int64_t padded_count);
 size_t push_lds_bytes(int n_nodes, int n_cells, int diag);
-int push_occupancy(int ppt, int threads, bool general, size_t lds);
+int push_occupancy(int ppt, int threads, bool general, bool fuse, size_t lds);
 
 }  // namespace pic

@@ -351,7 +351,23 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 
 }  // namespace
 
-template <int PPT, int BS, bool GENERAL>
+// The events pass over one chunk of 64 events (defined with the events
+// kernel below): chunk kc of push workgroup g's tile range, one event per
+// lane.
+struct EvPass {
+    int32_t T;                    // particles of the push's tile
+    int32_t chunk_t, NT;          // tiles per push workgroup, tiles in all
+    uint32_t bpt;                 // births staged per tile at most
+    int32_t diag;
+    float eepf_inv_bin;
+};
+
+__device__ __forceinline__ void event_chunk(const DevPtrs& d, const int32_t* s_pref, int NS, const EvPass& ps,
+                                            int g, uint32_t nev, uint32_t kc);
+
+// FUSE: the workgroup does its own tile range's events after its push (no
+// events launch; for workloads too small to fill the GPU twice)
+template <int PPT, int BS, bool GENERAL, bool FUSE>
 __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 {
     constexpr int kBS = BS;
@@ -366,10 +382,12 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     __shared__ unsigned int s_cnt[C_N];
     __shared__ unsigned long long s_wen[2];   // energy carried into each wall by the run (eV, 2^20)
     __shared__ float s_red[kBS / 64];
+    __shared__ uint32_t s_evn;                // events recorded by the workgroup
 
     tile_prefix(d, T, s_pref);
     if (tid < C_N) s_cnt[tid] = 0;
     if (tid < 2) s_wen[tid] = 0ull;
+    if (tid == 0) s_evn = 0u;
     __syncthreads();
     const int32_t NT = s_pref[NS];
 
@@ -592,8 +610,10 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 if (base + j < n) p_z[base + j] = zax[j];
         }
         if (GENERAL) {
-            // this wave's events, in slot order: lanes in order, a lane's
-            // particles in order (ballots and lane counts, no barrier)
+            // this wave's events, appended to the workgroup's packed list at
+            // a place one LDS atomic per wave claims (no barrier): the order
+            // of the records does not matter, each is self-contained and
+            // every result of the events pass is independent of it
             uint32_t below = 0, total = 0;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
@@ -601,21 +621,24 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                 below += lanes_below(m);
                 total += (uint32_t)__popcll(m);
             }
-            // each event's record carries the particle's id and new velocity,
-            // so the events kernel reads records, not scattered particle slots
-            const size_t r0 = (size_t)t * T + (size_t)wid * 64 * PPT;
-            uint4* evr = d.evr + r0;
-            float* evz = d.evz + r0;
+            if (total) {
+                uint32_t wbase = 0;
+                if (lane == 0) wbase = atomicAdd(&s_evn, total);
+                wbase = (uint32_t)__builtin_amdgcn_readfirstlane((int)wbase);
+                // the particle after the push: slot, event bits, id, velocity,
+                // position and tile, so the events pass reads the record only
+                const size_t r0 = (size_t)t_begin * T + wbase;
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                if (evw[j]) {
-                    evr[below] = make_uint4(evw[j] | (uint32_t)(tid * PPT + j), pid[j], __float_as_uint(vx[j]),
-                                            __float_as_uint(vy[j]));
-                    evz[below] = vz[j];
-                    ++below;
+                for (int j = 0; j < PPT; ++j) {
+                    if (evw[j]) {
+                        d.evr[r0 + below] = make_uint4(evw[j] | (uint32_t)(tid * PPT + j), pid[j],
+                                                       __float_as_uint(vx[j]), __float_as_uint(vy[j]));
+                        d.evq[r0 + below] = make_uint4(__float_as_uint(vz[j]), (uint32_t)cell[j],
+                                                       __float_as_uint(off[j]), (uint32_t)t);
+                        ++below;
+                    }
                 }
             }
-            if (lane == 0) d.evc[(size_t)t * kWavesPerTile + wid] = total;
         }
         if (tid == 0 && tin == ntiles - 1) {
             d.segs[sg].tile_first = tile_first;
@@ -625,38 +648,18 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     }
     if (cur_g >= 0) flush(cur_g);
     if (GENERAL) {
-        // the events of this workgroup's tile range, in unit order (a unit is
-        // one wave's list of one tile): each unit's exclusive prefix within the
-        // range, the unit holding every 64th event of the range, the range's
-        // total -- the events kernel's index, built where the counts are hot
-        __shared__ uint32_t s_sc[kBS / 64];
-        const int64_t u_begin = (int64_t)t_begin * kWavesPerTile;
-        const int64_t u_end = t_begin < t_end ? (int64_t)t_end * kWavesPerTile : u_begin;
-        uint32_t* ev_idx = d.evidx + (size_t)t_begin * T / 64;
-        uint32_t run = 0;
-        __syncthreads();                          // this workgroup's counts are written
-        for (int64_t r = u_begin; r < u_end; r += kBS) {
-            const int64_t u = r + tid;
-            const uint32_t c = u < u_end ? d.evc[u] : 0u;
-            const uint32_t incl = wave_incl_scan_u32(c);
-            if (lane == 63) s_sc[wid] = incl;
-            __syncthreads();
-            uint32_t before = 0, tot = 0;
-#pragma unroll
-            for (int k = 0; k < kBS / 64; ++k) {
-                const uint32_t v = s_sc[k];
-                if (k < wid) before += v;
-                tot += v;
-            }
-            if (u < u_end) {
-                const uint32_t p0 = run + before + incl - c;
-                d.evp[u] = p0;
-                for (uint32_t k = (p0 + 63u) >> 6; c > 0 && (k << 6) < p0 + c; ++k) ev_idx[k] = (uint32_t)(u - u_begin);
-            }
-            run += tot;
-            __syncthreads();                      // s_sc is rewritten
+        __syncthreads();                          // every wave's records are written
+        const uint32_t nev = s_evn;
+        if (tid == 0) d.evg[blockIdx.x] = nev;    // the events pass's count of this range
+        if (FUSE) {
+            // this workgroup's own events, in chunks of 64 over its waves:
+            // the same pass as the events kernel's, on the records and the
+            // tiles this workgroup has just written
+            const EvPass ps{T, chunk, NT, (uint32_t)(T / kBirthsDiv), a.diag, a.eepf_inv_bin};
+            const uint32_t nch = (nev + 63u) >> 6;
+            for (uint32_t kc = (uint32_t)wid; kc < nch; kc += (uint32_t)kWavesPerTile)
+                event_chunk(d, s_pref, NS, ps, (int)blockIdx.x, nev, kc);
         }
-        if (tid == 0) d.evg[blockIdx.x] = run;
     }
 }
 
@@ -825,6 +828,139 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) { return (uint32_t)__pop
 
 }  // namespace
 
+// the events pass over one chunk (declared above the push kernel): events
+// 64 kc .. 64 kc + 63 of the nev that push workgroup g recorded
+__device__ __forceinline__ void event_chunk(const DevPtrs& d, const int32_t* s_pref, int NS, const EvPass& ps,
+                                            int g, uint32_t nev, uint32_t kc)
+{
+    const int S = d.S;
+    const int lane = threadIdx.x & 63;
+    const uint32_t e = (kc << 6) + (uint32_t)lane;       // event of the workgroup's list
+    const bool act = e < nev;
+    bool hb = false, see = false, cand = false, viol = false, lost = false;
+    int wall = 0, ch = -1, sg = -1;
+    if (act) {
+        const size_t ri = (size_t)g * ps.chunk_t * ps.T + e;
+        const uint4 rec = d.evr[ri];
+        const uint4 rq = d.evq[ri];
+        const int32_t t = (int32_t)rq.w;
+        const uint32_t word = rec.x;
+        sg = tile_segment(s_pref, NS, t);
+        const int b = sg / S, s = sg - b * S;
+        const DisConst& dc = d.disc[b];
+        const SegConst& sc = d.segc[sg];
+        const int32_t tin = t - s_pref[sg];
+        const int io = d.segs[sg].parity;
+        const uint32_t step = (uint32_t)d.diss[b].step;
+        const int nc = dc.n_cells;
+        const int periodic = dc.bc == PIC_BC_PERIODIC;
+        const uint32_t key = word & kEvSlot;
+        const int64_t slot = (int64_t)tin * ps.T + key;
+        const uint32_t pid = rec.y;
+        Birth bb;
+        if (word & kEvSee) {
+            see = true;
+            wall = (word & kEvWall1) ? 1 : 0;
+            const int r = secondary(sc, dc, s, step, wall, pid, bb);
+            hb = r > 0;
+            lost = r < 0;
+        } else {
+            double ux = __uint_as_float(rec.z), uy = __uint_as_float(rec.w), uz = __uint_as_float(rq.x);
+            if (word & kEvRenew) {
+                const uint4 r6 = philox10(pid, step, ((uint32_t)s << 24) | 6u, 0u, dc.key0, dc.key1);
+                double g0, g1, g2, g3;
+                box_muller_d(u01d(r6.x), u01d(r6.y), g0, g1);
+                box_muller_d(u01d(r6.z), u01d(r6.w), g2, g3);
+                ux = sc.drift0[0] + sc.vth0 * g0;
+                uy = sc.drift0[1] + sc.vth0 * g1;
+                uz = sc.drift0[2] + sc.vth0 * g2;
+            }
+            if (word & kEvCand) {
+                cand = true;
+                ch = collide_particle(sc, dc, s, step, ux, uy, uz, pid, bb, viol, hb);
+            }
+            // the position (the push's, in the record): for an ionization's
+            // pair and the diagnostics
+            const int c = (int)rq.y;
+            const float f = __uint_as_float(rq.z);
+            if (hb) {
+                bb.cell = c;
+                bb.off = f;
+            }
+            const float fx = (float)ux, fy = (float)uy, fz = (float)uz;
+            sc.vx[io][slot] = fx;
+            sc.vy[io][slot] = fy;
+            sc.vz[io][slot] = fz;
+            if (ps.diag) {
+                unsigned long long* fh = d.macc + (size_t)sg * 2 * d.nodes_max;
+                moment_diag(sc.mscale1, sc.mscale2, fh, fh + d.nodes_max, c, f, fx, nc, periodic);
+                if (s == 0)
+                    electron_diag(sc.half_m_over_e, dc.bulk_lo, dc.bulk_hi, ps.eepf_inv_bin,
+                                  d.eacc + (size_t)b * d.nodes_max,
+                                  d.eepf + (size_t)b * 2 * kEepfBins, c, f, fx, fy, fz, nc, periodic);
+            }
+        }
+        if (hb) {
+            const uint32_t pos = atomicAdd(reinterpret_cast<uint32_t*>(&d.bcnt[t]), 1u);
+            if (pos < ps.bpt) {
+                bb.key = key;
+                d.births[(size_t)t * ps.bpt + pos] = bb;
+                unsigned long long* acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
+                global_deposit(acc_e, bb.cell, bb.off, nc, periodic);
+                if (!see && S > 1)          // no ions in a swarm
+                    global_deposit(d.acc + ((size_t)b * S + 1) * kRep * d.nodes_max, bb.cell, bb.off, nc,
+                                   periodic);
+                if (ps.diag) {
+                    // the births' velocity moments and the electron's
+                    // energy, with the particles of the step
+                    const SegConst& se = d.segc[b * S + 0];
+                    unsigned long long* fe = d.macc + (size_t)(b * S + 0) * 2 * d.nodes_max;
+                    moment_diag(se.mscale1, se.mscale2, fe, fe + d.nodes_max, bb.cell, bb.off, bb.vx, nc,
+                                periodic);
+                    electron_diag(se.half_m_over_e, dc.bulk_lo, dc.bulk_hi, ps.eepf_inv_bin,
+                                  d.eacc + (size_t)b * d.nodes_max, d.eepf + (size_t)b * 2 * kEepfBins,
+                                  bb.cell, bb.off, bb.vx, bb.vy, bb.vz, nc, periodic);
+                    if (!see && S > 1) {
+                        const SegConst& si = d.segc[b * S + 1];
+                        unsigned long long* fi = d.macc + (size_t)(b * S + 1) * 2 * d.nodes_max;
+                        moment_diag(si.mscale1, si.mscale2, fi, fi + d.nodes_max, bb.cell, bb.off, bb.ivx, nc,
+                                    periodic);
+                    }
+                }
+                atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[sg].staged), 1ull);
+            } else {
+                hb = false;
+                lost = true;
+                atomicOr(&d.diss[b].flags, kFlagCapacity);
+            }
+        }
+    }
+    // counters of the chunk, one segment at a time (a chunk spans more
+    // than one only at a segment's end): lane i holds counter i
+    uint64_t todo = __ballot(act);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lsg = __shfl(sg, leader, 64);
+        const bool mine = act && sg == lsg;
+        uint32_t cnt_lane = 0u;
+        auto count = [&](int i, bool p) {
+            const uint32_t v = popc_ballot(mine && p);
+            cnt_lane += lane == i ? v : 0u;
+        };
+        count(C_CAND, cand);
+        count(C_NULL, cand && ch < 0);
+        count(C_VIOL, viol);
+        const int nch = d.segc[lsg].nch;
+        for (int k = 0; k < nch; ++k) count(C_COLL + k, ch == k);
+        count(C_SEE0, hb && see && wall == 0);
+        count(C_SEE1, hb && see && wall == 1);
+        count(C_DROP, lost);
+        if (lane < C_N && cnt_lane)
+            atomicAdd(&d.cnt[((size_t)lsg * kRep) * C_N + lane], (unsigned long long)cnt_lane);
+        todo &= ~__ballot(mine);
+    }
+}
+
 // The events of a step, after the push: chunks of 64 consecutive events of
 // one push workgroup's range (in unit order: tiles, waves, slots), fully
 // packed but for the last of each range, strided over all the waves of the
@@ -842,18 +978,21 @@ template <int BS>
 __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
 {
     const DevPtrs& d = a.d;
-    const int S = d.S, NS = d.B * d.S;
+    const int NS = d.B * d.S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int kW = BS / 64;
     __shared__ int32_t s_pref[kMaxSeg + 1];
     __shared__ uint32_t s_cp[kMaxPushGrid + 1];   // chunks of the push workgroups before each
+    __shared__ uint32_t s_ne[kMaxPushGrid];       // events of each push workgroup
     __shared__ uint32_t s_w[kW];
     tile_prefix(d, a.T, s_pref);
     const int G = a.push_grid;
     uint32_t run = 0;
     for (int r = 0; r < G; r += BS) {
         const int g = r + tid;
-        const uint32_t c = g < G ? (d.evg[g] + 63u) >> 6 : 0u;
+        const uint32_t ne = g < G ? d.evg[g] : 0u;
+        const uint32_t c = (ne + 63u) >> 6;
+        if (g < G) s_ne[g] = ne;
         const uint32_t incl = wave_incl_scan_u32(c);
         if (lane == 63) s_w[wid] = incl;
         __syncthreads();
@@ -872,11 +1011,11 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
     __syncthreads();
     const int32_t NT = s_pref[NS];
     const int32_t chunk_t = (NT + G - 1) / G;     // the push workgroups' tile ranges
-    const int W = a.waves;
     const uint32_t bpt = (uint32_t)a.births_per_tile;
     const uint32_t nchunk = s_cp[G];
     const uint32_t stride = gridDim.x * kW;
 
+    const EvPass e{a.T, chunk_t, NT, bpt, a.diag, a.eepf_inv_bin};
     for (uint32_t ck = blockIdx.x * kW + wid; ck < nchunk; ck += stride) {
         // the push workgroup of chunk ck: the last g with s_cp[g] <= ck
         int glo = 0, ghi = G;
@@ -884,158 +1023,27 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
             const int mid = (glo + ghi) >> 1;
             if (s_cp[mid] <= ck) glo = mid; else ghi = mid;
         }
-        const int g = glo;
-        const uint32_t kc = ck - s_cp[g];
-        const uint32_t e = (kc << 6) + (uint32_t)lane;       // event of the range
-        const bool act = e < d.evg[g];
-        const int32_t t_begin = g * chunk_t;
-        const int32_t t_end = t_begin + chunk_t < NT ? t_begin + chunk_t : NT;
-        const int64_t u_end = (int64_t)t_end * W;
-        // the unit of event e: the last unit whose prefix is <= e, searched
-        // in windows of 64 units from the one holding the chunk's first event
-        int64_t ub = (int64_t)t_begin * W + d.evidx[(size_t)t_begin * a.T / 64 + kc];
-        int64_t unit = -1;
-        for (;;) {
-            const int64_t uj = ub + lane;
-            const uint32_t pj = uj < u_end ? d.evp[uj] : 0xffffffffu;
-            const uint32_t pend = ub + 64 < u_end ? d.evp[ub + 64] : 0xffffffffu;
-            // the last window entry <= e (lanes 0..63 hold the prefixes, in
-            // order; entry 0 is <= e), by binary lifting with whole-wave shuffles
-            int lo = 0;
-#pragma unroll
-            for (int h = 32; h >= 1; h >>= 1) {
-                const uint32_t pm = (uint32_t)__shfl((int)pj, lo + h, 64);
-                if (pm <= e) lo += h;
-            }
-            const bool found = !act || e < pend;
-            if (act && found && unit < 0) unit = ub + lo;
-            if (__ballot(!found) == 0ull) break;
-            ub += 64;                     // past 64 units that are all empty or earlier
-        }
-        bool hb = false, see = false, cand = false, viol = false, lost = false;
-        int wall = 0, ch = -1, sg = -1;
-        if (act) {
-            const int32_t t = (int32_t)(unit / W);
-            const int w = (int)(unit - (int64_t)t * W);
-            const uint32_t idx = e - d.evp[unit];   // both relative to the range
-            const size_t ri = (size_t)t * a.T + (size_t)w * 64 * a.ppt + idx;
-            const uint4 rec = d.evr[ri];
-            const uint32_t word = rec.x;
-            sg = tile_segment(s_pref, NS, t);
-            const int b = sg / S, s = sg - b * S;
-            const DisConst& dc = d.disc[b];
-            const SegConst& sc = d.segc[sg];
-            const int32_t tin = t - s_pref[sg];
-            const int io = d.segs[sg].parity;
-            const uint32_t step = (uint32_t)d.diss[b].step;
-            const int nc = dc.n_cells;
-            const int periodic = dc.bc == PIC_BC_PERIODIC;
-            const uint32_t key = word & kEvSlot;
-            const int64_t slot = (int64_t)tin * a.T + key;
-            const uint32_t pid = rec.y;
-            Birth bb;
-            if (word & kEvSee) {
-                see = true;
-                wall = (word & kEvWall1) ? 1 : 0;
-                const int r = secondary(sc, dc, s, step, wall, pid, bb);
-                hb = r > 0;
-                lost = r < 0;
-            } else {
-                double ux = __uint_as_float(rec.z), uy = __uint_as_float(rec.w), uz = d.evz[ri];
-                if (word & kEvRenew) {
-                    const uint4 r6 = philox10(pid, step, ((uint32_t)s << 24) | 6u, 0u, dc.key0, dc.key1);
-                    double g0, g1, g2, g3;
-                    box_muller_d(u01d(r6.x), u01d(r6.y), g0, g1);
-                    box_muller_d(u01d(r6.z), u01d(r6.w), g2, g3);
-                    ux = sc.drift0[0] + sc.vth0 * g0;
-                    uy = sc.drift0[1] + sc.vth0 * g1;
-                    uz = sc.drift0[2] + sc.vth0 * g2;
-                }
-                if (word & kEvCand) {
-                    cand = true;
-                    ch = collide_particle(sc, dc, s, step, ux, uy, uz, pid, bb, viol, hb);
-                }
-                // the position: for an ionization's pair and the diagnostics
-                int c = 0;
-                float f = 0.0f;
-                if (hb || a.diag) {
-                    c = sc.cell[io][slot];
-                    f = sc.off[io][slot];
-                    bb.cell = c;
-                    bb.off = f;
-                }
-                const float fx = (float)ux, fy = (float)uy, fz = (float)uz;
-                sc.vx[io][slot] = fx;
-                sc.vy[io][slot] = fy;
-                sc.vz[io][slot] = fz;
-                if (a.diag) {
-                    unsigned long long* fh = d.macc + (size_t)sg * 2 * d.nodes_max;
-                    moment_diag(sc.mscale1, sc.mscale2, fh, fh + d.nodes_max, c, f, fx, nc, periodic);
-                    if (s == 0)
-                        electron_diag(sc.half_m_over_e, dc.bulk_lo, dc.bulk_hi, a.eepf_inv_bin,
-                                      d.eacc + (size_t)b * d.nodes_max,
-                                      d.eepf + (size_t)b * 2 * kEepfBins, c, f, fx, fy, fz, nc, periodic);
-                }
-            }
-            if (hb) {
-                const uint32_t pos = atomicAdd(reinterpret_cast<uint32_t*>(&d.bcnt[t]), 1u);
-                if (pos < bpt) {
-                    bb.key = key;
-                    d.births[(size_t)t * bpt + pos] = bb;
-                    unsigned long long* acc_e = d.acc + ((size_t)b * S + 0) * kRep * d.nodes_max;
-                    global_deposit(acc_e, bb.cell, bb.off, nc, periodic);
-                    if (!see && S > 1)          // no ions in a swarm
-                        global_deposit(d.acc + ((size_t)b * S + 1) * kRep * d.nodes_max, bb.cell, bb.off, nc,
-                                       periodic);
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[sg].staged), 1ull);
-                } else {
-                    hb = false;
-                    lost = true;
-                    atomicOr(&d.diss[b].flags, kFlagCapacity);
-                }
-            }
-        }
-        // counters of the chunk, one segment at a time (a chunk spans more
-        // than one only at a segment's end): lane i holds counter i
-        uint64_t todo = __ballot(act);
-        while (todo) {
-            const int leader = __ffsll((long long)todo) - 1;
-            const int lsg = __shfl(sg, leader, 64);
-            const bool mine = act && sg == lsg;
-            uint32_t cnt_lane = 0u;
-            auto count = [&](int i, bool p) {
-                const uint32_t v = popc_ballot(mine && p);
-                cnt_lane += lane == i ? v : 0u;
-            };
-            count(C_CAND, cand);
-            count(C_NULL, cand && ch < 0);
-            count(C_VIOL, viol);
-            const int nch = d.segc[lsg].nch;
-            for (int k = 0; k < nch; ++k) count(C_COLL + k, ch == k);
-            count(C_SEE0, hb && see && wall == 0);
-            count(C_SEE1, hb && see && wall == 1);
-            count(C_DROP, lost);
-            if (lane < C_N && cnt_lane)
-                atomicAdd(&d.cnt[((size_t)lsg * kRep) * C_N + lane], (unsigned long long)cnt_lane);
-            todo &= ~__ballot(mine);
-        }
+        event_chunk(d, s_pref, NS, e, glo, s_ne[glo], ck - s_cp[glo]);
     }
 }
 
-#define PIC_KERNELS(X)   \
-    X(1, 256, false)     \
-    X(2, 256, false)     \
-    X(4, 256, false)     \
-    X(8, 256, false)     \
-    X(4, 512, false)     \
-    X(4, 1024, false)    \
-    X(1, 256, true)      \
-    X(2, 256, true)      \
-    X(4, 256, true)      \
-    X(4, 512, true)      \
-    X(4, 1024, true)
+#define PIC_KERNELS(X)        \
+    X(1, 256, false, false)   \
+    X(2, 256, false, false)   \
+    X(4, 256, false, false)   \
+    X(8, 256, false, false)   \
+    X(4, 512, false, false)   \
+    X(4, 1024, false, false)  \
+    X(1, 256, true, false)    \
+    X(2, 256, true, false)    \
+    X(4, 256, true, false)    \
+    X(4, 512, true, false)    \
+    X(4, 1024, true, false)   \
+    X(1, 256, true, true)     \
+    X(2, 256, true, true)     \
+    X(4, 256, true, true)
 
-#define PIC_INST(P, B, G) template __global__ void push_kernel<P, B, G>(PushArgs);
+#define PIC_INST(P, B, G, F) template __global__ void push_kernel<P, B, G, F>(PushArgs);
 PIC_KERNELS(PIC_INST)
 #undef PIC_INST
 
@@ -1065,13 +1073,16 @@ void push_shape(int& ppt, int& threads, bool general)
     }
 }
 
-hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, int64_t grid, hipStream_t st)
+bool push_fusable(int threads, bool general) { return general && threads == 256; }
+
+hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, bool fuse, int64_t grid,
+                       hipStream_t st)
 {
     const size_t lds = push_lds_bytes(a.nodes_max_dyn, a.cells_max_dyn, a.diag);
     const dim3 g((unsigned)grid);
-#define PIC_LAUNCH(P, B, G)                                                              \
-    if (ppt == P && threads == B && general == G) {                                      \
-        hipLaunchKernelGGL((push_kernel<P, B, G>), g, dim3(B), lds, st, a);             \
+#define PIC_LAUNCH(P, B, G, F)                                                           \
+    if (ppt == P && threads == B && general == G && fuse == F) {                         \
+        hipLaunchKernelGGL((push_kernel<P, B, G, F>), g, dim3(B), lds, st, a);          \
         return hipGetLastError();                                                        \
     }
     PIC_KERNELS(PIC_LAUNCH)
@@ -1079,13 +1090,13 @@ hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, in
     return hipErrorInvalidValue;
 }
 
-int push_occupancy(int ppt, int threads, bool general, size_t lds)
+int push_occupancy(int ppt, int threads, bool general, bool fuse, size_t lds)
 {
     int nb = 0;
-#define PIC_OCC(P, B, G)                                                                            \
-    if (ppt == P && threads == B && general == G) {                                                 \
+#define PIC_OCC(P, B, G, F)                                                                         \
+    if (ppt == P && threads == B && general == G && fuse == F) {                                    \
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                           \
-                &nb, reinterpret_cast<const void*>(push_kernel<P, B, G>), B, lds) != hipSuccess)     \
+                &nb, reinterpret_cast<const void*>(push_kernel<P, B, G, F>), B, lds) != hipSuccess)  \
             nb = 0;                                                                                 \
     }
     PIC_KERNELS(PIC_OCC)

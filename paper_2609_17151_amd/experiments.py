@@ -96,7 +96,7 @@ def cmd_sweep(a):
     grouped by frequency; windows, references and timings per draw."""
     draws = SETS[a.set]()[a.start:a.start + a.count]
     order = sorted(range(len(draws)), key=lambda i: -draws[i].get("freq", 13.56e6))
-    X, REF, DIST, TIMES, STEPS, CONV, CNT, TOL = [], [], [], [], [], [], [], []
+    X, REF, DIST, TIMES, STEPS, CONV, CNT, TOL, FLG = [], [], [], [], [], [], [], [], []
     ids = []
     total = 0.0
 
@@ -106,7 +106,8 @@ def cmd_sweep(a):
         pad = lambda rows: np.array([np.pad(np.asarray(r, dtype=np.float64), (0, nw - len(r)),
                                             constant_values=np.nan) for r in rows])
         np.savez(a.out, ids=np.array(ids), x=np.array(X), y=np.array(REF), dist=pad(DIST), times=pad(TIMES),
-                 steps=pad(STEPS), conv=np.array(CONV), counts=np.array(CNT), tol=np.array(TOL))
+                 steps=pad(STEPS), conv=np.array(CONV), counts=np.array(CNT), tol=np.array(TOL),
+                 flags=np.array(FLG))
 
     for k in range(0, len(order), a.batch):
         grp = order[k:k + a.batch]
@@ -128,6 +129,7 @@ def cmd_sweep(a):
             TOL.append(steady.noise_tolerance(DIST[-1]))
             CONV.append(convergence(sw.windows[j], ref, TOL[-1])[1] or -1)
             CNT.append(sim.counts(j)["count"])
+            FLG.append(sw.flags[j])
         cnt = [sim.counts(j)["count"] for j in range(len(grp))]
         flags = [sw.flags[j] for j in range(len(grp))]
         print(json.dumps(dict(batch=k // a.batch, discharges=len(grp), seconds=time.perf_counter() - t0,
@@ -143,11 +145,12 @@ def cmd_sweep(a):
 
 def cmd_train(a):
     """Train on the references of the sustained discharges (a discharge that
-    died out has no steady profile to learn)."""
+    died out, or stopped early on a device flag, has no steady profile to
+    learn)."""
     X, Y = [], []
     for f in a.data:
         d = np.load(f)
-        alive = np.all(d["counts"] > 0, axis=1)
+        alive = np.array([s["alive"] for s in cold_summary(d)], dtype=bool)
         X.append(d["x"][alive])
         Y.append(d["y"][alive])
     X, Y = np.concatenate(X), np.concatenate(Y)
@@ -166,15 +169,20 @@ def cmd_train(a):
 
 def cold_summary(cold):
     """Per cold draw: tolerance, periods to convergence and whether the
-    discharge survived (from the stored distances and counts)."""
+    discharge survived (from the stored distances and counts).  A discharge
+    that stopped before the others (a device flag latched, e.g. its particle
+    store filled up) has no valid reference and counts as not alive."""
     out = []
+    full = max(int(np.sum(np.isfinite(cold["dist"][k]))) for k in range(len(cold["ids"])))
     for k in range(len(cold["ids"])):
         d = cold["dist"][k]
         d = d[np.isfinite(d)]
         tol = steady.noise_tolerance(d)
         ok = [x <= tol for x in d]
         i = next((j for j in range(len(ok) - steady.NRUN + 1) if all(ok[j:j + steady.NRUN])), None)
-        alive = int(cold["counts"][k][0]) > 0 and int(cold["counts"][k][1]) > 0
+        alive = int(cold["counts"][k][0]) > 0 and int(cold["counts"][k][1]) > 0 and len(d) == full
+        if "flags" in cold.files:
+            alive = alive and int(cold["flags"][k]) == 0
         t = cold["times"][k]
         out.append(dict(tol=tol, periods=(i + 1) * 5 if i is not None else None, alive=alive,
                         steps=int(cold["steps"][k][i]) if i is not None else None,

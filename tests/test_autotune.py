@@ -13,13 +13,16 @@ from paper_2609_17151_amd import autotune
 class FakeSim:
     def __init__(self, cfg):
         self.cfgs, self.B, self.S = [cfg], 1, len(cfg["species"])
-        self.applied, self.stepped = [], 0
+        self.applied, self.stepped, self.fused = [], 0, []
 
     def counts(self, b):
         return dict(count=[1000] * self.S, step=0, flags=0, next_id=[1000 + 10 * self.stepped] * self.S)
 
     def config_tiles(self, ppt, threads, sort_every, compact_every):
         self.applied.append((ppt, threads, sort_every, compact_every))
+
+    def config_events(self, in_push):
+        self.fused.append(bool(in_push))
 
     def step(self, n):
         self.stepped += n
@@ -43,6 +46,9 @@ def test_candidates_by_kernel_mode():
     # random numbers of a run with births: no sort in the general kernel
     assert {c["sort_every"] for c in g} == {0}
     assert {c["sort_every"] for c in s} == set(autotune.SORT_EVERY)
+    # events in the push workgroups: general 256-thread tiles only
+    assert {(c["threads"], c["fuse"]) for c in g} == {(256, 0), (256, 1), (512, 0), (1024, 0)}
+    assert {c["fuse"] for c in s} == {0}
 
 
 def test_picks_fastest_and_caches(tmp_path):
@@ -50,10 +56,11 @@ def test_picks_fastest_and_caches(tmp_path):
     sim = FakeSim(cfg)
     cache = str(tmp_path / "tune.json")
     choice, table = autotune.tune(sim, steps=8, warm=0, cache=cache, timer=fake_timer)
-    assert choice == dict(ppt=1, threads=256, sort_every=0, compact_every=16)
+    assert choice == dict(ppt=1, threads=256, sort_every=0, compact_every=16, fuse=0)
     best = min(table, key=lambda r: r["ms_per_step"])
     assert all(choice[k] == best[k] for k in choice)
     assert sim.applied[-1] == (choice["ppt"], choice["threads"], choice["sort_every"], choice["compact_every"])
+    assert sim.fused[-1] is False
     stored = json.load(open(cache))
     assert autotune.signature(sim) in stored
     # a known workload is applied from the cache without timing
