@@ -12,6 +12,7 @@ import json
 import os
 import sys
 import time
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -167,7 +168,7 @@ def tuned(sim, tune):
                                             round(1e3 * r["ms_per_step"], 2) for r in table})
 
 
-def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True):
+def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True, sweep_particles=0):
     """The bounded, colliding path at steady-state counts: one argon RF
     discharge (2.5 cm, 30 mTorr, 200 V, 13.56 MHz, 1600 steps per period,
     2e5 macro-particles per species) and the sweep of 64 such discharges
@@ -175,7 +176,9 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True):
     batched step.  Each discharge starts from a half-sine density at those
     counts (electrons 3 eV, ions at the gas temperature) and runs `warm`
     steps before it is timed; with `tune` the autotuner then picks the step
-    schedule (tile shape and compaction interval) on the live run."""
+    schedule (tile shape and compaction interval) on the live run.  With
+    `sweep_particles` the sweep's counts are scaled to that total (both
+    species), keeping their log-uniform spread."""
     out = {}
     dens, temp = W.discharge_profile()
     if only in (None, "argon_rf"):
@@ -191,6 +194,8 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True):
         return out
     draws = W.sweep_draws(64, seed=4)
     counts = W.steady_counts(64)
+    if sweep_particles:
+        counts = np.maximum(1000, np.rint(counts * (sweep_particles / (2.0 * counts.sum())))).astype(int)
     cfgs = [W.argon_rf(gap=d["gap"], n_cells=d["n_cells"], pressure_mtorr=d["pressure_mtorr"], v_amp=d["v_amp"],
                        seed=1000 + i, capacity=4 * int(counts[i]) + 65536) for i, d in enumerate(draws)]
     sim = P.Sim(cfgs, W.argon_tables())
@@ -221,6 +226,8 @@ def main():
     ap.add_argument("--cpu-steps-one", type=int, default=60, help="oracle steps of the sequential step")
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="argon lines: the default schedule, no autotuning")
+    ap.add_argument("--sweep-particles", type=float, default=0.0,
+                    help="argon_sweep: scale the 64 discharges' counts to this total (both species)")
     ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
                     help="argon_rf / argon_sweep: only that secondary workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -246,7 +253,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "exb":
         r = secondary(P, W, torch, args.secondary_steps, only=args.workload, warm=args.secondary_warm,
-                      graphs=not args.no_graph, tune=not args.no_tune)
+                      graphs=not args.no_graph, tune=not args.no_tune, sweep_particles=args.sweep_particles)
         print(json.dumps(dict(workload=args.workload, **r[next(iter(r))])), flush=True)
         return
     cfg = W.exb()

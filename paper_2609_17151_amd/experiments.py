@@ -94,7 +94,9 @@ def cmd_plain(a):
 def cmd_sweep(a):
     """Cold runs of a set of draws, in batches of up to `batch` discharges
     grouped by frequency; windows, references and timings per draw."""
-    draws = SETS[a.set]()[a.start:a.start + a.count]
+    every = SETS[a.set]()
+    pick = [int(i) for i in a.ids.split(",")] if a.ids else list(range(a.start, min(a.start + a.count, len(every))))
+    draws = [every[i] for i in pick]
     order = sorted(range(len(draws)), key=lambda i: -draws[i].get("freq", 13.56e6))
     X, REF, DIST, TIMES, STEPS, CONV, CNT, TOL, FLG = [], [], [], [], [], [], [], [], []
     ids = []
@@ -111,7 +113,7 @@ def cmd_sweep(a):
 
     for k in range(0, len(order), a.batch):
         grp = order[k:k + a.batch]
-        cfgs = [warm.config(draws[i], weight=weight_of(draws[i], a), seed=1000 + a.start + i,
+        cfgs = [warm.config(draws[i], weight=weight_of(draws[i], a), seed=1000 + pick[i],
                             capacity=a.capacity) for i in grp]
         sim = _sim(cfgs)
         t0 = time.perf_counter()
@@ -120,7 +122,7 @@ def cmd_sweep(a):
         total += time.perf_counter() - t0
         for j, i in enumerate(grp):
             ref = sw.reference(j)
-            ids.append(a.start + i)
+            ids.append(pick[i])
             X.append(warm.inputs(draws[i]))
             REF.append(steady.to_features(ref))
             DIST.append([steady.distance(w, ref) for w in sw.windows[j]])
@@ -227,7 +229,7 @@ def cmd_warm(a):
     done = [t for t in t_conv if t is not None]
     cold_periods = [summ[k]["periods"] for k in keep]
     out = dict(kind="warm", draws=len(ids), seconds_inference_and_load=t_ready, converged=len(done),
-               schedule=sw.schedule,
+               schedule=sw.schedule, schedules=sw.schedules,
                seconds_to_last_convergence=max(done) if done else None,
                seconds_per_converged_discharge=(max(done) / len(ids)) if len(done) == len(ids) else None,
                mean_periods_warm=float(np.mean([c for c in conv if c > 0])) if done else None,
@@ -300,6 +302,7 @@ def main(argv=None):
     p.add_argument("--set", choices=sorted(SETS), required=True)
     p.add_argument("--start", type=int, default=0)
     p.add_argument("--count", type=int, default=64)
+    p.add_argument("--ids", default=None, help="comma-separated draw indices (instead of --start/--count)")
     p.add_argument("--batch", type=int, default=64)
     p.add_argument("--periods", type=int, default=300)
     p.add_argument("--weight-scale", type=float, default=1.0)

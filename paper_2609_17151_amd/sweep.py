@@ -28,11 +28,14 @@ from . import steady
 
 class Sweep:
     def __init__(self, sim, steps_per_period, window_periods=5, max_periods=300, electron=0, ion=1,
-                 progress=20.0, chunk=2048, tune=False, tune_cache=None):
+                 progress=20.0, chunk=2048, tune=False, tune_cache=None, retune=True):
         self.sim = sim
         self.tune = bool(tune)
         self.tune_cache = tune_cache
+        self.retune = bool(retune)
         self.schedule = None                            # the autotuner's choice, when tuned
+        self.schedules = []                             # (step, running discharges, choice) of every tuning
+        self._tuned_running = 0
         self.chunk = int(chunk)
         self.B = sim.B
         self.spp = [int(s) for s in steps_per_period]
@@ -53,20 +56,29 @@ class Sweep:
     def window_steps(self, b):
         return self.window_periods * self.spp[b]
 
-    def _tune(self):
-        """Time the step schedules on the batch itself (real steps: the
-        windows start after them) and apply the fastest."""
+    def _tune(self, cache=None):
+        """Time the step schedules on the batch itself (real steps) and apply
+        the fastest; returns the steps the tuning took."""
         from . import autotune
-        self.schedule, _ = autotune.tune(self.sim, steps=16, warm=8, cache=self.tune_cache)
+        running = [b for b in range(self.B) if not self.done[b]]
+        s0 = self.sim.counts(running[0])["step"]
+        self.schedule, _ = autotune.tune(self.sim, steps=16, warm=8, cache=cache)
+        took = self.sim.counts(running[0])["step"] - s0
+        self._tuned_running = len(running)
+        self.schedules.append((int(s0), len(running), self.schedule))
+        return took
 
     def run(self, stop=None):
         """Advance until every discharge is done.  `stop(b, sweep)` is called
         after each window of discharge b; a true result retires it early.
         With tune=True the autotuner first picks the step schedule on the
-        batch (its steps come before the first window, inside the wall time)."""
+        batch (its steps come before the first window, inside the wall time),
+        and with retune (device windows) again whenever the running
+        discharges have halved since, as a smaller batch can favour another
+        schedule (its steps count as steps of the run)."""
         t_start = time.perf_counter()
         if self.tune:
-            self._tune()
+            self._tune(self.tune_cache)
         if self.chunk > 0:
             return self._run_device(stop, t_start)
             return self._run_device(stop)
@@ -147,6 +159,9 @@ class Sweep:
                     sim.retire(b)
                     sim.set_windows(b, 0)
                     self.done[b] = True
+            running = self.done.count(False)
+            if self.tune and self.retune and 0 < running <= self._tuned_running // 2:
+                self.steps += self._tune()
             now = time.perf_counter()
             if self.progress and now - last >= self.progress:
                 last = now

@@ -7,7 +7,9 @@ library's own BF16 kernels, and the 4 held-out draws started from its
 prediction.  The held-out draws' first 5-period window lies much closer to
 their cold runs' references than the first window of the cold start does:
 the network starts them near their periodic steady state instead of from a
-uniform plasma.
+uniform plasma; and, under the convergence rule of the sweeps (10 windows in
+a row within max(2 %, 3 sigma) of the reference), they converge in fewer RF
+periods than their cold runs did.
 """
 import numpy as np
 import pytest
@@ -55,9 +57,21 @@ def test_warm_start_starts_near_the_steady_state():
     sim2 = P.Sim(warm_cfgs, tabs)
     for j in range(len(held)):
         warm.start_from_features(sim2, j, warm_cfgs[j], feats[j])
-    sw2 = Sweep(sim2, [spp[b] for b in held], window_periods=5, max_periods=5, progress=0).run()
+    tols = {b: steady.noise_tolerance([steady.distance(w, refs[b]) for w in sw.windows[b]]) for b in held}
+
+    def stop(j, s):
+        return steady.converged_at(s.windows[j], refs[held[j]], tol=tols[held[j]]) is not None
+
+    sw2 = Sweep(sim2, [spp[b] for b in held], window_periods=5, max_periods=150, progress=0).run(stop=stop)
     d_warm = [steady.distance(sw2.windows[j][0], refs[b]) for j, b in enumerate(held)]
     d_cold = [steady.distance(sw.windows[b][0], refs[b]) for b in held]
     sim2.close()
     # the network's start is at least three times closer than the cold start
     assert np.median(d_warm) < np.median(d_cold) / 3.0, (d_warm, d_cold)
+    # and reaches the steady state in fewer RF periods (a run that does not
+    # converge counts with its whole length)
+    per = lambda i, n: 5 * (i + 1) if i is not None else n
+    p_cold = [per(steady.converged_at(sw.windows[b], refs[b], tol=tols[b]), 240) for b in held]
+    p_warm = [per(steady.converged_at(sw2.windows[j], refs[b], tol=tols[b]), 150) for j, b in enumerate(held)]
+    print("periods to convergence, cold:", p_cold, "warm:", p_warm, flush=True)
+    assert np.median(p_warm) < np.median(p_cold), (p_warm, p_cold)
