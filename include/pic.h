@@ -422,14 +422,16 @@ pic_status pic_use_graphs(pic_ctx* ctx, int32_t enable);
  * step.  in_push = 1: each push workgroup processes the events of its own
  * tiles after its push, with no further launch, which shortens the step of
  * a workload too small to fill the GPU; this applies to tiles of 256
- * threads (other shapes keep the events kernel).  The results are the same
+ * threads with one to four particles each (other shapes keep the events
+ * kernel).  The results are the same
  * either way, bit for bit.  PIC_EINVAL for another value.  Synchronous;
  * takes effect at the next pic_step. */
 pic_status pic_config_events(pic_ctx* ctx, int32_t in_push);
 
 /* pic_config_tiles: tile shape of the particle kernels (particles per thread
  * 1, 2, 4 or 8; threads per workgroup 256, 512 or 1024; the nearest built
- * shape is used), the interval in steps of the sort by cell (0 = never) and
+ * shape is used: 1024 threads take four particles each, 512 four or, in
+ * the general kernel, eight), the interval in steps of the sort by cell (0 = never) and
  * the interval in steps of the compaction that removes the holes absorbed
  * particles leave (1 .. 1024, default 16; bounded runs only).  With graphs,
  * the replayed chunk is the least multiple of 32 steps both intervals

@@ -1,8 +1,8 @@
 """Autotuner of the step schedule: particles per thread, threads per
 workgroup, the interval of the sort by cell, the interval of the hole
-compaction and, for 256-thread tiles of the general kernel, whether the push
-workgroups process their own events (collisions, renewals, secondary
-emission) instead of the events kernel.
+compaction and, for 256-thread tiles of one to four particles per thread in
+the general kernel, whether the push workgroups process their own events
+(collisions, renewals, secondary emission) instead of the events kernel.
 
 None of the choices it makes changes the results: the deposit sums are
 exact integers, the random draws are keyed by particle id and step, and the
@@ -21,7 +21,7 @@ import json
 import os
 
 STREAMING = [(ppt, thr) for ppt, thr in ((4, 1024), (4, 512), (4, 256), (8, 256), (2, 256), (1, 256))]
-GENERAL = [(4, 1024), (4, 512), (4, 256), (2, 256), (1, 256)]
+GENERAL = [(4, 1024), (8, 512), (4, 512), (8, 256), (4, 256), (2, 256), (1, 256)]
 SORT_EVERY = (0, 32, 16)
 # intervals that divide the 32-step chunk a captured graph replays
 COMPACT_EVERY = (16, 32, 8)
@@ -47,7 +47,7 @@ def candidates(general):
     for ppt, thr in shapes:
         for srt in (SORT_EVERY if not general else (0,)):
             for cmp_ in (COMPACT_EVERY if general else (16,)):
-                for fuse in ((0, 1) if general and thr == 256 else (0,)):
+                for fuse in ((0, 1) if general and thr == 256 and ppt <= 4 else (0,)):
                     out.append(dict(ppt=ppt, threads=thr, sort_every=srt, compact_every=cmp_, fuse=fuse))
     return out
 

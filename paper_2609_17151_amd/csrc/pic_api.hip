@@ -813,7 +813,7 @@ pic_status plan_step(pic_ctx* ctx, StepPlan& p)
         if (sc.compacts || sc.nch > 0 || sc.emits || sc.renew_lz > 0.0) p.general = true;
     }
     push_shape(p.ppt, p.threads, p.general);
-    p.fuse = ctx->events_in_push && push_fusable(p.threads, p.general);
+    p.fuse = ctx->events_in_push && push_fusable(p.ppt, p.threads, p.general);
     const int T = p.threads * p.ppt;
     int64_t tiles = 0;
     for (int g = 0; g < B * S; ++g) tiles += (pad_cap(ctx->segc[g].cap) + T - 1) / T;

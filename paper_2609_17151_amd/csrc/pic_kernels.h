@@ -67,7 +67,7 @@ hipError_t launch_profile_load(const ProfileArgs& a, hipStream_t st);
 hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, bool fuse, int64_t grid,
                        hipStream_t st);
 // whether a push of this shape can do its workgroups' own events
-bool push_fusable(int threads, bool general);
+bool push_fusable(int ppt, int threads, bool general);
 void push_shape(int& ppt, int& threads, bool general);
 hipError_t launch_events(const EvArgs& a, int64_t grid, hipStream_t st);
 int events_occupancy();

@@ -1039,6 +1039,8 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
     X(4, 256, true, false)    \
     X(4, 512, true, false)    \
     X(4, 1024, true, false)   \
+    X(8, 256, true, false)    \
+    X(8, 512, true, false)    \
     X(1, 256, true, true)     \
     X(2, 256, true, true)     \
     X(4, 256, true, true)
@@ -1056,8 +1058,8 @@ size_t push_lds_bytes(int n_nodes, int n_cells, int diag)
     return b;
 }
 
-// nearest instantiated shape (general kernels: up to four particles per
-// thread)
+// nearest instantiated shape (1024 threads: four particles per thread; 512:
+// four, or eight in the general kernel; 256: one to eight)
 void push_shape(int& ppt, int& threads, bool general)
 {
     if (threads >= 1024) {
@@ -1065,15 +1067,14 @@ void push_shape(int& ppt, int& threads, bool general)
         ppt = 4;
     } else if (threads >= 512) {
         threads = 512;
-        ppt = 4;
+        ppt = (general && ppt >= 8) ? 8 : 4;
     } else {
         threads = 256;
         ppt = ppt >= 8 ? 8 : (ppt >= 4 ? 4 : (ppt >= 2 ? 2 : 1));
-        if (general && ppt > 4) ppt = 4;
     }
 }
 
-bool push_fusable(int threads, bool general) { return general && threads == 256; }
+bool push_fusable(int ppt, int threads, bool general) { return general && threads == 256 && ppt <= 4; }
 
 hipError_t launch_push(const PushArgs& a, int ppt, int threads, bool general, bool fuse, int64_t grid,
                        hipStream_t st)

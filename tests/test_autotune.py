@@ -47,6 +47,7 @@ def test_candidates_by_kernel_mode():
     assert {c["sort_every"] for c in g} == {0}
     assert {c["sort_every"] for c in s} == set(autotune.SORT_EVERY)
     # events in the push workgroups: general 256-thread tiles only
+    assert {(c["ppt"], c["threads"], c["fuse"]) for c in g if c["fuse"]} == {(1, 256, 1), (2, 256, 1), (4, 256, 1)}
     assert {(c["threads"], c["fuse"]) for c in g} == {(256, 0), (256, 1), (512, 0), (1024, 0)}
     assert {c["fuse"] for c in s} == {0}
 

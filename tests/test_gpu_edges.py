@@ -72,7 +72,7 @@ def test_ragged_counts_general_kernel(pic, n):
     # exactly, kinematics to binary32 rounding (at most one particle per
     # species may differ by a collision decided on the other side of a
     # rounding edge)
-    for ppt, thr in ((1, 256), (2, 256), (4, 256), (4, 512), (4, 1024)):
+    for ppt, thr in ((1, 256), (2, 256), (4, 256), (8, 256), (4, 512), (8, 512), (4, 1024)):
         cfg, tabs = small_argon(n_init=n)
         cfg["species"][0]["capacity"] = cfg["species"][1]["capacity"] = 8 * n + 64
         sim = pic.Sim(cfg, tabs)

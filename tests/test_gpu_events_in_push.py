@@ -107,3 +107,19 @@ def test_config_events_rejects_other_values(pic):
     with pytest.raises(RuntimeError):
         sim._check(pic._lib.pic_config_events(sim.h, 2), "pic_config_events")
     sim.close()
+
+
+@pytest.mark.parametrize("ppt,threads", [(8, 256), (8, 512), (4, 1024)])
+def test_tile_shapes_reach_the_same_state(pic, ppt, threads):
+    # the general kernel's other tile shapes (events kernel) against four
+    # particles per thread on 256 threads: the same steps, the same state
+    cfgs, tabs = _argon_batch(), W.argon_tables()
+    runs = []
+    for shape in ((4, 256), (ppt, threads)):
+        sim = pic.Sim(cfgs, tabs)
+        sim.config_tiles(shape[0], shape[1], 0, 16)
+        sim.set_diag(True)
+        sim.step(200)
+        runs.append(_state(sim))     # every quantity here is an integer sum or follows from one
+        sim.close()
+    _equal(runs[0], runs[1])
