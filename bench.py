@@ -158,8 +158,14 @@ def timed_rate(sim, torch, steps):
 
 
 def tuned(sim, tune):
-    """The autotuner's schedule for the workload (timed on the live run), or
-    the default one; returns what ran: the choice and each candidate's time."""
+    """The autotuner's schedule for the workload (timed on the live run), a
+    given one ("ppt,threads,compact_every,events_in_push"), or the default
+    one; returns what ran: the choice and each candidate's time."""
+    if isinstance(tune, str):
+        ppt, thr, cmp_, fuse = (int(v) for v in tune.split(","))
+        sim.config_tiles(ppt, thr, 0, cmp_)
+        sim.config_events(bool(fuse))
+        return dict(choice=dict(ppt=ppt, threads=thr, sort_every=0, compact_every=cmp_, fuse=fuse))
     if not tune:
         return dict(choice="default")
     from paper_2609_17151_amd import autotune
@@ -226,6 +232,8 @@ def main():
     ap.add_argument("--cpu-steps-one", type=int, default=60, help="oracle steps of the sequential step")
     ap.add_argument("--no-graph", action="store_true", help="direct launches (counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="argon lines: the default schedule, no autotuning")
+    ap.add_argument("--schedule", default=None, metavar="PPT,THREADS,COMPACT,FUSE",
+                    help="argon_rf / argon_sweep: this schedule instead of autotuning (counter runs)")
     ap.add_argument("--sweep-particles", type=float, default=0.0,
                     help="argon_sweep: scale the 64 discharges' counts to this total (both species)")
     ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
@@ -253,7 +261,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "exb":
         r = secondary(P, W, torch, args.secondary_steps, only=args.workload, warm=args.secondary_warm,
-                      graphs=not args.no_graph, tune=not args.no_tune, sweep_particles=args.sweep_particles)
+                      graphs=not args.no_graph, tune=args.schedule or not args.no_tune,
+                      sweep_particles=args.sweep_particles)
         print(json.dumps(dict(workload=args.workload, **r[next(iter(r))])), flush=True)
         return
     cfg = W.exb()

@@ -120,6 +120,8 @@ constexpr uint32_t kEvCand = 1u << 16;      // collision candidate
 constexpr uint32_t kEvRenew = 1u << 17;     // axial renewal: a fresh velocity
 constexpr uint32_t kEvSee = 1u << 18;       // an emitting ion absorbed at a wall: secondary emission test
 constexpr uint32_t kEvWall1 = 1u << 19;     // ... at the wall x = L
+constexpr int kEvSegShift = 20;             // the particle's segment (kMaxSeg <= 1024: 10 bits)
+static_assert(kMaxSeg <= 1024, "the event word holds the segment in 10 bits");
 
 // The constants of a tile's segment that the particle loop reads, copied to
 // registers once per tile.  The segment index is made wave-uniform, so these
@@ -474,9 +476,12 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
     };
 
+    // the tile's segment, wave-uniform (its constants become scalar loads):
+    // found once, then followed along the workgroup's contiguous range
+    int sg_walk = t_begin < t_end ? tile_segment(s_pref, NS, t_begin) : 0;
     for (int32_t t = t_begin; t < t_end; ++t) {
-        // the tile's segment, wave-uniform (its constants become scalar loads)
-        const int sg = __builtin_amdgcn_readfirstlane(tile_segment(s_pref, NS, t));
+        while (s_pref[sg_walk + 1] <= t) ++sg_walk;
+        const int sg = __builtin_amdgcn_readfirstlane(sg_walk);
         const int b = sg / S, s = sg - b * S;
         const DisConst& dc = d.disc[b];
         if (sg != cur_g) {
@@ -631,8 +636,9 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     if (evw[j]) {
-                        d.evr[r0 + below] = make_uint4(evw[j] | (uint32_t)(tid * PPT + j), pid[j],
-                                                       __float_as_uint(vx[j]), __float_as_uint(vy[j]));
+                        d.evr[r0 + below] = make_uint4(evw[j] | (uint32_t)(tid * PPT + j) |
+                                                           ((uint32_t)sg << kEvSegShift),
+                                                       pid[j], __float_as_uint(vx[j]), __float_as_uint(vy[j]));
                         d.evq[r0 + below] = make_uint4(__float_as_uint(vz[j]), (uint32_t)cell[j],
                                                        __float_as_uint(off[j]), (uint32_t)t);
                         ++below;
@@ -845,7 +851,7 @@ __device__ __forceinline__ void event_chunk(const DevPtrs& d, const int32_t* s_p
         const uint4 rq = d.evq[ri];
         const int32_t t = (int32_t)rq.w;
         const uint32_t word = rec.x;
-        sg = tile_segment(s_pref, NS, t);
+        sg = (int)(word >> kEvSegShift);
         const int b = sg / S, s = sg - b * S;
         const DisConst& dc = d.disc[b];
         const SegConst& sc = d.segc[sg];
