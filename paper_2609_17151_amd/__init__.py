@@ -547,11 +547,11 @@ class MLP:
         self._keep = x
         return y
 
-    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None):
         """One Adam update; returns the batch loss as a 1-element CUDA tensor
-        (taken before the update)."""
+        (taken before the update; written into `loss_out` when given)."""
         x, t = self._dev(x, self.widths[0]), self._dev(t, self.widths[-1])
-        loss = self._torch.empty(1, dtype=self._torch.float32, device="cuda")
+        loss = loss_out if loss_out is not None else self._torch.empty(1, dtype=self._torch.float32, device="cuda")
         self._check(_lib.pic_mlp_train_step(self.h, x.shape[0], x.data_ptr(), t.data_ptr(), lr, beta1, beta2,
                                             eps, loss.data_ptr()), "pic_mlp_train_step")
         self._keep = (x, t)

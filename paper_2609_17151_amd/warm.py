@@ -77,17 +77,23 @@ class Model:
         self.mean = Y.mean(axis=0)
         self.std = np.maximum(Y.std(axis=0), 1e-6)
         Z = (Y - self.mean) / self.std
-        xd = torch.as_tensor(X, dtype=torch.float32, device="cuda")
-        zd = torch.as_tensor(Z, dtype=torch.float32, device="cuda")
+        xh = X.astype(np.float32)
+        zh = Z.astype(np.float32)
         rng = np.random.default_rng(seed)
         n = len(X)
         batch = min(batch, n)
-        losses = []
+        # device memory for one minibatch and the losses; the minibatch rows
+        # are picked on the host and copied in (torch only holds memory here)
+        xb = torch.empty((batch, xh.shape[1]), dtype=torch.float32, device="cuda")
+        zb = torch.empty((batch, zh.shape[1]), dtype=torch.float32, device="cuda")
+        losses = torch.empty(steps, dtype=torch.float32, device="cuda")
         for k in range(steps):
             rate = lr * (lr_end / lr) ** (k / max(steps - 1, 1))
-            idx = torch.as_tensor(rng.choice(n, size=batch, replace=False), device="cuda")
-            losses.append(self.net.train_step(xd[idx], zd[idx], lr=rate))
-        self.history = [float(v) for v in torch.cat(losses).cpu()]
+            idx = rng.choice(n, size=batch, replace=False)
+            xb.copy_(torch.from_numpy(xh[idx]))
+            zb.copy_(torch.from_numpy(zh[idx]))
+            self.net.train_step(xb, zb, lr=rate, loss_out=losses[k:k + 1])
+        self.history = [float(v) for v in losses.cpu().numpy()]
         return self
 
     def predict(self, X):

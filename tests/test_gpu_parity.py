@@ -171,6 +171,9 @@ def test_argon_counts_and_order_bit_exact(pic):
 
 
 def test_numax_matches_oracle(pic):
+    # a consistency check, not parity: the bound is a definition written the
+    # same way on both sides so that the integer candidate thresholds agree
+    # (the pin of the bound itself is the oracle's own bound test)
     cfg, tabs = small_argon(n_init=1000)
     sim = pic.Sim(cfg, tabs)
     o = oracle.Oracle(cfg, tabs, load=False)
