@@ -22,7 +22,7 @@ BYTES_PER_PARTICLE_STEP = 40      # read cell, off, vx, vy, vz; write the same (
 PUSH_SOURCES = ("pic_push.hip", "pic_device.h", "pic_internal.h")
 COUNTERS = os.path.join(ROOT, "profiles", "push_kernel_exb_counters.txt")
 STATS = os.path.join(ROOT, "profiles", "push_kernel_exb_stats.txt")
-PUSH_KERNEL = "push_kernel<4, 1024, false>"
+PUSH_KERNEL = "push_kernel<4, 1024, false, false>"
 
 
 def push_source_hash():
