@@ -389,6 +389,18 @@ pic_status pic_retire(pic_ctx* ctx, int32_t batch, int32_t retired);
  * Asynchronous. */
 pic_status pic_sort(pic_ctx* ctx);
 
+/* pic_thin: population control of a species over every running discharge of
+ * the context, for the swarm setting of Section 4, where ionization makes an
+ * electron swarm grow without bound: where `species` holds more than `above`
+ * live particles, each is kept with probability keep / live, by an integer
+ * test on a Philox draw keyed by the particle's id and the step (call 7), and
+ * the removed ones are compacted away at once.  The survivors keep their
+ * order and ids (next_id is unchanged), so every per-particle average is
+ * unbiased; the kept count is keep on average, not exactly.  PIC_EINVAL for
+ * a species out of range, keep < 0 or keep > above.  Asynchronous, on the
+ * context's stream; call it between steps. */
+pic_status pic_thin(pic_ctx* ctx, int32_t species, int64_t above, int64_t keep);
+
 /* pic_sort_noalloc: pic_sort for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same kernels and the same result, with their scratch (the

@@ -102,6 +102,7 @@ def load_library():
         "pic_free": (None, [P]),
         "pic_config_tiles": (i32, [P, i32, i32, i32, i32]),
         "pic_config_events": (i32, [P, i32]),
+        "pic_thin": (i32, [P, i32, i64, i64]),
         "pic_set_diag": (i32, [P, i32, d]),
         "pic_set_wall_edf": (i32, [P, i32, d]),
         "pic_get_axial": (i32, [P, i32, i32, i64, dp, C.POINTER(i64)]),
@@ -239,6 +240,12 @@ class Sim:
 
     def config_tiles(self, ppt=4, threads=256, sort_every=0, compact_every=16):
         self._check(_lib.pic_config_tiles(self.h, ppt, threads, sort_every, compact_every), "pic_config_tiles")
+
+    def thin(self, species, above, keep):
+        """In every running discharge whose `species` holds more than `above`
+        particles, keep each with probability keep / live (on the device; the
+        survivors keep their order and ids)."""
+        self._check(_lib.pic_thin(self.h, int(species), int(above), int(keep)), "pic_thin")
 
     def config_events(self, in_push=False):
         """Events (collisions, renewals, secondary emission) in the push

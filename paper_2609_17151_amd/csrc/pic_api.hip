@@ -997,6 +997,17 @@ pic_status pic_retire(pic_ctx* ctx, int32_t batch, int32_t retired)
     return hip_st(hipMemcpy(&ctx->d.diss[batch].retired, &v, sizeof(v), hipMemcpyHostToDevice));
 }
 
+pic_status pic_thin(pic_ctx* ctx, int32_t species, int64_t above, int64_t keep)
+{
+    if (!ctx || species < 0 || species >= ctx->S || keep < 0 || keep > above) return PIC_EINVAL;
+    int64_t max_count = 0;
+    for (int b = 0; b < ctx->B; ++b) max_count = std::max(max_count, pad_cap(ctx->segc[b * ctx->S + species].cap));
+    return launch_thin(ctx->d, species, above, keep, max_count, ctx->compact_tiles, ctx->n_cu, ctx->stream) ==
+                   hipSuccess
+               ? PIC_OK
+               : PIC_EHIP;
+}
+
 pic_status pic_sort(pic_ctx* ctx)
 {
     if (!ctx) return PIC_EINVAL;

@@ -194,7 +194,66 @@ __global__ __launch_bounds__(256) void compact_finish_kernel(DevPtrs d)
     st.count = st.live;
 }
 
+// Population control of one species over every discharge (the swarm's
+// replicas): where the species holds more than `above` live particles, each
+// is kept with probability keep / live, by an integer test on a Philox draw
+// keyed by its id and the step (call 7); a removed particle becomes a hole,
+// counted in the segment's dead count (zero between steps), which
+// thin_finish takes off the live count before the compaction.  The live
+// count is only read here, so every workgroup uses the same probability.
+__global__ __launch_bounds__(256) void thin_mark_kernel(DevPtrs d, int32_t s, int64_t above, int64_t keep)
+{
+    const int b = (int)blockIdx.y;
+    const int g = b * d.S + s;
+    if (d.diss[b].retired) return;
+    const SegState& st = d.segs[g];
+    const int64_t live = st.live;
+    if (live <= above || live <= keep) return;
+    const uint32_t t24 = (uint32_t)(((uint64_t)keep << 24) / (uint64_t)live);   // < 2^24
+    const SegConst& sc = d.segc[g];
+    const DisConst& dc = d.disc[b];
+    const uint32_t step = (uint32_t)d.diss[b].step;
+    int32_t* cell = sc.cell[st.parity];
+    const uint32_t* id = sc.id[st.parity];
+    const int64_t n = st.count;
+    uint32_t removed = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (cell[i] < 0) continue;
+        const uint4 r = philox10(id[i], step, ((uint32_t)s << 24) | 7u, 0u, dc.key0, dc.key1);
+        if (!(odd24(r.x) < t24)) {
+            cell[i] = -1;
+            ++removed;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) removed += (uint32_t)__shfl_xor((int)removed, m, 64);
+    if ((threadIdx.x & 63) == 0 && removed)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[g].dead), (unsigned long long)removed);
+}
+
+__global__ __launch_bounds__(256) void thin_finish_kernel(DevPtrs d, int32_t s)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= d.B) return;
+    SegState& st = d.segs[b * d.S + s];
+    if (st.dead > 0) {
+        st.live -= st.dead;
+        st.dead = 0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_thin(const DevPtrs& d, int32_t species, int64_t above, int64_t keep, int64_t max_count,
+                       int64_t max_tiles, int n_cu, hipStream_t st)
+{
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_count + 255) / 256, 1024));
+    hipLaunchKernelGGL(thin_mark_kernel, dim3(gx, (unsigned)d.B), dim3(256), 0, st, d, species, above, keep);
+    hipLaunchKernelGGL(thin_finish_kernel, dim3((unsigned)((d.B + 255) / 256)), dim3(256), 0, st, d, species);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_compact(d, max_tiles, n_cu, st);
+}
 
 hipError_t launch_compact(const DevPtrs& d, int64_t max_tiles, int n_cu, hipStream_t st)
 {

@@ -78,6 +78,9 @@ hipError_t launch_halfstep(const DevPtrs& d, int only_b, int64_t max_count, hipS
 hipError_t launch_sort(const DevPtrs& d, int s, int64_t max_tiles, void* scratch, size_t scratch_bytes,
                        hipStream_t st);
 hipError_t launch_compact(const DevPtrs& d, int64_t max_tiles, int n_cu, hipStream_t st);
+// population control of one species (then a compaction); see pic_thin
+hipError_t launch_thin(const DevPtrs& d, int32_t species, int64_t above, int64_t keep, int64_t max_count,
+                       int64_t max_tiles, int n_cu, hipStream_t st);
 int64_t compact_tiles_for(int64_t padded_count);
 size_t sort_scratch_bytes(int64_t max_tiles, int B, int cells_max);
 int64_t sort_tiles_for(int64_t padded_count);

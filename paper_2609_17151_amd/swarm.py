@@ -5,9 +5,10 @@ gas as functions of E/N; the error bars come from independent replicas.
 Each (E/N, replica) pair is one discharge of a single context: electrons
 only, periodic, field_solve = 0, the field imposed along x.  Ionization
 adds electrons (the ion is not followed); when a replica has grown past
-`control` times its initial count it is thinned back to that count by a
-seeded uniform draw (the order of the survivors is kept), which leaves
-every per-electron average unchanged.
+`control` times its initial count it is thinned back to about that count on
+the device (pic_thin: each electron kept with the same probability, by a
+Philox draw keyed by its id and the step; the order of the survivors is
+kept), which leaves every per-electron average unchanged.
 
 Coefficients over a sampling window that follows a relaxation:
   * flux drift velocity W = <v_x> along the electrons' drift (-E direction);
@@ -80,21 +81,13 @@ class Swarm:
                      for i, en in enumerate(self.en) for r in range(self.R)]
         self.sim = Sim(self.cfgs, self.tables, stream=stream)
         self.B = len(self.cfgs)
-        self._rng = np.random.default_rng(seed)
-        self.thinned = 0
+        self.thinned = 0                # thinning rounds (every replica at once)
 
     def _thin(self):
-        """Thin every replica that has outgrown control x its initial count."""
-        sim = self.sim
-        for b in range(self.B):
-            c = sim.counts(b)
-            if c["count"][0] <= self.control * self.n0:
-                continue
-            p = sim.get_particles(0, b)
-            keep = np.sort(self._rng.choice(len(p["id"]), self.n0, replace=False))
-            sim.set_particles(0, p["cell"][keep], p["off"][keep], p["vx"][keep], p["vy"][keep], p["vz"][keep],
-                              p["id"][keep], p["next_id"], c["step"], batch=b)
-            self.thinned += 1
+        """Thin every replica that has outgrown control x its initial count
+        back to about that count, on the device, with no host round trip."""
+        self.sim.thin(0, int(self.control * self.n0), self.n0)
+        self.thinned += 1
 
     def run(self, relax_steps, sample_steps, every=128, eepf_emax=40.0, progress=None):
         """Relax, then sample; returns a dict of per-(E/N) means and errors

@@ -79,3 +79,41 @@ def test_argon_coefficients_trend_with_e_over_n(pic):
     for i in range(3):
         h = out["eepf"][i]
         assert abs(h.sum() * 40.0 / 256 - 1.0) < 1e-9 or h.sum() == 0.0
+
+
+def test_device_thinning_keeps_an_unbiased_ordered_subset(pic):
+    # two discharges: the larger one above the threshold is thinned, each
+    # particle kept with probability keep / live; the smaller one is left as it is
+    big, small = W.langmuir(n_particles=20000, seed=3), W.langmuir(n_particles=5000, seed=4)
+    sim = pic.Sim([big, small])
+    sim.step(3)
+    before = [sim.get_particles(0, b) for b in range(2)]
+    sim.thin(0, 10000, 8000)
+    after = [sim.get_particles(0, b) for b in range(2)]
+    # untouched below the threshold
+    for k in ("cell", "off", "vx", "vy", "vz", "id"):
+        assert np.array_equal(after[1][k], before[1][k]), k
+    # the survivors: the same particles, in their order, ids and next id kept
+    n = len(after[0]["id"])
+    sigma = math.sqrt(20000 * 0.4 * 0.6)
+    assert abs(n - 8000) < 5 * sigma, n
+    idx = np.searchsorted(before[0]["id"], after[0]["id"])
+    assert np.all(np.diff(after[0]["id"].astype(np.int64)) > 0)
+    assert np.array_equal(before[0]["id"][idx], after[0]["id"])
+    for k in ("cell", "off", "vx", "vy", "vz"):
+        assert np.array_equal(before[0][k][idx], after[0][k]), k
+    assert after[0]["next_id"] == before[0]["next_id"]
+    # an unbiased subset: the mean velocity moves by sampling noise only
+    sd = np.std(before[0]["vx"]) * math.sqrt((1.0 - n / 20000) / n)
+    assert abs(np.mean(after[0]["vx"]) - np.mean(before[0]["vx"])) < 5 * sd
+    # the store stays consistent: more steps, no flags, the same thinning twice
+    sim.step(5)
+    assert sim.flags(0) == 0 and sim.flags(1) == 0
+    twin = pic.Sim([big, small])
+    twin.step(3)
+    twin.thin(0, 10000, 8000)
+    assert np.array_equal(twin.get_particles(0, 0)["id"], after[0]["id"])
+    with pytest.raises(RuntimeError):
+        sim.thin(0, 100, 200)          # keep above the threshold
+    sim.close()
+    twin.close()
