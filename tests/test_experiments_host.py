@@ -1,0 +1,49 @@
+"""Host logic of the experiment drivers: which cold runs give a valid
+reference, and the bench line's summary of the measured wall times."""
+import json
+import os
+
+import numpy as np
+
+import bench
+from paper_2609_17151_amd import experiments as E
+from paper_2609_17151_amd import steady
+
+
+def _cold(dists, counts, flags=None):
+    nw = max(len(d) for d in dists)
+    pad = lambda r: np.pad(np.asarray(r, dtype=np.float64), (0, nw - len(r)), constant_values=np.nan)
+    out = dict(ids=np.arange(len(dists)), dist=np.array([pad(d) for d in dists]),
+               times=np.array([pad(np.arange(1, len(d) + 1) * 10.0) for d in dists]),
+               steps=np.array([pad(np.arange(1, len(d) + 1) * 100) for d in dists]),
+               counts=np.array(counts))
+    if flags is not None:
+        out["flags"] = np.array(flags)
+
+    class F(dict):
+        files = list(out)
+    return F(out)
+
+
+def test_cold_summary_excludes_dead_flagged_and_short_runs():
+    steady_run = [0.5, 0.3] + [0.01] * 20               # converges at the third window
+    c = _cold([steady_run, steady_run, steady_run[:10] + [0.01] * 2, steady_run],
+              [[100, 100], [0, 50], [100, 100], [100, 100]], flags=[0, 0, 0, 1])
+    s = E.cold_summary(c)
+    assert s[0]["alive"] and s[0]["periods"] == 3 * 5
+    assert not s[1]["alive"]                             # an empty species: died out
+    assert not s[2]["alive"]                             # stopped before the others
+    assert not s[3]["alive"]                             # a device flag latched
+    assert s[0]["tol"] == steady.noise_tolerance(np.array(steady_run))
+
+
+def test_bench_line_carries_the_wall_time_summary():
+    out = bench.c5_summary()
+    assert out is not None and out["measured_in_this_run"] is False
+    path = os.path.join(bench.ROOT, out["source"])
+    assert os.path.exists(path)
+    with open(os.path.join(bench.ROOT, "profiles", "c5_wall_time_summary.json")) as f:
+        s = json.load(f)
+    # the batched warm start beats the plain method per converged discharge
+    assert out["batched_warm_s_per_converged_discharge"] < out["plain_s_per_converged_discharge"]
+    assert s["draws"] == out["draws"]
