@@ -128,14 +128,16 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
     // ---- births, appended after the last slot in the order of their tiles --
     // (and, inside a tile, of their parents): ionization electrons, then the
     // secondaries of each emitting ion species in turn; ionization ions in the
-    // order of their electrons.  Rounds of up to kFT tiles: a block scan of
-    // the tiles' birth counts, then one birth per thread (its tile found by a
-    // binary search of the scan), so the copies of a round go out together.
+    // order of their electrons.  One pass per source segment: every thread
+    // sums the birth counts of its run of consecutive tiles, a block scan of
+    // those sums, then one birth per thread (its run found by a binary search
+    // of the scan, its tile by a walk along the run), so the copies go out
+    // together.
     // A tile's births are staged in any order; each carries its parent's
     // slot, and its rank among the tile's keys is its place.
     __shared__ int64_t s_app[kMaxSpecies], s_want[kMaxSpecies];
     __shared__ uint32_t s_scan[kWaves];
-    __shared__ uint32_t s_tinc[kFT];         // inclusive prefix of the round's tiles' birth counts
+    __shared__ uint32_t s_tinc[kFT];         // inclusive prefix of the threads' runs' birth counts
     // the bookkeeping of a step, by one wave: counts, ids, kinetic energy
     auto bookkeeping = [&](bool births) {
         if (a.diag) {
@@ -184,64 +186,75 @@ __global__ __launch_bounds__(kFT) void finalize_kernel(FinArgs a)
             if (d.segs[g].staged == 0) continue;          // no tile of this segment staged a birth
             const int64_t tf = d.segs[g].tile_first, nt = d.segs[g].ntiles;
             const bool pair = src == 0 && S > 1;            // ionization: an ion with every electron
-            for (int64_t r0 = 0; r0 < nt; r0 += kFT) {
-                const int64_t i = r0 + tid;
-                const uint32_t bc = i < nt ? (uint32_t)d.bcnt[tf + i] : 0u;
-                const uint32_t bpt = (uint32_t)a.births_per_tile;
-                const uint32_t c = bc < bpt ? bc : bpt;   // more were counted as dropped
-                const uint32_t incl = wave_incl_scan_u32(c);
-                if (lane == 63) s_scan[wid] = incl;
-                __syncthreads();
-                uint32_t wex = 0, tot = 0;
+            // thread tid covers the kt consecutive tiles from tid kt on (one
+            // pass however many tiles the segment has)
+            const int64_t kt = (nt + kFT - 1) / kFT;
+            const uint32_t bpt = (uint32_t)a.births_per_tile;
+            auto tile_births = [&](int64_t i) -> uint32_t {
+                if (i >= nt) return 0u;
+                const uint32_t bc = (uint32_t)d.bcnt[tf + i];
+                return bc < bpt ? bc : bpt;               // more were counted as dropped
+            };
+            uint32_t c = 0;
+            for (int64_t i = (int64_t)tid * kt; i < (int64_t)tid * kt + kt; ++i) c += tile_births(i);
+            const uint32_t incl = wave_incl_scan_u32(c);
+            if (lane == 63) s_scan[wid] = incl;
+            __syncthreads();
+            uint32_t wex = 0, tot = 0;
 #pragma unroll
-                for (int w = 0; w < kWaves; ++w) {
-                    if (w < wid) wex += s_scan[w];
-                    tot += s_scan[w];
-                }
-                s_tinc[tid] = wex + incl;
-                __syncthreads();
-                const int64_t nr = nt - r0 < kFT ? nt - r0 : kFT;   // tiles in this round
-                for (uint32_t j = tid; j < tot; j += kFT) {
-                    // the tile of birth j: the first with an inclusive prefix above j
-                    int lo = 0, hi = (int)nr - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_tinc[mid] > j) hi = mid; else lo = mid + 1;
-                    }
-                    const uint32_t t0 = lo > 0 ? s_tinc[lo - 1] : 0u;
-                    const uint32_t k = j - t0, nk = s_tinc[lo] - t0;
-                    const Birth* tb = d.births + (size_t)(tf + r0 + lo) * a.births_per_tile;
-                    const Birth bb = tb[k];
-                    uint32_t rank = 0;
-                    for (uint32_t q = 0; q < nk; ++q) rank += tb[q].key < bb.key;
-                    const int64_t e = pos0 + t0 + rank;
-                    if (e < cap0) {
-                        c0.cell[io0][e] = bb.cell;
-                        c0.off[io0][e] = bb.off;
-                        c0.vx[io0][e] = bb.vx;
-                        c0.vy[io0][e] = bb.vy;
-                        c0.vz[io0][e] = bb.vz;
-                        c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
-                        if (c0.z[0]) c0.z[io0][e] = 0.0;
-                    }
-                    if (pair) {
-                        const SegConst& c1 = d.segc[b * S + 1];
-                        const int64_t q = pos1 + t0 + rank;
-                        if (q < cap1) {
-                            c1.cell[io1][q] = bb.cell;
-                            c1.off[io1][q] = bb.off;
-                            c1.vx[io1][q] = bb.ivx;
-                            c1.vy[io1][q] = bb.ivy;
-                            c1.vz[io1][q] = bb.ivz;
-                            c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
-                            if (c1.z[0]) c1.z[io1][q] = 0.0;
-                        }
-                    }
-                }
-                pos0 += tot;
-                if (pair) pos1 += tot;
-                __syncthreads();                          // s_scan is reused
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wid) wex += s_scan[w];
+                tot += s_scan[w];
             }
+            s_tinc[tid] = wex + incl;
+            __syncthreads();
+            for (uint32_t j = tid; j < tot; j += kFT) {
+                // the thread holding birth j: the first with an inclusive
+                // prefix above j; then the tile among its kt
+                int lo = 0, hi = kFT - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_tinc[mid] > j) hi = mid; else lo = mid + 1;
+                }
+                uint32_t t0 = lo > 0 ? s_tinc[lo - 1] : 0u;
+                int64_t ti = (int64_t)lo * kt;
+                uint32_t nk = tile_births(ti);
+                while (j - t0 >= nk) {
+                    t0 += nk;
+                    nk = tile_births(++ti);
+                }
+                const uint32_t k = j - t0;
+                const Birth* tb = d.births + (size_t)(tf + ti) * a.births_per_tile;
+                const Birth bb = tb[k];
+                uint32_t rank = 0;
+                for (uint32_t q = 0; q < nk; ++q) rank += tb[q].key < bb.key;
+                const int64_t e = pos0 + t0 + rank;
+                if (e < cap0) {
+                    c0.cell[io0][e] = bb.cell;
+                    c0.off[io0][e] = bb.off;
+                    c0.vx[io0][e] = bb.vx;
+                    c0.vy[io0][e] = bb.vy;
+                    c0.vz[io0][e] = bb.vz;
+                    c0.id[io0][e] = id0 + (uint32_t)(e - slot0);
+                    if (c0.z[0]) c0.z[io0][e] = 0.0;
+                }
+                if (pair) {
+                    const SegConst& c1 = d.segc[b * S + 1];
+                    const int64_t q = pos1 + t0 + rank;
+                    if (q < cap1) {
+                        c1.cell[io1][q] = bb.cell;
+                        c1.off[io1][q] = bb.off;
+                        c1.vx[io1][q] = bb.ivx;
+                        c1.vy[io1][q] = bb.ivy;
+                        c1.vz[io1][q] = bb.ivz;
+                        c1.id[io1][q] = id1 + (uint32_t)(q - slot1);
+                        if (c1.z[0]) c1.z[io1][q] = 0.0;
+                    }
+                }
+            }
+            pos0 += tot;
+            if (pair) pos1 += tot;
+            __syncthreads();                              // s_scan and s_tinc are reused
         }
         if (tid == 0) {
             for (int s = 0; s < S; ++s) {

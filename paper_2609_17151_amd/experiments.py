@@ -260,6 +260,9 @@ def cmd_plainset(a):
         w = np.load(a.warm)
         done = {int(i) for i, c in zip(w["ids"], w["conv"]) if c > 0}
         keep = [k for k in keep if int(cold["ids"][k]) in done]
+    if a.ids:
+        only = {int(i) for i in a.ids.split(",")}
+        keep = [k for k in keep if int(cold["ids"][k]) in only]
     keep = keep[a.first:a.first + a.count] if a.count else keep[a.first:]
     ids, secs, per, steps = [], [], [], []
     for k in keep:
@@ -326,6 +329,7 @@ def main(argv=None):
     p = sub.add_parser("plainset")
     p.add_argument("--cold", required=True)
     p.add_argument("--warm", default=None)
+    p.add_argument("--ids", default=None, help="comma-separated draw indices (a subset of the kept draws)")
     p.add_argument("--first", type=int, default=0)
     p.add_argument("--count", type=int, default=0)
     p.add_argument("--periods", type=int, default=1200)

@@ -123,3 +123,21 @@ def test_tile_shapes_reach_the_same_state(pic, ppt, threads):
         runs.append(_state(sim))     # every quantity here is an integer sum or follows from one
         sim.close()
     _equal(runs[0], runs[1])
+
+
+def test_births_of_more_tiles_than_finalize_threads(pic):
+    # one discharge whose species span more than 1024 tiles of 256 particles:
+    # the finalize's births workgroup covers several tiles per thread; the
+    # state must equal that of a run with 1024-particle tiles (fewer tiles)
+    n = 300_000
+    cfg = W.argon_rf(n_init=n, capacity=2 * n, weight=3e13 / n, seed=7, te_ev=6.0, pressure_mtorr=120.0)
+    tabs = W.argon_tables()
+    runs = []
+    for shape in ((1, 256), (4, 1024)):
+        sim = pic.Sim(cfg, tabs)
+        sim.config_tiles(shape[0], shape[1], 0, 16)
+        sim.step(40)
+        runs.append(_state(sim))
+        sim.close()
+    assert runs[0][("counts", 0)]["next_id"][1] > n        # ions were born
+    _equal(runs[0], runs[1])
