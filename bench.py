@@ -10,6 +10,7 @@ JSON line.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 import numpy as np
@@ -25,13 +26,24 @@ STATS = os.path.join(ROOT, "profiles", "push_kernel_exb_stats.txt")
 PUSH_KERNEL = "push_kernel<4, 1024, false, false>"
 
 
+_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_only(text):
+    """C++ source without its comments, trailing blanks and empty lines:
+    what a kernel is compiled from (string and character literals kept)."""
+    text = _TOKENS.sub(lambda m: m.group(0) if m.group(0)[0] in "\"'" else " ", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
 def push_source_hash():
-    """SHA-256 over the sources the push kernel is compiled from."""
+    """SHA-256 over the code (comments and layout aside) of the sources the
+    push kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
     for name in PUSH_SOURCES:
-        with open(os.path.join(ROOT, "paper_2609_17151_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2609_17151_amd", "csrc", name)) as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()
 
 

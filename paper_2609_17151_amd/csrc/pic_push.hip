@@ -18,16 +18,17 @@
 // absorption at a wall, and the null-collision candidate test (an integer
 // test on one Philox draw).  What only a few particles need per step is
 // recorded as an event instead: a collision candidate, an axial renewal, the
-// secondary-emission test of an absorbed ion.  Each wave writes its events in
-// slot order to its tile's list (ballots and lane counts: no barrier, no
-// queue), and the events kernel then does that work for all of them with full
-// waves, in FP64.
+// secondary-emission test of an absorbed ion.  Each wave appends its events'
+// records to its workgroup's packed list at a place one LDS atomic claims
+// (ballots and lane counts: no barrier, no queue); the events pass then does
+// that work for all of them with full waves, in FP64: in the events kernel,
+// or at the end of each push workgroup for its own list (FUSE).
 //
 // Absorbed particles leave holes (cell = -1) that later steps skip; a stable
 // compaction every few steps removes them.  Holes do not change the order of
 // the live particles, and births are appended after the last slot in the
 // order of their parents, so the particle order after a compaction is the
-// order that compacting every step would give.  The events kernel stages a
+// order that compacting every step would give.  The events pass stages a
 // tile's births in any order, each with a key made of its parent's slot and
 // its rank among that parent's births; the finalize writes each birth at the
 // rank of its key within its tile, the tiles in order, which also gives their
@@ -113,7 +114,7 @@ __device__ __forceinline__ void vstore(S* __restrict__ p, const S* in)
     }
 }
 
-// Events of the step, recorded by the push for the events kernel: the slot
+// Events of the step, recorded by the push for the events pass: the slot
 // of the particle in its tile and what happens to it there.
 constexpr uint32_t kEvSlot = 0xffffu;       // slot in the tile (tiles hold at most 4096 particles)
 constexpr uint32_t kEvCand = 1u << 16;      // collision candidate
@@ -167,7 +168,7 @@ __device__ __forceinline__ PushC push_consts(const SegConst& sc, const DisConst&
 // A particle's step in the push: gather, Boris push, cell-relative move,
 // periodic wrap or absorption, and the collision test.  Returns whether the
 // particle stays; `ev` collects its event bits (the collision itself, the
-// secondary emission and the renewal are the events kernel's).
+// secondary emission and the renewal are the events pass's).
 template <bool GENERAL>
 __device__ __forceinline__ bool advance(const DevPtrs& d, const PushC& k, const PushArgs& a, int s, int b,
                                         uint32_t step, const float2* ep, unsigned int* s_cnt,
@@ -254,7 +255,7 @@ __device__ __forceinline__ bool advance(const DevPtrs& d, const PushC& k, const 
 
 // velocity moments of a particle at the nodes, fixed point (diagnostics);
 // fh and mh are LDS histograms in the push and the discharge's global sums
-// in the events kernel; ms1, ms2 the species' fixed-point scales
+// in the events pass; ms1, ms2 the species' fixed-point scales
 __device__ __forceinline__ void moment_diag(float ms1, float ms2, unsigned long long* fh, unsigned long long* mh,
                                             int c, float f, float ux, int nc, int periodic)
 {
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
                                                vz[j], pid[j], ke_tile, evw[j]);
             if (renews && keep) {
                 // past L_z the particle gets a fresh velocity from its
-                // species' initial distribution at the same x (events kernel)
+                // species' initial distribution at the same x (events pass)
                 const double zz = zax[j] + (double)vz[j] * dt_d;
                 if (fabs(zz) >= renew_lz) {
                     evw[j] |= kEvRenew;
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             }
             if (keep) {
                 lds_deposit(hist, cell[j], off[j], nc, periodic);
-                // a particle whose velocity the events kernel changes is
+                // a particle whose velocity the events pass changes is
                 // sampled there
                 if (a.diag && !(evw[j] & (kEvCand | kEvRenew))) {
                     moment_diag(k.mscale1, k.mscale2, fhist, mhist, cell[j], off[j], vx[j], nc, periodic);
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
             d.segs[sg].tile_first = tile_first;
             d.segs[sg].ntiles = ntiles;
         }
-        if (GENERAL && tid == 0) d.bcnt[t] = 0;   // the events kernel counts this tile's births
+        if (GENERAL && tid == 0) d.bcnt[t] = 0;   // the events pass counts this tile's births
     }
     if (cur_g >= 0) flush(cur_g);
     if (GENERAL) {

@@ -47,3 +47,14 @@ def test_bench_line_carries_the_wall_time_summary():
     # the batched warm start beats the plain method per converged discharge
     assert out["batched_warm_s_per_converged_discharge"] < out["plain_s_per_converged_discharge"]
     assert s["draws"] == out["draws"]
+
+
+def test_kernel_hash_follows_code_not_comments():
+    src = 'int f(int a) {  // the first "word"\n  /* two\n lines */ return a + 1;\n}\n\nconst char* s = "// kept";\n'
+    edited = src.replace("the first", "the last").replace("two\n lines", "one line") + "\n// more\n"
+    assert bench.code_only(src) == bench.code_only(edited)
+    assert "// kept" in bench.code_only(src)
+    assert bench.code_only(src) != bench.code_only(src.replace("a + 1", "a + 2"))
+    # every committed push summary was taken of the kernel built from this tree
+    assert bench.measured_traffic() is not None
+    assert bench.rocprof_push_us() is not None
