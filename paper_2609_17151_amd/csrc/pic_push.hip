@@ -123,6 +123,7 @@ constexpr uint32_t kEvSee = 1u << 18;       // an emitting ion absorbed at a wal
 constexpr uint32_t kEvWall1 = 1u << 19;     // ... at the wall x = L
 constexpr int kEvSegShift = 20;             // the particle's segment (kMaxSeg <= 1024: 10 bits)
 static_assert(kMaxSeg <= 1024, "the event word holds the segment in 10 bits");
+static_assert(C_N <= 64, "the flush's counters are held by one wave's lanes");
 
 // The constants of a tile's segment that the particle loop reads, copied to
 // registers once per tile.  The segment index is made wave-uniform, so these
@@ -424,55 +425,61 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
     const int32_t t_end = t_begin + chunk < NT ? t_begin + chunk : NT;
 
     // flush the run of tiles of segment cg: deposit, diagnostics, counters,
-    // kinetic energy (ranges are fixed, so the grouping of the sums is too)
-    auto flush = [&](int cg) {
+    // kinetic energy (ranges are fixed, so the grouping of the sums is too).
+    // The first `quiet` threads (whole waves) take part in the barriers only,
+    // so that no memory operation of the flush is outstanding in those waves
+    // when they go on to the events pass.
+    auto flush = [&](int cg, int quiet) {
         __syncthreads();
+        const int ft = tid - quiet, nt = kBS - quiet;
         const int cb = cg / S, cs = cg - cb * S;
         const DisConst& dcf = d.disc[cb];
         const int rep = blockIdx.x % kRep;
-        unsigned long long* acc_s = d.acc + ((size_t)cg * kRep + rep) * d.nodes_max;
-        for (int i = tid; i < dcf.n_nodes; i += kBS) {
-            const unsigned long long v = hist[i];
-            if (v) atomicAdd(&acc_s[i], v);
-        }
-        if (a.diag) {
-            unsigned long long* ma = d.macc + (size_t)cg * 2 * d.nodes_max;
-            for (int i = tid; i < dcf.n_nodes; i += kBS) {
-                const unsigned long long v = fhist[i], w = mhist[i];
-                if (v) atomicAdd(&ma[i], v);
-                if (w) atomicAdd(&ma[d.nodes_max + i], w);
+        if (ft >= 0) {
+            unsigned long long* acc_s = d.acc + ((size_t)cg * kRep + rep) * d.nodes_max;
+            for (int i = ft; i < dcf.n_nodes; i += nt) {
+                const unsigned long long v = hist[i];
+                if (v) atomicAdd(&acc_s[i], v);
             }
-        }
-        if (a.diag && cs == 0) {
-            unsigned long long* ea = d.eacc + (size_t)cb * d.nodes_max;
-            for (int i = tid; i < dcf.n_nodes; i += kBS) {
-                const unsigned long long v = ehist[i];
-                if (v) atomicAdd(&ea[i], v);
+            if (a.diag) {
+                unsigned long long* ma = d.macc + (size_t)cg * 2 * d.nodes_max;
+                for (int i = ft; i < dcf.n_nodes; i += nt) {
+                    const unsigned long long v = fhist[i], w = mhist[i];
+                    if (v) atomicAdd(&ma[i], v);
+                    if (w) atomicAdd(&ma[d.nodes_max + i], w);
+                }
             }
-            unsigned long long* eg = d.eepf + (size_t)cb * 2 * kEepfBins;
-            for (int i = tid; i < kEepfBins; i += kBS) {
-                const unsigned int v = eepf[i];
-                if (v) atomicAdd(&eg[i], (unsigned long long)v);
+            if (a.diag && cs == 0) {
+                unsigned long long* ea = d.eacc + (size_t)cb * d.nodes_max;
+                for (int i = ft; i < dcf.n_nodes; i += nt) {
+                    const unsigned long long v = ehist[i];
+                    if (v) atomicAdd(&ea[i], v);
+                }
+                unsigned long long* eg = d.eepf + (size_t)cb * 2 * kEepfBins;
+                for (int i = ft; i < kEepfBins; i += nt) {
+                    const unsigned int v = eepf[i];
+                    if (v) atomicAdd(&eg[i], (unsigned long long)v);
+                }
             }
-        }
-        unsigned long long* cnt = d.cnt + ((size_t)cg * kRep + rep) * C_N;
-        if (tid < C_N) {
-            const unsigned int v = s_cnt[tid];
-            if (v) {
-                atomicAdd(&cnt[tid], (unsigned long long)v);
-                if (tid == C_ABS0 || tid == C_ABS1)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[cg].dead), (unsigned long long)v);
+            unsigned long long* cnt = d.cnt + ((size_t)cg * kRep + rep) * C_N;
+            if (ft < C_N) {
+                const unsigned int v = s_cnt[ft];
+                if (v) {
+                    atomicAdd(&cnt[ft], (unsigned long long)v);
+                    if (ft == C_ABS0 || ft == C_ABS1)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(&d.segs[cg].dead), (unsigned long long)v);
+                }
+                s_cnt[ft] = 0;
             }
-            s_cnt[tid] = 0;
-        }
-        if (tid < 2) {
-            const unsigned long long v = s_wen[tid];
-            if (v) atomicAdd(&d.wen[(size_t)cg * 2 + tid], v);
-            s_wen[tid] = 0ull;
+            if (ft < 2) {
+                const unsigned long long v = s_wen[ft];
+                if (v) atomicAdd(&d.wen[(size_t)cg * 2 + ft], v);
+                s_wen[ft] = 0ull;
+            }
         }
         if (a.diag) {
             const double kt = block_sum_f32<BS>(ke_run, s_red);
-            if (tid == 0) d.ke_part[run_first] = 0.5 * d.segc[cg].mw_half * kt;
+            if (ft == 0) d.ke_part[run_first] = 0.5 * d.segc[cg].mw_half * kt;
             ke_run = 0.0f;
         }
     };
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         const int b = sg / S, s = sg - b * S;
         const DisConst& dc = d.disc[b];
         if (sg != cur_g) {
-            if (cur_g >= 0) flush(cur_g);
+            if (cur_g >= 0) flush(cur_g, 0);
             __syncthreads();
             if (b != cur_b) {
                 const float2* epg = d.epair + (size_t)b * d.cells_max;
@@ -653,20 +660,27 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         }
         if (GENERAL && tid == 0) d.bcnt[t] = 0;   // the events pass counts this tile's births
     }
-    if (cur_g >= 0) flush(cur_g);
-    if (GENERAL) {
-        __syncthreads();                          // every wave's records are written
-        const uint32_t nev = s_evn;
-        if (tid == 0) d.evg[blockIdx.x] = nev;    // the events pass's count of this range
-        if (FUSE) {
-            // this workgroup's own events, in chunks of 64 over its waves:
-            // the same pass as the events kernel's, on the records and the
-            // tiles this workgroup has just written
-            const EvPass ps{T, chunk, NT, (uint32_t)(T / kBirthsDiv), a.diag, a.eepf_inv_bin};
-            const uint32_t nch = (nev + 63u) >> 6;
-            for (uint32_t kc = (uint32_t)wid; kc < nch; kc += (uint32_t)kWavesPerTile)
-                event_chunk(d, s_pref, NS, ps, (int)blockIdx.x, nev, kc);
-        }
+    if (!GENERAL) {
+        if (cur_g >= 0) flush(cur_g, 0);
+        return;
+    }
+    __syncthreads();                              // every wave's records are written
+    const uint32_t nev = s_evn;
+    // with fewer chunks of events than waves (FUSE), the first waves run
+    // them while the others flush the deposit: each wave waits only on its
+    // own memory operations, so the events pass does not wait for the
+    // flush's atomics to complete
+    const uint32_t nch = FUSE ? (nev + 63u) >> 6 : 0u;
+    const int quiet = nch < (uint32_t)kWavesPerTile ? (int)nch * 64 : 0;
+    if (cur_g >= 0) flush(cur_g, quiet);
+    if (tid == kBS - 1) d.evg[blockIdx.x] = nev;  // the events pass's count of this range
+    if (FUSE) {
+        // this workgroup's own events, in chunks of 64 over its waves:
+        // the same pass as the events kernel's, on the records and the
+        // tiles this workgroup has just written
+        const EvPass ps{T, chunk, NT, (uint32_t)(T / kBirthsDiv), a.diag, a.eepf_inv_bin};
+        for (uint32_t kc = (uint32_t)wid; kc < nch; kc += (uint32_t)kWavesPerTile)
+            event_chunk(d, s_pref, NS, ps, (int)blockIdx.x, nev, kc);
     }
 }
 
