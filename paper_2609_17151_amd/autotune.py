@@ -114,10 +114,14 @@ def tune(sim, steps=64, warm=32, cache=None, timer=None, verbose=False):
             return c, store[key]["table"]
     general = key.endswith("general")
     rate = birth_rate(sim) if general else None
+    cands = candidates(general)
+    if general:
+        ok = [c for c in cands if fits(sim, c["compact_every"], rate)]
+        # no interval leaves the headroom (a discharge near its capacity):
+        # the most frequent compaction is the least bad
+        cands = ok or [c for c in cands if c["compact_every"] == min(COMPACT_EVERY)]
     table = []
-    for c in candidates(general):
-        if general and not fits(sim, c["compact_every"], rate):
-            continue
+    for c in cands:
         apply(sim, c)
         if warm:
             sim.step(warm)

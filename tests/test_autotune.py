@@ -108,3 +108,15 @@ def test_compaction_interval_needs_capacity_headroom():
     choice, table = autotune.tune(sim, steps=4, warm=0, timer=fake_timer)
     assert {r["compact_every"] for r in table} == {8, 16}
     assert choice["compact_every"] in (8, 16)
+
+
+def test_most_frequent_compaction_when_no_interval_fits():
+    # 1000 slots in use, 10 births per step, capacity 1100 (90 %: 990): no
+    # interval fits, so the candidates compact every 8 steps
+    cfg = W.argon_rf(n_init=1000)
+    for sp in cfg["species"]:
+        sp["capacity"] = 1100
+    sim = FakeSim(cfg)
+    choice, table = autotune.tune(sim, steps=4, warm=0, timer=fake_timer)
+    assert table and {r["compact_every"] for r in table} == {min(autotune.COMPACT_EVERY)}
+    assert choice["compact_every"] == min(autotune.COMPACT_EVERY)
