@@ -213,7 +213,9 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True, 
     steps before it is timed; with `tune` the autotuner then picks the step
     schedule (tile shape and compaction interval) on the live run.  With
     `sweep_particles` the sweep's counts are scaled to that total (both
-    species), keeping their log-uniform spread."""
+    species), keeping their log-uniform spread, and each discharge's
+    macro-particle weight by the inverse of its own factor, so that its
+    densities, and so its state, are those of the unscaled sweep."""
     out = {}
     dens, temp = W.discharge_profile()
     if only in (None, "argon_rf"):
@@ -228,11 +230,14 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True, 
     if only not in (None, "argon_sweep"):
         return out
     draws = W.sweep_draws(64, seed=4)
-    counts = W.steady_counts(64)
+    counts0 = W.steady_counts(64)
+    counts = counts0
     if sweep_particles:
-        counts = np.maximum(1000, np.rint(counts * (sweep_particles / (2.0 * counts.sum())))).astype(int)
+        counts = np.maximum(1000, np.rint(counts0 * (sweep_particles / (2.0 * counts0.sum())))).astype(int)
+    weights = W.PILOT_WEIGHT * counts0 / counts
     cfgs = [W.argon_rf(gap=d["gap"], n_cells=d["n_cells"], pressure_mtorr=d["pressure_mtorr"], v_amp=d["v_amp"],
-                       seed=1000 + i, capacity=4 * int(counts[i]) + 65536) for i, d in enumerate(draws)]
+                       seed=1000 + i, capacity=4 * int(counts[i]) + 65536, weight=float(weights[i]))
+            for i, d in enumerate(draws)]
     sim = P.Sim(cfgs, W.argon_tables())
     sim.use_graphs(graphs)
     for b in range(64):
@@ -264,7 +269,7 @@ def main():
     ap.add_argument("--schedule", default=None, metavar="PPT,THREADS,COMPACT,FUSE",
                     help="argon_rf / argon_sweep: this schedule instead of autotuning (counter runs)")
     ap.add_argument("--sweep-particles", type=float, default=0.0,
-                    help="argon_sweep: scale the 64 discharges' counts to this total (both species)")
+                    help="argon_sweep: scale the 64 discharges' counts to this total (both species), their weights inversely")
     ap.add_argument("--workload", choices=["exb", "argon_rf", "argon_sweep"], default="exb",
                     help="argon_rf / argon_sweep: only that secondary workload (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
