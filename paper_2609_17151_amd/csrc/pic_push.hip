@@ -75,10 +75,12 @@ __device__ __forceinline__ void global_deposit(unsigned long long* acc, int c, f
 // memory instructions (measured 8 % faster on the streaming push).
 #define PIC_GLOBAL __attribute__((address_space(1)))
 
-// NT: non-temporal (streaming) accesses, which leave the L2 to the rest of
-// the step.  Measured on the 64-discharge argon sweep: push 541 -> 511 us and
-// the events kernel after it 97 -> 80 us; on the E x B box, whose step is the
-// push alone, they cost 11 % and are not used.
+// NT: non-temporal (streaming) accesses, which leave the caches to the rest
+// of the step.  Measured on the 64-discharge argon sweep (4.7e7 particles):
+// the general push 541 -> 461 us (each at its fastest tile shape) and the
+// events kernel after it 97 -> 80 us.  The streaming push on the E x B box,
+// whose particle arrays fit the Infinity Cache between steps, is 11 % slower
+// with them and does not use them.
 template <int N, typename V, bool NT = false, typename S>
 __device__ __forceinline__ void vload(const S* __restrict__ p, S* out)
 {
