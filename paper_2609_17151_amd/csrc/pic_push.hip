@@ -386,8 +386,10 @@ struct EvPass {
     float eepf_inv_bin;
 };
 
+__device__ __forceinline__ bool event_record(const DevPtrs& d, const EvPass& ps, int g, uint32_t nev, uint32_t kc,
+                                             uint4& rec, uint4& rq);
 __device__ __forceinline__ void event_chunk(const DevPtrs& d, const int32_t* s_pref, int NS, const EvPass& ps,
-                                            int g, uint32_t nev, uint32_t kc);
+                                            bool act, uint4 rec, uint4 rq);
 
 // FUSE: the workgroup does its own tile range's events after its push (no
 // events launch; for workloads too small to fill the GPU twice)
@@ -699,8 +701,11 @@ __global__ __launch_bounds__(BS) void push_kernel(PushArgs a)
         // the same pass as the events kernel's, on the records and the
         // tiles this workgroup has just written
         const EvPass ps{T, chunk, NT, (uint32_t)(T / kBirthsDiv), a.diag, a.eepf_inv_bin};
-        for (uint32_t kc = (uint32_t)wid; kc < nch; kc += (uint32_t)kWavesPerTile)
-            event_chunk(d, s_pref, NS, ps, (int)blockIdx.x, nev, kc);
+        for (uint32_t kc = (uint32_t)wid; kc < nch; kc += (uint32_t)kWavesPerTile) {
+            uint4 rec, rq;
+            const bool act = event_record(d, ps, (int)blockIdx.x, nev, kc, rec, rq);
+            event_chunk(d, s_pref, NS, ps, act, rec, rq);
+        }
     }
 }
 
@@ -871,19 +876,27 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) { return (uint32_t)__pop
 
 // the events pass over one chunk (declared above the push kernel): events
 // 64 kc .. 64 kc + 63 of the nev that push workgroup g recorded
+// This lane's event of chunk kc (64 consecutive events) of push workgroup
+// g's list of nev: its two record words; false past the list's end.
+__device__ __forceinline__ bool event_record(const DevPtrs& d, const EvPass& ps, int g, uint32_t nev, uint32_t kc,
+                                             uint4& rec, uint4& rq)
+{
+    const uint32_t e = (kc << 6) + (uint32_t)(threadIdx.x & 63);
+    if (e >= nev) return false;
+    const size_t ri = (size_t)g * ps.chunk_t * ps.T + e;
+    rec = d.evr[ri];
+    rq = d.evq[ri];
+    return true;
+}
+
 __device__ __forceinline__ void event_chunk(const DevPtrs& d, const int32_t* s_pref, int NS, const EvPass& ps,
-                                            int g, uint32_t nev, uint32_t kc)
+                                            bool act, uint4 rec, uint4 rq)
 {
     const int S = d.S;
     const int lane = threadIdx.x & 63;
-    const uint32_t e = (kc << 6) + (uint32_t)lane;       // event of the workgroup's list
-    const bool act = e < nev;
     bool hb = false, see = false, cand = false, viol = false, lost = false;
     int wall = 0, ch = -1, sg = -1;
     if (act) {
-        const size_t ri = (size_t)g * ps.chunk_t * ps.T + e;
-        const uint4 rec = d.evr[ri];
-        const uint4 rq = d.evq[ri];
         const int32_t t = (int32_t)rq.w;
         const uint32_t word = rec.x;
         sg = (int)(word >> kEvSegShift);
@@ -1057,14 +1070,30 @@ __global__ __launch_bounds__(BS) void events_kernel(EvArgs a)
     const uint32_t stride = gridDim.x * kW;
 
     const EvPass e{a.T, chunk_t, NT, bpt, a.diag, a.eepf_inv_bin};
-    for (uint32_t ck = blockIdx.x * kW + wid; ck < nchunk; ck += stride) {
-        // the push workgroup of chunk ck: the last g with s_cp[g] <= ck
+    // the records of chunk ck, for the lanes that hold one; the push
+    // workgroup of chunk ck is the last g with s_cp[g] <= ck
+    auto records = [&](uint32_t ck, uint4& rec, uint4& rq) -> bool {
         int glo = 0, ghi = G;
         while (ghi - glo > 1) {
             const int mid = (glo + ghi) >> 1;
             if (s_cp[mid] <= ck) glo = mid; else ghi = mid;
         }
-        event_chunk(d, s_pref, NS, e, glo, s_ne[glo], ck - s_cp[glo]);
+        return event_record(d, e, glo, s_ne[glo], ck - s_cp[glo], rec, rq);
+    };
+    // each wave's next chunk's records are loaded before it works on the
+    // current one, so that their latency overlaps the current chunk's loads
+    uint32_t ck = blockIdx.x * kW + wid;
+    uint4 rec = make_uint4(0u, 0u, 0u, 0u), rq = rec;
+    bool act = ck < nchunk && records(ck, rec, rq);
+    while (ck < nchunk) {
+        const uint32_t nx = ck + stride;
+        uint4 rec_n = make_uint4(0u, 0u, 0u, 0u), rq_n = rec_n;
+        const bool act_n = nx < nchunk && records(nx, rec_n, rq_n);
+        event_chunk(d, s_pref, NS, e, act, rec, rq);
+        rec = rec_n;
+        rq = rq_n;
+        act = act_n;
+        ck = nx;
     }
 }
 
