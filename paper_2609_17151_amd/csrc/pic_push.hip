@@ -375,9 +375,9 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 
 }  // namespace
 
-// The events pass over one chunk of 64 events (defined with the events
-// kernel below): chunk kc of push workgroup g's tile range, one event per
-// lane.
+// The events pass over one chunk of 64 events of a push workgroup's list,
+// one event per lane (defined with the events kernel below): the records of
+// the chunk, then the work on them.
 struct EvPass {
     int32_t T;                    // particles of the push's tile
     int32_t chunk_t, NT;          // tiles per push workgroup, tiles in all
@@ -874,10 +874,8 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) { return (uint32_t)__pop
 
 }  // namespace
 
-// the events pass over one chunk (declared above the push kernel): events
-// 64 kc .. 64 kc + 63 of the nev that push workgroup g recorded
-// This lane's event of chunk kc (64 consecutive events) of push workgroup
-// g's list of nev: its two record words; false past the list's end.
+// This lane's event of chunk kc (events 64 kc .. 64 kc + 63) of the nev that
+// push workgroup g recorded: its two record words; false past the list's end.
 __device__ __forceinline__ bool event_record(const DevPtrs& d, const EvPass& ps, int g, uint32_t nev, uint32_t kc,
                                              uint4& rec, uint4& rq)
 {
@@ -889,6 +887,7 @@ __device__ __forceinline__ bool event_record(const DevPtrs& d, const EvPass& ps,
     return true;
 }
 
+// The events pass on one chunk: lanes with `act` hold an event's records.
 __device__ __forceinline__ void event_chunk(const DevPtrs& d, const int32_t* s_pref, int NS, const EvPass& ps,
                                             bool act, uint4 rec, uint4 rq)
 {
