@@ -286,7 +286,7 @@ def main():
         print(json.dumps({"calibration_copy_bytes": n * 4, "reads_bytes": n * 4, "writes_bytes": n * 4}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the step runs on one GPU; --gpus must be 1 (the design for more GPUs is described, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W
