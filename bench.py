@@ -203,6 +203,19 @@ def tuned(sim, tune):
                                             round(1e3 * r["ms_per_step"], 2) for r in table})
 
 
+def sweep_counts(W, sweep_particles=0):
+    """The 64-discharge sweep's macro-particles per species and their
+    weights: the steady-state counts at the pilot weight, or those counts
+    scaled to `sweep_particles` in all (both species; at least 1000 each)
+    with each weight scaled by the inverse of its count's factor, so that
+    every discharge keeps its densities."""
+    counts0 = W.steady_counts(64)
+    counts = counts0
+    if sweep_particles:
+        counts = np.maximum(1000, np.rint(counts0 * (sweep_particles / (2.0 * counts0.sum())))).astype(int)
+    return counts, W.PILOT_WEIGHT * counts0 / counts
+
+
 def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True, sweep_particles=0):
     """The bounded, colliding path at steady-state counts: one argon RF
     discharge (2.5 cm, 30 mTorr, 200 V, 13.56 MHz, 1600 steps per period,
@@ -230,11 +243,7 @@ def secondary(P, W, torch, steps, only=None, warm=3200, graphs=True, tune=True, 
     if only not in (None, "argon_sweep"):
         return out
     draws = W.sweep_draws(64, seed=4)
-    counts0 = W.steady_counts(64)
-    counts = counts0
-    if sweep_particles:
-        counts = np.maximum(1000, np.rint(counts0 * (sweep_particles / (2.0 * counts0.sum())))).astype(int)
-    weights = W.PILOT_WEIGHT * counts0 / counts
+    counts, weights = sweep_counts(W, sweep_particles)
     cfgs = [W.argon_rf(gap=d["gap"], n_cells=d["n_cells"], pressure_mtorr=d["pressure_mtorr"], v_amp=d["v_amp"],
                        seed=1000 + i, capacity=4 * int(counts[i]) + 65536, weight=float(weights[i]))
             for i, d in enumerate(draws)]

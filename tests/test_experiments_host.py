@@ -58,3 +58,13 @@ def test_kernel_hash_follows_code_not_comments():
     # every committed push summary was taken of the kernel built from this tree
     assert bench.measured_traffic() is not None
     assert bench.rocprof_push_us() is not None
+
+
+def test_scaled_sweep_keeps_each_discharges_density():
+    import workloads as W
+    c0, w0 = bench.sweep_counts(W)
+    assert np.all(w0 == W.PILOT_WEIGHT)
+    c, w = bench.sweep_counts(W, 1.77e7)
+    assert abs(2 * c.sum() - 1.77e7) < 0.01 * 1.77e7 and c.min() >= 1000
+    # the real particles each discharge represents are unchanged
+    np.testing.assert_allclose(c * w, c0 * w0, rtol=1e-12)
