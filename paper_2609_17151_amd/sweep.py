@@ -81,7 +81,6 @@ class Sweep:
             self._tune(self.tune_cache)
         if self.chunk > 0:
             return self._run_device(stop, t_start)
-            return self._run_device(stop)
         sim = self.sim
         sim.set_diag(True)
         for b in range(self.B):

@@ -159,3 +159,27 @@ def test_device_windows_early_stop():
     assert len(sw.windows[0]) == 3 and len(sw.windows[1]) == 100
     with pytest.raises(ValueError):
         Sweep(FakeWindowSim(1), [1], window_periods=1, chunk=64).run()
+
+
+def test_retune_when_the_running_discharges_halve(monkeypatch):
+    # four discharges of 1, 1, 2 and 4 windows: the schedule is tuned at the
+    # start (4 running), again when 2 run, and again when 1 runs
+    tuned = []
+
+    def fake_tune(self, cache=None):
+        running = self.done.count(False)
+        tuned.append(running)
+        self._tuned_running = running
+        return 0
+
+    monkeypatch.setattr(Sweep, "_tune", fake_tune)
+    sim = FakeWindowSim(4)
+    lengths = [1, 1, 2, 4]
+    sw = Sweep(sim, [8, 8, 8, 8], window_periods=1, max_periods=4, chunk=8, tune=True)
+    sw.run(stop=lambda b, s: len(s.windows[b]) >= lengths[b])
+    assert tuned == [4, 2, 1]
+    sim2 = FakeWindowSim(4)
+    tuned.clear()
+    Sweep(sim2, [8, 8, 8, 8], window_periods=1, max_periods=4, chunk=8, tune=True, retune=False).run(
+        stop=lambda b, s: len(s.windows[b]) >= lengths[b])
+    assert tuned == [4]
