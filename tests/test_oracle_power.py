@@ -12,7 +12,6 @@ the sampled steps.  Statistical: the Maxwell-model swarm at its steady drift
 in a periodic box, where dGamma/dt averages out and the gradient terms
 vanish summed over the box, so the ohmic term carries the field's power."""
 import numpy as np
-import pytest
 
 import oracle
 import workloads as W
