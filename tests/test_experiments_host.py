@@ -68,3 +68,22 @@ def test_scaled_sweep_keeps_each_discharges_density():
     assert abs(2 * c.sum() - 1.77e7) < 0.01 * 1.77e7 and c.min() >= 1000
     # the real particles each discharge represents are unchanged
     np.testing.assert_allclose(c * w, c0 * w0, rtol=1e-12)
+
+
+def test_bench_schedule_string_is_applied_as_given():
+    class Sim:
+        def __init__(self):
+            self.tiles, self.events = None, None
+
+        def config_tiles(self, ppt, threads, sort_every, compact_every):
+            self.tiles = (ppt, threads, sort_every, compact_every)
+
+        def config_events(self, in_push):
+            self.events = in_push
+
+    sim = Sim()
+    out = bench.tuned(sim, "4,1024,32,0")
+    assert sim.tiles == (4, 1024, 0, 32) and sim.events is False
+    assert out["choice"] == dict(ppt=4, threads=1024, sort_every=0, compact_every=32, fuse=0)
+    sim = Sim()
+    assert bench.tuned(sim, False) == dict(choice="default") and sim.tiles is None
